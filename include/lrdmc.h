@@ -1,0 +1,196 @@
+/*
+ * lrdmc.h -- C ABI of the MI355X (gfx950) lattice-regularized diffusion Monte
+ * Carlo hot path: the per-walker projection step between branchings, run for
+ * the whole walker population on one GPU, and the weight-based
+ * reconfiguration that follows it.
+ *
+ * Method: K. Nakano, S. Sorella, M. Casula, "Load-Balanced Diffusion Monte
+ * Carlo Method with Lattice Regularization", arXiv:2508.12033.
+ *   - conventional continuous-time scheme: Sec. II.B, Algorithm 1;
+ *   - load-balanced fixed-N_proj scheme: Sec. II.C, Algorithm 2;
+ *   - reconfiguration and estimators: Sec. II.A;
+ *   - fixed-node lattice Hamiltonian, regularized potential: App. D.
+ *
+ * Conventions for every call:
+ *   - Return value: 0 = success, < 0 = error (LRDMC_ERR_*).  No C++
+ *     exception crosses this boundary.  lrdmc_last_error() returns a
+ *     thread-local message describing the last error of the calling thread.
+ *   - Host arrays are owned by the caller and are copied during the call.
+ *   - The device workspace is owned by the caller (any device allocation,
+ *     e.g. a torch tensor), must stay valid until lrdmc_destroy and is never
+ *     freed by the library.  The handle owns only host-side metadata.
+ *   - All device work is enqueued on the caller's HIP stream (passed as
+ *     void* = hipStream_t); calls that return host results synchronise that
+ *     stream.  A handle is not thread-safe.
+ *   - Units: bohr and hartree.
+ *   - Electrons 0..n_up-1 are spin up.  Lattice move p = (3 i + d) * 2 + s
+ *     moves electron i by +a (s = 0) or -a (s = 1) along axis d (x, y, z).
+ */
+#ifndef LRDMC_H
+#define LRDMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define LRDMC_OK                   0
+#define LRDMC_ERR_INVALID_ARG     -1  /* bad size, pointer or parameter */
+#define LRDMC_ERR_HIP             -2  /* a HIP runtime call failed */
+#define LRDMC_ERR_WORKSPACE       -3  /* workspace smaller than lrdmc_workspace_bytes */
+#define LRDMC_ERR_SINGULAR        -4  /* a Slater matrix is exactly singular */
+#define LRDMC_ERR_ALL_DEAD        -5  /* every walker weight is zero at branching */
+#define LRDMC_ERR_UNSUPPORTED     -6  /* sizes beyond what the kernels support */
+
+/* ---- enumerations ------------------------------------------------------ */
+#define LRDMC_SCHEME_LB    0   /* load-balanced, fixed N_proj (Algorithm 2) */
+#define LRDMC_SCHEME_CONV  1   /* conventional continuous time (Algorithm 1) */
+
+#define LRDMC_FP64         0   /* every step in FP64 */
+
+#define LRDMC_BASIS_S      0   /* exp(-alpha r^2) */
+#define LRDMC_BASIS_PX     1   /* (x-X) exp(-alpha r^2), likewise PY, PZ */
+#define LRDMC_BASIS_PY     2
+#define LRDMC_BASIS_PZ     3
+#define LRDMC_BASIS_STO1S  4   /* exp(-zeta r) */
+
+#define LRDMC_CORE_BARE    0   /* -Z/r; lattice bound -Z/max(r,a) (App. D) */
+#define LRDMC_CORE_SOFT    1   /* -Z erf(r/rc)/r, a smooth local core */
+
+#define LRDMC_NU_OPT_OWN   0   /* nu_max for electron i iff one of its own 6
+                                  moves crosses the node (App. D nu_opt) */
+#define LRDMC_NU_OPT_ANY   1   /* iff any of the 6N moves crosses the node */
+#define LRDMC_NU_MAX       2   /* nu_max = max(nu_zv, nu^a_ei) for every electron */
+
+/* ---- system description (App. D Hamiltonian, Jastrow-Slater guide) ---- */
+typedef struct lrdmc_system {
+    int32_t n_atoms;
+    const double *atom_pos;      /* [n_atoms][3] */
+    const double *atom_charge;   /* [n_atoms] Z (bare) or valence Z_v (soft core) */
+    const int32_t *atom_core;    /* [n_atoms] LRDMC_CORE_* */
+    const double *core_rc;       /* [n_atoms] soft-core radius (ignored if bare) */
+    const int32_t *atom_species; /* [n_atoms] in [0, n_species): e-n Jastrow row */
+    int32_t n_basis;
+    const int32_t *basis_atom;   /* [n_basis] centre */
+    const int32_t *basis_type;   /* [n_basis] LRDMC_BASIS_* */
+    const double *basis_exp;     /* [n_basis] alpha (Gaussian) or zeta (Slater) */
+    int32_t n_orb;               /* >= max(n_up, n_dn); spin s uses columns 0..n_s-1 */
+    const double *mo_coeff;      /* [n_basis][n_orb] row-major */
+    int32_t n_up, n_dn;
+    int32_t n_species;
+    const double *jastrow;       /* [2 + n_species][3]: (A, B, b) of
+                                    u(r) = (A r + B r^2)/(1 + b r); row 0 parallel
+                                    e-e, row 1 antiparallel e-e, row 2+s e-n */
+    int32_t n_walkers;           /* walkers of this system */
+    uint64_t system_id;          /* second Philox key word */
+} lrdmc_system;
+
+/* ---- run parameters ---------------------------------------------------- */
+typedef struct lrdmc_params {
+    int32_t scheme;          /* LRDMC_SCHEME_* */
+    int32_t precision;       /* LRDMC_FP64 */
+    double a;                /* lattice space (bohr) */
+    double tau;              /* conventional: projection time per branching */
+    int32_t n_proj;          /* load-balanced: steps per branching */
+    uint64_t seed;           /* first Philox key word */
+    int32_t refresh_every;   /* FP64 inverse / Jastrow refresh cadence (steps), >= 1 */
+    int32_t nu_opt_mode;     /* LRDMC_NU_* */
+    int32_t p_corr;          /* correcting factors: product of the p previous
+                                average weights (Sec. II.A) */
+    int32_t e0_window;       /* E_0 = mean of the last e0_window walker-averaged
+                                local energies (load-balanced, Algorithm 2) */
+    int32_t trace_cap;       /* > 0: record every walker's moves, up to this many
+                                per branching, for the parity harness */
+} lrdmc_params;
+
+/* ---- statistics returned to the caller --------------------------------- */
+typedef struct lrdmc_step_stats {
+    int64_t walker_iters;    /* sum over walkers of the iterations that
+                                evaluated all 6N ratios */
+    int32_t max_iters;       /* slowest walker (conventional) or N_proj */
+    int32_t min_iters;
+    int64_t n_neg_weight;    /* evaluations with W - E_0 <= 0 (walker weight set to 0) */
+    int64_t n_no_move;       /* evaluations with no allowed move (bbar = 0) */
+    int64_t n_refresh;       /* FP64 refreshes performed (scheduled + forced) */
+    int64_t n_small_ratio;   /* forced refreshes after |R_det| < 1e-6 */
+    int64_t n_capped;        /* conventional walkers stopped by the termination
+                                bound of 1000 * tau * 3N / a^2 + 10000 iterations */
+    double elapsed_ms;       /* device time of the phase (HIP events) */
+} lrdmc_step_stats;
+
+typedef struct lrdmc_branch_stats {
+    double log_wbar;         /* log of the average weight before reconfiguration */
+    double e_bar;            /* walker-averaged local energy (Sec. II.A / II.C) */
+    double e0;               /* E_0 after the update */
+    double max_lw;           /* largest log-weight */
+    int32_t n_distinct;      /* distinct parents kept by the comb */
+    double elapsed_ms;       /* device time of the reconfiguration */
+} lrdmc_branch_stats;
+
+typedef struct lrdmc_energy {
+    double energy;           /* correcting-factor estimate of E_0 (Sec. II.A) */
+    double sigma;            /* blocking error bar */
+    int32_t n_used;          /* branchings used */
+} lrdmc_energy;
+
+/* ---- calls ------------------------------------------------------------- */
+
+/* Bytes of device workspace needed for these systems and parameters.  Pure
+ * function; 0 on invalid input (see lrdmc_last_error). */
+size_t lrdmc_workspace_bytes(const lrdmc_system *sys, int n_sys, const lrdmc_params *prm);
+
+/* Validate the inputs, upload the systems into the workspace, place every
+ * walker at init_pos ([sum of n_walkers][n_up+n_dn][3] host FP64, walkers of
+ * system 0 first), evaluate the local energies and set E_0 to their
+ * unweighted mean.  Synchronises `stream`.  *out receives the handle. */
+int lrdmc_init_system(const lrdmc_system *sys, int n_sys, const lrdmc_params *prm,
+                      const double *init_pos, void *dev_workspace, size_t ws_bytes,
+                      void *stream, struct lrdmc_handle **out);
+
+/* One projection phase for every walker (Algorithm 1 inner loop until every
+ * tau_left = 0, or Algorithm 2 inner loop of N_proj steps): ratios of all 6N
+ * lattice moves, lattice-regularized local energy with the fixed-node terms
+ * on the diagonal, weight update, heat-bath move, Sherman-Morrison update.
+ * Asynchronous on the handle's stream when st == NULL; otherwise synchronises
+ * and fills *st. */
+int lrdmc_step(struct lrdmc_handle *h, lrdmc_step_stats *st);
+
+/* Reconfiguration (Sec. II.A): walker-averaged local energy, FP64 prefix sum
+ * of the weights, comb with N_w correlated numbers, gather of the selected
+ * walkers, weights reset to 1; then appends (log wbar, e_bar) to the history
+ * and updates E_0.  Synchronises (one small device-to-host copy). */
+int lrdmc_branch(struct lrdmc_handle *h, lrdmc_branch_stats *st);
+
+/* Energy estimate from the branching history (Sec. II.A correcting factors,
+ * first 10 % of branchings dropped).  forces ([n_atoms][3]) and jgrad are
+ * reserved for the adjoint and must be NULL in this build. */
+int lrdmc_energy_forces(struct lrdmc_handle *h, lrdmc_energy *e, double *forces, double *jgrad);
+
+/* Host copies of the walker state of system `isys` for the parity harness.
+ * Any pointer may be NULL.  pos [nw][N][3], lw/eL/W [nw], iters [nw],
+ * sel [nw] (parents chosen by the last lrdmc_branch), trace [nw][trace_cap]
+ * (moves of the last phase; -1 marks the conventional stopping iteration,
+ * -2 unused).  Synchronises. */
+int lrdmc_get_walkers(struct lrdmc_handle *h, int isys, double *pos, double *lw, double *eL,
+                      double *W, int32_t *iters, int32_t *sel, int32_t *trace);
+
+/* Overwrite positions (and log-weights if lw != NULL) of system `isys`. */
+int lrdmc_set_walkers(struct lrdmc_handle *h, int isys, const double *pos, const double *lw);
+
+/* Current E_0 of system isys; set_e0 overrides it (for the parity harness). */
+double lrdmc_get_e0(struct lrdmc_handle *h, int isys);
+int lrdmc_set_e0(struct lrdmc_handle *h, int isys, double e0);
+
+/* Branching index j used in the Philox counters of the next phase. */
+int lrdmc_get_branch_index(struct lrdmc_handle *h);
+
+void lrdmc_destroy(struct lrdmc_handle *h);
+const char *lrdmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRDMC_H */

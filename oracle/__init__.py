@@ -83,7 +83,7 @@ def lib():
         L.orc_conv_phase.argtypes = [vp, vp, u64, u64, vp, vp, vp, vp, vp, vp, i32, vp, vp]
         L.orc_comb.argtypes = [i32, vp, dbl, vp, vp, vp, dbl, vp]
         L.orc_population_phase.argtypes = [vp, vp, i32, i32, u64, i32, dbl, vp, vp, vp,
-                                           vp, vp, vp, i32, vp, i32, vp]
+                                           vp, vp, vp, i32, vp, i32, vp, vp]
         _lib = L
     return _lib
 
@@ -183,9 +183,10 @@ def comb(lw, xi, follow=None, band=1e-12):
 
 
 def population_phase(sys, prm, scheme, j, E0, pos, lw, follow=None, cap=None,
-                     slot0=0, nthreads=None, record=True):
+                     slot0=0, nthreads=None, record=True, slots=None):
     """One projection phase for every walker in `pos` ([nw,N,3], updated in
-    place); lw updated in place.  scheme 'lb' or 'conv'.  Returns
+    place); lw updated in place.  scheme 'lb' or 'conv'.  Walker w draws its
+    random numbers from Philox slot slots[w] (default slot0 + w).  Returns
     (eL, W, moves, iters, counters)."""
     nw = pos.shape[0]
     sch = 0 if scheme == "lb" else 1
@@ -198,10 +199,11 @@ def population_phase(sys, prm, scheme, j, E0, pos, lw, follow=None, cap=None,
     cnt = np.zeros(8, np.int64)
     f = None if follow is None else np.ascontiguousarray(follow, np.int32)
     nt = nthreads or os.cpu_count() or 1
+    sl = None if slots is None else np.ascontiguousarray(slots, np.int64)
     rc = lib().orc_population_phase(ct.byref(sys.c), ct.byref(prm), sch, nw, slot0, j, E0,
                                     pos.ctypes.data, lw.ctypes.data, eL.ctypes.data,
                                     W.ctypes.data, _p(f), _p(moves), cap, iters.ctypes.data,
-                                    nt, cnt.ctypes.data)
+                                    nt, cnt.ctypes.data, _p(sl))
     if rc:
         raise ArithmeticError("oracle phase failed (singular Slater matrix)")
     return eL, W, moves, iters, dict(zip(CNT_NAMES, cnt.tolist()))

@@ -688,7 +688,7 @@ typedef struct {
     double E0;
     double *pos, *lw, *eL, *W;
     const int32_t *follow; int32_t *moves; int32_t *iters;
-    uint64_t slot0;
+    uint64_t slot0; const int64_t *slots;
     int64_t cnt[CNT_LEN];
     int rc;
 } orc_job;
@@ -701,14 +701,15 @@ static void *phase_worker(void *arg)
     for (int w = jb->w0; w < jb->w1; w++) {
         const int32_t *f = jb->follow ? jb->follow + (size_t)w * stride : 0;
         int32_t *m = jb->moves ? jb->moves + (size_t)w * stride : 0;
+        uint64_t slot = jb->slots ? (uint64_t)jb->slots[w] : jb->slot0 + w;
         int rc;
         if (jb->scheme == 0) {
-            rc = orc_lb_phase(jb->s, jb->prm, jb->slot0 + w, jb->j, jb->E0, jb->pos + (size_t)w * 3 * N,
+            rc = orc_lb_phase(jb->s, jb->prm, slot, jb->j, jb->E0, jb->pos + (size_t)w * 3 * N,
                               jb->lw + w, jb->eL + w, jb->W + w, f, m, jb->cnt);
             if (jb->iters) jb->iters[w] = jb->prm->nproj;
         } else {
             int it = 0;
-            rc = orc_conv_phase(jb->s, jb->prm, jb->slot0 + w, jb->j, jb->pos + (size_t)w * 3 * N,
+            rc = orc_conv_phase(jb->s, jb->prm, slot, jb->j, jb->pos + (size_t)w * 3 * N,
                                 jb->lw + w, jb->eL + w, jb->W + w, f, m, jb->cap, &it, jb->cnt);
             if (jb->iters) jb->iters[w] = it;
         }
@@ -718,12 +719,13 @@ static void *phase_worker(void *arg)
 }
 
 /* scheme 0 = load-balanced, 1 = conventional.  Walker w uses Philox slot
- * slot0 + w.  follow/moves are [nw][stride] with stride nproj (LB) or cap
+ * slots[w] when slots is given, else slot0 + w.  follow/moves are [nw][stride] with stride nproj (LB) or cap
  * (conventional).  cnt_out[CNT_LEN] accumulates the counters. */
 int orc_population_phase(const orc_system *s, const orc_params *prm, int scheme, int nw,
                          uint64_t slot0, int j, double E0, double *pos, double *lw,
                          double *eL, double *W, const int32_t *follow, int32_t *moves,
-                         int cap, int32_t *iters, int nthreads, int64_t *cnt_out)
+                         int cap, int32_t *iters, int nthreads, int64_t *cnt_out,
+                         const int64_t *slots)
 {
     if (nthreads < 1) nthreads = 1;
     if (nthreads > nw) nthreads = nw > 0 ? nw : 1;
@@ -735,6 +737,7 @@ int orc_population_phase(const orc_system *s, const orc_params *prm, int scheme,
         jb->w0 = (int)((long)nw * t / nthreads); jb->w1 = (int)((long)nw * (t + 1) / nthreads);
         jb->E0 = E0; jb->pos = pos; jb->lw = lw; jb->eL = eL; jb->W = W;
         jb->follow = follow; jb->moves = moves; jb->iters = iters; jb->slot0 = slot0;
+        jb->slots = slots;
         pthread_create(&th[t], 0, phase_worker, jb);
     }
     int rc = 0;

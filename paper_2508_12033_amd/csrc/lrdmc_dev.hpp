@@ -1,0 +1,61 @@
+// Device-side descriptors shared by the host orchestration and the kernels of
+// the lattice-regularized DMC library.  Everything here is plain data: the
+// host fills these structs and passes them by value as kernel arguments.
+#pragma once
+#include <stdint.h>
+
+namespace lrdmc {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kMaxBranchBlock = 1024;
+
+enum : int { kMove = 0, kPersist = 1, kComb = 2, kInit = 3 };   // Philox purposes
+
+// counters accumulated by one projection phase (device, 64-bit)
+enum : int {
+    kCntIters = 0, kCntNegW = 1, kCntNoMove = 2, kCntRefresh = 3, kCntSmallR = 4,
+    kCntSingular = 5, kCntMaxIters = 6, kCntMinIters = 7, kCntCapped = 8, kCntLen = 9
+};
+
+// One molecular system, its walkers, and the per-walker state layout.
+struct DevSys {
+    // sizes
+    int M, Nb, Norb, Nup, Ndn, N, P, ns, nspec, nw, has_en;
+    double vii;              // ion-ion repulsion (host-computed constant)
+    uint64_t sysid;
+    // system arrays (device)
+    const double *R, *Z, *rc, *bexp, *C, *jas;
+    const int32_t *core, *spec, *batom, *btype;
+    // walker arrays (device)
+    double *pos;             // [nw][N][3]
+    double *lw, *eL, *Wd;    // [nw]
+    double *spill;           // [nw][spill_stride]: orbital rows at the 6N moves and
+                             // orbital derivatives at the current positions
+    long spill_stride;
+    int32_t *iters;          // [nw]
+    int32_t *trace;          // [nw][trace_cap] or null
+    int trace_cap;
+    // LDS layout of one walker (offsets in doubles)
+    int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje,
+        o_scal, o_B, o_rows, o_tmp, lds_doubles;
+    // spill layout (offsets in doubles inside a walker's spill block)
+    int s_Phi, s_dPhi;
+};
+
+struct PhaseArgs {
+    int scheme;              // 0 load-balanced, 1 conventional
+    int nproj;
+    int j;                   // branching index (Philox counter word 1)
+    int refresh_every;
+    int nu_mode;
+    int conv_cap;            // hard bound on conventional iterations per phase
+    double a, tau, E0;
+    uint64_t seed;
+    unsigned long long *counters;   // [kCntLen]
+};
+
+// per-walker scalars stored at o_scal
+enum : int { kScLogdet0 = 0, kScLogdet1 = 1, kScSign0 = 2, kScSign1 = 3, kScVee = 4,
+             kScLen = 8 };
+
+}  // namespace lrdmc

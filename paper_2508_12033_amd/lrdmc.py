@@ -1,0 +1,236 @@
+"""Thin ctypes binding of liblrdmc.so (C ABI in include/lrdmc.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of the library.  PyTorch supplies the device workspace and the HIP stream.
+There is no CPU fallback: if the library or a GPU is missing, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblrdmc.so")
+
+SCHEME_LB, SCHEME_CONV = 0, 1
+FP64 = 0
+NU_OPT_OWN, NU_OPT_ANY, NU_MAX = 0, 1, 2
+
+ERRORS = {-1: "INVALID_ARG", -2: "HIP", -3: "WORKSPACE", -4: "SINGULAR", -5: "ALL_DEAD",
+          -6: "UNSUPPORTED"}
+
+
+class LrdmcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("lrdmc error %d (%s): %s" % (code, ERRORS.get(code, "?"), msg))
+        self.code = code
+
+
+class lrdmc_system(ct.Structure):
+    _fields_ = [("n_atoms", ct.c_int32), ("atom_pos", ct.c_void_p), ("atom_charge", ct.c_void_p),
+                ("atom_core", ct.c_void_p), ("core_rc", ct.c_void_p),
+                ("atom_species", ct.c_void_p), ("n_basis", ct.c_int32),
+                ("basis_atom", ct.c_void_p), ("basis_type", ct.c_void_p),
+                ("basis_exp", ct.c_void_p), ("n_orb", ct.c_int32), ("mo_coeff", ct.c_void_p),
+                ("n_up", ct.c_int32), ("n_dn", ct.c_int32), ("n_species", ct.c_int32),
+                ("jastrow", ct.c_void_p), ("n_walkers", ct.c_int32), ("system_id", ct.c_uint64)]
+
+
+class lrdmc_params(ct.Structure):
+    _fields_ = [("scheme", ct.c_int32), ("precision", ct.c_int32), ("a", ct.c_double),
+                ("tau", ct.c_double), ("n_proj", ct.c_int32), ("seed", ct.c_uint64),
+                ("refresh_every", ct.c_int32), ("nu_opt_mode", ct.c_int32),
+                ("p_corr", ct.c_int32), ("e0_window", ct.c_int32), ("trace_cap", ct.c_int32)]
+
+
+class lrdmc_step_stats(ct.Structure):
+    _fields_ = [("walker_iters", ct.c_int64), ("max_iters", ct.c_int32),
+                ("min_iters", ct.c_int32), ("n_neg_weight", ct.c_int64),
+                ("n_no_move", ct.c_int64), ("n_refresh", ct.c_int64),
+                ("n_small_ratio", ct.c_int64), ("n_capped", ct.c_int64),
+                ("elapsed_ms", ct.c_double)]
+
+
+class lrdmc_branch_stats(ct.Structure):
+    _fields_ = [("log_wbar", ct.c_double), ("e_bar", ct.c_double), ("e0", ct.c_double),
+                ("max_lw", ct.c_double), ("n_distinct", ct.c_int32), ("elapsed_ms", ct.c_double)]
+
+
+class lrdmc_energy(ct.Structure):
+    _fields_ = [("energy", ct.c_double), ("sigma", ct.c_double), ("n_used", ct.c_int32)]
+
+
+EXPORTS = ["lrdmc_workspace_bytes", "lrdmc_init_system", "lrdmc_step", "lrdmc_branch",
+           "lrdmc_energy_forces", "lrdmc_get_walkers", "lrdmc_set_walkers", "lrdmc_get_e0",
+           "lrdmc_set_e0", "lrdmc_get_branch_index", "lrdmc_destroy", "lrdmc_last_error"]
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load the HIP library (torch first, so that one HIP runtime serves both)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads the HIP runtime torch was built with)
+    if not os.path.exists(path):
+        raise ImportError("liblrdmc.so is not built (run paper_2508_12033_amd.build)")
+    L = ct.CDLL(path)
+    vp, i32, sz, dbl = ct.c_void_p, ct.c_int32, ct.c_size_t, ct.c_double
+    L.lrdmc_workspace_bytes.argtypes = [vp, ct.c_int, vp]
+    L.lrdmc_workspace_bytes.restype = sz
+    L.lrdmc_init_system.argtypes = [vp, ct.c_int, vp, vp, vp, sz, vp, ct.POINTER(vp)]
+    L.lrdmc_step.argtypes = [vp, vp]
+    L.lrdmc_branch.argtypes = [vp, vp]
+    L.lrdmc_energy_forces.argtypes = [vp, vp, vp, vp]
+    L.lrdmc_get_walkers.argtypes = [vp, ct.c_int, vp, vp, vp, vp, vp, vp, vp]
+    L.lrdmc_set_walkers.argtypes = [vp, ct.c_int, vp, vp]
+    L.lrdmc_get_e0.argtypes = [vp, ct.c_int]
+    L.lrdmc_get_e0.restype = dbl
+    L.lrdmc_set_e0.argtypes = [vp, ct.c_int, dbl]
+    L.lrdmc_get_branch_index.argtypes = [vp]
+    L.lrdmc_destroy.argtypes = [vp]
+    L.lrdmc_destroy.restype = None
+    L.lrdmc_last_error.restype = ct.c_char_p
+    for k in ("lrdmc_init_system", "lrdmc_step", "lrdmc_branch", "lrdmc_energy_forces",
+              "lrdmc_get_walkers", "lrdmc_set_walkers", "lrdmc_set_e0",
+              "lrdmc_get_branch_index"):
+        getattr(L, k).restype = ct.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc < 0:
+        raise LrdmcError(rc, _lib.lrdmc_last_error().decode())
+    return rc
+
+
+def _sys_struct(d, keep):
+    arrs = {}
+    for k, dt in (("atom_pos", np.float64), ("atom_charge", np.float64), ("atom_core", np.int32),
+                  ("core_rc", np.float64), ("atom_species", np.int32), ("basis_atom", np.int32),
+                  ("basis_type", np.int32), ("basis_exp", np.float64), ("mo_coeff", np.float64),
+                  ("jastrow", np.float64)):
+        arrs[k] = np.ascontiguousarray(d[k], dtype=dt)
+        keep.append(arrs[k])
+    n_walkers = int(d.get("n_walkers_run", d["init_pos"].shape[0]))
+    return lrdmc_system(
+        int(arrs["atom_pos"].shape[0]), arrs["atom_pos"].ctypes.data,
+        arrs["atom_charge"].ctypes.data, arrs["atom_core"].ctypes.data,
+        arrs["core_rc"].ctypes.data, arrs["atom_species"].ctypes.data,
+        int(arrs["basis_exp"].shape[0]), arrs["basis_atom"].ctypes.data,
+        arrs["basis_type"].ctypes.data, arrs["basis_exp"].ctypes.data,
+        int(arrs["mo_coeff"].shape[1]), arrs["mo_coeff"].ctypes.data, int(d["n_up"]),
+        int(d["n_dn"]), int(arrs["jastrow"].shape[0] - 2), arrs["jastrow"].ctypes.data,
+        n_walkers, int(d.get("system_id", 0)))
+
+
+def make_params(scheme="lb", a=0.2, tau=0.25, n_proj=300, seed=12033, refresh_every=16,
+                nu_opt_mode=NU_OPT_OWN, p_corr=10, e0_window=50, trace_cap=0):
+    return lrdmc_params(SCHEME_LB if scheme == "lb" else SCHEME_CONV, FP64, float(a), float(tau),
+                        int(n_proj), int(seed), int(refresh_every), int(nu_opt_mode), int(p_corr),
+                        int(e0_window), int(trace_cap))
+
+
+def params_for(d, scheme="lb", **kw):
+    """Parameters from a generated system dict (a, tau, n_proj, seed, nu mode)."""
+    base = dict(a=d["a"], tau=d["tau"], n_proj=d["n_proj"], seed=d["seed"],
+                nu_opt_mode=int(d.get("nu_opt_mode", 0)))
+    base.update(kw)
+    return make_params(scheme, **base)
+
+
+class Handle:
+    """Owns the torch workspace tensor and the library handle of one run.
+
+    systems: list of generator dicts; init_pos of each is used (or the
+    n_walkers_run first walkers if that key is present)."""
+
+    def __init__(self, systems, prm, device="cuda:0", stream=None):
+        import torch
+        L = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the lattice-regularized DMC library runs only on gfx950")
+        if isinstance(systems, dict):
+            systems = [systems]
+        self.systems = systems
+        self.prm = prm
+        self.keep = []
+        arr = (lrdmc_system * len(systems))(*[_sys_struct(d, self.keep) for d in systems])
+        self.sys_arr = arr
+        self.nw = [int(s.n_walkers) for s in arr]
+        self.N = [int(s.n_up + s.n_dn) for s in arr]
+        init = np.concatenate([np.ascontiguousarray(d["init_pos"][:nw], np.float64).reshape(-1)
+                               for d, nw in zip(systems, self.nw)])
+        self.keep.append(init)
+        nbytes = L.lrdmc_workspace_bytes(ct.byref(arr), len(systems), ct.byref(prm))
+        if nbytes == 0:
+            raise LrdmcError(-1, L.lrdmc_last_error().decode())
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.ws.data_ptr()
+            off = (-base) % 256
+            self.stream = stream or torch.cuda.current_stream(self.device)
+            h = ct.c_void_p()
+            _check(L.lrdmc_init_system(ct.byref(arr), len(systems), ct.byref(prm), init.ctypes.data,
+                                       base + off, nbytes, self.stream.cuda_stream, ct.byref(h)))
+        self.h = h
+        self.L = L
+
+    def step(self, stats=True):
+        st = lrdmc_step_stats()
+        _check(self.L.lrdmc_step(self.h, ct.byref(st) if stats else None))
+        return st if stats else None
+
+    def branch(self):
+        st = lrdmc_branch_stats()
+        _check(self.L.lrdmc_branch(self.h, ct.byref(st)))
+        return st
+
+    def energy(self):
+        e = lrdmc_energy()
+        _check(self.L.lrdmc_energy_forces(self.h, ct.byref(e), None, None))
+        return e.energy, e.sigma, e.n_used
+
+    def walkers(self, isys=0, trace=False):
+        nw, N = self.nw[isys], self.N[isys]
+        pos = np.zeros((nw, N, 3)); lw = np.zeros(nw); eL = np.zeros(nw); W = np.zeros(nw)
+        it = np.zeros(nw, np.int32); sel = np.zeros(nw, np.int32)
+        tr = np.zeros((nw, max(1, self.prm.trace_cap)), np.int32) if trace else None
+        _check(self.L.lrdmc_get_walkers(self.h, isys, pos.ctypes.data, lw.ctypes.data,
+                                        eL.ctypes.data, W.ctypes.data, it.ctypes.data,
+                                        sel.ctypes.data, None if tr is None else tr.ctypes.data))
+        out = dict(pos=pos, lw=lw, eL=eL, W=W, iters=it, sel=sel)
+        if trace:
+            out["trace"] = tr
+        return out
+
+    def set_walkers(self, pos, lw=None, isys=0):
+        pos = np.ascontiguousarray(pos, np.float64)
+        lwa = None if lw is None else np.ascontiguousarray(lw, np.float64)
+        _check(self.L.lrdmc_set_walkers(self.h, isys, pos.ctypes.data,
+                                        None if lwa is None else lwa.ctypes.data))
+
+    def e0(self, isys=0):
+        return self.L.lrdmc_get_e0(self.h, isys)
+
+    def set_e0(self, e0, isys=0):
+        _check(self.L.lrdmc_set_e0(self.h, isys, float(e0)))
+
+    def branch_index(self):
+        return self.L.lrdmc_get_branch_index(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.lrdmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

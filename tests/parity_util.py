@@ -1,0 +1,82 @@
+"""Helpers that run the GPU library and the CPU oracle side by side on the same
+seeded inputs and compare them (follow mode: where a decision of the two
+sides differs only inside the 1e-12 ambiguity band, the oracle adopts the GPU
+choice and the event is counted; any other difference is a hard mismatch)."""
+import sys
+
+import numpy as np
+
+import oracle as O
+from paper_2508_12033_amd import lrdmc as B
+
+# tolerances (FP64 path): local energy 1e-9 Ha per walker-step; ratios,
+# weights and the diagonal to 1e-12 relative (the accumulated log-weight
+# carries one rounding per step, hence the N_proj-scaled bound)
+TOL_EL = 1e-9
+TOL_W_REL = 1e-12
+TOL_LW = 1e-11
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def conv_cap(d, tau=None):
+    tau = d["tau"] if tau is None else tau
+    return int(3.0 * tau * 3 * d["n_elec"] / d["a"] ** 2) + 64
+
+
+def make_handle(d, scheme, nw, **kw):
+    d2 = dict(d)
+    d2["n_walkers_run"] = nw
+    cap = kw.pop("trace_cap", None)
+    if cap is None:
+        cap = d2["n_proj"] if scheme == "lb" else conv_cap(d2, kw.get("tau"))
+        if "n_proj" in kw and scheme == "lb":
+            cap = kw["n_proj"]
+    prm = B.params_for(d2, scheme, trace_cap=cap, **kw)
+    return B.Handle(d2, prm), d2, prm
+
+
+def oracle_params(S, prm):
+    return S.params(a=prm.a, tau=prm.tau, nproj=prm.n_proj, nu_opt_mode=prm.nu_opt_mode,
+                    seed=prm.seed)
+
+
+def compare_phase(d, prm, scheme, j, E0, pos0, lw0, g, idx, nthreads=8):
+    """Run the oracle on walkers idx from (pos0, lw0) following the GPU trace
+    and compare with the GPU result g (dict from Handle.walkers(trace=True)).
+    Returns a dict of the largest deviations and the counters."""
+    S = O.System(d)
+    op = oracle_params(S, prm)
+    idx = np.asarray(idx)
+    pos = np.array(pos0[idx], np.float64, copy=True)
+    lw = np.array(lw0[idx], np.float64, copy=True)
+    cap = prm.trace_cap
+    eL, W, moves, iters, cnt = O.population_phase(
+        S, op, scheme, j, E0, pos, lw, follow=g["trace"][idx], cap=cap, nthreads=nthreads,
+        slots=idx)
+    res = dict(cnt=cnt)
+    res["pos_equal"] = bool(np.array_equal(pos, g["pos"][idx]))
+    res["iters_equal"] = bool(np.array_equal(iters, g["iters"][idx]))
+    fin = np.isfinite(lw)
+    res["lw_dead_equal"] = bool(np.array_equal(fin, np.isfinite(g["lw"][idx])))
+    dl = np.abs(lw[fin] - g["lw"][idx][fin]) / np.maximum(1.0, np.abs(lw[fin]))
+    res["lw_err"] = float(dl.max()) if dl.size else 0.0
+    res["eL_err"] = float(np.max(np.abs(eL - g["eL"][idx])))
+    res["W_err"] = float(np.max(np.abs(W - g["W"][idx]) / np.abs(W)))
+    res["oracle"] = dict(pos=pos, lw=lw, eL=eL, W=W, iters=iters)
+    return res
+
+
+def assert_phase_ok(res, lw_tol=TOL_LW):
+    c = res["cnt"]
+    assert c["hard_mismatch"] == 0, res
+    assert c["singular"] == 0, res
+    assert res["pos_equal"], res
+    assert res["iters_equal"], res
+    assert res["lw_dead_equal"], res
+    assert res["lw_err"] < lw_tol, res
+    assert res["eL_err"] < TOL_EL, res
+    assert res["W_err"] < TOL_W_REL, res

@@ -1,0 +1,56 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and validates its inputs (no GPU needed: only pure host
+functions are called)."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+from paper_2508_12033_amd import inputs as I
+from paper_2508_12033_amd import lrdmc as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lrdmc.h")).read()
+    return sorted(set(re.findall(r"\b(lrdmc_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    L = B.load()
+    names = _declared()
+    assert set(names) == set(B.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_workspace_bytes_and_validation():
+    L = B.load()
+    d = I.c1_system(n_walkers=4096)
+    keep = []
+    s = B._sys_struct(d, keep)
+    prm = B.params_for(d)
+    n = L.lrdmc_workspace_bytes(ct.byref(s), 1, ct.byref(prm))
+    # walker state dominates: > positions + orbital rows of 4096 walkers
+    assert n > 4096 * (16 * 3 * 8 + 96 * 8 * 8)
+    assert n % 256 == 0
+    bad = B.params_for(d, a=-1.0)
+    assert L.lrdmc_workspace_bytes(ct.byref(s), 1, ct.byref(bad)) == 0
+    assert b"lattice space" in L.lrdmc_last_error()
+    h = ct.c_void_p()
+    rc = L.lrdmc_init_system(ct.byref(s), 1, ct.byref(prm), None, None, 0, None, ct.byref(h))
+    assert rc == -1 and not h.value
+    bad = B.params_for(d, refresh_every=0)
+    assert L.lrdmc_workspace_bytes(ct.byref(s), 1, ct.byref(bad)) == 0
+
+
+def test_layout_rejects_oversized_system():
+    L = B.load()
+    d = I.c3_system(n_walkers=2)
+    keep = []
+    s = B._sys_struct(d, keep)
+    prm = B.params_for(d)
+    assert L.lrdmc_workspace_bytes(ct.byref(s), 1, ct.byref(prm)) == 0
+    assert b"too large" in L.lrdmc_last_error()
