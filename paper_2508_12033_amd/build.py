@@ -21,10 +21,11 @@ FLAGS = [
 ]
 
 
-def build(verbose=False):
+def build(verbose=False, out=None, defines=()):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc] + FLAGS + SRC + ["-o", tmp]
+    lib = out or LIB
+    tmp = lib + ".tmp"
+    cmd = [hipcc] + FLAGS + ["-D" + d for d in defines] + SRC + ["-o", tmp]
     if verbose:
         print(" ".join(cmd))
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -34,8 +35,8 @@ def build(verbose=False):
         raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
     if verbose and msgs:
         print("\n".join(msgs))
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -15,7 +15,7 @@
 #include "lrdmc_dev.hpp"
 
 namespace lrdmc {
-__global__ void phase_fp64(DevSys s, PhaseArgs pa);
+__global__ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa);
 __global__ void branch_scan(DevSys s, int scheme, double E0, double* cum, double* out);
 __global__ void branch_comb(DevSys s, uint64_t seed, int j, const double* cum, const double* out,
                             int32_t* sel);
@@ -82,7 +82,7 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
     L.o_scal = take(kScLen);
     L.o_B = take(std::max(11 * s.n_basis, 2 * L.ns * L.ns));
     L.o_rows = take(11 * L.ns);
-    L.o_tmp = take(3 * L.ns + 2);
+    L.o_tmp = take(3 * L.ns + 8);
     L.lds_doubles = o;
     L.s_Phi = 0;
     L.s_dPhi = L.P * L.ns;
@@ -100,6 +100,7 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
                 + align_up(nw * 8)                  // cumulative weights
                 + align_up(8 * 8)                   // branch outputs
                 + align_up(8)                       // distinct counter
+                + 2 * align_up(sizeof(DevSys))      // device copies of the descriptor
                 + (p.trace_cap > 0 ? align_up(nw * (size_t)p.trace_cap * 4) : 0);
     (void)p;
     return L;
@@ -147,6 +148,9 @@ std::string validate(const lrdmc_system* sys, int n_sys, const lrdmc_params* prm
 
 struct SysRun {
     DevSys d;             // current buffers
+    DevSys* dsys[2];      // device copies of d for the two buffer parities
+    DevSys hsys[2];       // their host sources
+    int parity;
     double *pos_alt, *eL_alt, *W_alt;
     double *cum, *bout;
     int32_t* sel;
@@ -208,7 +212,8 @@ static int launch_phase(lrdmc_handle* h, SysRun& r)
     pa.E0 = r.e0;
     pa.seed = h->prm.seed;
     pa.counters = h->counters;
-    hipLaunchKernelGGL(phase_fp64, dim3(r.d.nw), dim3(kWave), r.lds_bytes, h->stream, r.d, pa);
+    hipLaunchKernelGGL(phase_fp64, dim3(r.d.nw), dim3(kWave), r.lds_bytes, h->stream,
+                       (const DevSys*)r.dsys[r.parity], pa);
     HIPCHK(hipGetLastError());
     return LRDMC_OK;
 }
@@ -321,6 +326,9 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
         d.o_B = L.o_B; d.o_rows = L.o_rows; d.o_tmp = L.o_tmp; d.lds_doubles = L.lds_doubles;
         d.s_Phi = L.s_Phi; d.s_dPhi = L.s_dPhi;
         r.lds_bytes = (size_t)L.lds_doubles * 8;
+        r.dsys[0] = (DevSys*)carve(sizeof(DevSys));
+        r.dsys[1] = (DevSys*)carve(sizeof(DevSys));
+        r.parity = 0;
         if (up(d.pos, ip, nw * 3 * L.N * 8) != hipSuccess ||
             hipMemsetAsync(d.lw, 0, nw * 8, h->stream) != hipSuccess) {
             rc = fail(LRDMC_ERR_HIP, "upload of walkers failed");
@@ -332,8 +340,17 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
         }
         ip += nw * 3 * L.N;
         h->sys.push_back(r);
+        SysRun& rr = h->sys.back();
+        rr.hsys[0] = rr.d;
+        rr.hsys[1] = rr.d;
+        rr.hsys[1].pos = rr.pos_alt; rr.hsys[1].eL = rr.eL_alt; rr.hsys[1].Wd = rr.W_alt;
     }
     if (rc == LRDMC_OK && off > ws_bytes) rc = fail(LRDMC_ERR_WORKSPACE, "workspace layout overflow");
+    for (auto& r : h->sys) {
+        if (rc) break;
+        if (up(r.dsys[0], &r.hsys[0], sizeof(DevSys)) || up(r.dsys[1], &r.hsys[1], sizeof(DevSys)))
+            rc = fail(LRDMC_ERR_HIP, "upload of system descriptors failed");
+    }
     if (rc == LRDMC_OK) {
         static bool attr = false;
         if (!attr) {
@@ -350,8 +367,8 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             pa.nu_mode = prm->nu_opt_mode; pa.a = prm->a; pa.tau = prm->tau; pa.E0 = 0.0;
             pa.conv_cap = 1;
             pa.seed = prm->seed; pa.counters = h->counters;
-            hipLaunchKernelGGL(phase_fp64, dim3(r.d.nw), dim3(kWave), r.lds_bytes, h->stream, r.d,
-                               pa);
+            hipLaunchKernelGGL(phase_fp64, dim3(r.d.nw), dim3(kWave), r.lds_bytes, h->stream,
+                               (const DevSys*)r.dsys[r.parity], pa);
             if (hipGetLastError() != hipSuccess) { rc = fail(LRDMC_ERR_HIP, "init launch failed"); break; }
             std::vector<double> eL(r.d.nw);
             if (hipMemcpyAsync(eL.data(), r.d.eL, r.d.nw * 8, hipMemcpyDeviceToHost, h->stream) ||
@@ -440,6 +457,7 @@ int lrdmc_branch(lrdmc_handle* h, lrdmc_branch_stats* st)
         HIPCHK(hipMemcpyAsync(&nd[k], r.ndist, sizeof(int), hipMemcpyDeviceToHost, h->stream));
         r.pos_alt = r.d.pos; r.eL_alt = r.d.eL; r.W_alt = r.d.Wd;
         r.d.pos = dn.pos; r.d.eL = dn.eL; r.d.Wd = dn.Wd;
+        r.parity ^= 1;
     }
     HIPCHK(hipEventRecord(h->ev1, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));

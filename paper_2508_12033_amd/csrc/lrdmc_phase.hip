@@ -46,43 +46,88 @@ __device__ __forceinline__ double philox_uniform(uint64_t k0, uint64_t k1, uint6
 }
 
 // ---------------------------------------------------------------------------
-// wavefront collectives; every lane receives lane 0's value so that all
-// lanes hold bit-identical results and control flow stays uniform
+// wavefront collectives on DPP (data-parallel primitives: lane shuffles that
+// run in the VALU, no LDS round trip).  A double moves as two 32-bit halves.
+// Every lane receives the same (lane 63) result so that control flow stays
+// uniform; the reduction order is fixed, so results are bit-reproducible.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_mov(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return __shfl(v, 0);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+    return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ double wave_incl_scan(double v, int lane)
+__device__ __forceinline__ double lane63(double v)
 {
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const double t = __shfl_up(v, o);
-        if (lane >= o) v += t;
-    }
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += dpp_mov<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_mov<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_mov<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_mov<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return lane63(v);
+}
+
+// inclusive prefix sum over the 64 lanes (Hillis-Steele inside 16-lane rows,
+// then row broadcasts)
+__device__ __forceinline__ double wave_incl_scan(double v, int)
+{
+    v += dpp_mov<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_mov<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_mov<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_mov<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_mov<0x142, 0xa>(v);   // row_bcast:15
+    v += dpp_mov<0x143, 0xc>(v);   // row_bcast:31
     return v;
 }
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
 
 // Pade pair function u(r) = (A r + B r^2)/(1 + b r) with u' and u''.
 __device__ __forceinline__ double pade_u(const double* p, double r)
 {
     return (p[0] * r + p[1] * r * r) / (1.0 + p[2] * r);
 }
-__device__ __forceinline__ void pade_all(const double* p, double r, double& u, double& du,
-                                         double& d2u)
+// u, u'/r and u'' + 2u'/r (the pieces of the gradient and Laplacian), with
+// one division for 1/(1 + b r) and one for 1/r
+__device__ __forceinline__ void pade_derivs(const double* p, double r, double& u, double& du_r,
+                                            double& lap)
 {
-    const double A = p[0], B = p[1], b = p[2], den = 1.0 + b * r;
-    u = (A * r + B * r * r) / den;
-    du = (A + 2.0 * B * r + B * b * r * r) / (den * den);
-    d2u = 2.0 * (B - A * b) / (den * den * den);
+    const double A = p[0], B = p[1], b = p[2];
+    const double iden = 1.0 / (1.0 + b * r), ir = 1.0 / r;
+    const double i2 = iden * iden;
+    u = (A * r + B * r * r) * iden;
+    const double du = (A + 2.0 * B * r + B * b * r * r) * i2;
+    du_r = du * ir;
+    lap = 2.0 * (B - A * b) * i2 * iden + 2.0 * du_r;
 }
 
 __device__ __forceinline__ double norm3(double x, double y, double z)
 {
     return sqrt(x * x + y * y + z * z);
+}
+
+// Point q of electron position r: r itself (q = 0) or its lattice neighbour
+// q = 1..6 in move order (+a x, -a x, +a y, -a y, +a z, -a z); the displaced
+// coordinate is formed by the same single addition as the move itself.
+__device__ __forceinline__ void point_q(const double* r, int q, double a, double* o)
+{
+    o[0] = r[0]; o[1] = r[1]; o[2] = r[2];
+    if (q == 1) o[0] = r[0] + a;
+    if (q == 2) o[0] = r[0] + (-a);
+    if (q == 3) o[1] = r[1] + a;
+    if (q == 4) o[1] = r[1] + (-a);
+    if (q == 5) o[2] = r[2] + a;
+    if (q == 6) o[2] = r[2] + (-a);
 }
 
 // Value of basis function mu at point r.
@@ -128,49 +173,96 @@ __device__ __forceinline__ void basis_vgl(const DevSys& s, int mu, const double*
 // ---------------------------------------------------------------------------
 // per-walker state views
 // ---------------------------------------------------------------------------
+// Per-walker state: offsets (in doubles) of the LDS-resident arrays inside
+// the dynamic shared-memory block, and the walker's block of the global
+// spill area (orbital rows at the 6N moves, orbital derivatives).
+extern __shared__ double lds[];
+
 struct Walker {
-    double *pos, *R, *Rdet, *dJ, *Arow, *AinvT, *Jg, *Jl, *nue, *nua, *dje, *scal, *B, *rows,
-        *tmp;
-    double *Phi, *dPhi;   // global spill
+    int pos, R, Rdet, dJ, Arow, AinvT, Jg, Jl, nue, nua, dje, scal, B, rows, tmp;
+    double* Phi;
+    double* dPhi;
 };
+
+__device__ __forceinline__ Walker walker_view(const DevSys& s)
+{
+    Walker w;
+    w.pos = s.o_pos; w.R = s.o_R; w.Rdet = s.o_Rdet; w.dJ = s.o_dJ; w.Arow = s.o_Arow;
+    w.AinvT = s.o_AinvT; w.Jg = s.o_Jg; w.Jl = s.o_Jl; w.nue = s.o_nue; w.nua = s.o_nua;
+    w.dje = s.o_dje; w.scal = s.o_scal; w.B = s.o_B; w.rows = s.o_rows; w.tmp = s.o_tmp;
+    double* base = s.spill + (long)blockIdx.x * s.spill_stride;
+    w.Phi = base + s.s_Phi;
+    w.dPhi = base + s.s_dPhi;
+    return w;
+}
 
 __device__ __forceinline__ int spin_of(const DevSys& s, int i) { return i >= s.Nup; }
 __device__ __forceinline__ int col_of(const DevSys& s, int i) { return i >= s.Nup ? i - s.Nup : i; }
 __device__ __forceinline__ int nspin(const DevSys& s, int sp) { return sp ? s.Ndn : s.Nup; }
-__device__ __forceinline__ const double* ee_par(const DevSys& s, int i, int k)
+__device__ __forceinline__ int ee_row(const DevSys& s, int i, int k)
 {
-    return s.jas + 3 * ((i >= s.Nup) == (k >= s.Nup) ? 0 : 1);
+    return ((i >= s.Nup) == (k >= s.Nup)) ? 0 : 1;
+}
+
+// Partner k of an electron: another electron (k < N, position in LDS) or a
+// nucleus (k >= N).  Returns its position and the row of its Pade parameters.
+__device__ __forceinline__ void partner(const DevSys& s, const Walker& w, int i, int k, double* pk,
+                                       int& jrow)
+{
+    if (k < s.N) {
+        pk[0] = lds[w.pos + 3 * k]; pk[1] = lds[w.pos + 3 * k + 1]; pk[2] = lds[w.pos + 3 * k + 2];
+        jrow = ee_row(s, i, k);
+    } else {
+        const int I = k - s.N;
+        pk[0] = s.R[3 * I]; pk[1] = s.R[3 * I + 1]; pk[2] = s.R[3 * I + 2];
+        jrow = 2 + s.spec[I];
+    }
 }
 
 // Orbital rows of electron j at position r (11 rows, columns k < n_j):
 // row 0 the value at r, rows 1..6 the values at the six lattice neighbours
 // r +- a e_d (move order), rows 7..9 the gradient, row 10 the Laplacian.
-__device__ void electron_rows(const DevSys& s, const Walker& w, int j, const double* r,
-                              double a, int lane)
+// Basis functions: one lane per (point, function).  Orbitals: the 11 x Nb
+// basis block times the Nb x n coefficient block on FP64 MFMA (16x16x4
+// tiles; rows 11..15 and columns >= n are padding).
+__device__ void electron_rows(const DevSys& s, const Walker& w, int j, const double* r, double a,
+                              int lane)
 {
-    for (int mu = lane; mu < s.Nb; mu += kWave) {
-        double v, g[3], l;
-        basis_vgl(s, mu, r, v, g, l);
-        w.B[0 * s.Nb + mu] = v;
-        for (int d = 0; d < 3; ++d)
-            for (int sg = 0; sg < 2; ++sg) {
-                double q[3] = {r[0], r[1], r[2]};
-                q[d] = q[d] + (sg ? -a : a);
-                w.B[(1 + 2 * d + sg) * s.Nb + mu] = basis_value(s, mu, q);
-            }
-        w.B[7 * s.Nb + mu] = g[0];
-        w.B[8 * s.Nb + mu] = g[1];
-        w.B[9 * s.Nb + mu] = g[2];
-        w.B[10 * s.Nb + mu] = l;
+    const int Nb = s.Nb;
+    for (int it = lane; it < 7 * Nb; it += kWave) {
+        const int q = it / Nb, mu = it - q * Nb;
+        double p[3];
+        point_q(r, q, a, p);
+        if (q == 0) {
+            double v, g[3], l;
+            basis_vgl(s, mu, p, v, g, l);
+            lds[w.B + mu] = v;
+            lds[w.B + 7 * Nb + mu] = g[0];
+            lds[w.B + 8 * Nb + mu] = g[1];
+            lds[w.B + 9 * Nb + mu] = g[2];
+            lds[w.B + 10 * Nb + mu] = l;
+        } else {
+            lds[w.B + q * Nb + mu] = basis_value(s, mu, p);
+        }
     }
     __syncthreads();
     const int n = nspin(s, spin_of(s, j));
-    for (int idx = lane; idx < 11 * n; idx += kWave) {
-        const int row = idx / n, k = idx - row * n;
-        const double* b = w.B + row * s.Nb;
-        double acc = 0.0;
-        for (int mu = 0; mu < s.Nb; ++mu) acc += s.C[mu * s.Norb + k] * b[mu];
-        w.rows[row * s.ns + k] = acc;
+    const int i16 = lane & 15, k4 = lane >> 4;
+    for (int t = 0; t * 16 < n; ++t) {
+        double4_t acc = {0.0, 0.0, 0.0, 0.0};
+        const int col = 16 * t + i16;
+        for (int k0 = 0; k0 < Nb; k0 += 4) {
+            const int mu = k0 + k4;
+            // A operand: row i16, inner index k4; B operand: inner k4, column i16
+            const double av = (i16 < 11 && mu < Nb) ? lds[w.B + i16 * Nb + mu] : 0.0;
+            const double bv = (col < n && mu < Nb) ? s.C[mu * s.Norb + col] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+        // D[row][col] with row = (lane >> 4) + 4 v
+        for (int v = 0; v < 4; ++v) {
+            const int row = k4 + 4 * v;
+            if (row < 11 && col < n) lds[w.rows + row * s.ns + col] = acc[v];
+        }
     }
     __syncthreads();
 }
@@ -181,8 +273,8 @@ __device__ void store_rows(const DevSys& s, const Walker& w, int j, int lane, bo
     const int n = nspin(s, spin_of(s, j));
     for (int idx = lane; idx < 11 * n; idx += kWave) {
         const int row = idx / n, k = idx - row * n;
-        const double v = w.rows[row * s.ns + k];
-        if (row == 0) { if (arow) w.Arow[j * s.ns + k] = v; }
+        const double v = lds[w.rows + row * s.ns + k];
+        if (row == 0) { if (arow) lds[w.Arow + j * s.ns + k] = v; }
         else if (row <= 6) w.Phi[(6 * j + row - 1) * s.ns + k] = v;
         else w.dPhi[(4 * j + row - 7) * s.ns + k] = v;
     }
@@ -190,67 +282,62 @@ __device__ void store_rows(const DevSys& s, const Walker& w, int j, int lane, bo
 }
 
 // FP64 Gauss-Jordan inverse with partial pivoting of the transposed Slater
-// matrix of spin sp: AinvT[c][k] = (A^-1)[k][c].  Accumulates log|det| and
-// sign.  Returns false for an exactly singular matrix.
+// matrix of spin sp: AinvT[c][k] = (A^-1)[k][c].  Sets log|det| and sign.
+// Returns false for an exactly singular matrix.
 __device__ bool refresh_inverse(const DevSys& s, const Walker& w, int sp, int lane)
 {
     const int n = nspin(s, sp);
     if (!n) return true;
     const int off = sp ? s.Nup : 0, n2 = 2 * n;
-    double* M = w.B;                     // [n][2n]
+    const int M = w.B;                   // [n][2n] scratch
     for (int idx = lane; idx < n * n2; idx += kWave) {
         const int r = idx / n2, c = idx - r * n2;
-        M[idx] = c < n ? w.Arow[(off + c) * s.ns + r] : (c - n == r ? 1.0 : 0.0);
+        lds[M + idx] = c < n ? lds[w.Arow + (off + c) * s.ns + r] : (c - n == r ? 1.0 : 0.0);
     }
     __syncthreads();
     double logdet = 0.0, sign = 1.0;
     bool ok = true;
     for (int j = 0; j < n; ++j) {
-        // pivot: largest |M[r][j]| for r >= j, first one on ties
+        // pivot: largest |M[r][j]| for r >= j, first one on ties (every lane
+        // scans the same LDS column, so the choice is uniform)
         double best = -1.0;
         int bi = n;
-        for (int r = j + lane; r < n; r += kWave) {
-            const double v = fabs(M[r * n2 + j]);
+        for (int r = j; r < n; ++r) {
+            const double v = fabs(lds[M + r * n2 + j]);
             if (v > best) { best = v; bi = r; }
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            const double ob = __shfl_xor(best, o);
-            const int oi = __shfl_xor(bi, o);
-            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-        best = __shfl(best, 0); bi = __shfl(bi, 0);
         if (!(best > 0.0)) { ok = false; break; }
         if (bi != j) {
             for (int c = lane; c < n2; c += kWave) {
-                const double t = M[j * n2 + c];
-                M[j * n2 + c] = M[bi * n2 + c];
-                M[bi * n2 + c] = t;
+                const double t = lds[M + j * n2 + c];
+                lds[M + j * n2 + c] = lds[M + bi * n2 + c];
+                lds[M + bi * n2 + c] = t;
             }
             sign = -sign;
             __syncthreads();
         }
-        const double pv = M[j * n2 + j];
+        const double pv = lds[M + j * n2 + j];
         logdet += log(fabs(pv));
         if (pv < 0) sign = -sign;
         __syncthreads();
-        for (int c = lane; c < n2; c += kWave) M[j * n2 + c] = M[j * n2 + c] / pv;
-        for (int r = lane; r < n; r += kWave) w.tmp[r] = M[r * n2 + j];
+        for (int c = lane; c < n2; c += kWave) lds[M + j * n2 + c] = lds[M + j * n2 + c] / pv;
+        for (int r = lane; r < n; r += kWave) lds[w.tmp + r] = lds[M + r * n2 + j];
         __syncthreads();
         for (int idx = lane; idx < n * n2; idx += kWave) {
             const int r = idx / n2, c = idx - r * n2;
-            if (r != j) M[idx] -= w.tmp[r] * M[j * n2 + c];
+            if (r != j) lds[M + idx] -= lds[w.tmp + r] * lds[M + j * n2 + c];
         }
         __syncthreads();
     }
     if (ok) {
-        double* Ai = w.AinvT + sp * s.ns * s.ns;
+        const int Ai = w.AinvT + sp * s.ns * s.ns;
         for (int idx = lane; idx < n * n; idx += kWave) {
             const int c = idx / n, k = idx - c * n;
-            Ai[c * s.ns + k] = M[c * n2 + n + k];
+            lds[Ai + c * s.ns + k] = lds[M + c * n2 + n + k];
         }
         if (lane == 0) {
-            w.scal[kScLogdet0 + sp] = logdet;
-            w.scal[kScSign0 + sp] = sign;
+            lds[w.scal + kScLogdet0 + sp] = logdet;
+            lds[w.scal + kScSign0 + sp] = sign;
         }
     }
     __syncthreads();
@@ -260,40 +347,48 @@ __device__ bool refresh_inverse(const DevSys& s, const Walker& w, int sp, int la
 // Full Jastrow / potential pieces of electron j from scratch: the Jastrow
 // exponent change of its 6 moves, grad_j J, lap_j J, nu_ei(r_j), nu^a_ei(r_j),
 // and its pair contribution to V_ee (pairs k > j).  Returns the V_ee part.
+// Partners k (other electrons, then nuclei) are spread over the lanes; the
+// 7 points of electron j are processed one after the other.
 __device__ double electron_jastrow(const DevSys& s, const Walker& w, int j, double a, int lane)
 {
-    const double* rj = w.pos + 3 * j;
-    double pts[7][3];
-    for (int q = 0; q < 7; ++q) {
-        pts[q][0] = rj[0]; pts[q][1] = rj[1]; pts[q][2] = rj[2];
-    }
-    for (int d = 0; d < 3; ++d)
-        for (int sg = 0; sg < 2; ++sg) pts[1 + 2 * d + sg][d] = rj[d] + (sg ? -a : a);
-    double S[7] = {0, 0, 0, 0, 0, 0, 0}, g[3] = {0, 0, 0}, l = 0.0, vee = 0.0, nu = 0.0,
-           nua = 0.0;
+    const double rj[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
     const int K = s.N + s.M;
+    const int Kj = s.has_en ? K : s.N;           // partners that carry Jastrow terms
+    double S0 = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < 7; ++q) {
+        double pq[3];
+        point_q(rj, q, a, pq);
+        double acc = 0.0;
+        for (int k = lane; k < Kj; k += kWave) {
+            if (k == j) continue;
+            double pk[3];
+            int jr;
+            partner(s, w, j, k, pk, jr);
+            acc += pade_u(s.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+        }
+        acc = wave_sum(acc);
+        if (q == 0) S0 = acc;
+        else if (lane == 0) lds[w.dJ + 6 * j + q - 1] = acc - S0;
+    }
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0, vee = 0.0, nu = 0.0, nua = 0.0;
     for (int k = lane; k < K; k += kWave) {
         if (k == j) continue;
-        const double* pk;
-        const double* prm;
         const bool isel = k < s.N;
-        if (isel) { pk = w.pos + 3 * k; prm = ee_par(s, j, k); }
-        else { pk = s.R + 3 * (k - s.N); prm = s.jas + 3 * (2 + s.spec[k - s.N]); }
-        const bool jas_on = isel || s.has_en;
-        if (jas_on) {
-            for (int q = 0; q < 7; ++q)
-                S[q] += pade_u(prm, norm3(pts[q][0] - pk[0], pts[q][1] - pk[1], pts[q][2] - pk[2]));
-            const double d[3] = {rj[0] - pk[0], rj[1] - pk[1], rj[2] - pk[2]};
-            const double r = norm3(d[0], d[1], d[2]);
-            double u, du, d2u;
-            pade_all(prm, r, u, du, d2u);
-            for (int c = 0; c < 3; ++c) g[c] += du * d[c] / r;
-            l += d2u + 2.0 * du / r;
+        double pk[3];
+        int jr;
+        partner(s, w, j, k, pk, jr);
+        const double d0 = rj[0] - pk[0], d1 = rj[1] - pk[1], d2 = rj[2] - pk[2];
+        const double r = norm3(d0, d1, d2);
+        if (isel || s.has_en) {
+            double u, dur, lp;
+            pade_derivs(s.jas + 3 * jr, r, u, dur, lp);
+            g0 += dur * d0; g1 += dur * d1; g2 += dur * d2;
+            l += lp;
             if (isel && k > j) vee += 1.0 / r;
         }
         if (!isel) {
             const int I = k - s.N;
-            const double r = norm3(rj[0] - pk[0], rj[1] - pk[1], rj[2] - pk[2]);
             if (s.core[I] == 0) {
                 nu += -s.Z[I] / r;
                 nua += -s.Z[I] / (r > a ? r : a);
@@ -303,13 +398,11 @@ __device__ double electron_jastrow(const DevSys& s, const Walker& w, int j, doub
             }
         }
     }
-    for (int q = 0; q < 7; ++q) S[q] = wave_sum(S[q]);
-    for (int c = 0; c < 3; ++c) g[c] = wave_sum(g[c]);
+    g0 = wave_sum(g0); g1 = wave_sum(g1); g2 = wave_sum(g2);
     l = wave_sum(l); vee = wave_sum(vee); nu = wave_sum(nu); nua = wave_sum(nua);
     if (lane == 0) {
-        for (int q = 0; q < 6; ++q) w.dJ[6 * j + q] = S[q + 1] - S[0];
-        for (int c = 0; c < 3; ++c) w.Jg[3 * j + c] = g[c];
-        w.Jl[j] = l; w.nue[j] = nu; w.nua[j] = nua;
+        lds[w.Jg + 3 * j] = g0; lds[w.Jg + 3 * j + 1] = g1; lds[w.Jg + 3 * j + 2] = g2;
+        lds[w.Jl + j] = l; lds[w.nue + j] = nu; lds[w.nua + j] = nua;
     }
     return vee;
 }
@@ -322,13 +415,13 @@ __device__ void recompute_ratios(const DevSys& s, const Walker& w, int sp, int l
         const int j = p / 6, spj = spin_of(s, j);
         if (sp < 0 || spj == sp) {
             const int n = nspin(s, spj), c = col_of(s, j);
-            const double* ai = w.AinvT + spj * s.ns * s.ns + c * s.ns;
+            const int ai = w.AinvT + spj * s.ns * s.ns + c * s.ns;
             const double* ph = w.Phi + p * s.ns;
             double rd = 0.0;
-            for (int k = 0; k < n; ++k) rd += ph[k] * ai[k];
-            w.Rdet[p] = rd;
+            for (int k = 0; k < n; ++k) rd += ph[k] * lds[ai + k];
+            lds[w.Rdet + p] = rd;
         }
-        w.R[p] = w.Rdet[p] * exp(w.dJ[p]);
+        lds[w.R + p] = lds[w.Rdet + p] * exp(lds[w.dJ + p]);
     }
     __syncthreads();
 }
@@ -341,7 +434,7 @@ __device__ bool refresh_all(const DevSys& s, const Walker& w, double a, int lane
     ok = refresh_inverse(s, w, 1, lane) && ok;
     double vee = 0.0;
     for (int j = 0; j < s.N; ++j) vee += electron_jastrow(s, w, j, a, lane);
-    if (lane == 0) w.scal[kScVee] = vee;
+    if (lane == 0) lds[w.scal + kScVee] = vee;
     __syncthreads();
     recompute_ratios(s, w, -1, lane);
     return ok;
@@ -351,13 +444,13 @@ __device__ bool refresh_all(const DevSys& s, const Walker& w, double a, int lane
 // (App. D; Sec. II.C e_L = W - bbar).
 struct Local { double bbar, W, eL; };
 
-__device__ Local evaluate(const DevSys& s, const Walker& w, const PhaseArgs& pa, int lane)
+__device__ Local evaluate(const DevSys& s, const Walker& w, double a, int nu_mode, int lane)
 {
-    const double a = pa.a, ia2 = 1.0 / (a * a), inv2a2 = 1.0 / (2.0 * a * a);
+    const double inv2a2 = 1.0 / (2.0 * a * a);
     double bs = 0.0, vs = 0.0;
     int anyneg = 0;
     for (int p = lane; p < s.P; p += kWave) {
-        const double r = w.R[p];
+        const double r = lds[w.R + p];
         if (r > 0) bs += r;
         else if (r < 0) { vs += -r; anyneg = 1; }
     }
@@ -367,38 +460,38 @@ __device__ Local evaluate(const DevSys& s, const Walker& w, const PhaseArgs& pa,
     double sum_opt = 0.0;
     for (int j = lane; j < s.N; j += kWave) {
         const int sp = spin_of(s, j), n = nspin(s, sp), c = col_of(s, j);
-        const double* ai = w.AinvT + sp * s.ns * s.ns + c * s.ns;
+        const int ai = w.AinvT + sp * s.ns * s.ns + c * s.ns;
         const double* dp = w.dPhi + 4 * j * s.ns;
         double g0 = 0, g1 = 0, g2 = 0, ld = 0;
         for (int k = 0; k < n; ++k) {
-            const double x = ai[k];
+            const double x = lds[ai + k];
             g0 += dp[k] * x;
             g1 += dp[s.ns + k] * x;
             g2 += dp[2 * s.ns + k] * x;
             ld += dp[3 * s.ns + k] * x;
         }
-        const double* jg = w.Jg + 3 * j;
-        const double lap = ld + 2.0 * (g0 * jg[0] + g1 * jg[1] + g2 * jg[2]) + w.Jl[j] +
-                           jg[0] * jg[0] + jg[1] * jg[1] + jg[2] * jg[2];
+        const double j0 = lds[w.Jg + 3 * j], j1 = lds[w.Jg + 3 * j + 1], j2 = lds[w.Jg + 3 * j + 2];
+        const double lap = ld + 2.0 * (g0 * j0 + g1 * j1 + g2 * j2) + lds[w.Jl + j] +
+                           j0 * j0 + j1 * j1 + j2 * j2;
         double lapA = 0.0;
         int nd = 0;
         for (int q = 0; q < 6; ++q) {
-            const double r = w.R[6 * j + q];
+            const double r = lds[w.R + 6 * j + q];
             lapA += (r - 1.0) / (a * a);
             if (r < 0) nd = 1;
         }
-        (void)ia2;
-        if (pa.nu_mode == 1) nd = anynode;
-        if (pa.nu_mode == 2) nd = 1;
-        const double nuzv = w.nue[j] + 0.5 * (lapA - lap);
-        const double numax = nuzv > w.nua[j] ? nuzv : w.nua[j];
+        if (nu_mode == 1) nd = anynode;
+        if (nu_mode == 2) nd = 1;
+        const double nuzv = lds[w.nue + j] + 0.5 * (lapA - lap);
+        const double nua = lds[w.nua + j];
+        const double numax = nuzv > nua ? nuzv : nua;
         sum_opt += nd ? numax : nuzv;
     }
     sum_opt = wave_sum(sum_opt);
     Local L;
     L.bbar = bs * inv2a2;
     const double vsf = vs * inv2a2;
-    L.W = 3.0 * s.N / (a * a) + sum_opt + w.scal[kScVee] + vsf + s.vii;
+    L.W = 3.0 * s.N / (a * a) + sum_opt + lds[w.scal + kScVee] + vsf + s.vii;
     L.eL = L.W - L.bbar;
     return L;
 }
@@ -410,18 +503,18 @@ __device__ int heat_bath(const DevSys& s, const Walker& w, double xi, int lane)
     const int p0 = lane * per, p1 = min(p0 + per, s.P);
     double loc = 0.0;
     for (int p = p0; p < p1; ++p) {
-        const double r = w.R[p];
+        const double r = lds[w.R + p];
         if (r > 0) loc += r;
     }
     const double inc = wave_incl_scan(loc, lane);
-    const double tot = __shfl(inc, kWave - 1);
+    const double tot = lane63(inc);
     if (!(tot > 0)) return -1;
     const double t = xi * tot;
     double c = __shfl_up(inc, 1);
     if (lane == 0) c = 0.0;
     int found = -1, lastpos = -1;
     for (int p = p0; p < p1; ++p) {
-        const double r = w.R[p];
+        const double r = lds[w.R + p];
         if (r > 0) {
             c += r;
             lastpos = p;
@@ -429,50 +522,46 @@ __device__ int heat_bath(const DevSys& s, const Walker& w, double xi, int lane)
         }
     }
     const unsigned long long m = __ballot(found >= 0);
-    if (m) return __shfl(found, __ffsll((long long)m) - 1);
+    if (m) return __builtin_amdgcn_readlane(found, __ffsll((long long)m) - 1);
     const unsigned long long mp = __ballot(lastpos >= 0);
-    return __shfl(lastpos, 63 - __clzll((long long)mp));
+    return __builtin_amdgcn_readlane(lastpos, 63 - __clzll((long long)mp));
 }
 
 // Apply move p: position, Sherman-Morrison inverse update of the moved spin,
 // new orbital rows of the moved electron, Jastrow / potential caches, ratios.
 // Returns true when the determinant ratio was tiny (a refresh is forced).
-__device__ bool apply_move(const DevSys& s, const Walker& w, const PhaseArgs& pa, int p,
-                           int lane)
+__device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, int lane)
 {
-    const double a = pa.a;
     const int i = p / 6, d = (p / 2) % 3, sg = p % 2;
     const int sp = spin_of(s, i), c = col_of(s, i), n = nspin(s, sp);
-    const double Rd = w.Rdet[p];
-    double rold[3] = {w.pos[3 * i], w.pos[3 * i + 1], w.pos[3 * i + 2]};
+    const double Rd = lds[w.Rdet + p];
+    const double rold[3] = {lds[w.pos + 3 * i], lds[w.pos + 3 * i + 1], lds[w.pos + 3 * i + 2]};
     double rnew[3] = {rold[0], rold[1], rold[2]};
     rnew[d] = rnew[d] + (sg ? -a : a);
 
     // Sherman-Morrison on AinvT of spin sp with the accepted orbital row u
-    double* Ai = w.AinvT + sp * s.ns * s.ns;
-    double* u = w.tmp;                  // [ns]
-    double* rowc = w.tmp + s.ns;        // [ns]
-    double* beta = w.tmp + 2 * s.ns;    // [ns]
+    const int Ai = w.AinvT + sp * s.ns * s.ns;
+    const int u = w.tmp, rowc = w.tmp + s.ns, beta = w.tmp + 2 * s.ns;
     for (int k = lane; k < n; k += kWave) {
-        u[k] = w.Phi[p * s.ns + k];
-        rowc[k] = Ai[c * s.ns + k];
+        lds[u + k] = w.Phi[p * s.ns + k];
+        lds[rowc + k] = lds[Ai + c * s.ns + k];
     }
     __syncthreads();
     for (int cc = lane; cc < n; cc += kWave) {
         double acc = 0.0;
-        for (int k = 0; k < n; ++k) acc += u[k] * Ai[cc * s.ns + k];
-        beta[cc] = acc;
+        for (int k = 0; k < n; ++k) acc += lds[u + k] * lds[Ai + cc * s.ns + k];
+        lds[beta + cc] = acc;
     }
     __syncthreads();
     for (int idx = lane; idx < n * n; idx += kWave) {
         const int cc = idx / n, k = idx - cc * n;
-        if (cc == c) Ai[cc * s.ns + k] = rowc[k] / Rd;
-        else Ai[cc * s.ns + k] -= rowc[k] * (beta[cc] / Rd);
+        if (cc == c) lds[Ai + cc * s.ns + k] = lds[rowc + k] / Rd;
+        else lds[Ai + cc * s.ns + k] -= lds[rowc + k] * (lds[beta + cc] / Rd);
     }
-    for (int k = lane; k < n; k += kWave) w.Arow[i * s.ns + k] = u[k];
+    for (int k = lane; k < n; k += kWave) lds[w.Arow + i * s.ns + k] = lds[u + k];
     if (lane == 0) {
-        w.scal[kScLogdet0 + sp] += log(fabs(Rd));
-        if (Rd < 0) w.scal[kScSign0 + sp] = -w.scal[kScSign0 + sp];
+        lds[w.scal + kScLogdet0 + sp] += log(fabs(Rd));
+        if (Rd < 0) lds[w.scal + kScSign0 + sp] = -lds[w.scal + kScSign0 + sp];
     }
     __syncthreads();
 
@@ -480,57 +569,68 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, const PhaseArgs& pa
     electron_rows(s, w, i, rnew, a, lane);
     store_rows(s, w, i, lane, false);
 
-    // Jastrow and potential caches: pairs (i, k) change from rold to rnew
-    double pts[7][3];
-    for (int q = 0; q < 7; ++q) { pts[q][0] = rnew[0]; pts[q][1] = rnew[1]; pts[q][2] = rnew[2]; }
-    for (int dd = 0; dd < 3; ++dd)
-        for (int s2 = 0; s2 < 2; ++s2) pts[1 + 2 * dd + s2][dd] = rnew[dd] + (s2 ? -a : a);
-    double S[7] = {0, 0, 0, 0, 0, 0, 0}, g[3] = {0, 0, 0}, l = 0.0, dvee = 0.0, nu = 0.0,
-           nua = 0.0;
+    // Jastrow and potential caches: pairs (i, k) change from rold to rnew.
+    // Points of the moved electron one at a time, partners over the lanes.
     const int K = s.N + s.M;
+    const int Kj = s.has_en ? K : s.N;
+    const int dJi = w.tmp + 3 * s.ns;            // 6 new exponent changes of electron i
+    double S0 = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < 7; ++q) {
+        double pq[3];
+        point_q(rnew, q, a, pq);
+        double acc = 0.0;
+        for (int k = lane; k < Kj; k += kWave) {
+            if (k == i) continue;
+            double pk[3];
+            int jr;
+            partner(s, w, i, k, pk, jr);
+            acc += pade_u(s.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+        }
+        acc = wave_sum(acc);
+        if (q == 0) S0 = acc;
+        else if (lane == 0) lds[dJi + q - 1] = acc - S0;
+    }
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0, dvee = 0.0, nu = 0.0, nua = 0.0;
     for (int k = lane; k < K; k += kWave) {
         if (k == i) continue;
         const bool isel = k < s.N;
-        const double* pk;
-        const double* prm;
-        if (isel) { pk = w.pos + 3 * k; prm = ee_par(s, i, k); }
-        else { pk = s.R + 3 * (k - s.N); prm = s.jas + 3 * (2 + s.spec[k - s.N]); }
+        double pk[3];
+        int jr;
+        partner(s, w, i, k, pk, jr);
+        const double n0 = rnew[0] - pk[0], n1 = rnew[1] - pk[1], n2 = rnew[2] - pk[2];
+        const double rn = norm3(n0, n1, n2);
         if (isel || s.has_en) {
-            for (int q = 0; q < 7; ++q)
-                S[q] += pade_u(prm, norm3(pts[q][0] - pk[0], pts[q][1] - pk[1], pts[q][2] - pk[2]));
-            const double dn[3] = {rnew[0] - pk[0], rnew[1] - pk[1], rnew[2] - pk[2]};
-            const double rn = norm3(dn[0], dn[1], dn[2]);
-            double un, dun, d2un;
-            pade_all(prm, rn, un, dun, d2un);
-            for (int cc = 0; cc < 3; ++cc) g[cc] += dun * dn[cc] / rn;
-            l += d2un + 2.0 * dun / rn;
+            double un, dnr, lpn;
+            pade_derivs(s.jas + 3 * jr, rn, un, dnr, lpn);
+            g0 += dnr * n0; g1 += dnr * n1; g2 += dnr * n2;
+            l += lpn;
             if (isel) {
-                const double dol[3] = {rold[0] - pk[0], rold[1] - pk[1], rold[2] - pk[2]};
-                const double ro = norm3(dol[0], dol[1], dol[2]);
-                double uo, duo, d2uo;
-                pade_all(prm, ro, uo, duo, d2uo);
-                w.dje[k] = un - uo;
+                const double o0 = rold[0] - pk[0], o1 = rold[1] - pk[1], o2 = rold[2] - pk[2];
+                const double ro = norm3(o0, o1, o2);
+                double uo, dor, lpo;
+                pade_derivs(s.jas + 3 * jr, ro, uo, dor, lpo);
+                lds[w.dje + k] = un - uo;
                 // electron k sees the pair through r_k - r_i = -(r_i - r_k)
-                for (int cc = 0; cc < 3; ++cc)
-                    w.Jg[3 * k + cc] += -(dun * dn[cc] / rn) + duo * dol[cc] / ro;
-                w.Jl[k] += (d2un + 2.0 * dun / rn) - (d2uo + 2.0 * duo / ro);
+                lds[w.Jg + 3 * k] += -(dnr * n0) + dor * o0;
+                lds[w.Jg + 3 * k + 1] += -(dnr * n1) + dor * o1;
+                lds[w.Jg + 3 * k + 2] += -(dnr * n2) + dor * o2;
+                lds[w.Jl + k] += lpn - lpo;
                 dvee += 1.0 / rn - 1.0 / ro;
             }
         }
         if (!isel) {
             const int I = k - s.N;
-            const double r = norm3(rnew[0] - pk[0], rnew[1] - pk[1], rnew[2] - pk[2]);
             if (s.core[I] == 0) {
-                nu += -s.Z[I] / r;
-                nua += -s.Z[I] / (r > a ? r : a);
+                nu += -s.Z[I] / rn;
+                nua += -s.Z[I] / (rn > a ? rn : a);
             } else {
-                const double t = -s.Z[I] * erf(r / s.rc[I]) / r;
+                const double t = -s.Z[I] * erf(rn / s.rc[I]) / rn;
                 nu += t; nua += t;
             }
         }
     }
-    for (int q = 0; q < 7; ++q) S[q] = wave_sum(S[q]);
-    for (int cc = 0; cc < 3; ++cc) g[cc] = wave_sum(g[cc]);
+    g0 = wave_sum(g0); g1 = wave_sum(g1); g2 = wave_sum(g2);
     l = wave_sum(l); dvee = wave_sum(dvee); nu = wave_sum(nu); nua = wave_sum(nua);
     __syncthreads();
     // Jastrow exponent changes of the other electrons' moves
@@ -538,19 +638,19 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, const PhaseArgs& pa
         const int j = q / 6;
         if (j == i) continue;
         const int dd = (q / 2) % 3, s2 = q % 2;
-        const double* prm = ee_par(s, i, j);
-        double r2[3] = {w.pos[3 * j], w.pos[3 * j + 1], w.pos[3 * j + 2]};
+        const double* prm = s.jas + 3 * ee_row(s, i, j);
+        double r2[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
         r2[dd] = r2[dd] + (s2 ? -a : a);
         const double un = pade_u(prm, norm3(r2[0] - rnew[0], r2[1] - rnew[1], r2[2] - rnew[2]));
         const double uo = pade_u(prm, norm3(r2[0] - rold[0], r2[1] - rold[1], r2[2] - rold[2]));
-        w.dJ[q] += (un - uo) - w.dje[j];
+        lds[w.dJ + q] += (un - uo) - lds[w.dje + j];
     }
     if (lane == 0) {
-        for (int q = 0; q < 6; ++q) w.dJ[6 * i + q] = S[q + 1] - S[0];
-        for (int cc = 0; cc < 3; ++cc) w.Jg[3 * i + cc] = g[cc];
-        w.Jl[i] = l; w.nue[i] = nu; w.nua[i] = nua;
-        w.scal[kScVee] += dvee;
-        w.pos[3 * i + d] = rnew[d];
+        for (int q = 0; q < 6; ++q) lds[w.dJ + 6 * i + q] = lds[dJi + q];
+        lds[w.Jg + 3 * i] = g0; lds[w.Jg + 3 * i + 1] = g1; lds[w.Jg + 3 * i + 2] = g2;
+        lds[w.Jl + i] = l; lds[w.nue + i] = nu; lds[w.nua + i] = nua;
+        lds[w.scal + kScVee] += dvee;
+        lds[w.pos + 3 * i + d] = rnew[d];
     }
     __syncthreads();
     recompute_ratios(s, w, sp, lane);
@@ -560,27 +660,27 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, const PhaseArgs& pa
 // ---------------------------------------------------------------------------
 // the phase kernel: one workgroup = one wavefront = one walker
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kWave) void phase_fp64(DevSys s, PhaseArgs pa)
+// Occupancy target of the phase kernel (waves per SIMD); the compiler caps
+// the register budget accordingly.
+#ifndef LRDMC_PHASE_WAVES
+#define LRDMC_PHASE_WAVES 2
+#endif
+
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(LRDMC_PHASE_WAVES)))
+void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
 {
-    extern __shared__ double lds[];
+    const DevSys& s = *sys;
     const int wid = blockIdx.x;
     if (wid >= s.nw) return;
     const int lane = threadIdx.x;
-    Walker w;
-    w.pos = lds + s.o_pos; w.R = lds + s.o_R; w.Rdet = lds + s.o_Rdet; w.dJ = lds + s.o_dJ;
-    w.Arow = lds + s.o_Arow; w.AinvT = lds + s.o_AinvT; w.Jg = lds + s.o_Jg; w.Jl = lds + s.o_Jl;
-    w.nue = lds + s.o_nue; w.nua = lds + s.o_nua; w.dje = lds + s.o_dje; w.scal = lds + s.o_scal;
-    w.B = lds + s.o_B; w.rows = lds + s.o_rows; w.tmp = lds + s.o_tmp;
-    double* sp_base = s.spill + (long)wid * s.spill_stride;
-    w.Phi = sp_base + s.s_Phi;
-    w.dPhi = sp_base + s.s_dPhi;
+    const Walker w = walker_view(s);
 
-    for (int q = lane; q < 3 * s.N; q += kWave) w.pos[q] = s.pos[(long)wid * 3 * s.N + q];
+    for (int q = lane; q < 3 * s.N; q += kWave) lds[w.pos + q] = s.pos[(long)wid * 3 * s.N + q];
     __syncthreads();
     const double a = pa.a;
     // orbital rows of every electron, then the FP64 refresh
     for (int j = 0; j < s.N; ++j) {
-        double r[3] = {w.pos[3 * j], w.pos[3 * j + 1], w.pos[3 * j + 2]};
+        const double r[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
         electron_rows(s, w, j, r, a, lane);
         store_rows(s, w, j, lane, true);
     }
@@ -595,7 +695,7 @@ __global__ __launch_bounds__(kWave) void phase_fp64(DevSys s, PhaseArgs pa)
     int32_t* tr = s.trace ? s.trace + (long)wid * s.trace_cap : nullptr;
     for (;;) {
         if (pa.scheme == 0 && it >= pa.nproj) break;
-        L = evaluate(s, w, pa, lane);
+        L = evaluate(s, w, a, pa.nu_mode, lane);
         int q;
         if (pa.scheme == 0) {
             const double den = L.W - pa.E0;
@@ -631,7 +731,7 @@ __global__ __launch_bounds__(kWave) void phase_fp64(DevSys s, PhaseArgs pa)
             if (tr && it - 1 < s.trace_cap && lane == 0) tr[it - 1] = q;
         }
         if (q >= 0) {
-            const bool small = apply_move(s, w, pa, q, lane);
+            const bool small = apply_move(s, w, a, q, lane);
             ++since;
             if (small) n_small++;
             if (small || since >= pa.refresh_every) {
@@ -641,9 +741,9 @@ __global__ __launch_bounds__(kWave) void phase_fp64(DevSys s, PhaseArgs pa)
             }
         }
     }
-    if (pa.scheme == 0) L = evaluate(s, w, pa, lane);
+    if (pa.scheme == 0) L = evaluate(s, w, a, pa.nu_mode, lane);
 
-    for (int q = lane; q < 3 * s.N; q += kWave) s.pos[(long)wid * 3 * s.N + q] = w.pos[q];
+    for (int q = lane; q < 3 * s.N; q += kWave) s.pos[(long)wid * 3 * s.N + q] = lds[w.pos + q];
     if (lane == 0) {
         s.lw[wid] = lw;
         s.eL[wid] = L.eL;
