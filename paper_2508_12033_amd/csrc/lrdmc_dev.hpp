@@ -25,6 +25,7 @@ struct DevSys {
     uint64_t sysid;
     // system arrays (device)
     const double *R, *Z, *rc, *bexp, *C, *jas;
+    const double *btab;      // [Nb][4]: centre x, y, z and exponent of each basis function
     const int32_t *core, *spec, *batom, *btype;
     // walker arrays (device)
     double *pos;             // [nw][N][3]
@@ -37,7 +38,7 @@ struct DevSys {
     int trace_cap;
     // LDS layout of one walker (offsets in doubles)
     int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje,
-        o_scal, o_B, o_rows, o_tmp, lds_doubles;
+        o_scal, o_B, o_rows, o_tmp, o_C, lds_doubles;
     // spill layout (offsets in doubles inside a walker's spill block)
     int s_Phi, s_dPhi;
 };
@@ -52,6 +53,7 @@ struct PhaseArgs {
     double a, tau, E0;
     uint64_t seed;
     unsigned long long *counters;   // [kCntLen]
+    unsigned long long *timers;     // [nw][8] section cycles (instrumentation builds)
 };
 
 // per-walker scalars stored at o_scal

@@ -53,7 +53,7 @@ struct Layout {
     int N, P, ns;
     // LDS offsets (doubles)
     int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje, o_scal, o_B,
-        o_rows, o_tmp, lds_doubles;
+        o_rows, o_tmp, o_C, lds_doubles;
     int s_Phi, s_dPhi;
     long spill_stride;
     // workspace bytes of each device array
@@ -80,9 +80,10 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
     L.o_nua = take(L.N);
     L.o_dje = take(L.N);
     L.o_scal = take(kScLen);
-    L.o_B = take(std::max(11 * s.n_basis, 2 * L.ns * L.ns));
+    L.o_B = take(std::max(std::max(11 * s.n_basis, 2 * L.ns * L.ns), 7 * L.N));
     L.o_rows = take(11 * L.ns);
     L.o_tmp = take(3 * L.ns + 8);
+    L.o_C = take(s.n_basis * L.ns);
     L.lds_doubles = o;
     L.s_Phi = 0;
     L.s_dPhi = L.P * L.ns;
@@ -90,7 +91,7 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
     const int M = s.n_atoms, Nb = s.n_basis;
     L.b_sys = align_up(M * 3 * 8) + 2 * align_up(M * 8) + 2 * align_up(M * 4) + 2 * align_up(Nb * 4) +
               align_up(Nb * 8) + align_up((size_t)Nb * s.n_orb * 8) +
-              align_up((2 + s.n_species) * 3 * 8);
+              align_up((2 + s.n_species) * 3 * 8) + align_up((size_t)Nb * 4 * 8);
     const size_t nw = s.n_walkers;
     L.b_state = 2 * align_up(nw * 3 * L.N * 8)      // positions, double-buffered
                 + align_up(nw * 8)                  // lw
@@ -158,6 +159,7 @@ struct SysRun {
     Layout L;
     double e0;
     std::vector<double> hist_lwb, hist_e;
+    std::vector<double> btab_host;
     size_t lds_bytes;
 };
 
@@ -171,6 +173,7 @@ struct lrdmc_handle {
     unsigned long long* counters;   // [kCntLen] device
     unsigned long long cnt_init[kCntLen];   // host source of the counter reset
     hipEvent_t ev0, ev1;
+    unsigned long long* timers = nullptr;   // instrumentation builds: [nw][8]
 };
 
 extern "C" {
@@ -212,6 +215,7 @@ static int launch_phase(lrdmc_handle* h, SysRun& r)
     pa.E0 = r.e0;
     pa.seed = h->prm.seed;
     pa.counters = h->counters;
+    pa.timers = h->timers;
     hipLaunchKernelGGL(phase_fp64, dim3(r.d.nw), dim3(kWave), r.lds_bytes, h->stream,
                        (const DevSys*)r.dsys[r.parity], pa);
     HIPCHK(hipGetLastError());
@@ -293,16 +297,24 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
         double* bexp = (double*)carve(Nb * 8);
         double* C = (double*)carve((size_t)Nb * s.n_orb * 8);
         double* jas = (double*)carve((2 + s.n_species) * 3 * 8);
+        double* btab = (double*)carve((size_t)Nb * 4 * 8);
+        r.btab_host.resize((size_t)Nb * 4);
+        for (int mu = 0; mu < Nb; ++mu) {
+            const int at = s.basis_atom[mu];
+            for (int c = 0; c < 3; ++c) r.btab_host[4 * mu + c] = s.atom_pos[3 * at + c];
+            r.btab_host[4 * mu + 3] = s.basis_exp[mu];
+        }
         if (up(R, s.atom_pos, M * 24) || up(Z, s.atom_charge, M * 8) || up(rcs, s.core_rc, M * 8) ||
             up(core, s.atom_core, M * 4) || up(spec, s.atom_species, M * 4) ||
             up(batom, s.basis_atom, Nb * 4) || up(btype, s.basis_type, Nb * 4) ||
             up(bexp, s.basis_exp, Nb * 8) || up(C, s.mo_coeff, (size_t)Nb * s.n_orb * 8) ||
-            up(jas, s.jastrow, (2 + s.n_species) * 24)) {
+            up(jas, s.jastrow, (2 + s.n_species) * 24) ||
+            up(btab, r.btab_host.data(), (size_t)Nb * 32)) {
             rc = fail(LRDMC_ERR_HIP, "upload of system arrays failed");
             break;
         }
         d.R = R; d.Z = Z; d.rc = rcs; d.core = core; d.spec = spec; d.batom = batom;
-        d.btype = btype; d.bexp = bexp; d.C = C; d.jas = jas;
+        d.btype = btype; d.bexp = bexp; d.C = C; d.jas = jas; d.btab = btab;
         const size_t nw = s.n_walkers;
         d.pos = (double*)carve(nw * 3 * L.N * 8);
         r.pos_alt = (double*)carve(nw * 3 * L.N * 8);
@@ -323,7 +335,8 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
         d.o_pos = L.o_pos; d.o_R = L.o_R; d.o_Rdet = L.o_Rdet; d.o_dJ = L.o_dJ;
         d.o_Arow = L.o_Arow; d.o_AinvT = L.o_AinvT; d.o_Jg = L.o_Jg; d.o_Jl = L.o_Jl;
         d.o_nue = L.o_nue; d.o_nua = L.o_nua; d.o_dje = L.o_dje; d.o_scal = L.o_scal;
-        d.o_B = L.o_B; d.o_rows = L.o_rows; d.o_tmp = L.o_tmp; d.lds_doubles = L.lds_doubles;
+        d.o_B = L.o_B; d.o_rows = L.o_rows; d.o_tmp = L.o_tmp; d.o_C = L.o_C;
+        d.lds_doubles = L.lds_doubles;
         d.s_Phi = L.s_Phi; d.s_dPhi = L.s_dPhi;
         r.lds_bytes = (size_t)L.lds_doubles * 8;
         r.dsys[0] = (DevSys*)carve(sizeof(DevSys));
@@ -393,9 +406,22 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
         delete h;
         return rc;
     }
+#ifdef LRDMC_SECTION_TIMERS
+    if (hipMalloc((void**)&h->timers, (size_t)h->sys[0].d.nw * 8 * 8) != hipSuccess) h->timers = nullptr;
+#endif
     *out = h;
     return LRDMC_OK;
 }
+
+#ifdef LRDMC_SECTION_TIMERS
+// instrumentation builds only: per-walker section cycle counts of the last phase
+int lrdmc_section_timers(lrdmc_handle* h, unsigned long long* out)
+{
+    if (!h || !h->timers) return fail(LRDMC_ERR_INVALID_ARG, "no timers");
+    HIPCHK(hipMemcpy(out, h->timers, (size_t)h->sys[0].d.nw * 64, hipMemcpyDeviceToHost));
+    return LRDMC_OK;
+}
+#endif
 
 int lrdmc_step(lrdmc_handle* h, lrdmc_step_stats* st)
 {

@@ -25,6 +25,22 @@
 
 namespace lrdmc {
 
+// Optional per-section cycle counters (instrumentation builds only): the
+// wavefront's s_memtime clock accumulated per section and written out per
+// walker.  Compiled away unless LRDMC_SECTION_TIMERS is defined.
+#ifdef LRDMC_SECTION_TIMERS
+#define LRDMC_T0() unsigned long long t_mark_ = __builtin_amdgcn_s_memtime()
+#define LRDMC_T(k)                                                           \
+    do {                                                                     \
+        const unsigned long long t_now_ = __builtin_amdgcn_s_memtime();      \
+        sect[k] += t_now_ - t_mark_;                                         \
+        t_mark_ = t_now_;                                                    \
+    } while (0)
+#else
+#define LRDMC_T0() (void)0
+#define LRDMC_T(k) (void)0
+#endif
+
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter (c0..c3), key
 // (k0, k1); uniform = top 53 bits of the first output word times 2^-53.
@@ -133,9 +149,9 @@ __device__ __forceinline__ void point_q(const double* r, int q, double a, double
 // Value of basis function mu at point r.
 __device__ __forceinline__ double basis_value(const DevSys& s, int mu, const double* r)
 {
-    const double* Ra = s.R + 3 * s.batom[mu];
+    const double* Ra = s.btab + 4 * mu;
     const double dx = r[0] - Ra[0], dy = r[1] - Ra[1], dz = r[2] - Ra[2];
-    const double d2 = dx * dx + dy * dy + dz * dz, al = s.bexp[mu];
+    const double d2 = dx * dx + dy * dy + dz * dz, al = Ra[3];
     const int t = s.btype[mu];
     if (t == 4) return exp(-al * sqrt(d2));
     const double g = exp(-al * d2);
@@ -147,9 +163,9 @@ __device__ __forceinline__ double basis_value(const DevSys& s, int mu, const dou
 __device__ __forceinline__ void basis_vgl(const DevSys& s, int mu, const double* r, double& v,
                                           double* g, double& l)
 {
-    const double* Ra = s.R + 3 * s.batom[mu];
+    const double* Ra = s.btab + 4 * mu;
     const double d[3] = {r[0] - Ra[0], r[1] - Ra[1], r[2] - Ra[2]};
-    const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2], al = s.bexp[mu];
+    const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2], al = Ra[3];
     const int t = s.btype[mu];
     if (t == 4) {
         const double dd = sqrt(d2), e = exp(-al * dd);
@@ -170,16 +186,61 @@ __device__ __forceinline__ void basis_vgl(const DevSys& s, int mu, const double*
     }
 }
 
+// The same two functions from the displacement d = r - R, d2 = |d|^2.
+__device__ __forceinline__ double basis_value_d(int t, double al, double dx, double dy, double dz,
+                                                double d2)
+{
+    if (t == 4) return exp(-al * sqrt(d2));
+    const double g = exp(-al * d2);
+    if (t == 0) return g;
+    return (t == 1 ? dx : (t == 2 ? dy : dz)) * g;
+}
+
+__device__ __forceinline__ void basis_vgl_d(int t, double al, double dx, double dy, double dz,
+                                            double d2, double& v, double* g, double& l)
+{
+    const double d[3] = {dx, dy, dz};
+    if (t == 4) {
+        const double dd = sqrt(d2), e = exp(-al * dd), id = 1.0 / dd;
+        v = e;
+        for (int c = 0; c < 3; ++c) g[c] = -al * d[c] * id * e;
+        l = (al * al - 2.0 * al * id) * e;
+    } else if (t == 0) {
+        const double e = exp(-al * d2);
+        v = e;
+        for (int c = 0; c < 3; ++c) g[c] = -2.0 * al * d[c] * e;
+        l = (4.0 * al * al * d2 - 6.0 * al) * e;
+    } else {
+        const int q = t - 1;
+        const double e = exp(-al * d2), dq = d[q];
+        v = dq * e;
+        for (int c = 0; c < 3; ++c) g[c] = ((c == q) ? e : 0.0) - 2.0 * al * dq * d[c] * e;
+        l = dq * e * (4.0 * al * al * d2 - 10.0 * al);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // per-walker state views
 // ---------------------------------------------------------------------------
+// A workgroup is one wavefront: LDS operations of a wavefront complete in
+// issue order, so exchanging data between its lanes through LDS needs only a
+// compiler-level barrier (no s_barrier and no drain of outstanding memory
+// operations).  Global-memory data written by one lane and read by another
+// additionally needs block_visible().
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+__device__ __forceinline__ void block_visible()
+{
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Per-walker state: offsets (in doubles) of the LDS-resident arrays inside
 // the dynamic shared-memory block, and the walker's block of the global
 // spill area (orbital rows at the 6N moves, orbital derivatives).
 extern __shared__ double lds[];
 
 struct Walker {
-    int pos, R, Rdet, dJ, Arow, AinvT, Jg, Jl, nue, nua, dje, scal, B, rows, tmp;
+    int pos, R, Rdet, dJ, Arow, AinvT, Jg, Jl, nue, nua, dje, scal, B, rows, tmp, C;
     double* Phi;
     double* dPhi;
 };
@@ -190,6 +251,7 @@ __device__ __forceinline__ Walker walker_view(const DevSys& s)
     w.pos = s.o_pos; w.R = s.o_R; w.Rdet = s.o_Rdet; w.dJ = s.o_dJ; w.Arow = s.o_Arow;
     w.AinvT = s.o_AinvT; w.Jg = s.o_Jg; w.Jl = s.o_Jl; w.nue = s.o_nue; w.nua = s.o_nua;
     w.dje = s.o_dje; w.scal = s.o_scal; w.B = s.o_B; w.rows = s.o_rows; w.tmp = s.o_tmp;
+    w.C = s.o_C;
     double* base = s.spill + (long)blockIdx.x * s.spill_stride;
     w.Phi = base + s.s_Phi;
     w.dPhi = base + s.s_dPhi;
@@ -228,34 +290,69 @@ __device__ __forceinline__ void partner(const DevSys& s, const Walker& w, int i,
 __device__ void electron_rows(const DevSys& s, const Walker& w, int j, const double* r, double a,
                               int lane)
 {
-    const int Nb = s.Nb;
-    for (int it = lane; it < 7 * Nb; it += kWave) {
+    const int Nb = s.Nb, items = 7 * Nb;
+    // basis records of the next item are fetched one iteration ahead
+    int it = lane;
+    double4_t rec = {0.0, 0.0, 0.0, 0.0};
+    int typ = 0;
+    if (it < items) {
+        const int mu = it % Nb;
+        rec = *(const double4_t*)(s.btab + 4 * mu);
+        typ = s.btype[mu];
+    }
+    for (; it < items; it += kWave) {
         const int q = it / Nb, mu = it - q * Nb;
+        const double4_t cur = rec;
+        const int ct = typ;
+        const int nx = it + kWave;
+        if (nx < items) {
+            const int mun = nx % Nb;
+            rec = *(const double4_t*)(s.btab + 4 * mun);
+            typ = s.btype[mun];
+        }
         double p[3];
         point_q(r, q, a, p);
+        const double dx = p[0] - cur[0], dy = p[1] - cur[1], dz = p[2] - cur[2];
+        const double d2 = dx * dx + dy * dy + dz * dz, al = cur[3];
         if (q == 0) {
             double v, g[3], l;
-            basis_vgl(s, mu, p, v, g, l);
+            basis_vgl_d(ct, al, dx, dy, dz, d2, v, g, l);
             lds[w.B + mu] = v;
             lds[w.B + 7 * Nb + mu] = g[0];
             lds[w.B + 8 * Nb + mu] = g[1];
             lds[w.B + 9 * Nb + mu] = g[2];
             lds[w.B + 10 * Nb + mu] = l;
         } else {
-            lds[w.B + q * Nb + mu] = basis_value(s, mu, p);
+            lds[w.B + q * Nb + mu] = basis_value_d(ct, al, dx, dy, dz, d2);
         }
     }
-    __syncthreads();
+    wave_sync();
     const int n = nspin(s, spin_of(s, j));
     const int i16 = lane & 15, k4 = lane >> 4;
+    const bool arow_ok = i16 < 11;
     for (int t = 0; t * 16 < n; ++t) {
         double4_t acc = {0.0, 0.0, 0.0, 0.0};
         const int col = 16 * t + i16;
-        for (int k0 = 0; k0 < Nb; k0 += 4) {
+        const bool bcol_ok = col < n;
+        int k0 = 0;
+        // four k-steps per round: operands loaded first, then the MFMA chain
+        for (; k0 + 16 <= Nb; k0 += 16) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int mu = k0 + 4 * u + k4;
+                av[u] = arow_ok ? lds[w.B + i16 * Nb + mu] : 0.0;
+                bv[u] = bcol_ok ? lds[w.C + mu * s.ns + col] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+        }
+        for (; k0 < Nb; k0 += 4) {
             const int mu = k0 + k4;
             // A operand: row i16, inner index k4; B operand: inner k4, column i16
-            const double av = (i16 < 11 && mu < Nb) ? lds[w.B + i16 * Nb + mu] : 0.0;
-            const double bv = (col < n && mu < Nb) ? s.C[mu * s.Norb + col] : 0.0;
+            const double av = (arow_ok && mu < Nb) ? lds[w.B + i16 * Nb + mu] : 0.0;
+            const double bv = (bcol_ok && mu < Nb) ? lds[w.C + mu * s.ns + col] : 0.0;
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
         }
         // D[row][col] with row = (lane >> 4) + 4 v
@@ -264,7 +361,7 @@ __device__ void electron_rows(const DevSys& s, const Walker& w, int j, const dou
             if (row < 11 && col < n) lds[w.rows + row * s.ns + col] = acc[v];
         }
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // Store electron j's rows: Slater row, the 6 neighbour rows, derivatives.
@@ -278,7 +375,7 @@ __device__ void store_rows(const DevSys& s, const Walker& w, int j, int lane, bo
         else if (row <= 6) w.Phi[(6 * j + row - 1) * s.ns + k] = v;
         else w.dPhi[(4 * j + row - 7) * s.ns + k] = v;
     }
-    __syncthreads();
+    block_visible();
 }
 
 // FP64 Gauss-Jordan inverse with partial pivoting of the transposed Slater
@@ -294,7 +391,7 @@ __device__ bool refresh_inverse(const DevSys& s, const Walker& w, int sp, int la
         const int r = idx / n2, c = idx - r * n2;
         lds[M + idx] = c < n ? lds[w.Arow + (off + c) * s.ns + r] : (c - n == r ? 1.0 : 0.0);
     }
-    __syncthreads();
+    wave_sync();
     double logdet = 0.0, sign = 1.0;
     bool ok = true;
     for (int j = 0; j < n; ++j) {
@@ -314,20 +411,20 @@ __device__ bool refresh_inverse(const DevSys& s, const Walker& w, int sp, int la
                 lds[M + bi * n2 + c] = t;
             }
             sign = -sign;
-            __syncthreads();
+            wave_sync();
         }
         const double pv = lds[M + j * n2 + j];
         logdet += log(fabs(pv));
         if (pv < 0) sign = -sign;
-        __syncthreads();
+        wave_sync();
         for (int c = lane; c < n2; c += kWave) lds[M + j * n2 + c] = lds[M + j * n2 + c] / pv;
         for (int r = lane; r < n; r += kWave) lds[w.tmp + r] = lds[M + r * n2 + j];
-        __syncthreads();
+        wave_sync();
         for (int idx = lane; idx < n * n2; idx += kWave) {
             const int r = idx / n2, c = idx - r * n2;
             if (r != j) lds[M + idx] -= lds[w.tmp + r] * lds[M + j * n2 + c];
         }
-        __syncthreads();
+        wave_sync();
     }
     if (ok) {
         const int Ai = w.AinvT + sp * s.ns * s.ns;
@@ -340,71 +437,8 @@ __device__ bool refresh_inverse(const DevSys& s, const Walker& w, int sp, int la
             lds[w.scal + kScSign0 + sp] = sign;
         }
     }
-    __syncthreads();
+    wave_sync();
     return ok;
-}
-
-// Full Jastrow / potential pieces of electron j from scratch: the Jastrow
-// exponent change of its 6 moves, grad_j J, lap_j J, nu_ei(r_j), nu^a_ei(r_j),
-// and its pair contribution to V_ee (pairs k > j).  Returns the V_ee part.
-// Partners k (other electrons, then nuclei) are spread over the lanes; the
-// 7 points of electron j are processed one after the other.
-__device__ double electron_jastrow(const DevSys& s, const Walker& w, int j, double a, int lane)
-{
-    const double rj[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
-    const int K = s.N + s.M;
-    const int Kj = s.has_en ? K : s.N;           // partners that carry Jastrow terms
-    double S0 = 0.0;
-#pragma unroll 1
-    for (int q = 0; q < 7; ++q) {
-        double pq[3];
-        point_q(rj, q, a, pq);
-        double acc = 0.0;
-        for (int k = lane; k < Kj; k += kWave) {
-            if (k == j) continue;
-            double pk[3];
-            int jr;
-            partner(s, w, j, k, pk, jr);
-            acc += pade_u(s.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
-        }
-        acc = wave_sum(acc);
-        if (q == 0) S0 = acc;
-        else if (lane == 0) lds[w.dJ + 6 * j + q - 1] = acc - S0;
-    }
-    double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0, vee = 0.0, nu = 0.0, nua = 0.0;
-    for (int k = lane; k < K; k += kWave) {
-        if (k == j) continue;
-        const bool isel = k < s.N;
-        double pk[3];
-        int jr;
-        partner(s, w, j, k, pk, jr);
-        const double d0 = rj[0] - pk[0], d1 = rj[1] - pk[1], d2 = rj[2] - pk[2];
-        const double r = norm3(d0, d1, d2);
-        if (isel || s.has_en) {
-            double u, dur, lp;
-            pade_derivs(s.jas + 3 * jr, r, u, dur, lp);
-            g0 += dur * d0; g1 += dur * d1; g2 += dur * d2;
-            l += lp;
-            if (isel && k > j) vee += 1.0 / r;
-        }
-        if (!isel) {
-            const int I = k - s.N;
-            if (s.core[I] == 0) {
-                nu += -s.Z[I] / r;
-                nua += -s.Z[I] / (r > a ? r : a);
-            } else {
-                const double t = -s.Z[I] * erf(r / s.rc[I]) / r;
-                nu += t; nua += t;
-            }
-        }
-    }
-    g0 = wave_sum(g0); g1 = wave_sum(g1); g2 = wave_sum(g2);
-    l = wave_sum(l); vee = wave_sum(vee); nu = wave_sum(nu); nua = wave_sum(nua);
-    if (lane == 0) {
-        lds[w.Jg + 3 * j] = g0; lds[w.Jg + 3 * j + 1] = g1; lds[w.Jg + 3 * j + 2] = g2;
-        lds[w.Jl + j] = l; lds[w.nue + j] = nu; lds[w.nua + j] = nua;
-    }
-    return vee;
 }
 
 // Ratios of the moves of spin sp (or of every spin when sp < 0), from the
@@ -423,7 +457,74 @@ __device__ void recompute_ratios(const DevSys& s, const Walker& w, int sp, int l
         }
         lds[w.R + p] = lds[w.Rdet + p] * exp(lds[w.dJ + p]);
     }
-    __syncthreads();
+    wave_sync();
+}
+
+// Jastrow caches of every electron from scratch, without cross-lane sums:
+// one lane per (electron, point) pair accumulates over all partners, then one
+// lane per electron accumulates its gradient, Laplacian and potentials.
+// Returns V_ee.
+__device__ double jastrow_all(const DevSys& s, const Walker& w, double a, int lane)
+{
+    const int K = s.N + s.M;
+    const int Kj = s.has_en ? K : s.N;
+    const int S = w.B;                            // [N][7] point sums
+    for (int it = lane; it < 7 * s.N; it += kWave) {
+        const int j = it / 7, q = it - 7 * j;
+        const double rj[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
+        double pq[3];
+        point_q(rj, q, a, pq);
+        double acc = 0.0;
+        for (int k = 0; k < Kj; ++k) {
+            if (k == j) continue;
+            double pk[3];
+            int jr;
+            partner(s, w, j, k, pk, jr);
+            acc += pade_u(s.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+        }
+        lds[S + it] = acc;
+    }
+    double vee = 0.0;
+    for (int j = lane; j < s.N; j += kWave) {
+        const double rj[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0, nu = 0.0, nua = 0.0;
+        for (int k = 0; k < K; ++k) {
+            if (k == j) continue;
+            const bool isel = k < s.N;
+            double pk[3];
+            int jr;
+            partner(s, w, j, k, pk, jr);
+            const double d0 = rj[0] - pk[0], d1 = rj[1] - pk[1], d2 = rj[2] - pk[2];
+            const double r = norm3(d0, d1, d2);
+            if (isel || s.has_en) {
+                double u, dur, lp;
+                pade_derivs(s.jas + 3 * jr, r, u, dur, lp);
+                g0 += dur * d0; g1 += dur * d1; g2 += dur * d2;
+                l += lp;
+                if (isel && k > j) vee += 1.0 / r;
+            }
+            if (!isel) {
+                const int I = k - s.N;
+                if (s.core[I] == 0) {
+                    nu += -s.Z[I] / r;
+                    nua += -s.Z[I] / (r > a ? r : a);
+                } else {
+                    const double t = -s.Z[I] * erf(r / s.rc[I]) / r;
+                    nu += t; nua += t;
+                }
+            }
+        }
+        lds[w.Jg + 3 * j] = g0; lds[w.Jg + 3 * j + 1] = g1; lds[w.Jg + 3 * j + 2] = g2;
+        lds[w.Jl + j] = l; lds[w.nue + j] = nu; lds[w.nua + j] = nua;
+    }
+    vee = wave_sum(vee);
+    wave_sync();
+    for (int p = lane; p < s.P; p += kWave) {
+        const int j = p / 6, q = p - 6 * j;
+        lds[w.dJ + p] = lds[S + 7 * j + q + 1] - lds[S + 7 * j];
+    }
+    wave_sync();
+    return vee;
 }
 
 // FP64 refresh: inverses and log-determinants from the exact orbital rows,
@@ -432,10 +533,9 @@ __device__ bool refresh_all(const DevSys& s, const Walker& w, double a, int lane
 {
     bool ok = refresh_inverse(s, w, 0, lane);
     ok = refresh_inverse(s, w, 1, lane) && ok;
-    double vee = 0.0;
-    for (int j = 0; j < s.N; ++j) vee += electron_jastrow(s, w, j, a, lane);
+    const double vee = jastrow_all(s, w, a, lane);
     if (lane == 0) lds[w.scal + kScVee] = vee;
-    __syncthreads();
+    wave_sync();
     recompute_ratios(s, w, -1, lane);
     return ok;
 }
@@ -530,7 +630,12 @@ __device__ int heat_bath(const DevSys& s, const Walker& w, double xi, int lane)
 // Apply move p: position, Sherman-Morrison inverse update of the moved spin,
 // new orbital rows of the moved electron, Jastrow / potential caches, ratios.
 // Returns true when the determinant ratio was tiny (a refresh is forced).
+#ifdef LRDMC_SECTION_TIMERS
+__device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, int lane,
+                           unsigned long long* sect, unsigned long long& t_mark_)
+#else
 __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, int lane)
+#endif
 {
     const int i = p / 6, d = (p / 2) % 3, sg = p % 2;
     const int sp = spin_of(s, i), c = col_of(s, i), n = nspin(s, sp);
@@ -546,13 +651,13 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
         lds[u + k] = w.Phi[p * s.ns + k];
         lds[rowc + k] = lds[Ai + c * s.ns + k];
     }
-    __syncthreads();
+    wave_sync();
     for (int cc = lane; cc < n; cc += kWave) {
         double acc = 0.0;
         for (int k = 0; k < n; ++k) acc += lds[u + k] * lds[Ai + cc * s.ns + k];
         lds[beta + cc] = acc;
     }
-    __syncthreads();
+    wave_sync();
     for (int idx = lane; idx < n * n; idx += kWave) {
         const int cc = idx / n, k = idx - cc * n;
         if (cc == c) lds[Ai + cc * s.ns + k] = lds[rowc + k] / Rd;
@@ -563,11 +668,13 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
         lds[w.scal + kScLogdet0 + sp] += log(fabs(Rd));
         if (Rd < 0) lds[w.scal + kScSign0 + sp] = -lds[w.scal + kScSign0 + sp];
     }
-    __syncthreads();
+    wave_sync();
 
+    LRDMC_T(2);
     // new orbital rows of electron i at rnew
     electron_rows(s, w, i, rnew, a, lane);
     store_rows(s, w, i, lane, false);
+    LRDMC_T(3);
 
     // Jastrow and potential caches: pairs (i, k) change from rold to rnew.
     // Points of the moved electron one at a time, partners over the lanes.
@@ -632,7 +739,8 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     }
     g0 = wave_sum(g0); g1 = wave_sum(g1); g2 = wave_sum(g2);
     l = wave_sum(l); dvee = wave_sum(dvee); nu = wave_sum(nu); nua = wave_sum(nua);
-    __syncthreads();
+    wave_sync();
+    LRDMC_T(4);
     // Jastrow exponent changes of the other electrons' moves
     for (int q = lane; q < s.P; q += kWave) {
         const int j = q / 6;
@@ -652,8 +760,10 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
         lds[w.scal + kScVee] += dvee;
         lds[w.pos + 3 * i + d] = rnew[d];
     }
-    __syncthreads();
+    wave_sync();
+    LRDMC_T(5);
     recompute_ratios(s, w, sp, lane);
+    LRDMC_T(6);
     return fabs(Rd) < 1e-6;
 }
 
@@ -676,7 +786,11 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
     const Walker w = walker_view(s);
 
     for (int q = lane; q < 3 * s.N; q += kWave) lds[w.pos + q] = s.pos[(long)wid * 3 * s.N + q];
-    __syncthreads();
+    for (int q = lane; q < s.Nb * s.ns; q += kWave) {
+        const int mu = q / s.ns, k = q - mu * s.ns;
+        lds[w.C + q] = s.C[mu * s.Norb + k];
+    }
+    wave_sync();
     const double a = pa.a;
     // orbital rows of every electron, then the FP64 refresh
     for (int j = 0; j < s.N; ++j) {
@@ -693,9 +807,14 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
     int it = 0, since = 0;
     Local L;
     int32_t* tr = s.trace ? s.trace + (long)wid * s.trace_cap : nullptr;
+#ifdef LRDMC_SECTION_TIMERS
+    unsigned long long sect[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#endif
+    LRDMC_T0();
     for (;;) {
         if (pa.scheme == 0 && it >= pa.nproj) break;
         L = evaluate(s, w, a, pa.nu_mode, lane);
+        LRDMC_T(0);
         int q;
         if (pa.scheme == 0) {
             const double den = L.W - pa.E0;
@@ -730,8 +849,13 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
             q = heat_bath(s, w, xi, lane);
             if (tr && it - 1 < s.trace_cap && lane == 0) tr[it - 1] = q;
         }
+        LRDMC_T(1);
         if (q >= 0) {
+#ifdef LRDMC_SECTION_TIMERS
+            const bool small = apply_move(s, w, a, q, lane, sect, t_mark_);
+#else
             const bool small = apply_move(s, w, a, q, lane);
+#endif
             ++since;
             if (small) n_small++;
             if (small || since >= pa.refresh_every) {
@@ -739,8 +863,13 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
                 n_refresh++;
                 since = 0;
             }
+            LRDMC_T(7);
         }
     }
+#ifdef LRDMC_SECTION_TIMERS
+    if (lane == 0 && pa.timers)
+        for (int k = 0; k < 8; ++k) pa.timers[(long)wid * 8 + k] = sect[k];
+#endif
     if (pa.scheme == 0) L = evaluate(s, w, a, pa.nu_mode, lane);
 
     for (int q = lane; q < 3 * s.N; q += kWave) s.pos[(long)wid * 3 * s.N + q] = lds[w.pos + q];
