@@ -56,6 +56,37 @@ struct PhaseArgs {
     unsigned long long *timers;     // [nw][8] section cycles (instrumentation builds)
 };
 
+// Mixed-precision walker layout for large systems: one 256-thread workgroup
+// per walker, orbital data in HBM (FP32), the small per-electron and
+// per-move arrays in LDS, FP64 for positions, potentials, weights, sums and
+// the periodic Gauss-Jordan refresh.
+constexpr int kMixThreads = 256;
+enum : int { kGemmFP32 = 0, kGemmBF16 = 1 };
+
+struct DevMix {
+    int M, Nb, Norb, Nup, Ndn, N, P, ns, nspec, nw, has_en, gemm;
+    double vii;
+    uint64_t sysid;
+    const double *R, *Z, *rc, *jas, *btab;
+    const int32_t *core, *spec, *btype;
+    const float *Cf;             // [Nb][ns] coefficients, FP32
+    const uint16_t *Cbf;         // [tiles][Nb/32][64 lanes][8] BF16 MFMA B operands
+    int nb32;                    // Nb rounded up to a multiple of 32
+    double *pos, *lw, *eL, *Wd;  // [nw][N][3], [nw]
+    float *state;                // [nw][stride] walker blocks (current buffer)
+    long stride;                 // floats per walker block
+    // offsets (floats) inside a walker block
+    long g_Phi;                  // [2][ns][6 ns]  orbital values at the moves, k-major per spin
+    long g_dPhi;                 // [2][ns][4 ns]  gradient and Laplacian, k-major per spin
+    long g_Arow;                 // [N][ns]        Slater rows
+    long g_AinvT;                // [2][ns][ns]    transposed inverses
+    int32_t *iters, *trace;
+    int trace_cap;
+    // LDS layout, byte offsets
+    int l_pos, l_nue, l_nua, l_scal, l_red, l_U, l_R, l_Rdet, l_dJ, l_gD, l_Jg, l_Jl, l_dje,
+        l_rows, l_tmp, l_bytes;
+};
+
 // per-walker scalars stored at o_scal
 enum : int { kScLogdet0 = 0, kScLogdet1 = 1, kScSign0 = 2, kScSign1 = 3, kScVee = 4,
              kScLen = 8 };

@@ -22,6 +22,7 @@
 #include <math.h>
 
 #include "lrdmc_dev.hpp"
+#include "lrdmc_devfn.hpp"
 
 namespace lrdmc {
 
@@ -41,187 +42,6 @@ namespace lrdmc {
 #define LRDMC_T(k) (void)0
 #endif
 
-// ---------------------------------------------------------------------------
-// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter (c0..c3), key
-// (k0, k1); uniform = top 53 bits of the first output word times 2^-53.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double philox_uniform(uint64_t k0, uint64_t k1, uint64_t c0,
-                                                 uint64_t c1, uint64_t c2, uint64_t c3)
-{
-    const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
-    const uint64_t w0 = 0x9E3779B97F4A7C15ull, w1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) { k0 += w0; k1 += w1; }
-        const uint64_t h0 = __umul64hi(m0, c0), l0 = m0 * c0;
-        const uint64_t h1 = __umul64hi(m1, c2), l1 = m1 * c2;
-        const uint64_t n0 = h1 ^ c1 ^ k0, n2 = h0 ^ c3 ^ k1;
-        c0 = n0; c1 = l1; c2 = n2; c3 = l0;
-    }
-    return (double)(c0 >> 11) * 0x1.0p-53;
-}
-
-// ---------------------------------------------------------------------------
-// wavefront collectives on DPP (data-parallel primitives: lane shuffles that
-// run in the VALU, no LDS round trip).  A double moves as two 32-bit halves.
-// Every lane receives the same (lane 63) result so that control flow stays
-// uniform; the reduction order is fixed, so results are bit-reproducible.
-// ---------------------------------------------------------------------------
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_mov(double v)
-{
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double lane63(double v)
-{
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-    v += dpp_mov<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
-    v += dpp_mov<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
-    v += dpp_mov<0x114, 0xf>(v);   // row_shr:4
-    v += dpp_mov<0x118, 0xf>(v);   // row_shr:8
-    v += dpp_mov<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
-    v += dpp_mov<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
-    return lane63(v);
-}
-
-// inclusive prefix sum over the 64 lanes (Hillis-Steele inside 16-lane rows,
-// then row broadcasts)
-__device__ __forceinline__ double wave_incl_scan(double v, int)
-{
-    v += dpp_mov<0x111, 0xf>(v);   // row_shr:1
-    v += dpp_mov<0x112, 0xf>(v);   // row_shr:2
-    v += dpp_mov<0x114, 0xf>(v);   // row_shr:4
-    v += dpp_mov<0x118, 0xf>(v);   // row_shr:8
-    v += dpp_mov<0x142, 0xa>(v);   // row_bcast:15
-    v += dpp_mov<0x143, 0xc>(v);   // row_bcast:31
-    return v;
-}
-
-typedef double double4_t __attribute__((ext_vector_type(4)));
-
-// Pade pair function u(r) = (A r + B r^2)/(1 + b r) with u' and u''.
-__device__ __forceinline__ double pade_u(const double* p, double r)
-{
-    return (p[0] * r + p[1] * r * r) / (1.0 + p[2] * r);
-}
-// u, u'/r and u'' + 2u'/r (the pieces of the gradient and Laplacian), with
-// one division for 1/(1 + b r) and one for 1/r
-__device__ __forceinline__ void pade_derivs(const double* p, double r, double& u, double& du_r,
-                                            double& lap)
-{
-    const double A = p[0], B = p[1], b = p[2];
-    const double iden = 1.0 / (1.0 + b * r), ir = 1.0 / r;
-    const double i2 = iden * iden;
-    u = (A * r + B * r * r) * iden;
-    const double du = (A + 2.0 * B * r + B * b * r * r) * i2;
-    du_r = du * ir;
-    lap = 2.0 * (B - A * b) * i2 * iden + 2.0 * du_r;
-}
-
-__device__ __forceinline__ double norm3(double x, double y, double z)
-{
-    return sqrt(x * x + y * y + z * z);
-}
-
-// Point q of electron position r: r itself (q = 0) or its lattice neighbour
-// q = 1..6 in move order (+a x, -a x, +a y, -a y, +a z, -a z); the displaced
-// coordinate is formed by the same single addition as the move itself.
-__device__ __forceinline__ void point_q(const double* r, int q, double a, double* o)
-{
-    o[0] = r[0]; o[1] = r[1]; o[2] = r[2];
-    if (q == 1) o[0] = r[0] + a;
-    if (q == 2) o[0] = r[0] + (-a);
-    if (q == 3) o[1] = r[1] + a;
-    if (q == 4) o[1] = r[1] + (-a);
-    if (q == 5) o[2] = r[2] + a;
-    if (q == 6) o[2] = r[2] + (-a);
-}
-
-// Value of basis function mu at point r.
-__device__ __forceinline__ double basis_value(const DevSys& s, int mu, const double* r)
-{
-    const double* Ra = s.btab + 4 * mu;
-    const double dx = r[0] - Ra[0], dy = r[1] - Ra[1], dz = r[2] - Ra[2];
-    const double d2 = dx * dx + dy * dy + dz * dz, al = Ra[3];
-    const int t = s.btype[mu];
-    if (t == 4) return exp(-al * sqrt(d2));
-    const double g = exp(-al * d2);
-    if (t == 0) return g;
-    return (t == 1 ? dx : (t == 2 ? dy : dz)) * g;
-}
-
-// Value, gradient and Laplacian of basis function mu at r.
-__device__ __forceinline__ void basis_vgl(const DevSys& s, int mu, const double* r, double& v,
-                                          double* g, double& l)
-{
-    const double* Ra = s.btab + 4 * mu;
-    const double d[3] = {r[0] - Ra[0], r[1] - Ra[1], r[2] - Ra[2]};
-    const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2], al = Ra[3];
-    const int t = s.btype[mu];
-    if (t == 4) {
-        const double dd = sqrt(d2), e = exp(-al * dd);
-        v = e;
-        for (int c = 0; c < 3; ++c) g[c] = -al * d[c] / dd * e;
-        l = (al * al - 2.0 * al / dd) * e;
-    } else if (t == 0) {
-        const double e = exp(-al * d2);
-        v = e;
-        for (int c = 0; c < 3; ++c) g[c] = -2.0 * al * d[c] * e;
-        l = (4.0 * al * al * d2 - 6.0 * al) * e;
-    } else {
-        const int q = t - 1;
-        const double e = exp(-al * d2);
-        v = d[q] * e;
-        for (int c = 0; c < 3; ++c) g[c] = ((c == q) ? e : 0.0) - 2.0 * al * d[q] * d[c] * e;
-        l = d[q] * e * (4.0 * al * al * d2 - 10.0 * al);
-    }
-}
-
-// The same two functions from the displacement d = r - R, d2 = |d|^2.
-__device__ __forceinline__ double basis_value_d(int t, double al, double dx, double dy, double dz,
-                                                double d2)
-{
-    if (t == 4) return exp(-al * sqrt(d2));
-    const double g = exp(-al * d2);
-    if (t == 0) return g;
-    return (t == 1 ? dx : (t == 2 ? dy : dz)) * g;
-}
-
-__device__ __forceinline__ void basis_vgl_d(int t, double al, double dx, double dy, double dz,
-                                            double d2, double& v, double* g, double& l)
-{
-    const double d[3] = {dx, dy, dz};
-    if (t == 4) {
-        const double dd = sqrt(d2), e = exp(-al * dd), id = 1.0 / dd;
-        v = e;
-        for (int c = 0; c < 3; ++c) g[c] = -al * d[c] * id * e;
-        l = (al * al - 2.0 * al * id) * e;
-    } else if (t == 0) {
-        const double e = exp(-al * d2);
-        v = e;
-        for (int c = 0; c < 3; ++c) g[c] = -2.0 * al * d[c] * e;
-        l = (4.0 * al * al * d2 - 6.0 * al) * e;
-    } else {
-        const int q = t - 1;
-        const double e = exp(-al * d2), dq = d[q];
-        v = dq * e;
-        for (int c = 0; c < 3; ++c) g[c] = ((c == q) ? e : 0.0) - 2.0 * al * dq * d[c] * e;
-        l = dq * e * (4.0 * al * al * d2 - 10.0 * al);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// per-walker state views
-// ---------------------------------------------------------------------------
 // A workgroup is one wavefront: LDS operations of a wavefront complete in
 // issue order, so exchanging data between its lanes through LDS needs only a
 // compiler-level barrier (no s_barrier and no drain of outstanding memory
