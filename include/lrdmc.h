@@ -49,7 +49,15 @@ extern "C" {
 #define LRDMC_SCHEME_LB    0   /* load-balanced, fixed N_proj (Algorithm 2) */
 #define LRDMC_SCHEME_CONV  1   /* conventional continuous time (Algorithm 1) */
 
-#define LRDMC_FP64         0   /* every step in FP64 */
+#define LRDMC_FP64         0   /* every step in FP64; walker state in LDS */
+#define LRDMC_MIXED_FP32   1   /* Sec. III.B mixed precision: orbital rows,
+                                  Sherman-Morrison updates, ratios and Jastrow
+                                  in FP32; positions, weights, local-energy
+                                  accumulation and the periodic refresh of
+                                  the inverse in FP64; orbital product on
+                                  FP32 MFMA */
+#define LRDMC_MIXED_BF16   2   /* as LRDMC_MIXED_FP32, with the orbital
+                                  product on BF16 MFMA (FP32 accumulation) */
 
 #define LRDMC_BASIS_S      0   /* exp(-alpha r^2) */
 #define LRDMC_BASIS_PX     1   /* (x-X) exp(-alpha r^2), likewise PY, PZ */
@@ -58,7 +66,7 @@ extern "C" {
 #define LRDMC_BASIS_STO1S  4   /* exp(-zeta r) */
 
 #define LRDMC_CORE_BARE    0   /* -Z/r; lattice bound -Z/max(r,a) (App. D) */
-#define LRDMC_CORE_SOFT    1   /* -Z erf(r/rc)/r, a smooth local core */
+#define LRDMC_CORE_SOFT    1   /* -Z/sqrt(r^2 + rc^2), a softened local core */
 
 #define LRDMC_NU_OPT_OWN   0   /* nu_max for electron i iff one of its own 6
                                   moves crosses the node (App. D nu_opt) */
@@ -91,7 +99,9 @@ typedef struct lrdmc_system {
 /* ---- run parameters ---------------------------------------------------- */
 typedef struct lrdmc_params {
     int32_t scheme;          /* LRDMC_SCHEME_* */
-    int32_t precision;       /* LRDMC_FP64 */
+    int32_t precision;       /* LRDMC_FP64 or LRDMC_MIXED_*; the mixed kinds keep
+                                per-walker orbital data in HBM and support
+                                larger systems than the FP64 layout */
     double a;                /* lattice space (bohr) */
     double tau;              /* conventional: projection time per branching */
     int32_t n_proj;          /* load-balanced: steps per branching */

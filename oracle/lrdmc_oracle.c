@@ -32,7 +32,7 @@ typedef struct {
     int M;                    /* atoms */
     const double *R;          /* [M][3] */
     const double *Z;          /* [M] charge seen by electrons */
-    const int32_t *core;      /* [M] 0 bare Coulomb, 1 smooth erf core */
+    const int32_t *core;      /* [M] 0 bare Coulomb, 1 softened core -Z/sqrt(r^2+rc^2) */
     const double *rc;         /* [M] */
     const int32_t *spec;      /* [M] species for e-n Jastrow */
     int Nb;
@@ -277,7 +277,7 @@ static void nuclear_potential(const orc_system *s, const double r[3], double a,
             v += -s->Z[I] / d;
             va += -s->Z[I] / (d > a ? d : a);
         } else {
-            double t = -s->Z[I] * erf(d / s->rc[I]) / d;
+            double t = -s->Z[I] / sqrt(d * d + s->rc[I] * s->rc[I]);
             v += t; va += t;
         }
     }

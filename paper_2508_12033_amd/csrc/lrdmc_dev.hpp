@@ -87,6 +87,13 @@ struct DevMix {
         l_rows, l_tmp, l_bytes;
 };
 
+// What the reconfiguration kernels see of a system (either layout).
+struct BranchView {
+    int nw, N;
+    uint64_t sysid;
+    double *pos, *lw, *eL, *Wd;   // current buffers
+};
+
 // per-walker scalars stored at o_scal
 enum : int { kScLogdet0 = 0, kScLogdet1 = 1, kScSign0 = 2, kScSign1 = 3, kScVee = 4,
              kScLen = 8 };

@@ -2,6 +2,11 @@
 // carving, kernel launches on the caller's stream, and the host-level pieces
 // of the method (E_0 update after each branching, Algorithm 2; the
 // correcting-factor energy estimate and its blocking error bar, Sec. II.A).
+//
+// Two walker layouts: FP64 runs use the LDS-resident one-wavefront-per-walker
+// phase kernel (phase_fp64); mixed-precision runs use the 256-thread
+// workgroup-per-walker kernel with orbital data in HBM (phase_mixed).  Both
+// share the reconfiguration kernels.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,12 +21,16 @@
 
 namespace lrdmc {
 __global__ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa);
-__global__ void branch_scan(DevSys s, int scheme, double E0, double* cum, double* out);
-__global__ void branch_comb(DevSys s, uint64_t seed, int j, const double* cum, const double* out,
+__global__ void phase_mixed(const DevMix* __restrict__ sys, PhaseArgs pa, int build);
+__global__ void branch_scan(BranchView s, int scheme, double E0, double* cum, double* out);
+__global__ void branch_comb(BranchView s, uint64_t seed, int j, const double* cum, const double* out,
                             int32_t* sel);
 __global__ void branch_count(const int32_t* sel, int nw, int* n_distinct);
-__global__ void branch_gather(DevSys s, const int32_t* sel, const double* pos_old,
+__global__ void branch_gather(BranchView s, const int32_t* sel, const double* pos_old,
                               const double* eL_old, const double* W_old);
+__global__ void branch_gather_mixed(const DevMix* __restrict__ sys, const int32_t* sel,
+                                    const float* old_state, const double* pos_old,
+                                    const double* eL_old, const double* W_old);
 }  // namespace lrdmc
 
 using namespace lrdmc;
@@ -45,65 +54,106 @@ int fail(int code, const std::string& msg)
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxLdsBytes = 160 * 1024;
+enum { kKindLds = 0, kKindMixed = 1 };
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int kind_of(const lrdmc_params& p) { return p.precision == LRDMC_FP64 ? kKindLds : kKindMixed; }
 
 // Per-system sizes and layout, computed identically by workspace_bytes and init.
 struct Layout {
-    int N, P, ns;
-    // LDS offsets (doubles)
+    int kind, N, P, ns;
+    // FP64 kernel: LDS offsets (doubles), spill layout
     int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje, o_scal, o_B,
         o_rows, o_tmp, o_C, lds_doubles;
     int s_Phi, s_dPhi;
     long spill_stride;
-    // workspace bytes of each device array
+    // mixed kernel: LDS byte offsets, walker block (floats)
+    int l_pos, l_nue, l_nua, l_scal, l_red, l_U, l_R, l_Rdet, l_dJ, l_gD, l_Jg, l_Jl, l_dje, l_rows,
+        l_tmp, l_bytes;
+    long g_Phi, g_dPhi, g_Arow, g_AinvT, m_stride;
+    int nb32, tiles;
+    size_t lds_bytes;
+    // workspace bytes
     size_t b_sys, b_state;
 };
 
 Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
 {
     Layout L{};
+    L.kind = kind_of(p);
     L.N = s.n_up + s.n_dn;
     L.P = 6 * L.N;
     L.ns = std::max(1, std::max(s.n_up, s.n_dn));
-    int o = 0;
-    auto take = [&](int n) { int r = o; o += (n + 1) / 2 * 2; return r; };
-    L.o_pos = take(3 * L.N);
-    L.o_R = take(L.P);
-    L.o_Rdet = take(L.P);
-    L.o_dJ = take(L.P);
-    L.o_Arow = take(L.N * L.ns);
-    L.o_AinvT = take(2 * L.ns * L.ns);
-    L.o_Jg = take(3 * L.N);
-    L.o_Jl = take(L.N);
-    L.o_nue = take(L.N);
-    L.o_nua = take(L.N);
-    L.o_dje = take(L.N);
-    L.o_scal = take(kScLen);
-    L.o_B = take(std::max(std::max(11 * s.n_basis, 2 * L.ns * L.ns), 7 * L.N));
-    L.o_rows = take(11 * L.ns);
-    L.o_tmp = take(3 * L.ns + 8);
-    L.o_C = take(s.n_basis * L.ns);
-    L.lds_doubles = o;
-    L.s_Phi = 0;
-    L.s_dPhi = L.P * L.ns;
-    L.spill_stride = (long)(align_up((size_t)(L.P * L.ns + 4 * L.N * L.ns) * 8) / 8);
-    const int M = s.n_atoms, Nb = s.n_basis;
-    L.b_sys = align_up(M * 3 * 8) + 2 * align_up(M * 8) + 2 * align_up(M * 4) + 2 * align_up(Nb * 4) +
-              align_up(Nb * 8) + align_up((size_t)Nb * s.n_orb * 8) +
-              align_up((2 + s.n_species) * 3 * 8) + align_up((size_t)Nb * 4 * 8);
+    const int M = s.n_atoms, Nb = s.n_basis, N = L.N, P = L.P, ns = L.ns;
     const size_t nw = s.n_walkers;
-    L.b_state = 2 * align_up(nw * 3 * L.N * 8)      // positions, double-buffered
-                + align_up(nw * 8)                  // lw
-                + 4 * align_up(nw * 8)              // eL, W double-buffered
-                + align_up(nw * L.spill_stride * 8) // spill
-                + 2 * align_up(nw * 4)              // iters, sel
-                + align_up(nw * 8)                  // cumulative weights
-                + align_up(8 * 8)                   // branch outputs
-                + align_up(8)                       // distinct counter
-                + 2 * align_up(sizeof(DevSys))      // device copies of the descriptor
-                + (p.trace_cap > 0 ? align_up(nw * (size_t)p.trace_cap * 4) : 0);
-    (void)p;
+    L.b_sys = align_up(M * 3 * 8) + 2 * align_up(M * 8) + 2 * align_up(M * 4) +
+              2 * align_up(Nb * 4) + align_up(Nb * 8) + align_up((size_t)Nb * s.n_orb * 8) +
+              align_up((2 + s.n_species) * 3 * 8) + align_up((size_t)Nb * 4 * 8);
+    size_t common = 2 * align_up(nw * 3 * N * 8)    // positions, double-buffered
+                    + align_up(nw * 8)              // lw
+                    + 4 * align_up(nw * 8)          // eL, W double-buffered
+                    + 2 * align_up(nw * 4)          // iters, sel
+                    + align_up(nw * 8)              // cumulative weights
+                    + align_up(8 * 8)               // branch outputs
+                    + align_up(8)                   // distinct counter
+                    + (p.trace_cap > 0 ? align_up(nw * (size_t)p.trace_cap * 4) : 0);
+    if (L.kind == kKindLds) {
+        int o = 0;
+        auto take = [&](int n) { int r = o; o += (n + 1) / 2 * 2; return r; };
+        L.o_pos = take(3 * N);
+        L.o_R = take(P);
+        L.o_Rdet = take(P);
+        L.o_dJ = take(P);
+        L.o_Arow = take(N * ns);
+        L.o_AinvT = take(2 * ns * ns);
+        L.o_Jg = take(3 * N);
+        L.o_Jl = take(N);
+        L.o_nue = take(N);
+        L.o_nua = take(N);
+        L.o_dje = take(N);
+        L.o_scal = take(kScLen);
+        L.o_B = take(std::max(std::max(11 * Nb, 2 * ns * ns), 7 * N));
+        L.o_rows = take(11 * ns);
+        L.o_tmp = take(3 * ns + 8);
+        L.o_C = take(Nb * ns);
+        L.lds_doubles = o;
+        L.lds_bytes = (size_t)o * 8;
+        L.s_Phi = 0;
+        L.s_dPhi = P * ns;
+        L.spill_stride = (long)(align_up((size_t)(P * ns + 4 * N * ns) * 8) / 8);
+        L.b_state = common + align_up(nw * L.spill_stride * 8) + 2 * align_up(sizeof(DevSys));
+    } else {
+        L.nb32 = (Nb + 31) / 32 * 32;
+        L.tiles = (ns + 15) / 16;
+        int o = 0;
+        auto take = [&](size_t bytes) { int r = o; o += (int)((bytes + 15) / 16 * 16); return r; };
+        L.l_pos = take(3 * N * 8);
+        L.l_nue = take(N * 8);
+        L.l_nua = take(N * 8);
+        L.l_scal = take(kScLen * 8);
+        L.l_red = take(8 * 8);
+        L.l_U = take(std::max(std::max((size_t)11 * L.nb32 * 4, (size_t)(ns * ns + ns) * 8),
+                              (size_t)7 * N * 4));
+        L.l_R = take(P * 4);
+        L.l_Rdet = take(P * 4);
+        L.l_dJ = take(P * 4);
+        L.l_gD = take(4 * N * 4);
+        L.l_Jg = take(3 * N * 4);
+        L.l_Jl = take(N * 4);
+        L.l_dje = take(N * 4);
+        L.l_rows = take(11 * ns * 4);
+        L.l_tmp = take((3 * ns + 8) * 4);
+        L.l_bytes = o;
+        L.lds_bytes = o;
+        L.g_Phi = 0;
+        L.g_dPhi = L.g_Phi + 2L * ns * 6 * ns;
+        L.g_Arow = L.g_dPhi + 2L * ns * 4 * ns;
+        L.g_AinvT = L.g_Arow + (long)N * ns;
+        L.m_stride = (L.g_AinvT + 2L * ns * ns + 63) / 64 * 64;
+        L.b_sys += align_up((size_t)Nb * ns * 4) +
+                   align_up((size_t)L.tiles * (L.nb32 / 32) * 64 * 8 * 2);
+        L.b_state = common + 2 * align_up(nw * L.m_stride * 4) + 2 * align_up(sizeof(DevMix));
+    }
     return L;
 }
 
@@ -112,7 +162,9 @@ std::string validate(const lrdmc_system* sys, int n_sys, const lrdmc_params* prm
     if (!sys || n_sys < 1) return "no systems";
     if (!prm) return "null params";
     if (prm->scheme != LRDMC_SCHEME_LB && prm->scheme != LRDMC_SCHEME_CONV) return "bad scheme";
-    if (prm->precision != LRDMC_FP64) return "only LRDMC_FP64 precision is available";
+    if (prm->precision != LRDMC_FP64 && prm->precision != LRDMC_MIXED_FP32 &&
+        prm->precision != LRDMC_MIXED_BF16)
+        return "bad precision";
     if (!(prm->a > 0)) return "lattice space a must be > 0";
     if (prm->scheme == LRDMC_SCHEME_CONV && !(prm->tau > 0)) return "tau must be > 0";
     if (prm->scheme == LRDMC_SCHEME_LB && prm->n_proj < 1) return "n_proj must be >= 1";
@@ -140,28 +192,59 @@ std::string validate(const lrdmc_system* sys, int n_sys, const lrdmc_params* prm
             if (!(s.basis_exp[mu] > 0)) return "basis exponent <= 0";
         }
         const Layout L = make_layout(s, *prm);
-        if ((size_t)L.lds_doubles * 8 > (size_t)kMaxLdsBytes)
-            return "system too large for the LDS-resident walker layout";
+        if (L.lds_bytes > (size_t)kMaxLdsBytes)
+            return L.kind == kKindLds ? "system too large for the LDS-resident FP64 walker layout "
+                                        "(use a mixed precision)"
+                                      : "system too large for the mixed-precision walker layout";
         if (s.n_walkers > (1 << 24)) return "too many walkers";
     }
     return "";
 }
 
+uint16_t to_bf16(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);   // inf / nan
+    const uint32_t rounding = 0x7fffu + ((u >> 16) & 1u);                // nearest even
+    return (uint16_t)((u + rounding) >> 16);
+}
+
 struct SysRun {
-    DevSys d;             // current buffers
-    DevSys* dsys[2];      // device copies of d for the two buffer parities
-    DevSys hsys[2];       // their host sources
-    int parity;
-    double *pos_alt, *eL_alt, *W_alt;
-    double *cum, *bout;
-    int32_t* sel;
-    int* ndist;
+    int kind;
     Layout L;
+    // common buffers (current + alternate)
+    double *pos, *lw, *eL, *Wd, *pos_alt, *eL_alt, *W_alt;
+    int32_t *iters, *trace, *sel;
+    double *cum, *bout;
+    int* ndist;
+    int nw, N;
+    uint64_t sysid;
+    // FP64 layout
+    DevSys d;
+    DevSys* dsys[2];
+    DevSys hsys[2];
+    // mixed layout
+    DevMix m;
+    DevMix* dmix[2];
+    DevMix hmix[2];
+    float *state, *state_alt;
+    bool need_build;
+    int parity;
     double e0;
     std::vector<double> hist_lwb, hist_e;
     std::vector<double> btab_host;
-    size_t lds_bytes;
+    std::vector<float> cf_host;
+    std::vector<uint16_t> cbf_host;
 };
+
+BranchView view_of(const SysRun& r)
+{
+    BranchView v;
+    v.nw = r.nw; v.N = r.N; v.sysid = r.sysid;
+    v.pos = r.pos; v.lw = r.lw; v.eL = r.eL; v.Wd = r.Wd;
+    return v;
+}
 
 }  // namespace
 
@@ -170,7 +253,7 @@ struct lrdmc_handle {
     lrdmc_params prm;
     hipStream_t stream;
     int j;
-    unsigned long long* counters;   // [kCntLen] device
+    unsigned long long* counters;           // [kCntLen] device
     unsigned long long cnt_init[kCntLen];   // host source of the counter reset
     hipEvent_t ev0, ev1;
     unsigned long long* timers = nullptr;   // instrumentation builds: [nw][8]
@@ -201,23 +284,36 @@ static int conv_cap(const lrdmc_params& p, int N)
     return cap > 2e9 ? 2000000000 : (int)cap;
 }
 
-static int launch_phase(lrdmc_handle* h, SysRun& r)
+static PhaseArgs phase_args(const lrdmc_handle* h, const SysRun& r, int nproj_override)
 {
     PhaseArgs pa{};
-    pa.scheme = h->prm.scheme;
-    pa.nproj = h->prm.n_proj;
+    pa.scheme = nproj_override >= 0 ? 0 : h->prm.scheme;
+    pa.nproj = nproj_override >= 0 ? nproj_override : h->prm.n_proj;
     pa.j = h->j;
     pa.refresh_every = h->prm.refresh_every;
     pa.nu_mode = h->prm.nu_opt_mode;
-    pa.conv_cap = conv_cap(h->prm, r.d.N);
+    pa.conv_cap = conv_cap(h->prm, r.N);
     pa.a = h->prm.a;
     pa.tau = h->prm.tau;
     pa.E0 = r.e0;
     pa.seed = h->prm.seed;
     pa.counters = h->counters;
     pa.timers = h->timers;
-    hipLaunchKernelGGL(phase_fp64, dim3(r.d.nw), dim3(kWave), r.lds_bytes, h->stream,
-                       (const DevSys*)r.dsys[r.parity], pa);
+    return pa;
+}
+
+// nproj_override >= 0: a load-balanced phase of that many steps (0 = evaluate only)
+static int launch_phase(lrdmc_handle* h, SysRun& r, int nproj_override)
+{
+    const PhaseArgs pa = phase_args(h, r, nproj_override);
+    if (r.kind == kKindLds) {
+        hipLaunchKernelGGL(phase_fp64, dim3(r.nw), dim3(kWave), r.L.lds_bytes, h->stream,
+                           (const DevSys*)r.dsys[r.parity], pa);
+    } else {
+        hipLaunchKernelGGL(phase_mixed, dim3(r.nw), dim3(kMixThreads), r.L.lds_bytes, h->stream,
+                           (const DevMix*)r.dmix[r.parity], pa, r.need_build ? 1 : 0);
+        r.need_build = false;
+    }
     HIPCHK(hipGetLastError());
     return LRDMC_OK;
 }
@@ -253,6 +349,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
     h->prm = *prm;
     h->stream = (hipStream_t)stream;
     h->j = 0;
+    h->sys.reserve(n_sys);
     char* base = (char*)dev_workspace;
     size_t off = 0;
     auto carve = [&](size_t bytes) { void* p = base + off; off += align_up(bytes); return p; };
@@ -267,16 +364,17 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
     int rc = LRDMC_OK;
     for (int k = 0; k < n_sys && rc == LRDMC_OK; ++k) {
         const lrdmc_system& s = sys[k];
-        SysRun r{};
+        h->sys.emplace_back();
+        SysRun& r = h->sys.back();
         r.L = make_layout(s, *prm);
+        r.kind = r.L.kind;
         const Layout& L = r.L;
-        DevSys& d = r.d;
-        d.M = s.n_atoms; d.Nb = s.n_basis; d.Norb = s.n_orb; d.Nup = s.n_up; d.Ndn = s.n_dn;
-        d.N = L.N; d.P = L.P; d.ns = L.ns; d.nspec = s.n_species; d.nw = s.n_walkers;
-        d.sysid = s.system_id;
-        d.has_en = 0;
+        r.nw = s.n_walkers;
+        r.N = L.N;
+        r.sysid = s.system_id;
+        int has_en = 0;
         for (int q = 0; q < s.n_species; ++q)
-            if (s.jastrow[3 * (2 + q)] != 0.0 || s.jastrow[3 * (2 + q) + 1] != 0.0) d.has_en = 1;
+            if (s.jastrow[3 * (2 + q)] != 0.0 || s.jastrow[3 * (2 + q) + 1] != 0.0) has_en = 1;
         double vii = 0.0;
         for (int I = 0; I < s.n_atoms; ++I)
             for (int J = I + 1; J < s.n_atoms; ++J) {
@@ -285,8 +383,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
                 const double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
                 vii += s.atom_charge[I] * s.atom_charge[J] / std::sqrt(dx * dx + dy * dy + dz * dz);
             }
-        d.vii = vii;
-        const int M = s.n_atoms, Nb = s.n_basis;
+        const int M = s.n_atoms, Nb = s.n_basis, ns = L.ns;
         double* R = (double*)carve(M * 3 * 8);
         double* Z = (double*)carve(M * 8);
         double* rcs = (double*)carve(M * 8);
@@ -313,85 +410,158 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             rc = fail(LRDMC_ERR_HIP, "upload of system arrays failed");
             break;
         }
-        d.R = R; d.Z = Z; d.rc = rcs; d.core = core; d.spec = spec; d.batom = batom;
-        d.btype = btype; d.bexp = bexp; d.C = C; d.jas = jas; d.btab = btab;
+        float* Cf = nullptr;
+        uint16_t* Cbf = nullptr;
+        if (r.kind == kKindMixed) {
+            Cf = (float*)carve((size_t)Nb * ns * 4);
+            Cbf = (uint16_t*)carve((size_t)L.tiles * (L.nb32 / 32) * 64 * 8 * 2);
+            r.cf_host.resize((size_t)Nb * ns);
+            for (int mu = 0; mu < Nb; ++mu)
+                for (int c = 0; c < ns; ++c)
+                    r.cf_host[(size_t)mu * ns + c] = (float)s.mo_coeff[(size_t)mu * s.n_orb + c];
+            // BF16 B operands of v_mfma_f32_16x16x32_bf16: lane l of k-block kb holds
+            // C[32 kb + 8 (l / 16) + e][16 t + l % 16], e = 0..7
+            r.cbf_host.assign((size_t)L.tiles * (L.nb32 / 32) * 64 * 8, 0);
+            for (int t = 0; t < L.tiles; ++t)
+                for (int kb = 0; kb < L.nb32 / 32; ++kb)
+                    for (int l = 0; l < 64; ++l)
+                        for (int e = 0; e < 8; ++e) {
+                            const int mu = 32 * kb + 8 * (l / 16) + e, col = 16 * t + l % 16;
+                            const float x = (mu < Nb && col < ns)
+                                                ? (float)s.mo_coeff[(size_t)mu * s.n_orb + col]
+                                                : 0.0f;
+                            r.cbf_host[(((size_t)t * (L.nb32 / 32) + kb) * 64 + l) * 8 + e] = to_bf16(x);
+                        }
+            if (up(Cf, r.cf_host.data(), r.cf_host.size() * 4) ||
+                up(Cbf, r.cbf_host.data(), r.cbf_host.size() * 2)) {
+                rc = fail(LRDMC_ERR_HIP, "upload of coefficients failed");
+                break;
+            }
+        }
         const size_t nw = s.n_walkers;
-        d.pos = (double*)carve(nw * 3 * L.N * 8);
+        r.pos = (double*)carve(nw * 3 * L.N * 8);
         r.pos_alt = (double*)carve(nw * 3 * L.N * 8);
-        d.lw = (double*)carve(nw * 8);
-        d.eL = (double*)carve(nw * 8);
+        r.lw = (double*)carve(nw * 8);
+        r.eL = (double*)carve(nw * 8);
         r.eL_alt = (double*)carve(nw * 8);
-        d.Wd = (double*)carve(nw * 8);
+        r.Wd = (double*)carve(nw * 8);
         r.W_alt = (double*)carve(nw * 8);
-        d.spill = (double*)carve(nw * L.spill_stride * 8);
-        d.spill_stride = L.spill_stride;
-        d.iters = (int32_t*)carve(nw * 4);
+        r.iters = (int32_t*)carve(nw * 4);
         r.sel = (int32_t*)carve(nw * 4);
         r.cum = (double*)carve(nw * 8);
         r.bout = (double*)carve(8 * 8);
         r.ndist = (int*)carve(8);
-        d.trace_cap = prm->trace_cap;
-        d.trace = prm->trace_cap > 0 ? (int32_t*)carve(nw * (size_t)prm->trace_cap * 4) : nullptr;
-        d.o_pos = L.o_pos; d.o_R = L.o_R; d.o_Rdet = L.o_Rdet; d.o_dJ = L.o_dJ;
-        d.o_Arow = L.o_Arow; d.o_AinvT = L.o_AinvT; d.o_Jg = L.o_Jg; d.o_Jl = L.o_Jl;
-        d.o_nue = L.o_nue; d.o_nua = L.o_nua; d.o_dje = L.o_dje; d.o_scal = L.o_scal;
-        d.o_B = L.o_B; d.o_rows = L.o_rows; d.o_tmp = L.o_tmp; d.o_C = L.o_C;
-        d.lds_doubles = L.lds_doubles;
-        d.s_Phi = L.s_Phi; d.s_dPhi = L.s_dPhi;
-        r.lds_bytes = (size_t)L.lds_doubles * 8;
-        r.dsys[0] = (DevSys*)carve(sizeof(DevSys));
-        r.dsys[1] = (DevSys*)carve(sizeof(DevSys));
+        r.trace = prm->trace_cap > 0 ? (int32_t*)carve(nw * (size_t)prm->trace_cap * 4) : nullptr;
         r.parity = 0;
-        if (up(d.pos, ip, nw * 3 * L.N * 8) != hipSuccess ||
-            hipMemsetAsync(d.lw, 0, nw * 8, h->stream) != hipSuccess) {
+        r.need_build = false;
+        if (r.kind == kKindLds) {
+            DevSys& d = r.d;
+            d.M = M; d.Nb = Nb; d.Norb = s.n_orb; d.Nup = s.n_up; d.Ndn = s.n_dn;
+            d.N = L.N; d.P = L.P; d.ns = ns; d.nspec = s.n_species; d.nw = r.nw;
+            d.has_en = has_en; d.vii = vii; d.sysid = s.system_id;
+            d.R = R; d.Z = Z; d.rc = rcs; d.core = core; d.spec = spec; d.batom = batom;
+            d.btype = btype; d.bexp = bexp; d.C = C; d.jas = jas; d.btab = btab;
+            d.pos = r.pos; d.lw = r.lw; d.eL = r.eL; d.Wd = r.Wd;
+            d.spill = (double*)carve(nw * L.spill_stride * 8);
+            d.spill_stride = L.spill_stride;
+            d.iters = r.iters; d.trace = r.trace; d.trace_cap = prm->trace_cap;
+            d.o_pos = L.o_pos; d.o_R = L.o_R; d.o_Rdet = L.o_Rdet; d.o_dJ = L.o_dJ;
+            d.o_Arow = L.o_Arow; d.o_AinvT = L.o_AinvT; d.o_Jg = L.o_Jg; d.o_Jl = L.o_Jl;
+            d.o_nue = L.o_nue; d.o_nua = L.o_nua; d.o_dje = L.o_dje; d.o_scal = L.o_scal;
+            d.o_B = L.o_B; d.o_rows = L.o_rows; d.o_tmp = L.o_tmp; d.o_C = L.o_C;
+            d.lds_doubles = L.lds_doubles;
+            d.s_Phi = L.s_Phi; d.s_dPhi = L.s_dPhi;
+            r.dsys[0] = (DevSys*)carve(sizeof(DevSys));
+            r.dsys[1] = (DevSys*)carve(sizeof(DevSys));
+            r.hsys[0] = d;
+            r.hsys[1] = d;
+            r.hsys[1].pos = r.pos_alt; r.hsys[1].eL = r.eL_alt; r.hsys[1].Wd = r.W_alt;
+        } else {
+            DevMix& m = r.m;
+            m.M = M; m.Nb = Nb; m.Norb = s.n_orb; m.Nup = s.n_up; m.Ndn = s.n_dn;
+            m.N = L.N; m.P = L.P; m.ns = ns; m.nspec = s.n_species; m.nw = r.nw;
+            m.has_en = has_en; m.vii = vii; m.sysid = s.system_id;
+            m.gemm = prm->precision == LRDMC_MIXED_BF16 ? kGemmBF16 : kGemmFP32;
+            m.R = R; m.Z = Z; m.rc = rcs; m.jas = jas; m.btab = btab;
+            m.core = core; m.spec = spec; m.btype = btype;
+            m.Cf = Cf; m.Cbf = Cbf; m.nb32 = L.nb32;
+            m.pos = r.pos; m.lw = r.lw; m.eL = r.eL; m.Wd = r.Wd;
+            r.state = (float*)carve(nw * L.m_stride * 4);
+            r.state_alt = (float*)carve(nw * L.m_stride * 4);
+            m.state = r.state;
+            m.stride = L.m_stride;
+            m.g_Phi = L.g_Phi; m.g_dPhi = L.g_dPhi; m.g_Arow = L.g_Arow; m.g_AinvT = L.g_AinvT;
+            m.iters = r.iters; m.trace = r.trace; m.trace_cap = prm->trace_cap;
+            m.l_pos = L.l_pos; m.l_nue = L.l_nue; m.l_nua = L.l_nua; m.l_scal = L.l_scal;
+            m.l_red = L.l_red; m.l_U = L.l_U; m.l_R = L.l_R; m.l_Rdet = L.l_Rdet; m.l_dJ = L.l_dJ;
+            m.l_gD = L.l_gD; m.l_Jg = L.l_Jg; m.l_Jl = L.l_Jl; m.l_dje = L.l_dje;
+            m.l_rows = L.l_rows; m.l_tmp = L.l_tmp; m.l_bytes = L.l_bytes;
+            r.dmix[0] = (DevMix*)carve(sizeof(DevMix));
+            r.dmix[1] = (DevMix*)carve(sizeof(DevMix));
+            r.hmix[0] = m;
+            r.hmix[1] = m;
+            r.hmix[1].pos = r.pos_alt; r.hmix[1].eL = r.eL_alt; r.hmix[1].Wd = r.W_alt;
+            r.hmix[1].state = r.state_alt;
+            r.need_build = true;
+        }
+        if (up(r.pos, ip, nw * 3 * L.N * 8) != hipSuccess ||
+            hipMemsetAsync(r.lw, 0, nw * 8, h->stream) != hipSuccess) {
             rc = fail(LRDMC_ERR_HIP, "upload of walkers failed");
             break;
         }
-        if (d.trace && hipMemsetAsync(d.trace, 0xfe, nw * (size_t)prm->trace_cap * 4, h->stream)) {
+        if (r.trace && hipMemsetAsync(r.trace, 0xfe, nw * (size_t)prm->trace_cap * 4, h->stream)) {
             rc = fail(LRDMC_ERR_HIP, "trace init failed");
             break;
         }
         ip += nw * 3 * L.N;
-        h->sys.push_back(r);
-        SysRun& rr = h->sys.back();
-        rr.hsys[0] = rr.d;
-        rr.hsys[1] = rr.d;
-        rr.hsys[1].pos = rr.pos_alt; rr.hsys[1].eL = rr.eL_alt; rr.hsys[1].Wd = rr.W_alt;
     }
     if (rc == LRDMC_OK && off > ws_bytes) rc = fail(LRDMC_ERR_WORKSPACE, "workspace layout overflow");
     for (auto& r : h->sys) {
         if (rc) break;
-        if (up(r.dsys[0], &r.hsys[0], sizeof(DevSys)) || up(r.dsys[1], &r.hsys[1], sizeof(DevSys)))
-            rc = fail(LRDMC_ERR_HIP, "upload of system descriptors failed");
+        const bool bad = r.kind == kKindLds
+                             ? (up(r.dsys[0], &r.hsys[0], sizeof(DevSys)) ||
+                                up(r.dsys[1], &r.hsys[1], sizeof(DevSys)))
+                             : (up(r.dmix[0], &r.hmix[0], sizeof(DevMix)) ||
+                                up(r.dmix[1], &r.hmix[1], sizeof(DevMix)));
+        if (bad) rc = fail(LRDMC_ERR_HIP, "upload of system descriptors failed");
     }
     if (rc == LRDMC_OK) {
-        static bool attr = false;
-        if (!attr) {
-            (void)hipFuncSetAttribute((const void*)phase_fp64,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
-            attr = true;
+        // allow each phase kernel the LDS that its static allocation leaves free
+        for (auto& r : h->sys) {
+            const void* fn = r.kind == kKindLds ? (const void*)phase_fp64 : (const void*)phase_mixed;
+            hipFuncAttributes fa;
+            if (hipFuncGetAttributes(&fa, fn) != hipSuccess) {
+                rc = fail(LRDMC_ERR_HIP, "hipFuncGetAttributes failed");
+                break;
+            }
+            const size_t dyn_max = (size_t)kMaxLdsBytes - fa.sharedSizeBytes;
+            if (r.L.lds_bytes > dyn_max) {
+                rc = fail(LRDMC_ERR_UNSUPPORTED, "system too large for the LDS of one workgroup");
+                break;
+            }
+            if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_max) !=
+                hipSuccess) {
+                rc = fail(LRDMC_ERR_HIP, "hipFuncSetAttribute failed");
+                break;
+            }
         }
+    }
+    if (rc == LRDMC_OK) {
         // initial local energies: a zero-step load-balanced phase
         rc = reset_counters(h);
         for (auto& r : h->sys) {
             if (rc) break;
-            PhaseArgs pa{};
-            pa.scheme = 0; pa.nproj = 0; pa.j = 0; pa.refresh_every = prm->refresh_every;
-            pa.nu_mode = prm->nu_opt_mode; pa.a = prm->a; pa.tau = prm->tau; pa.E0 = 0.0;
-            pa.conv_cap = 1;
-            pa.seed = prm->seed; pa.counters = h->counters;
-            hipLaunchKernelGGL(phase_fp64, dim3(r.d.nw), dim3(kWave), r.lds_bytes, h->stream,
-                               (const DevSys*)r.dsys[r.parity], pa);
-            if (hipGetLastError() != hipSuccess) { rc = fail(LRDMC_ERR_HIP, "init launch failed"); break; }
-            std::vector<double> eL(r.d.nw);
-            if (hipMemcpyAsync(eL.data(), r.d.eL, r.d.nw * 8, hipMemcpyDeviceToHost, h->stream) ||
+            r.e0 = 0.0;
+            if ((rc = launch_phase(h, r, 0))) break;
+            std::vector<double> eL(r.nw);
+            if (hipMemcpyAsync(eL.data(), r.eL, r.nw * 8, hipMemcpyDeviceToHost, h->stream) ||
                 hipStreamSynchronize(h->stream)) {
                 rc = fail(LRDMC_ERR_HIP, "init evaluation failed");
                 break;
             }
             double acc = 0.0;
             for (double x : eL) acc += x;
-            r.e0 = acc / r.d.nw;
+            r.e0 = acc / r.nw;
             if (!std::isfinite(r.e0)) rc = fail(LRDMC_ERR_SINGULAR, "non-finite initial local energy");
         }
         unsigned long long cnt[kCntLen];
@@ -402,12 +572,13 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
         if (!rc && cnt[kCntSingular]) rc = fail(LRDMC_ERR_SINGULAR, "singular Slater matrix at init");
     }
     if (rc) {
+        (void)hipStreamSynchronize(h->stream);
         (void)hipEventDestroy(h->ev0); (void)hipEventDestroy(h->ev1);
         delete h;
         return rc;
     }
 #ifdef LRDMC_SECTION_TIMERS
-    if (hipMalloc((void**)&h->timers, (size_t)h->sys[0].d.nw * 8 * 8) != hipSuccess) h->timers = nullptr;
+    if (hipMalloc((void**)&h->timers, (size_t)h->sys[0].nw * 8 * 8) != hipSuccess) h->timers = nullptr;
 #endif
     *out = h;
     return LRDMC_OK;
@@ -418,7 +589,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
 int lrdmc_section_timers(lrdmc_handle* h, unsigned long long* out)
 {
     if (!h || !h->timers) return fail(LRDMC_ERR_INVALID_ARG, "no timers");
-    HIPCHK(hipMemcpy(out, h->timers, (size_t)h->sys[0].d.nw * 64, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(out, h->timers, (size_t)h->sys[0].nw * 64, hipMemcpyDeviceToHost));
     return LRDMC_OK;
 }
 #endif
@@ -430,7 +601,7 @@ int lrdmc_step(lrdmc_handle* h, lrdmc_step_stats* st)
     if (rc) return rc;
     HIPCHK(hipEventRecord(h->ev0, h->stream));
     for (auto& r : h->sys)
-        if ((rc = launch_phase(h, r))) return rc;
+        if ((rc = launch_phase(h, r, -1))) return rc;
     HIPCHK(hipEventRecord(h->ev1, h->stream));
     if (st) {
         unsigned long long cnt[kCntLen];
@@ -460,12 +631,13 @@ int lrdmc_branch(lrdmc_handle* h, lrdmc_branch_stats* st)
     std::vector<int> nd(h->sys.size());
     for (size_t k = 0; k < h->sys.size(); ++k) {
         SysRun& r = h->sys[k];
-        const int nw = r.d.nw;
+        const int nw = r.nw;
+        const BranchView bv = view_of(r);
         const int nt = std::min(kMaxBranchBlock, std::max(64, 1 << (int)std::ceil(std::log2((double)nw))));
-        hipLaunchKernelGGL(branch_scan, dim3(1), dim3(nt), 0, h->stream, r.d, h->prm.scheme, r.e0,
+        hipLaunchKernelGGL(branch_scan, dim3(1), dim3(nt), 0, h->stream, bv, h->prm.scheme, r.e0,
                            r.cum, r.bout);
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(branch_comb, dim3((nw + 255) / 256), dim3(256), 0, h->stream, r.d,
+        hipLaunchKernelGGL(branch_comb, dim3((nw + 255) / 256), dim3(256), 0, h->stream, bv,
                            h->prm.seed, h->j, r.cum, r.bout, r.sel);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemsetAsync(r.ndist, 0, sizeof(int), h->stream));
@@ -473,16 +645,24 @@ int lrdmc_branch(lrdmc_handle* h, lrdmc_branch_stats* st)
                            r.ndist);
         HIPCHK(hipGetLastError());
         // gather into the alternate buffers, then swap
-        DevSys dn = r.d;
-        dn.pos = r.pos_alt; dn.eL = r.eL_alt; dn.Wd = r.W_alt;
-        const long tot = (long)nw * 3 * r.d.N;
-        hipLaunchKernelGGL(branch_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                           h->stream, dn, r.sel, r.d.pos, r.d.eL, r.d.Wd);
+        if (r.kind == kKindLds) {
+            BranchView dn = bv;
+            dn.pos = r.pos_alt; dn.eL = r.eL_alt; dn.Wd = r.W_alt;
+            const long tot = (long)nw * 3 * r.N;
+            hipLaunchKernelGGL(branch_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                               h->stream, dn, r.sel, r.pos, r.eL, r.Wd);
+        } else {
+            hipLaunchKernelGGL(branch_gather_mixed, dim3(nw), dim3(256), 0, h->stream,
+                               (const DevMix*)r.dmix[r.parity ^ 1], r.sel, r.state, r.pos, r.eL,
+                               r.Wd);
+            std::swap(r.state, r.state_alt);
+        }
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(outs[k].data(), r.bout, 5 * 8, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipMemcpyAsync(&nd[k], r.ndist, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-        r.pos_alt = r.d.pos; r.eL_alt = r.d.eL; r.W_alt = r.d.Wd;
-        r.d.pos = dn.pos; r.d.eL = dn.eL; r.d.Wd = dn.Wd;
+        std::swap(r.pos, r.pos_alt);
+        std::swap(r.eL, r.eL_alt);
+        std::swap(r.Wd, r.W_alt);
         r.parity ^= 1;
     }
     HIPCHK(hipEventRecord(h->ev1, h->stream));
@@ -494,7 +674,7 @@ int lrdmc_branch(lrdmc_handle* h, lrdmc_branch_stats* st)
         SysRun& r = h->sys[k];
         const double mx = outs[k][0], tot = outs[k][1], se = outs[k][2], so = outs[k][3];
         if (!(mx > -INFINITY) || !(tot > 0)) { rc = fail(LRDMC_ERR_ALL_DEAD, "every walker weight is zero"); continue; }
-        const double lwb = std::log(tot / r.d.nw) + mx;
+        const double lwb = std::log(tot / r.nw) + mx;
         const double eb = se / so;
         r.hist_lwb.push_back(lwb);
         r.hist_e.push_back(eb);
@@ -560,16 +740,16 @@ int lrdmc_get_walkers(lrdmc_handle* h, int isys, double* pos, double* lw, double
 {
     if (!h || isys < 0 || isys >= (int)h->sys.size()) return fail(LRDMC_ERR_INVALID_ARG, "bad handle/system");
     const SysRun& r = h->sys[isys];
-    const size_t nw = r.d.nw;
+    const size_t nw = r.nw;
     auto dn = [&](void* dst, const void* src, size_t b) {
         return dst ? hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToHost, h->stream) : hipSuccess;
     };
-    if (dn(pos, r.d.pos, nw * 3 * r.d.N * 8) || dn(lw, r.d.lw, nw * 8) || dn(eL, r.d.eL, nw * 8) ||
-        dn(W, r.d.Wd, nw * 8) || dn(iters, r.d.iters, nw * 4) || dn(sel, r.sel, nw * 4))
+    if (dn(pos, r.pos, nw * 3 * r.N * 8) || dn(lw, r.lw, nw * 8) || dn(eL, r.eL, nw * 8) ||
+        dn(W, r.Wd, nw * 8) || dn(iters, r.iters, nw * 4) || dn(sel, r.sel, nw * 4))
         return fail(LRDMC_ERR_HIP, "device-to-host copy failed");
     if (trace) {
-        if (!r.d.trace) return fail(LRDMC_ERR_INVALID_ARG, "tracing is off (trace_cap = 0)");
-        HIPCHK(hipMemcpyAsync(trace, r.d.trace, nw * (size_t)r.d.trace_cap * 4, hipMemcpyDeviceToHost,
+        if (!r.trace) return fail(LRDMC_ERR_INVALID_ARG, "tracing is off (trace_cap = 0)");
+        HIPCHK(hipMemcpyAsync(trace, r.trace, nw * (size_t)h->prm.trace_cap * 4, hipMemcpyDeviceToHost,
                               h->stream));
     }
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -580,11 +760,12 @@ int lrdmc_set_walkers(lrdmc_handle* h, int isys, const double* pos, const double
 {
     if (!h || isys < 0 || isys >= (int)h->sys.size() || !pos)
         return fail(LRDMC_ERR_INVALID_ARG, "bad arguments");
-    const SysRun& r = h->sys[isys];
-    const size_t nw = r.d.nw;
-    HIPCHK(hipMemcpyAsync(r.d.pos, pos, nw * 3 * r.d.N * 8, hipMemcpyHostToDevice, h->stream));
-    if (lw) HIPCHK(hipMemcpyAsync(r.d.lw, lw, nw * 8, hipMemcpyHostToDevice, h->stream));
+    SysRun& r = h->sys[isys];
+    const size_t nw = r.nw;
+    HIPCHK(hipMemcpyAsync(r.pos, pos, nw * 3 * r.N * 8, hipMemcpyHostToDevice, h->stream));
+    if (lw) HIPCHK(hipMemcpyAsync(r.lw, lw, nw * 8, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
+    r.need_build = r.kind == kKindMixed;   // mixed layout: orbital data follow the positions
     return LRDMC_OK;
 }
 

@@ -1,0 +1,807 @@
+// Mixed-precision projection phase for large systems (up to 128 electrons,
+// 64 orbitals per spin, hundreds of basis functions): one 256-thread
+// workgroup per walker.
+//
+// The same method steps as the FP64 phase kernel (ratios of all 6N lattice
+// moves, App. D lattice diagonal and local energy, Algorithm 1 / Algorithm 2
+// weight update, heat-bath move, Sherman-Morrison update), with the data
+// placement of a system whose walker state does not fit on chip:
+//   HBM (FP32, per walker): orbital values at the 6N moves and orbital
+//     derivatives at the current positions, both k-major per spin so that the
+//     determinant-ratio and gradient dot products read them coalesced; Slater
+//     rows; transposed inverses.
+//   LDS: positions and potentials (FP64), ratios, Jastrow caches, cached
+//     determinant gradients/Laplacians (FP32), the moved electron's basis
+//     rows, block-reduction scratch.
+// Precision: basis functions, Jastrow sums and ratios in FP32; the orbital
+// GEMM on MFMA in FP32 or BF16 with FP32 accumulation; positions, potentials,
+// weights, all sums that form W, bbar and e_L, and the periodic Gauss-Jordan
+// refresh in FP64.  The local energy is formed as the continuum local energy
+// plus sum_i (nu_opt,i - nu_zv,i) (App. D identity), which avoids the
+// cancellation in W - bbar when bbar is known only to FP32 accuracy.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "lrdmc_dev.hpp"
+#include "lrdmc_devfn.hpp"
+
+namespace lrdmc {
+
+extern __shared__ double lds[];
+
+#define LDSD(off) (reinterpret_cast<double*>(reinterpret_cast<char*>(lds) + (off)))
+#define LDSF(off) (reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + (off)))
+
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// block collectives (4 wavefronts); red is a 4-double LDS scratch
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double* red)
+{
+    v = wave_sum(v);
+    const int tid = threadIdx.x;
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// exclusive prefix of v over the block (thread order) and the block total
+__device__ __forceinline__ double block_excl_scan(double v, double* red, double& total)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const double inc = wave_incl_scan(v, lane);
+    double prev = __shfl_up(inc, 1);
+    if (lane == 0) prev = 0.0;
+    __syncthreads();
+    if (lane == 63) red[wv] = inc;
+    __syncthreads();
+    double off = 0.0;
+    for (int q = 0; q < wv; ++q) off += red[q];
+    total = ((red[0] + red[1]) + red[2]) + red[3];
+    return off + prev;
+}
+
+__device__ __forceinline__ float pade_uf(const double* p, float r)
+{
+    const float A = (float)p[0], B = (float)p[1], b = (float)p[2];
+    return (A * r + B * r * r) / (1.0f + b * r);
+}
+
+__device__ __forceinline__ void pade_derivs_f(const double* p, float r, float& u, float& du_r,
+                                              float& lap)
+{
+    const float A = (float)p[0], B = (float)p[1], b = (float)p[2];
+    const float iden = 1.0f / (1.0f + b * r), ir = 1.0f / r;
+    const float i2 = iden * iden;
+    u = (A * r + B * r * r) * iden;
+    const float du = (A + 2.0f * B * r + B * b * r * r) * i2;
+    du_r = du * ir;
+    lap = 2.0f * (B - A * b) * i2 * iden + 2.0f * du_r;
+}
+
+__device__ __forceinline__ int mspin(const DevMix& s, int i) { return i >= s.Nup; }
+__device__ __forceinline__ int mcol(const DevMix& s, int i) { return i >= s.Nup ? i - s.Nup : i; }
+__device__ __forceinline__ int mnspin(const DevMix& s, int sp) { return sp ? s.Ndn : s.Nup; }
+__device__ __forceinline__ int mee_row(const DevMix& s, int i, int k)
+{
+    return ((i >= s.Nup) == (k >= s.Nup)) ? 0 : 1;
+}
+
+// partner k of electron i: position (FP64) and Pade parameter row
+__device__ __forceinline__ void mpartner(const DevMix& s, const double* pos, int i, int k,
+                                         double* pk, int& jr)
+{
+    if (k < s.N) {
+        pk[0] = pos[3 * k]; pk[1] = pos[3 * k + 1]; pk[2] = pos[3 * k + 2];
+        jr = mee_row(s, i, k);
+    } else {
+        const int I = k - s.N;
+        pk[0] = s.R[3 * I]; pk[1] = s.R[3 * I + 1]; pk[2] = s.R[3 * I + 2];
+        jr = 2 + s.spec[I];
+    }
+}
+
+// nuclear potential of nucleus I at distance r: nu and its lattice bound nu^a
+__device__ __forceinline__ void nuc_pot(const DevMix& s, int I, double r, double a, double& nu,
+                                        double& nua)
+{
+    if (s.core[I] == 0) {
+        nu = -s.Z[I] / r;
+        nua = -s.Z[I] / (r > a ? r : a);
+    } else {
+        nu = nua = -s.Z[I] / sqrt(r * r + s.rc[I] * s.rc[I]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// orbital rows of electron j at r: 11 rows (value, 6 neighbours, gradient,
+// Laplacian) x n_j columns into LDS rows[11][ns]
+// ---------------------------------------------------------------------------
+__device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, const double* r, double a)
+{
+    const DevMix& s = *dm;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int Nb = s.Nb, items = 7 * Nb;
+    float* B = LDSF(s.l_U);                      // [11][nb32] basis rows (zero padded)
+    float* rows = LDSF(s.l_rows);
+    const int ldb = s.nb32;
+    for (int it = tid; it < items; it += kMixThreads) {
+        const int q = it / Nb, mu = it - q * Nb;
+        double p[3];
+        point_q(r, q, a, p);
+        const double* rec = s.btab + 4 * mu;
+        const float dx = (float)(p[0] - rec[0]), dy = (float)(p[1] - rec[1]),
+                    dz = (float)(p[2] - rec[2]);
+        const float d2 = dx * dx + dy * dy + dz * dz, al = (float)rec[3];
+        const int t = s.btype[mu];
+        if (q == 0) {
+            float v, g0, g1, g2, l;
+            if (t == 4) {
+                const float dd = sqrtf(d2), e = expf(-al * dd), id = 1.0f / dd;
+                v = e; g0 = -al * dx * id * e; g1 = -al * dy * id * e; g2 = -al * dz * id * e;
+                l = (al * al - 2.0f * al * id) * e;
+            } else if (t == 0) {
+                const float e = expf(-al * d2);
+                v = e; g0 = -2.0f * al * dx * e; g1 = -2.0f * al * dy * e; g2 = -2.0f * al * dz * e;
+                l = (4.0f * al * al * d2 - 6.0f * al) * e;
+            } else {
+                const float e = expf(-al * d2);
+                const float dq = t == 1 ? dx : (t == 2 ? dy : dz);
+                v = dq * e;
+                g0 = (t == 1 ? e : 0.0f) - 2.0f * al * dq * dx * e;
+                g1 = (t == 2 ? e : 0.0f) - 2.0f * al * dq * dy * e;
+                g2 = (t == 3 ? e : 0.0f) - 2.0f * al * dq * dz * e;
+                l = dq * e * (4.0f * al * al * d2 - 10.0f * al);
+            }
+            B[mu] = v;
+            B[7 * ldb + mu] = g0; B[8 * ldb + mu] = g1; B[9 * ldb + mu] = g2;
+            B[10 * ldb + mu] = l;
+        } else {
+            float v;
+            if (t == 4) v = expf(-al * sqrtf(d2));
+            else {
+                const float e = expf(-al * d2);
+                v = t == 0 ? e : (t == 1 ? dx : (t == 2 ? dy : dz)) * e;
+            }
+            B[q * ldb + mu] = v;
+        }
+    }
+    __syncthreads();
+    const int n = mnspin(s, mspin(s, j));
+    const int tiles = (n + 15) / 16;
+    const int i16 = lane & 15, k4 = lane >> 4;
+    for (int t = wv; t < tiles; t += kMixThreads / kWave) {
+        float4_t acc = {0.f, 0.f, 0.f, 0.f};
+        const int col = 16 * t + i16;
+        if (s.gemm == kGemmBF16) {
+            // 16x16x32 BF16 tiles: lane holds 8 consecutive inner indices
+            const bf16x8_t* cb = reinterpret_cast<const bf16x8_t*>(s.Cbf) +
+                                 (long)t * (s.nb32 / 32) * 64;
+            for (int kb = 0; kb < s.nb32 / 32; ++kb) {
+                bf16x8_t av;
+                const int k0 = 32 * kb + 8 * k4;
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    av[e] = (__bf16)(i16 < 11 ? B[i16 * ldb + k0 + e] : 0.0f);
+                const bf16x8_t bv = cb[(long)kb * 64 + lane];
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+            }
+        } else {
+            for (int k0 = 0; k0 < Nb; k0 += 4) {
+                const int mu = k0 + k4;
+                const float av = (i16 < 11 && mu < Nb) ? B[i16 * ldb + mu] : 0.0f;
+                const float bv = (col < n && mu < Nb) ? s.Cf[mu * s.ns + col] : 0.0f;
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+            }
+        }
+        // D[row][col]: row = 4 (lane >> 4) + v
+        for (int v = 0; v < 4; ++v) {
+            const int row = 4 * k4 + v;
+            if (row < 11 && col < n) rows[row * s.ns + col] = acc[v];
+        }
+    }
+    __syncthreads();
+}
+
+// store electron j's rows into the walker block (global, FP32)
+__device__ __noinline__ void mixed_store_rows(const DevMix* __restrict__ dm, float* st, int j, bool arow)
+{
+    const DevMix& s = *dm;
+    const int tid = threadIdx.x;
+    const int sp = mspin(s, j), c = mcol(s, j), n = mnspin(s, sp), ns = s.ns;
+    const float* rows = LDSF(s.l_rows);
+    float* Phi = st + s.g_Phi + (long)sp * ns * 6 * ns;
+    float* dPhi = st + s.g_dPhi + (long)sp * ns * 4 * ns;
+    for (int idx = tid; idx < 11 * n; idx += kMixThreads) {
+        const int row = idx / n, k = idx - row * n;
+        const float v = rows[row * ns + k];
+        if (row == 0) { if (arow) st[s.g_Arow + (long)j * ns + k] = v; }
+        else if (row <= 6) Phi[(long)k * 6 * ns + 6 * c + row - 1] = v;
+        else dPhi[(long)k * 4 * ns + 4 * c + row - 7] = v;
+    }
+    __threadfence_block();
+    __syncthreads();
+}
+
+// FP64 Gauss-Jordan (in place, partial pivoting) of the transposed Slater
+// matrix of spin sp; writes AinvT (FP32) and log|det|, sign.
+__device__ __noinline__ bool mixed_refresh_inverse(const DevMix* __restrict__ dm, float* st, int sp)
+{
+    const DevMix& s = *dm;
+    const int tid = threadIdx.x;
+    const int n = mnspin(s, sp);
+    if (!n) return true;
+    const int off = sp ? s.Nup : 0, ns = s.ns;
+    double* M = LDSD(s.l_U);                     // [n][n]
+    double* sc = LDSD(s.l_scal);
+    int* piv = reinterpret_cast<int*>(LDSF(s.l_tmp));
+    for (int idx = tid; idx < n * n; idx += kMixThreads) {
+        const int r = idx / n, c = idx - r * n;
+        M[idx] = (double)st[s.g_Arow + (long)(off + c) * ns + r];
+    }
+    __syncthreads();
+    double logdet = 0.0, sign = 1.0;
+    bool ok = true;
+    for (int k = 0; k < n; ++k) {
+        double best = -1.0;
+        int bi = k;
+        for (int r = k; r < n; ++r) {
+            const double v = fabs(M[r * n + k]);
+            if (v > best) { best = v; bi = r; }
+        }
+        if (!(best > 0.0)) { ok = false; break; }
+        if (tid == 0) piv[k] = bi;
+        if (bi != k) {
+            for (int c = tid; c < n; c += kMixThreads) {
+                const double t = M[k * n + c];
+                M[k * n + c] = M[bi * n + c];
+                M[bi * n + c] = t;
+            }
+            sign = -sign;
+            __syncthreads();
+        }
+        const double d = M[k * n + k];
+        logdet += log(fabs(d));
+        if (d < 0) sign = -sign;
+        const double id = 1.0 / d;
+        __syncthreads();
+        // row k scaled; column k of the other rows stored before elimination
+        double* colk = LDSD(s.l_U) + n * n;          // [n]
+        for (int r = tid; r < n; r += kMixThreads) colk[r] = M[r * n + k];
+        __syncthreads();
+        for (int c = tid; c < n; c += kMixThreads) M[k * n + c] = (c == k ? 1.0 : M[k * n + c]) * id;
+        __syncthreads();
+        for (int idx = tid; idx < n * n; idx += kMixThreads) {
+            const int r = idx / n, c = idx - r * n;
+            if (r == k) continue;
+            const double f = colk[r];
+            M[idx] = (c == k ? 0.0 : M[idx]) - f * M[k * n + c];
+        }
+        __syncthreads();
+    }
+    if (ok) {
+        // undo the row interchanges as column interchanges, in reverse order
+        for (int k = n - 1; k >= 0; --k) {
+            const int p = piv[k];
+            if (p != k)
+                for (int r = tid; r < n; r += kMixThreads) {
+                    const double t = M[r * n + k];
+                    M[r * n + k] = M[r * n + p];
+                    M[r * n + p] = t;
+                }
+            __syncthreads();
+        }
+        float* Ai = st + s.g_AinvT + (long)sp * ns * ns;
+        for (int idx = tid; idx < n * n; idx += kMixThreads) {
+            const int c = idx / n, k = idx - c * n;
+            Ai[(long)c * ns + k] = (float)M[idx];
+        }
+        if (tid == 0) { sc[kScLogdet0 + sp] = logdet; sc[kScSign0 + sp] = sign; }
+    }
+    __threadfence_block();
+    __syncthreads();
+    return ok;
+}
+
+// determinant gradients / Laplacians of the electrons of spin sp (sp < 0:
+// both spins): gD[j][q] = dPhi_j[q] . AinvT[c_j]
+__device__ __noinline__ void mixed_gD(const DevMix* __restrict__ dm, const float* st, int sp)
+{
+    const DevMix& s = *dm;
+    const int tid = threadIdx.x, ns = s.ns;
+    float* gD = LDSF(s.l_gD);
+    for (int spin = 0; spin < 2; ++spin) {
+        if (sp >= 0 && spin != sp) continue;
+        const int n = mnspin(s, spin), off = spin ? s.Nup : 0;
+        const float* dPhi = st + s.g_dPhi + (long)spin * ns * 4 * ns;
+        const float* Ai = st + s.g_AinvT + (long)spin * ns * ns;
+        for (int it = tid; it < 4 * n; it += kMixThreads) {
+            const int c = it >> 2;
+            float acc = 0.f;
+            for (int k = 0; k < n; ++k) acc += dPhi[(long)k * 4 * ns + it] * Ai[(long)c * ns + k];
+            gD[4 * (off + c) + (it & 3)] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+// ratios of the moves of spin sp (sp < 0: both); R = Rdet * exp(dJ) for all
+__device__ __noinline__ void mixed_ratios(const DevMix* __restrict__ dm, const float* st, int sp)
+{
+    const DevMix& s = *dm;
+    const int tid = threadIdx.x, ns = s.ns;
+    float* R = LDSF(s.l_R);
+    float* Rdet = LDSF(s.l_Rdet);
+    const float* dJ = LDSF(s.l_dJ);
+    for (int spin = 0; spin < 2; ++spin) {
+        if (sp >= 0 && spin != sp) continue;
+        const int n = mnspin(s, spin), off = spin ? s.Nup : 0;
+        const float* Phi = st + s.g_Phi + (long)spin * ns * 6 * ns;
+        const float* Ai = st + s.g_AinvT + (long)spin * ns * ns;
+        for (int q = tid; q < 6 * n; q += kMixThreads) {
+            const int c = q / 6;
+            float acc = 0.f;
+            for (int k = 0; k < n; ++k) acc += Phi[(long)k * 6 * ns + q] * Ai[(long)c * ns + k];
+            Rdet[6 * off + q] = acc;
+        }
+    }
+    __syncthreads();
+    for (int p = tid; p < s.P; p += kMixThreads) R[p] = Rdet[p] * expf(dJ[p]);
+    __syncthreads();
+}
+
+// Jastrow caches and potentials of every electron from scratch; returns V_ee
+__device__ __noinline__ double mixed_jastrow_all(const DevMix* __restrict__ dm, double a)
+{
+    const DevMix& s = *dm;
+    const int tid = threadIdx.x;
+    const double* pos = LDSD(s.l_pos);
+    float* dJ = LDSF(s.l_dJ);
+    float* Jg = LDSF(s.l_Jg);
+    float* Jl = LDSF(s.l_Jl);
+    double* nue = LDSD(s.l_nue);
+    double* nua = LDSD(s.l_nua);
+    float* S = LDSF(s.l_U);                       // [N][7]
+    const int K = s.N + s.M, Kj = s.has_en ? K : s.N;
+    for (int it = tid; it < 7 * s.N; it += kMixThreads) {
+        const int j = it / 7, q = it - 7 * j;
+        double pq[3];
+        point_q(pos + 3 * j, q, a, pq);
+        float acc = 0.f;
+        #pragma unroll 1
+        for (int k = 0; k < Kj; ++k) {
+            if (k == j) continue;
+            double pk[3];
+            int jr;
+            mpartner(s, pos, j, k, pk, jr);
+            acc += pade_uf(s.jas + 3 * jr, (float)norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+        }
+        S[it] = acc;
+    }
+    double vee = 0.0;
+    for (int j = tid; j < s.N; j += kMixThreads) {
+        const double* rj = pos + 3 * j;
+        float g0 = 0.f, g1 = 0.f, g2 = 0.f, l = 0.f;
+        double nu = 0.0, nv = 0.0;
+        #pragma unroll 1
+        for (int k = 0; k < K; ++k) {
+            if (k == j) continue;
+            const bool isel = k < s.N;
+            double pk[3];
+            int jr;
+            mpartner(s, pos, j, k, pk, jr);
+            const double d0 = rj[0] - pk[0], d1 = rj[1] - pk[1], d2 = rj[2] - pk[2];
+            const double r = norm3(d0, d1, d2);
+            if (isel || s.has_en) {
+                float u, dur, lp;
+                pade_derivs_f(s.jas + 3 * jr, (float)r, u, dur, lp);
+                g0 += dur * (float)d0; g1 += dur * (float)d1; g2 += dur * (float)d2;
+                l += lp;
+                if (isel && k > j) vee += 1.0 / r;
+            }
+            if (!isel) {
+                double a1, a2;
+                nuc_pot(s, k - s.N, r, a, a1, a2);
+                nu += a1; nv += a2;
+            }
+        }
+        Jg[3 * j] = g0; Jg[3 * j + 1] = g1; Jg[3 * j + 2] = g2; Jl[j] = l;
+        nue[j] = nu; nua[j] = nv;
+    }
+    vee = block_sum(vee, LDSD(s.l_red));
+    for (int p = tid; p < s.P; p += kMixThreads) {
+        const int j = p / 6, q = p - 6 * j;
+        dJ[p] = S[7 * j + q + 1] - S[7 * j];
+    }
+    __syncthreads();
+    return vee;
+}
+
+__device__ __noinline__ bool mixed_refresh(const DevMix* __restrict__ dm, float* st, double a)
+{
+    const DevMix& s = *dm;
+    bool ok = mixed_refresh_inverse(&s, st, 0);
+    ok = mixed_refresh_inverse(&s, st, 1) && ok;
+    const double vee = mixed_jastrow_all(&s, a);
+    if (threadIdx.x == 0) LDSD(s.l_scal)[kScVee] = vee;
+    mixed_gD(&s, st, -1);
+    mixed_ratios(&s, st, -1);
+    return ok;
+}
+
+struct MLocal { double bbar, W, eL; };
+
+// lattice-regularized diagonal and local energy (App. D), e_L formed as the
+// continuum local energy plus sum_i (nu_opt,i - nu_zv,i)
+__device__ __noinline__ MLocal mixed_evaluate(const DevMix* __restrict__ dm, double a, int nu_mode)
+{
+    const DevMix& s = *dm;
+    const int tid = threadIdx.x;
+    const float* R = LDSF(s.l_R);
+    const float* gD = LDSF(s.l_gD);
+    const float* Jg = LDSF(s.l_Jg);
+    const float* Jl = LDSF(s.l_Jl);
+    const double* nue = LDSD(s.l_nue);
+    const double* nua = LDSD(s.l_nua);
+    double* red = LDSD(s.l_red);
+    double bs = 0.0;
+    int anyneg = 0;
+    for (int p = tid; p < s.P; p += kMixThreads) {
+        const double r = (double)R[p];
+        if (r > 0) bs += r;
+        else if (r < 0) anyneg = 1;
+    }
+    const bool anynode = block_sum(anyneg ? 1.0 : 0.0, red) > 0.0;
+    bs = block_sum(bs, red);
+    double econt = 0.0, dnu = 0.0;
+    const double ia2 = 1.0 / (a * a);
+    for (int j = tid; j < s.N; j += kMixThreads) {
+        const double j0 = Jg[3 * j], j1 = Jg[3 * j + 1], j2 = Jg[3 * j + 2];
+        const double lap = (double)gD[4 * j + 3] +
+                           2.0 * ((double)gD[4 * j] * j0 + (double)gD[4 * j + 1] * j1 +
+                                  (double)gD[4 * j + 2] * j2) +
+                           (double)Jl[j] + j0 * j0 + j1 * j1 + j2 * j2;
+        double lapA = 0.0;
+        int nd = 0;
+        for (int q = 0; q < 6; ++q) {
+            const double r = (double)R[6 * j + q];
+            lapA += (r - 1.0) * ia2;
+            if (r < 0) nd = 1;
+        }
+        if (nu_mode == 1) nd = anynode;
+        if (nu_mode == 2) nd = 1;
+        const double nuzv = nue[j] + 0.5 * (lapA - lap);
+        const double numax = nuzv > nua[j] ? nuzv : nua[j];
+        const double nuopt = nd ? numax : nuzv;
+        econt += -0.5 * lap + nue[j];
+        dnu += nuopt - nuzv;
+    }
+    econt = block_sum(econt, red);
+    dnu = block_sum(dnu, red);
+    MLocal L;
+    L.bbar = bs / (2.0 * a * a);
+    L.eL = econt + LDSD(s.l_scal)[kScVee] + s.vii + dnu;
+    L.W = L.eL + L.bbar;
+    return L;
+}
+
+// heat-bath choice over the block: first p with cumulative positive ratio > xi * total
+__device__ __noinline__ int mixed_heat_bath(const DevMix* __restrict__ dm, double xi)
+{
+    const DevMix& s = *dm;
+    const int tid = threadIdx.x;
+    const float* R = LDSF(s.l_R);
+    double* red = LDSD(s.l_red);
+    int* pick = reinterpret_cast<int*>(LDSD(s.l_red) + 4);
+    const int per = (s.P + kMixThreads - 1) / kMixThreads;
+    const int p0 = tid * per, p1 = min(p0 + per, s.P);
+    double loc = 0.0;
+    for (int p = p0; p < p1; ++p) {
+        const double r = (double)R[p];
+        if (r > 0) loc += r;
+    }
+    double tot;
+    double c = block_excl_scan(loc, red, tot);
+    if (!(tot > 0)) return -1;
+    const double t = xi * tot;
+    int found = s.P, lastpos = -1;
+    for (int p = p0; p < p1; ++p) {
+        const double r = (double)R[p];
+        if (r > 0) {
+            c += r;
+            lastpos = p;
+            if (found == s.P && c > t) found = p;
+        }
+    }
+    if (tid == 0) { pick[0] = s.P; pick[1] = -1; }
+    __syncthreads();
+    if (found < s.P) atomicMin(pick, found);
+    if (lastpos >= 0) atomicMax(pick + 1, lastpos);
+    __syncthreads();
+    const int res = pick[0] < s.P ? pick[0] : pick[1];
+    __syncthreads();
+    return res;
+}
+
+// apply move p: Sherman-Morrison on the moved spin's inverse (HBM), new rows of
+// the moved electron, determinant gradients of the moved spin, Jastrow caches,
+// ratios of the moved spin
+__device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, float* st, double a, int p)
+{
+    const DevMix& s = *dm;
+    const int tid = threadIdx.x, ns = s.ns;
+    const int i = p / 6, d = (p / 2) % 3, sg = p % 2;
+    const int sp = mspin(s, i), c = mcol(s, i), n = mnspin(s, sp);
+    double* pos = LDSD(s.l_pos);
+    float* Rdet = LDSF(s.l_Rdet);
+    const float Rd = Rdet[p];
+    const double rold[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+    double rnew[3] = {rold[0], rold[1], rold[2]};
+    rnew[d] = rnew[d] + (sg ? -a : a);
+
+    float* Ai = st + s.g_AinvT + (long)sp * ns * ns;
+    const float* Phi = st + s.g_Phi + (long)sp * ns * 6 * ns;
+    float* tmp = LDSF(s.l_tmp);
+    float* u = tmp;               // [ns] accepted orbital row
+    float* rowc = tmp + ns;       // [ns] column c of the inverse
+    float* beta = tmp + 2 * ns;   // [ns]
+    const int q = 6 * c + (p - 6 * i);
+    for (int k = tid; k < n; k += kMixThreads) {
+        u[k] = Phi[(long)k * 6 * ns + q];
+        rowc[k] = Ai[(long)c * ns + k];
+    }
+    __syncthreads();
+    for (int cc = tid; cc < n; cc += kMixThreads) {
+        float acc = 0.f;
+        for (int k = 0; k < n; ++k) acc += u[k] * Ai[(long)cc * ns + k];
+        beta[cc] = acc;
+    }
+    __syncthreads();
+    const float iR = 1.0f / Rd;
+    for (int idx = tid; idx < n * n; idx += kMixThreads) {
+        const int cc = idx / n, k = idx - cc * n;
+        if (cc == c) Ai[(long)cc * ns + k] = rowc[k] * iR;
+        else Ai[(long)cc * ns + k] -= rowc[k] * (beta[cc] * iR);
+    }
+    for (int k = tid; k < n; k += kMixThreads) st[s.g_Arow + (long)i * ns + k] = u[k];
+    if (tid == 0) {
+        double* sc = LDSD(s.l_scal);
+        sc[kScLogdet0 + sp] += log(fabs((double)Rd));
+        if (Rd < 0) sc[kScSign0 + sp] = -sc[kScSign0 + sp];
+    }
+    __threadfence_block();
+    __syncthreads();
+
+    mixed_rows(&s, i, rnew, a);
+    mixed_store_rows(&s, st, i, false);
+    mixed_gD(&s, st, sp);
+
+    // Jastrow caches of the moved electron (7 points) and of its partners
+    const int K = s.N + s.M, Kj = s.has_en ? K : s.N;
+    float* dJ = LDSF(s.l_dJ);
+    float* Jg = LDSF(s.l_Jg);
+    float* Jl = LDSF(s.l_Jl);
+    float* dje = LDSF(s.l_dje);
+    double* red = LDSD(s.l_red);
+    // the 7 points of the moved electron, one block sum each
+    double S0 = 0.0;
+    float* dJi = tmp + 3 * ns;                   // [6] new exponent changes of electron i
+#pragma unroll 1
+    for (int qq = 0; qq < 7; ++qq) {
+        double pq[3];
+        point_q(rnew, qq, a, pq);
+        double acc = 0.0;
+        #pragma unroll 1
+        for (int k = tid; k < Kj; k += kMixThreads) {
+            if (k == i) continue;
+            double pk[3];
+            int jr;
+            mpartner(s, pos, i, k, pk, jr);
+            acc += (double)pade_uf(s.jas + 3 * jr,
+                                   (float)norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+        }
+        acc = block_sum(acc, red);
+        if (qq == 0) S0 = acc;
+        else if (tid == 0) dJi[qq - 1] = (float)(acc - S0);
+    }
+    double g0 = 0, g1 = 0, g2 = 0, l = 0, dvee = 0, nu = 0, nua = 0;
+    #pragma unroll 1
+    for (int k = tid; k < K; k += kMixThreads) {
+        if (k == i) continue;
+        const bool isel = k < s.N;
+        double pk[3];
+        int jr;
+        mpartner(s, pos, i, k, pk, jr);
+        const double* prm = s.jas + 3 * jr;
+        const double n0 = rnew[0] - pk[0], n1 = rnew[1] - pk[1], n2 = rnew[2] - pk[2];
+        const double rn = norm3(n0, n1, n2);
+        if (isel || s.has_en) {
+            float un, dnr, lpn;
+            pade_derivs_f(prm, (float)rn, un, dnr, lpn);
+            g0 += dnr * n0; g1 += dnr * n1; g2 += dnr * n2;
+            l += lpn;
+            if (isel) {
+                const double o0 = rold[0] - pk[0], o1 = rold[1] - pk[1], o2 = rold[2] - pk[2];
+                const double ro = norm3(o0, o1, o2);
+                float uo, dor, lpo;
+                pade_derivs_f(prm, (float)ro, uo, dor, lpo);
+                dje[k] = un - uo;
+                Jg[3 * k] += (float)(-(dnr * n0) + dor * o0);
+                Jg[3 * k + 1] += (float)(-(dnr * n1) + dor * o1);
+                Jg[3 * k + 2] += (float)(-(dnr * n2) + dor * o2);
+                Jl[k] += lpn - lpo;
+                dvee += 1.0 / rn - 1.0 / ro;
+            }
+        }
+        if (!isel) {
+            double a1, a2;
+            nuc_pot(s, k - s.N, rn, a, a1, a2);
+            nu += a1; nua += a2;
+        }
+    }
+    g0 = block_sum(g0, red); g1 = block_sum(g1, red); g2 = block_sum(g2, red);
+    l = block_sum(l, red); dvee = block_sum(dvee, red);
+    nu = block_sum(nu, red); nua = block_sum(nua, red);
+    // Jastrow exponent changes of the other electrons' moves
+    for (int qp = tid; qp < s.P; qp += kMixThreads) {
+        const int j = qp / 6;
+        if (j == i) continue;
+        const int dd = (qp / 2) % 3, s2 = qp % 2;
+        const double* prm = s.jas + 3 * mee_row(s, i, j);
+        double r2[3] = {pos[3 * j], pos[3 * j + 1], pos[3 * j + 2]};
+        r2[dd] = r2[dd] + (s2 ? -a : a);
+        const float un = pade_uf(prm, (float)norm3(r2[0] - rnew[0], r2[1] - rnew[1], r2[2] - rnew[2]));
+        const float uo = pade_uf(prm, (float)norm3(r2[0] - rold[0], r2[1] - rold[1], r2[2] - rold[2]));
+        dJ[qp] += (un - uo) - dje[j];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int qq = 0; qq < 6; ++qq) dJ[6 * i + qq] = dJi[qq];
+        Jg[3 * i] = (float)g0; Jg[3 * i + 1] = (float)g1; Jg[3 * i + 2] = (float)g2;
+        Jl[i] = (float)l;
+        LDSD(s.l_nue)[i] = nu; LDSD(s.l_nua)[i] = nua;
+        LDSD(s.l_scal)[kScVee] += dvee;
+        pos[3 * i + d] = rnew[d];
+    }
+    __syncthreads();
+    mixed_ratios(&s, st, sp);
+    return fabsf(Rd) < 1e-6f;
+}
+
+// ---------------------------------------------------------------------------
+// the phase kernel: one 256-thread workgroup per walker.  build != 0 first
+// evaluates every electron's orbital rows from its position.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kMixThreads) void phase_mixed(const DevMix* __restrict__ sys,
+                                                           PhaseArgs pa, int build)
+{
+    const DevMix& s = *sys;
+    const int wid = blockIdx.x;
+    if (wid >= s.nw) return;
+    const int tid = threadIdx.x;
+    float* st = s.state + (long)wid * s.stride;
+    double* pos = LDSD(s.l_pos);
+    for (int q = tid; q < 3 * s.N; q += kMixThreads) pos[q] = s.pos[(long)wid * 3 * s.N + q];
+    {
+        float* B = LDSF(s.l_U);   // zero the padding of the basis rows once
+        for (int q = tid; q < 11 * s.nb32; q += kMixThreads) B[q] = 0.0f;
+    }
+    __syncthreads();
+    const double a = pa.a;
+    if (build) {
+        for (int j = 0; j < s.N; ++j) {
+            const double r[3] = {pos[3 * j], pos[3 * j + 1], pos[3 * j + 2]};
+            mixed_rows(&s, j, r, a);
+            mixed_store_rows(&s, st, j, true);
+        }
+    }
+    unsigned long long n_neg = 0, n_nomove = 0, n_refresh = 1, n_small = 0, n_sing = 0,
+                       n_capped = 0;
+    if (!mixed_refresh(&s, st, a)) n_sing++;
+    // the Gauss-Jordan scratch overlaps the basis rows: restore their padding
+    {
+        float* B = LDSF(s.l_U);
+        for (int q = tid; q < 11 * s.nb32; q += kMixThreads) B[q] = 0.0f;
+        __syncthreads();
+    }
+
+    double lw = s.lw[wid];
+    double tau_left = pa.tau;
+    int it = 0, since = 0;
+    MLocal L;
+    int32_t* tr = s.trace ? s.trace + (long)wid * s.trace_cap : nullptr;
+    for (;;) {
+        if (pa.scheme == 0 && it >= pa.nproj) break;
+        L = mixed_evaluate(&s, a, pa.nu_mode);
+        int q;
+        if (pa.scheme == 0) {
+            const double den = L.W - pa.E0;
+            if (!(den > 0)) { lw = -INFINITY; n_neg++; }
+            else if (!(L.bbar > 0)) { lw = -INFINITY; n_nomove++; }
+            else lw += log(L.bbar) - log(den);
+            const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)pa.j,
+                                             (uint64_t)it, kMove);
+            q = mixed_heat_bath(&s, xi);
+            if (tr && it < s.trace_cap && tid == 0) tr[it] = q;
+            ++it;
+        } else {
+            const double xt = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)pa.j,
+                                             (uint64_t)it, kPersist);
+            const double t = (L.bbar > 0) ? -log1p(-xt) / L.bbar : INFINITY;
+            if (!(L.bbar > 0)) n_nomove++;
+            const bool capped = it + 1 >= pa.conv_cap;
+            if (capped && t < tau_left) n_capped++;
+            const bool stop = !(t < tau_left) || capped;
+            const double tx = stop ? tau_left : t;
+            lw -= tx * L.eL;
+            tau_left = stop ? 0.0 : tau_left - tx;
+            ++it;
+            if (stop) {
+                if (tr && it - 1 < s.trace_cap && tid == 0) tr[it - 1] = -1;
+                break;
+            }
+            const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)pa.j,
+                                             (uint64_t)(it - 1), kMove);
+            q = mixed_heat_bath(&s, xi);
+            if (tr && it - 1 < s.trace_cap && tid == 0) tr[it - 1] = q;
+        }
+        if (q >= 0) {
+            const bool small = mixed_apply_move(&s, st, a, q);
+            ++since;
+            if (small) n_small++;
+            if (small || since >= pa.refresh_every) {
+                if (!mixed_refresh(&s, st, a)) n_sing++;
+                float* B = LDSF(s.l_U);
+                for (int z = tid; z < 11 * s.nb32; z += kMixThreads) B[z] = 0.0f;
+                __syncthreads();
+                n_refresh++;
+                since = 0;
+            }
+        }
+    }
+    if (pa.scheme == 0) L = mixed_evaluate(&s, a, pa.nu_mode);
+
+    for (int q = tid; q < 3 * s.N; q += kMixThreads) s.pos[(long)wid * 3 * s.N + q] = pos[q];
+    if (tid == 0) {
+        s.lw[wid] = lw;
+        s.eL[wid] = L.eL;
+        s.Wd[wid] = L.W;
+        s.iters[wid] = it;
+        unsigned long long* cn = pa.counters;
+        atomicAdd(cn + kCntIters, (unsigned long long)it);
+        if (n_neg) atomicAdd(cn + kCntNegW, n_neg);
+        if (n_nomove) atomicAdd(cn + kCntNoMove, n_nomove);
+        atomicAdd(cn + kCntRefresh, n_refresh);
+        if (n_small) atomicAdd(cn + kCntSmallR, n_small);
+        if (n_sing) atomicAdd(cn + kCntSingular, n_sing);
+        if (n_capped) atomicAdd(cn + kCntCapped, n_capped);
+        atomicMax(cn + kCntMaxIters, (unsigned long long)it);
+        atomicMin(cn + kCntMinIters, (unsigned long long)it);
+    }
+}
+
+// gather of whole mixed walker blocks after the comb (state double-buffered)
+__global__ void branch_gather_mixed(const DevMix* __restrict__ sys, const int32_t* sel,
+                                    const float* old_state, const double* pos_old,
+                                    const double* eL_old, const double* W_old)
+{
+    const DevMix& s = *sys;
+    const int al = blockIdx.x;
+    if (al >= s.nw) return;
+    const int b = sel[al];
+    const float4_t* src = reinterpret_cast<const float4_t*>(old_state + (long)b * s.stride);
+    float4_t* dst = reinterpret_cast<float4_t*>(s.state + (long)al * s.stride);
+    for (long q = threadIdx.x; q < s.stride / 4; q += blockDim.x) dst[q] = src[q];
+    for (int q = threadIdx.x; q < 3 * s.N; q += blockDim.x)
+        s.pos[(long)al * 3 * s.N + q] = pos_old[(long)b * 3 * s.N + q];
+    if (threadIdx.x == 0) {
+        s.lw[al] = 0.0;
+        s.eL[al] = eL_old[b];
+        s.Wd[al] = W_old[b];
+    }
+}
+
+}  // namespace lrdmc

@@ -295,6 +295,7 @@ __device__ double jastrow_all(const DevSys& s, const Walker& w, double a, int la
         double pq[3];
         point_q(rj, q, a, pq);
         double acc = 0.0;
+        #pragma unroll 1
         for (int k = 0; k < Kj; ++k) {
             if (k == j) continue;
             double pk[3];
@@ -308,6 +309,7 @@ __device__ double jastrow_all(const DevSys& s, const Walker& w, double a, int la
     for (int j = lane; j < s.N; j += kWave) {
         const double rj[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
         double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0, nu = 0.0, nua = 0.0;
+        #pragma unroll 1
         for (int k = 0; k < K; ++k) {
             if (k == j) continue;
             const bool isel = k < s.N;
@@ -329,7 +331,7 @@ __device__ double jastrow_all(const DevSys& s, const Walker& w, double a, int la
                     nu += -s.Z[I] / r;
                     nua += -s.Z[I] / (r > a ? r : a);
                 } else {
-                    const double t = -s.Z[I] * erf(r / s.rc[I]) / r;
+                    const double t = -s.Z[I] / sqrt(r * r + s.rc[I] * s.rc[I]);
                     nu += t; nua += t;
                 }
             }
@@ -507,6 +509,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
         double pq[3];
         point_q(rnew, q, a, pq);
         double acc = 0.0;
+        #pragma unroll 1
         for (int k = lane; k < Kj; k += kWave) {
             if (k == i) continue;
             double pk[3];
@@ -519,6 +522,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
         else if (lane == 0) lds[dJi + q - 1] = acc - S0;
     }
     double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0, dvee = 0.0, nu = 0.0, nua = 0.0;
+    #pragma unroll 1
     for (int k = lane; k < K; k += kWave) {
         if (k == i) continue;
         const bool isel = k < s.N;
@@ -552,7 +556,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
                 nu += -s.Z[I] / rn;
                 nua += -s.Z[I] / (rn > a ? rn : a);
             } else {
-                const double t = -s.Z[I] * erf(rn / s.rc[I]) / rn;
+                const double t = -s.Z[I] / sqrt(rn * rn + s.rc[I] * s.rc[I]);
                 nu += t; nua += t;
             }
         }
@@ -716,7 +720,7 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
 // FP64 inclusive prefix of exp(lw - max) in slot order, and the weighted
 // local-energy sums; then one thread per new walker runs the comb search
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kMaxBranchBlock) void branch_scan(DevSys s, int scheme, double E0,
+__global__ __launch_bounds__(kMaxBranchBlock) void branch_scan(BranchView s, int scheme, double E0,
                                                                double* cum, double* out)
 {
     __shared__ double sh[kMaxBranchBlock];
@@ -783,7 +787,7 @@ __global__ __launch_bounds__(kMaxBranchBlock) void branch_scan(DevSys s, int sch
     }
 }
 
-__global__ void branch_comb(DevSys s, uint64_t seed, int j, const double* cum, const double* out,
+__global__ void branch_comb(BranchView s, uint64_t seed, int j, const double* cum, const double* out,
                             int32_t* sel)
 {
     const int al = blockIdx.x * blockDim.x + threadIdx.x;
@@ -809,7 +813,7 @@ __global__ void branch_count(const int32_t* sel, int nw, int* n_distinct)
     if (al == 0 || sel[al] != sel[al - 1]) atomicAdd(n_distinct, 1);
 }
 
-__global__ void branch_gather(DevSys s, const int32_t* sel, const double* pos_old,
+__global__ void branch_gather(BranchView s, const int32_t* sel, const double* pos_old,
                               const double* eL_old, const double* W_old)
 {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;

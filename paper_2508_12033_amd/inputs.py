@@ -18,7 +18,7 @@ System layout (all arrays numpy, C-contiguous):
   atom_charge  [M]   f64   charge seen by electrons (Z for bare nuclei,
                            the valence charge Z_v for local-potential cores)
   atom_core    [M]   i32   0 = bare Coulomb nucleus, 1 = smooth local core
-                           -Z_v*erf(r/rc)/r
+                           -Z_v/sqrt(r^2 + rc^2)
   core_rc      [M]   f64   core radius of the smooth core (bohr)
   atom_species [M]   i32   species index for electron-nucleus Jastrow terms
   basis_atom   [Nb]  i32   centre of each basis function
@@ -147,7 +147,7 @@ def h2_system(n_walkers=256, a=0.2, seed=BASE_SEED + 0, system_id=0):
 def molecule_system(n_c, n_o, n_h, n_s, n_p, n_walkers, a, box, seed,
                     system_id=0, name="mol", en_jastrow=None, rc=0.5):
     """Atoms: n_c C-like cores (Z_v=4), n_o O-like cores (Z_v=6), both smooth
-    local cores -Z_v erf(r/rc)/r, plus n_h bare protons, placed uniformly in a
+    local cores -Z_v/sqrt(r^2 + rc^2), plus n_h bare protons, placed uniformly in a
     cube with 1.8 bohr minimum separation.  Neutral, equal up/down counts."""
     rng = np.random.default_rng(seed)
     m = n_c + n_o + n_h

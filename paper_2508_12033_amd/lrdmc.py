@@ -16,6 +16,9 @@ LIB_PATH = os.path.join(HERE, "liblrdmc.so")
 
 SCHEME_LB, SCHEME_CONV = 0, 1
 FP64 = 0
+MIXED_FP32 = 1
+MIXED_BF16 = 2
+PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16": MIXED_BF16}
 NU_OPT_OWN, NU_OPT_ANY, NU_MAX = 0, 1, 2
 
 ERRORS = {-1: "INVALID_ARG", -2: "HIP", -3: "WORKSPACE", -4: "SINGULAR", -5: "ALL_DEAD",
@@ -129,8 +132,12 @@ def _sys_struct(d, keep):
 
 
 def make_params(scheme="lb", a=0.2, tau=0.25, n_proj=300, seed=12033, refresh_every=16,
-                nu_opt_mode=NU_OPT_OWN, p_corr=10, e0_window=50, trace_cap=0):
-    return lrdmc_params(SCHEME_LB if scheme == "lb" else SCHEME_CONV, FP64, float(a), float(tau),
+                nu_opt_mode=NU_OPT_OWN, p_corr=10, e0_window=50, trace_cap=0, precision="fp64"):
+    """precision: "fp64" (every step in FP64), "fp32" or "bf16" (mixed: the
+    orbital product on FP32 or BF16 MFMA, FP32 rank-one updates, FP64
+    accumulation and refreshes)."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return lrdmc_params(SCHEME_LB if scheme == "lb" else SCHEME_CONV, prec, float(a), float(tau),
                         int(n_proj), int(seed), int(refresh_every), int(nu_opt_mode), int(p_corr),
                         int(e0_window), int(trace_cap))
 

@@ -39,17 +39,18 @@ def make_handle(d, scheme, nw, **kw):
     return B.Handle(d2, prm), d2, prm
 
 
-def oracle_params(S, prm):
+def oracle_params(S, prm, band=1e-12):
     return S.params(a=prm.a, tau=prm.tau, nproj=prm.n_proj, nu_opt_mode=prm.nu_opt_mode,
-                    seed=prm.seed)
+                    seed=prm.seed, band=band)
 
 
-def compare_phase(d, prm, scheme, j, E0, pos0, lw0, g, idx, nthreads=8):
+def compare_phase(d, prm, scheme, j, E0, pos0, lw0, g, idx, nthreads=8, band=1e-12):
     """Run the oracle on walkers idx from (pos0, lw0) following the GPU trace
     and compare with the GPU result g (dict from Handle.walkers(trace=True)).
+    band: relative width inside which a differing decision is adopted.
     Returns a dict of the largest deviations and the counters."""
     S = O.System(d)
-    op = oracle_params(S, prm)
+    op = oracle_params(S, prm, band)
     idx = np.asarray(idx)
     pos = np.array(pos0[idx], np.float64, copy=True)
     lw = np.array(lw0[idx], np.float64, copy=True)
@@ -65,6 +66,8 @@ def compare_phase(d, prm, scheme, j, E0, pos0, lw0, g, idx, nthreads=8):
     dl = np.abs(lw[fin] - g["lw"][idx][fin]) / np.maximum(1.0, np.abs(lw[fin]))
     res["lw_err"] = float(dl.max()) if dl.size else 0.0
     res["eL_err"] = float(np.max(np.abs(eL - g["eL"][idx])))
+    res["eL_rel"] = float(np.max(np.abs(eL - g["eL"][idx]) / np.abs(eL)))
+    res["eL_rel_median"] = float(np.median(np.abs(eL - g["eL"][idx]) / np.abs(eL)))
     res["W_err"] = float(np.max(np.abs(W - g["W"][idx]) / np.abs(W)))
     res["oracle"] = dict(pos=pos, lw=lw, eL=eL, W=W, iters=iters)
     return res

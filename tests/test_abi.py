@@ -54,3 +54,22 @@ def test_layout_rejects_oversized_system():
     prm = B.params_for(d)
     assert L.lrdmc_workspace_bytes(ct.byref(s), 1, ct.byref(prm)) == 0
     assert b"too large" in L.lrdmc_last_error()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_layout_accepts_large_system(prec):
+    """The 128-electron, 640-function system fits the mixed-precision layout:
+    per walker 6N x n_s + 4N x n_s orbital floats, the Slater rows and both
+    inverses in HBM (about 393 KB), double-buffered for the reconfiguration."""
+    L = B.load()
+    d = I.c3_system(n_walkers=2)
+    keep = []
+    s = B._sys_struct(d, keep)
+    prm = B.params_for(d, precision=prec)
+    nb = L.lrdmc_workspace_bytes(ct.byref(s), 1, ct.byref(prm))
+    per_walker = 4 * (2 * 64 * 6 * 64 + 2 * 64 * 4 * 64 + 128 * 64 + 2 * 64 * 64)
+    assert nb >= 2 * 2 * per_walker
+    assert nb < 2 * 2 * per_walker + (4 << 20)
+    bad = B.params_for(d, precision=7)
+    assert L.lrdmc_workspace_bytes(ct.byref(s), 1, ct.byref(bad)) == 0
+    assert b"precision" in L.lrdmc_last_error()

@@ -1,0 +1,149 @@
+"""Mixed-precision projection phase (orbital product on FP32 or BF16 MFMA with
+FP32 accumulation; FP32 ratios, Jastrow sums and rank-one inverse updates;
+FP64 positions, potentials, weights, the sums that form W, bbar and e_L, and
+the periodic Gauss-Jordan refresh) against the FP64 oracle following the
+GPU's moves on identical seeded inputs.
+
+The oracle evaluates the exact wavefunction in FP64, so the comparison states
+the error of each result of the mixed path:
+  - move choices and conventional stopping decisions: identical, except
+    decisions whose draw falls inside the relative band that the FP32/BF16
+    ratio error can move a cumulative boundary by (adopted and counted);
+    positions therefore bit-exact;
+  - e_L and W per walker: relative error;
+  - log-weights: absolute error, which grows with the number of steps.
+Bounds (FP32): e_L and W within 1e-5 relative; log-weight within 2e-6 per
+step.  BF16 rounds every basis value and coefficient to 8 significant bits,
+so the orbitals, and with them the ratios and e_L, carry errors of order
+2^-8 relative; its bounds are stated with the test."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2508_12033_amd import inputs as I
+from parity_util import compare_phase, make_handle, say
+
+pytestmark = pytest.mark.gpu
+
+FP32_EL_REL = 1e-5
+FP32_W_REL = 1e-5
+FP32_LW_PER_STEP = 2e-6
+FP32_BAND = 1e-4
+BF16_BAND = 3e-2
+
+
+def _check(res, prec, nproj):
+    c = res["cnt"]
+    say(prec, {k: v for k, v in res.items() if k != "oracle"})
+    assert c["singular"] == 0, res
+    assert c["hard_mismatch"] == 0, res
+    assert res["pos_equal"], res
+    assert res["iters_equal"], res
+    assert res["lw_dead_equal"], res
+    if prec == "fp32":
+        assert res["eL_rel"] < FP32_EL_REL, res
+        assert res["W_err"] < FP32_W_REL, res
+        assert res["lw_err"] < FP32_LW_PER_STEP * nproj, res
+
+
+def _run(d, scheme, nw, prec, band, **kw):
+    h, d2, prm = make_handle(d, scheme, nw, precision=prec, **kw)
+    e0 = h.e0()
+    pos0 = d2["init_pos"][:nw].copy()
+    st = h.step()
+    g = h.walkers(trace=True)
+    res = compare_phase(d2, prm, scheme, 0, e0, pos0, np.zeros(nw), g, np.arange(nw), band=band)
+    h.close()
+    return res, st
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_c1_lb(prec):
+    d = I.c1_system(n_walkers=64)
+    say("case mixed c1 lb", prec, "64 walkers x 60 steps")
+    res, st = _run(d, "lb", 64, prec, FP32_BAND if prec == "fp32" else BF16_BAND, n_proj=60)
+    _check(res, prec, 60)
+    assert st.n_refresh >= 64 * (60 // 16)
+
+
+def test_mixed_c1_conv():
+    d = I.c1_system(n_walkers=40)
+    say("case mixed c1 conv fp32 40 walkers")
+    res, st = _run(d, "conv", 40, "fp32", FP32_BAND, tau=0.05)
+    _check(res, "fp32", int(res["oracle"]["iters"].max()))
+
+
+@pytest.mark.parametrize("nu_mode", [0, 1])
+def test_mixed_en_jastrow_nu_modes(nu_mode):
+    d = I.c4_system(n_walkers=32)
+    say("case mixed c4 nu_mode", nu_mode)
+    res, _ = _run(d, "lb", 32, "fp32", FP32_BAND, n_proj=40, nu_opt_mode=nu_mode)
+    _check(res, "fp32", 40)
+
+
+def test_mixed_exact_eigenstate():
+    """Hydrogen 1s trial: e_L = -1/2 at every step, to FP32 accuracy."""
+    d = I.hydrogenic_system(Z=1.0, zeta=1.0, n_walkers=32)
+    say("case mixed hydrogenic exact state")
+    h, d2, prm = make_handle(d, "lb", 32, precision="fp32", n_proj=50)
+    assert abs(h.e0() + 0.5) < 1e-5
+    h.step()
+    g = h.walkers()
+    assert np.all(np.abs(g["eL"] + 0.5) < 1e-5), g["eL"]
+    h.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_c3_sample(prec):
+    """128 electrons, 640 basis functions, 64 orbitals per spin: four MFMA
+    column tiles, several refreshes per phase."""
+    d = I.c3_system(n_walkers=16)
+    say("case mixed c3", prec, "16 walkers x 40 steps")
+    res, st = _run(d, "lb", 16, prec, FP32_BAND if prec == "fp32" else BF16_BAND, n_proj=40)
+    _check(res, prec, 40)
+
+
+def test_mixed_branching_gathers_state():
+    """Three phases with reconfiguration between them: the gathered walker
+    blocks (orbital data and inverses in HBM) must continue the trajectories
+    of the selected parents exactly as the oracle does from their positions."""
+    d = I.c1_system(n_walkers=64)
+    say("case mixed c1 branching")
+    nw, nproj = 64, 30
+    h, d2, prm = make_handle(d, "lb", nw, precision="fp32", n_proj=nproj, p_corr=1)
+    pos = d2["init_pos"][:nw].copy()
+    lw = np.zeros(nw)
+    e0 = h.e0()
+    for j in range(3):
+        h.step()
+        g = h.walkers(trace=True)
+        res = compare_phase(d2, prm, "lb", j, e0, pos, lw, g, np.arange(nw), band=FP32_BAND)
+        _check(res, "fp32", nproj)
+        bs = h.branch()
+        gsel = h.walkers()["sel"]
+        xi = O.uniform(prm.seed, 0, 0, j, 0, O.RNG_COMB)
+        sel, _, cnt = O.comb(g["lw"], xi, follow=gsel)
+        assert cnt["hard_mismatch"] == 0
+        assert np.array_equal(sel, gsel)
+        pos = res["oracle"]["pos"][sel].copy()
+        lw = np.zeros(nw)
+        e0 = bs.e0
+        assert np.array_equal(h.walkers()["pos"], pos)
+
+
+def test_mixed_set_walkers_rebuilds():
+    """New positions from the host: the orbital data of every walker are
+    rebuilt from them before the next phase."""
+    d = I.c1_system(n_walkers=32)
+    say("case mixed set_walkers")
+    nw = 32
+    h, d2, prm = make_handle(d, "lb", nw, precision="fp32", n_proj=20)
+    e0 = h.e0()
+    pos = d2["init_pos"][:nw][::-1].copy()
+    h.set_walkers(pos)
+    h.step()
+    g = h.walkers(trace=True)
+    res = compare_phase(d2, prm, "lb", 0, e0, pos, np.zeros(nw), g, np.arange(nw),
+                        band=FP32_BAND)
+    _check(res, "fp32", 20)
+    h.close()
