@@ -278,3 +278,90 @@ def run(sysd, scheme, n_branch, nproj=None, tau=None, nthreads=None, nu_opt_mode
     E, sig, m = energy_estimate(hist_lwb, hist_e, p=p, block=block)
     return dict(E=E, sigma=sig, n_used=m, log_wbar=np.array(hist_lwb), e_bar=np.array(hist_e),
                 E0=np.array(hist_E0), iters=np.array(iters_all), pos=pos)
+
+
+# ---------------------------------------------------------------------------
+# Parameter derivatives of the per-walker local energy and log|Psi_G|
+# ---------------------------------------------------------------------------
+# theta = (nuclear coordinates [M][3], then the Jastrow table [2 + n_species][3]
+# row-major: (A, B, b) of the parallel e-e, antiparallel e-e and each species'
+# e-n Pade function).  The basis functions move with their nucleus.  The
+# derivative is the plain definition, a fourth-order central difference of the
+# FP64 e_L (the lattice-regularized local energy W - bbar, App. D) and of
+# log|Psi_G| at a fixed configuration.  e_L is smooth only piecewise (node
+# indicators, the max in nu_opt, the sign of each R_p, and max(r, a) of bare
+# cores); a difference is reported as valid only when that branch pattern is
+# the same at every stencil point.
+
+def theta_of(d):
+    return np.concatenate([np.asarray(d["atom_pos"], np.float64).ravel(),
+                           np.asarray(d["jastrow"], np.float64).ravel()])
+
+
+def with_theta(d, theta):
+    """Copy of the system dict with its nuclear coordinates and Jastrow table
+    replaced by theta."""
+    M = np.asarray(d["atom_pos"]).shape[0]
+    d2 = dict(d)
+    d2["atom_pos"] = np.array(theta[:3 * M], np.float64).reshape(M, 3)
+    d2["jastrow"] = np.array(theta[3 * M:], np.float64).reshape(np.asarray(d["jastrow"]).shape)
+    return d2
+
+
+def _branch_pattern(sys, d, out, a):
+    """Discrete choices that select the smooth piece of e_L at a configuration."""
+    sgn = np.sign(out["R"]).astype(np.int8)
+    capped = out["nu_opt"] != out["nu_zv"]
+    return np.concatenate([sgn, out["node"].astype(np.int8), capped.astype(np.int8)])
+
+
+def _bare_inside(d, pos, a):
+    """Electron-nucleus pairs of bare cores closer than a (the max(r, a) branch)."""
+    R = np.asarray(d["atom_pos"]); bare = np.asarray(d["atom_core"]) == 0
+    r = np.linalg.norm(pos.reshape(-1, 1, 3) - R[None], axis=2)
+    return (r < a) & bare[None]
+
+
+def local_values(d, pos, a=None, nu_opt_mode=None):
+    """(e_L, log|Psi_G|, branch pattern) of one configuration."""
+    S = System(d)
+    prm = S.params(a=a, nu_opt_mode=nu_opt_mode)
+    out = evaluate(S, prm, pos)
+    pat = np.concatenate([_branch_pattern(S, d, out, prm.a),
+                          _bare_inside(d, np.asarray(pos), prm.a).ravel().astype(np.int8)])
+    return out["eL"], out["logabs"], pat
+
+
+def gradient_fd(d, pos, h=1e-3, a=None, nu_opt_mode=None, which=None):
+    """d e_L / d theta and d log|Psi_G| / d theta at configuration pos by the
+    fourth-order central difference with step h.  which: indices of theta to
+    differentiate (default all).  Returns (deL, dlogpsi, valid) where valid[k]
+    is False when the branch pattern changes inside component k's stencil."""
+    th0 = theta_of(d)
+    idx = np.arange(th0.size) if which is None else np.asarray(which)
+    _, _, pat0 = local_values(d, pos, a, nu_opt_mode)
+    deL = np.zeros(idx.size); dlp = np.zeros(idx.size); ok = np.ones(idx.size, bool)
+    for n, k in enumerate(idx):
+        vals = []
+        for s in (2, 1, -1, -2):
+            th = th0.copy()
+            th[k] += s * h
+            e, lp, pat = local_values(with_theta(d, th), pos, a, nu_opt_mode)
+            ok[n] &= bool(np.array_equal(pat, pat0))
+            vals.append((e, lp))
+        (e2, l2), (e1, l1), (em1, lm1), (em2, lm2) = vals
+        deL[n] = (-e2 + 8.0 * e1 - 8.0 * em1 + em2) / (12.0 * h)
+        dlp[n] = (-l2 + 8.0 * l1 - 8.0 * lm1 + lm2) / (12.0 * h)
+    return deL, dlp, ok
+
+
+def force_estimator(eL, dEL, dLP, omega):
+    """Population estimators from per-walker derivatives (mixed-estimator form,
+    an approximation in DMC): F = -<de_L/dR>_w - 2 <(e_L - E) d log|Psi|/dR>_w
+    for the nuclear block, and the energy gradient 2 <(e_L - E) d log|Psi|/dp>_w
+    for every theta component.  Returns (E, gradE) with gradE over all theta;
+    the nuclear forces are -gradE[:3M] of the same expression."""
+    w = np.asarray(omega, np.float64) / np.sum(omega)
+    E = float(np.sum(w * eL))
+    grad = (w[:, None] * dEL).sum(0) + 2.0 * (w[:, None] * (eL - E)[:, None] * dLP).sum(0)
+    return E, grad
