@@ -332,26 +332,52 @@ def local_values(d, pos, a=None, nu_opt_mode=None):
     return out["eL"], out["logabs"], pat
 
 
-def gradient_fd(d, pos, h=1e-3, a=None, nu_opt_mode=None, which=None):
+def gradient_fd(d, pos, h=1e-3, a=None, nu_opt_mode=None, which=None, tol=1e-9, max_halvings=6):
     """d e_L / d theta and d log|Psi_G| / d theta at configuration pos by the
-    fourth-order central difference with step h.  which: indices of theta to
-    differentiate (default all).  Returns (deL, dlogpsi, valid) where valid[k]
-    is False when the branch pattern changes inside component k's stencil."""
+    fourth-order central difference.  The step starts at h (for the nuclear
+    coordinates also below 1/50 of the closest electron-nucleus distance: the
+    functions of |r_i - R_I| are not smooth at r = 0) and is halved until two
+    successive estimates agree to 15 tol max(1, |D|) (their difference is about
+    15 times the error of the finer one), at most max_halvings times: close to
+    a node of Psi_G the higher derivatives grow and a fixed step is not enough.
+    which: indices of theta to differentiate (default all).  Returns (deL,
+    dlogpsi, valid) where valid[k] is False when the branch pattern changes
+    inside the final stencil of component k or the estimates did not settle."""
     th0 = theta_of(d)
+    M = np.asarray(d["atom_pos"]).shape[0]
     idx = np.arange(th0.size) if which is None else np.asarray(which)
     _, _, pat0 = local_values(d, pos, a, nu_opt_mode)
-    deL = np.zeros(idx.size); dlp = np.zeros(idx.size); ok = np.ones(idx.size, bool)
-    for n, k in enumerate(idx):
-        vals = []
+    rmin = float(np.min(np.linalg.norm(np.asarray(pos).reshape(-1, 1, 3) -
+                                       np.asarray(d["atom_pos"])[None], axis=2)))
+
+    def diff(k, hk):
+        vals, same = [], True
         for s in (2, 1, -1, -2):
             th = th0.copy()
-            th[k] += s * h
+            th[k] += s * hk
             e, lp, pat = local_values(with_theta(d, th), pos, a, nu_opt_mode)
-            ok[n] &= bool(np.array_equal(pat, pat0))
+            same &= bool(np.array_equal(pat, pat0))
             vals.append((e, lp))
         (e2, l2), (e1, l1), (em1, lm1), (em2, lm2) = vals
-        deL[n] = (-e2 + 8.0 * e1 - 8.0 * em1 + em2) / (12.0 * h)
-        dlp[n] = (-l2 + 8.0 * l1 - 8.0 * lm1 + lm2) / (12.0 * h)
+        return ((-e2 + 8.0 * e1 - 8.0 * em1 + em2) / (12.0 * hk),
+                (-l2 + 8.0 * l1 - 8.0 * lm1 + lm2) / (12.0 * hk), same)
+
+    deL = np.zeros(idx.size); dlp = np.zeros(idx.size); ok = np.ones(idx.size, bool)
+    for n, k in enumerate(idx):
+        hk = min(h, rmin / 50.0) if k < 3 * M else h
+        pe, pl, psame = diff(k, hk)
+        settled = False
+        for _ in range(max_halvings):
+            hk *= 0.5
+            e, l, same = diff(k, hk)
+            close = (abs(e - pe) <= 15 * tol * max(1.0, abs(e)) and
+                     abs(l - pl) <= 15 * tol * max(1.0, abs(l)))
+            pe, pl, psame = e, l, same
+            if close:
+                settled = True
+                break
+        deL[n], dlp[n] = pe, pl
+        ok[n] = psame and settled
     return deL, dlp, ok
 
 
