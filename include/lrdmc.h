@@ -175,9 +175,33 @@ int lrdmc_step(struct lrdmc_handle *h, lrdmc_step_stats *st);
 int lrdmc_branch(struct lrdmc_handle *h, lrdmc_branch_stats *st);
 
 /* Energy estimate from the branching history (Sec. II.A correcting factors,
- * first 10 % of branchings dropped).  forces ([n_atoms][3]) and jgrad are
- * reserved for the adjoint and must be NULL in this build. */
+ * first 10 % of branchings dropped).  When forces ([n_atoms][3], host) or
+ * jgrad ([3 (2 + n_species)], host) is non-NULL, the adjoint pass
+ * (lrdmc_walker_derivs) runs over the current walkers of system 0 and the
+ * weighted population (omega = w/(W - E_0) load-balanced, w conventional)
+ * gives, for every parameter theta,
+ *   dE/dtheta = <de_L/dtheta> + 2 <(e_L - E) d log|Psi|/dtheta>
+ * (the mixed-estimator form; an approximation in DMC, the paper defines no
+ * force estimator).  forces = -dE/dR_I; jgrad = dE/d(Jastrow table).
+ * Synchronises. */
 int lrdmc_energy_forces(struct lrdmc_handle *h, lrdmc_energy *e, double *forces, double *jgrad);
+
+/* Number of parameters theta of system isys: 3 n_atoms nuclear coordinates,
+ * then the Jastrow table [2 + n_species][3] row-major. */
+int lrdmc_n_theta(struct lrdmc_handle *h, int isys);
+
+/* Adjoint pass: per walker of system isys, at its current configuration, the
+ * lattice-regularized local energy e_L (App. D, W - bbar) and log|Psi_G|, and
+ * their derivatives with respect to theta (basis functions move with their
+ * nucleus; the nu_opt and node choices are held at the evaluated branch).
+ * FP64, inverses recomputed by Gauss-Jordan.  theta: host [n_theta]
+ * replacing the system's parameters for this call only, or NULL.  Outputs are
+ * device pointers: eL, logpsi [n_walkers]; deL, dlogpsi [n_walkers][n_theta]
+ * (NULL: kept in the library's workspace).  Synchronises.  Systems whose
+ * per-walker adjoint data exceed one workgroup's LDS return
+ * LRDMC_ERR_UNSUPPORTED. */
+int lrdmc_walker_derivs(struct lrdmc_handle *h, int isys, const double *theta, double *eL,
+                        double *logpsi, double *deL, double *dlogpsi);
 
 /* Host copies of the walker state of system `isys` for the parity harness.
  * Any pointer may be NULL.  pos [nw][N][3], lw/eL/W [nw], iters [nw],
@@ -186,6 +210,14 @@ int lrdmc_energy_forces(struct lrdmc_handle *h, lrdmc_energy *e, double *forces,
  * -2 unused).  Synchronises. */
 int lrdmc_get_walkers(struct lrdmc_handle *h, int isys, double *pos, double *lw, double *eL,
                       double *W, int32_t *iters, int32_t *sel, int32_t *trace);
+
+/* Mixed precisions only: per walker of system isys, [nw][4] host doubles
+ * describing the last phase at its final configuration: e_L, W and bbar as
+ * the mixed-precision step computed them, and the largest ratio error
+ * max_p |R_p - R_p(FP64)| / max(1, |R_p(FP64)|).  The e_L and W that the
+ * library reports (lrdmc_get_walkers) and uses for the reconfiguration are
+ * the FP64 evaluation of the same configuration.  Synchronises. */
+int lrdmc_get_precision_report(struct lrdmc_handle *h, int isys, double *out);
 
 /* Overwrite positions (and log-weights if lw != NULL) of system `isys`. */
 int lrdmc_set_walkers(struct lrdmc_handle *h, int isys, const double *pos, const double *lw);

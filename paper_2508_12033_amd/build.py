@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("lrdmc_phase.hip", "lrdmc_mixed.hip", "lrdmc_host.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("lrdmc_phase.hip", "lrdmc_mixed.hip", "lrdmc_adjoint.hip", "lrdmc_host.hip")]
 LIB = os.path.join(HERE, "liblrdmc.so")
 ARCH = "gfx950"
 

@@ -70,8 +70,15 @@ struct DevMix {
     const double *R, *Z, *rc, *jas, *btab;
     const int32_t *core, *spec, *btype;
     const float *Cf;             // [Nb][ns] coefficients, FP32
-    const uint16_t *Cbf;         // [tiles][Nb/32][64 lanes][8] BF16 MFMA B operands
+    const uint16_t *Cbf;         // [2][tiles][Nb/32][64 lanes][8] BF16 MFMA B operands:
+                                 // high part, then the BF16 residual (low part)
     int nb32;                    // Nb rounded up to a multiple of 32
+    const double *C64;           // [Nb][Norb] coefficients, FP64 (estimator evaluation)
+    double *s64;                 // [nw][stride64] FP64 scratch: Slater rows, inverses
+    long stride64;
+    double *diag;                // [nw][4] error report of the last phase: e_L, W, bbar of
+                                 // the mixed-precision step at the final configuration,
+                                 // largest ratio error against the FP64 evaluation
     double *pos, *lw, *eL, *Wd;  // [nw][N][3], [nw]
     float *state;                // [nw][stride] walker blocks (current buffer)
     long stride;                 // floats per walker block
@@ -84,7 +91,26 @@ struct DevMix {
     int trace_cap;
     // LDS layout, byte offsets
     int l_pos, l_nue, l_nua, l_scal, l_red, l_U, l_R, l_Rdet, l_dJ, l_gD, l_Jg, l_Jl, l_dje,
-        l_rows, l_tmp, l_bytes;
+        l_rows, l_tmp, l_F, l_bytes;
+};
+constexpr int kMixChunk = 64;   // basis functions per chunk of the FP64 estimator evaluation
+
+// Adjoint pass (parameter derivatives of e_L and log|Psi| at fixed walkers):
+// one 256-thread workgroup per walker, FP64, everything in LDS.
+constexpr int kAdjThreads = 256;
+struct DevAdj {
+    int M, Nb, Norb, Nup, Ndn, N, ns, nspec, nw, nth, nu_mode;
+    double a, vii;
+    const double *R, *Z, *rc, *jas, *btab, *C;   // R, jas and btab centres follow theta
+    const int32_t *core, *spec, *batom, *btype;
+    const double *pos;                          // [nw][N][3]
+    double *eL, *lp;                            // [nw]
+    double *deL, *dlp;                          // [nw][nth]
+    int *status;                                // walkers with a singular Slater matrix
+    // LDS layout (offsets in doubles)
+    int o_pos, o_phi, o_dphi, o_phi6, o_ainv, o_Z, o_T, o_Y, o_G, o_chi, o_gj, o_Lj, o_dJ, o_R,
+        o_Rdet, o_gd, o_Ld, o_nu, o_nua, o_al, o_sgd, o_sgj, o_sRd, o_sdJ, o_snu, o_snua, o_GeL,
+        o_Glp, o_sc, o_piv, lds_doubles;
 };
 
 // What the reconfiguration kernels see of a system (either layout).

@@ -31,6 +31,10 @@ __global__ void branch_gather(BranchView s, const int32_t* sel, const double* po
 __global__ void branch_gather_mixed(const DevMix* __restrict__ sys, const int32_t* sel,
                                     const float* old_state, const double* pos_old,
                                     const double* eL_old, const double* W_old);
+__global__ void walker_derivs(const DevAdj* __restrict__ sys);
+__global__ void derivs_reduce(int nw, int nth, int scheme, const double* lw, const double* Wd,
+                              const double* e0p, const double* eL, const double* deL,
+                              const double* dlp, double* out);
 }  // namespace lrdmc
 
 using namespace lrdmc;
@@ -69,12 +73,17 @@ struct Layout {
     long spill_stride;
     // mixed kernel: LDS byte offsets, walker block (floats)
     int l_pos, l_nue, l_nua, l_scal, l_red, l_U, l_R, l_Rdet, l_dJ, l_gD, l_Jg, l_Jl, l_dje, l_rows,
-        l_tmp, l_bytes;
-    long g_Phi, g_dPhi, g_Arow, g_AinvT, m_stride;
+        l_tmp, l_F, l_bytes;
+    long g_Phi, g_dPhi, g_Arow, g_AinvT, m_stride, stride64;
     int nb32, tiles;
     size_t lds_bytes;
+    // adjoint pass: LDS offsets (doubles)
+    int nth;
+    int a_pos, a_phi, a_dphi, a_phi6, a_ainv, a_Z, a_T, a_Y, a_G, a_chi, a_gj, a_Lj, a_dJ, a_R,
+        a_Rdet, a_gd, a_Ld, a_nu, a_nua, a_al, a_sgd, a_sgj, a_sRd, a_sdJ, a_snu, a_snua, a_GeL,
+        a_Glp, a_sc, a_piv, a_doubles;
     // workspace bytes
-    size_t b_sys, b_state;
+    size_t b_sys, b_state, b_adj;
 };
 
 Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
@@ -132,8 +141,9 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.l_nua = take(N * 8);
         L.l_scal = take(kScLen * 8);
         L.l_red = take(8 * 8);
-        L.l_U = take(std::max(std::max((size_t)11 * L.nb32 * 4, (size_t)(ns * ns + ns) * 8),
-                              (size_t)7 * N * 4));
+        L.l_U = take(std::max(std::max(std::max((size_t)11 * L.nb32 * 4, (size_t)(ns * ns + ns) * 8),
+                                       (size_t)7 * N * 8),
+                              (size_t)11 * kMixChunk * 8));
         L.l_R = take(P * 4);
         L.l_Rdet = take(P * 4);
         L.l_dJ = take(P * 4);
@@ -143,6 +153,7 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.l_dje = take(N * 4);
         L.l_rows = take(11 * ns * 4);
         L.l_tmp = take((3 * ns + 8) * 4);
+        L.l_F = take((size_t)(2 * P + 8 * N + 11 * ns) * 8);
         L.l_bytes = o;
         L.lds_bytes = o;
         L.g_Phi = 0;
@@ -150,9 +161,30 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.g_Arow = L.g_dPhi + 2L * ns * 4 * ns;
         L.g_AinvT = L.g_Arow + (long)N * ns;
         L.m_stride = (L.g_AinvT + 2L * ns * ns + 63) / 64 * 64;
+        L.stride64 = (long)N * ns + 2L * ns * ns;
         L.b_sys += align_up((size_t)Nb * ns * 4) +
-                   align_up((size_t)L.tiles * (L.nb32 / 32) * 64 * 8 * 2);
-        L.b_state = common + 2 * align_up(nw * L.m_stride * 4) + 2 * align_up(sizeof(DevMix));
+                   align_up((size_t)2 * L.tiles * (L.nb32 / 32) * 64 * 8 * 2);
+        L.b_state = common + 2 * align_up(nw * L.m_stride * 4) + align_up(nw * L.stride64 * 8) +
+                    align_up(nw * 4 * 8) + 2 * align_up(sizeof(DevMix));
+    }
+    {
+        int o = 0;
+        auto take = [&](int n) { int r = o; o += (n + 1) / 2 * 2; return r; };
+        L.nth = 3 * M + 3 * (2 + s.n_species);
+        L.a_pos = take(3 * N); L.a_phi = take(N * ns); L.a_dphi = take(4 * N * ns);
+        L.a_phi6 = take(6 * N * ns); L.a_ainv = take(2 * ns * ns); L.a_Z = take(2 * Nb * ns);
+        L.a_T = take(N * Nb); L.a_Y = take(2 * ns * ns); L.a_G = take(ns * ns + ns);
+        L.a_chi = take(11 * Nb); L.a_gj = take(3 * N); L.a_Lj = take(N); L.a_dJ = take(P);
+        L.a_R = take(P); L.a_Rdet = take(P); L.a_gd = take(3 * N); L.a_Ld = take(N);
+        L.a_nu = take(N); L.a_nua = take(N); L.a_al = take(N); L.a_sgd = take(3 * N);
+        L.a_sgj = take(3 * N); L.a_sRd = take(P); L.a_sdJ = take(P); L.a_snu = take(N);
+        L.a_snua = take(N); L.a_GeL = take(L.nth); L.a_Glp = take(L.nth); L.a_sc = take(16);
+        L.a_piv = take(ns / 2 + 1);
+        L.a_doubles = o;
+        const int nspec = s.n_species;
+        L.b_adj = align_up(M * 3 * 8) + align_up((2 + nspec) * 3 * 8) + align_up((size_t)Nb * 4 * 8) +
+                  2 * align_up(nw * 8) + 2 * align_up(nw * (size_t)L.nth * 8) + align_up(8) +
+                  align_up((3 * (size_t)L.nth + 2) * 8) + align_up(8) + align_up(sizeof(DevAdj));
     }
     return L;
 }
@@ -191,6 +223,8 @@ std::string validate(const lrdmc_system* sys, int n_sys, const lrdmc_params* prm
             if (s.basis_type[mu] < 0 || s.basis_type[mu] > 4) return "bad basis_type";
             if (!(s.basis_exp[mu] > 0)) return "basis exponent <= 0";
         }
+        if (prm->precision != LRDMC_FP64 && std::max(s.n_up, s.n_dn) > 64)
+            return "mixed-precision layout: at most 64 electrons per spin (too large)";
         const Layout L = make_layout(s, *prm);
         if (L.lds_bytes > (size_t)kMaxLdsBytes)
             return L.kind == kKindLds ? "system too large for the LDS-resident FP64 walker layout "
@@ -234,6 +268,13 @@ struct SysRun {
     double e0;
     std::vector<double> hist_lwb, hist_e;
     std::vector<double> btab_host;
+    // adjoint pass: theta-dependent copies of the system arrays, outputs
+    DevAdj ad;
+    DevAdj* dadj;
+    double *R_t, *jas_t, *btab_t, *a_eL, *a_lp, *a_deL, *a_dlp, *a_out, *a_e0;
+    int* a_status;
+    std::vector<double> h_R, h_Z, h_bexp, h_jas;
+    std::vector<int32_t> h_batom;
     std::vector<float> cf_host;
     std::vector<uint16_t> cbf_host;
 };
@@ -270,10 +311,13 @@ size_t lrdmc_workspace_bytes(const lrdmc_system* sys, int n_sys, const lrdmc_par
     size_t tot = align_up(kCntLen * 8);
     for (int k = 0; k < n_sys; ++k) {
         const Layout L = make_layout(sys[k], *prm);
-        tot += L.b_sys + L.b_state;
+        tot += L.b_sys + L.b_state + L.b_adj;
     }
     return tot;
 }
+
+static int run_derivs(lrdmc_handle* h, int isys, const double* theta, double* eL, double* lp,
+                      double* deL, double* dlp);
 
 // Termination bound of the conventional loop: 1000 times the mean number of
 // moves tau * 3N/a^2 (plus a floor).  Reaching it is counted and reported.
@@ -414,14 +458,16 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
         uint16_t* Cbf = nullptr;
         if (r.kind == kKindMixed) {
             Cf = (float*)carve((size_t)Nb * ns * 4);
-            Cbf = (uint16_t*)carve((size_t)L.tiles * (L.nb32 / 32) * 64 * 8 * 2);
+            Cbf = (uint16_t*)carve((size_t)2 * L.tiles * (L.nb32 / 32) * 64 * 8 * 2);
             r.cf_host.resize((size_t)Nb * ns);
             for (int mu = 0; mu < Nb; ++mu)
                 for (int c = 0; c < ns; ++c)
                     r.cf_host[(size_t)mu * ns + c] = (float)s.mo_coeff[(size_t)mu * s.n_orb + c];
             // BF16 B operands of v_mfma_f32_16x16x32_bf16: lane l of k-block kb holds
-            // C[32 kb + 8 (l / 16) + e][16 t + l % 16], e = 0..7
-            r.cbf_host.assign((size_t)L.tiles * (L.nb32 / 32) * 64 * 8, 0);
+            // C[32 kb + 8 (l / 16) + e][16 t + l % 16], e = 0..7; the high part
+            // bf16(c) and the low part bf16(c - bf16(c)) in two planes
+            const size_t plane = (size_t)L.tiles * (L.nb32 / 32) * 64 * 8;
+            r.cbf_host.assign(2 * plane, 0);
             for (int t = 0; t < L.tiles; ++t)
                 for (int kb = 0; kb < L.nb32 / 32; ++kb)
                     for (int l = 0; l < 64; ++l)
@@ -430,7 +476,13 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
                             const float x = (mu < Nb && col < ns)
                                                 ? (float)s.mo_coeff[(size_t)mu * s.n_orb + col]
                                                 : 0.0f;
-                            r.cbf_host[(((size_t)t * (L.nb32 / 32) + kb) * 64 + l) * 8 + e] = to_bf16(x);
+                            const uint16_t hi = to_bf16(x);
+                            uint32_t hb = (uint32_t)hi << 16;
+                            float hf;
+                            std::memcpy(&hf, &hb, 4);
+                            const size_t at = (((size_t)t * (L.nb32 / 32) + kb) * 64 + l) * 8 + e;
+                            r.cbf_host[at] = hi;
+                            r.cbf_host[plane + at] = to_bf16(x - hf);
                         }
             if (up(Cf, r.cf_host.data(), r.cf_host.size() * 4) ||
                 up(Cbf, r.cbf_host.data(), r.cbf_host.size() * 2)) {
@@ -454,6 +506,42 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
         r.trace = prm->trace_cap > 0 ? (int32_t*)carve(nw * (size_t)prm->trace_cap * 4) : nullptr;
         r.parity = 0;
         r.need_build = false;
+        {   // adjoint pass buffers and descriptor
+            const int nth = L.nth, nsp = s.n_species;
+            r.R_t = (double*)carve(M * 3 * 8);
+            r.jas_t = (double*)carve((2 + nsp) * 3 * 8);
+            r.btab_t = (double*)carve((size_t)Nb * 4 * 8);
+            r.a_eL = (double*)carve(nw * 8);
+            r.a_lp = (double*)carve(nw * 8);
+            r.a_deL = (double*)carve(nw * (size_t)nth * 8);
+            r.a_dlp = (double*)carve(nw * (size_t)nth * 8);
+            r.a_status = (int*)carve(8);
+            r.a_out = (double*)carve((3 * (size_t)nth + 2) * 8);
+            r.a_e0 = (double*)carve(8);
+            r.dadj = (DevAdj*)carve(sizeof(DevAdj));
+            r.h_R.assign(s.atom_pos, s.atom_pos + 3 * M);
+            r.h_Z.assign(s.atom_charge, s.atom_charge + M);
+            r.h_bexp.assign(s.basis_exp, s.basis_exp + Nb);
+            r.h_batom.assign(s.basis_atom, s.basis_atom + Nb);
+            r.h_jas.assign(s.jastrow, s.jastrow + 3 * (2 + nsp));
+            DevAdj& ad = r.ad;
+            ad.M = M; ad.Nb = Nb; ad.Norb = s.n_orb; ad.Nup = s.n_up; ad.Ndn = s.n_dn; ad.N = L.N;
+            ad.ns = ns; ad.nspec = nsp; ad.nw = r.nw; ad.nth = nth; ad.nu_mode = prm->nu_opt_mode;
+            ad.a = prm->a; ad.vii = vii;
+            ad.R = r.R_t; ad.Z = Z; ad.rc = rcs; ad.jas = r.jas_t; ad.btab = r.btab_t; ad.C = C;
+            ad.core = core; ad.spec = spec; ad.batom = batom; ad.btype = btype;
+            ad.pos = r.pos;
+            ad.eL = r.a_eL; ad.lp = r.a_lp; ad.deL = r.a_deL; ad.dlp = r.a_dlp;
+            ad.status = r.a_status;
+            ad.o_pos = L.a_pos; ad.o_phi = L.a_phi; ad.o_dphi = L.a_dphi; ad.o_phi6 = L.a_phi6;
+            ad.o_ainv = L.a_ainv; ad.o_Z = L.a_Z; ad.o_T = L.a_T; ad.o_Y = L.a_Y; ad.o_G = L.a_G;
+            ad.o_chi = L.a_chi; ad.o_gj = L.a_gj; ad.o_Lj = L.a_Lj; ad.o_dJ = L.a_dJ; ad.o_R = L.a_R;
+            ad.o_Rdet = L.a_Rdet; ad.o_gd = L.a_gd; ad.o_Ld = L.a_Ld; ad.o_nu = L.a_nu;
+            ad.o_nua = L.a_nua; ad.o_al = L.a_al; ad.o_sgd = L.a_sgd; ad.o_sgj = L.a_sgj;
+            ad.o_sRd = L.a_sRd; ad.o_sdJ = L.a_sdJ; ad.o_snu = L.a_snu; ad.o_snua = L.a_snua;
+            ad.o_GeL = L.a_GeL; ad.o_Glp = L.a_Glp; ad.o_sc = L.a_sc; ad.o_piv = L.a_piv;
+            ad.lds_doubles = L.a_doubles;
+        }
         if (r.kind == kKindLds) {
             DevSys& d = r.d;
             d.M = M; d.Nb = Nb; d.Norb = s.n_orb; d.Nup = s.n_up; d.Ndn = s.n_dn;
@@ -485,6 +573,10 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             m.R = R; m.Z = Z; m.rc = rcs; m.jas = jas; m.btab = btab;
             m.core = core; m.spec = spec; m.btype = btype;
             m.Cf = Cf; m.Cbf = Cbf; m.nb32 = L.nb32;
+            m.C64 = C;
+            m.s64 = (double*)carve(nw * L.stride64 * 8);
+            m.stride64 = L.stride64;
+            m.diag = (double*)carve(nw * 4 * 8);
             m.pos = r.pos; m.lw = r.lw; m.eL = r.eL; m.Wd = r.Wd;
             r.state = (float*)carve(nw * L.m_stride * 4);
             r.state_alt = (float*)carve(nw * L.m_stride * 4);
@@ -495,7 +587,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             m.l_pos = L.l_pos; m.l_nue = L.l_nue; m.l_nua = L.l_nua; m.l_scal = L.l_scal;
             m.l_red = L.l_red; m.l_U = L.l_U; m.l_R = L.l_R; m.l_Rdet = L.l_Rdet; m.l_dJ = L.l_dJ;
             m.l_gD = L.l_gD; m.l_Jg = L.l_Jg; m.l_Jl = L.l_Jl; m.l_dje = L.l_dje;
-            m.l_rows = L.l_rows; m.l_tmp = L.l_tmp; m.l_bytes = L.l_bytes;
+            m.l_rows = L.l_rows; m.l_tmp = L.l_tmp; m.l_F = L.l_F; m.l_bytes = L.l_bytes;
             r.dmix[0] = (DevMix*)carve(sizeof(DevMix));
             r.dmix[1] = (DevMix*)carve(sizeof(DevMix));
             r.hmix[0] = m;
@@ -695,7 +787,30 @@ int lrdmc_branch(lrdmc_handle* h, lrdmc_branch_stats* st)
 int lrdmc_energy_forces(lrdmc_handle* h, lrdmc_energy* e, double* forces, double* jgrad)
 {
     if (!h || !e) return fail(LRDMC_ERR_INVALID_ARG, "null argument");
-    if (forces || jgrad) return fail(LRDMC_ERR_UNSUPPORTED, "forces are not available in this build");
+    if (forces || jgrad) {
+        // per-walker derivatives at the current population, then the weighted
+        // population sums on the device
+        SysRun& r = h->sys[0];
+        int rc = run_derivs(h, 0, nullptr, nullptr, nullptr, nullptr, nullptr);
+        if (rc) return rc;
+        const int nth = r.L.nth, M = r.ad.M;
+        HIPCHK(hipMemcpyAsync(r.a_e0, &r.e0, 8, hipMemcpyHostToDevice, h->stream));
+        hipLaunchKernelGGL(derivs_reduce, dim3(3 * nth + 2), dim3(256), 0, h->stream, r.nw, nth,
+                           h->prm.scheme == LRDMC_SCHEME_LB ? 0 : 1, (const double*)r.lw,
+                           (const double*)r.Wd, (const double*)r.a_e0, (const double*)r.a_eL,
+                           (const double*)r.a_deL, (const double*)r.a_dlp, r.a_out);
+        HIPCHK(hipGetLastError());
+        std::vector<double> o(3 * (size_t)nth + 2);
+        HIPCHK(hipMemcpyAsync(o.data(), r.a_out, o.size() * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        const double S = o[0], E = o[1] / S;
+        if (!(S > 0)) return fail(LRDMC_ERR_ALL_DEAD, "every walker weight is zero");
+        for (int q = 0; q < nth; ++q) {
+            const double g = o[2 + q] / S + 2.0 * (o[2 + nth + q] / S - E * o[2 + 2 * nth + q] / S);
+            if (q < 3 * M) { if (forces) forces[q] = -g; }
+            else if (jgrad) jgrad[q - 3 * M] = g;
+        }
+    }
     const SysRun& r = h->sys[0];
     const int n = (int)r.hist_e.size(), p = std::max(0, h->prm.p_corr);
     const int start = std::max(p, n / 10);
@@ -735,6 +850,75 @@ int lrdmc_energy_forces(lrdmc_handle* h, lrdmc_energy* e, double* forces, double
     return LRDMC_OK;
 }
 
+int lrdmc_n_theta(lrdmc_handle* h, int isys)
+{
+    if (!h || isys < 0 || isys >= (int)h->sys.size()) return fail(LRDMC_ERR_INVALID_ARG, "bad handle/system");
+    return h->sys[isys].L.nth;
+}
+
+// Adjoint pass over the walkers of system isys at their current positions,
+// with the system's parameters replaced by theta (host, n_theta) when given.
+static int run_derivs(lrdmc_handle* h, int isys, const double* theta, double* eL, double* lp,
+                      double* deL, double* dlp)
+{
+    SysRun& r = h->sys[isys];
+    const Layout& L = r.L;
+    const size_t lds = (size_t)L.a_doubles * 8;
+    hipFuncAttributes fa;
+    HIPCHK(hipFuncGetAttributes(&fa, (const void*)walker_derivs));
+    if (lds + fa.sharedSizeBytes > (size_t)kMaxLdsBytes)
+        return fail(LRDMC_ERR_UNSUPPORTED, "system too large for the LDS layout of the adjoint pass");
+    HIPCHK(hipFuncSetAttribute((const void*)walker_derivs, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(kMaxLdsBytes - fa.sharedSizeBytes)));
+    const int M = r.ad.M, Nb = r.ad.Nb, nj = 3 * (2 + r.ad.nspec);
+    std::vector<double> R(r.h_R), jas(r.h_jas);
+    if (theta) {
+        for (int q = 0; q < 3 * M; ++q) R[q] = theta[q];
+        for (int q = 0; q < nj; ++q) jas[q] = theta[3 * M + q];
+        for (int q = 0; q < 3 * M + nj; ++q)
+            if (!std::isfinite(theta[q])) return fail(LRDMC_ERR_INVALID_ARG, "non-finite theta");
+    }
+    std::vector<double> btab((size_t)Nb * 4);
+    for (int mu = 0; mu < Nb; ++mu) {
+        for (int c = 0; c < 3; ++c) btab[4 * mu + c] = R[3 * r.h_batom[mu] + c];
+        btab[4 * mu + 3] = r.h_bexp[mu];
+    }
+    double vii = 0.0;
+    for (int I = 0; I < M; ++I)
+        for (int J = I + 1; J < M; ++J) {
+            const double dx = R[3 * I] - R[3 * J], dy = R[3 * I + 1] - R[3 * J + 1],
+                         dz = R[3 * I + 2] - R[3 * J + 2];
+            vii += r.h_Z[I] * r.h_Z[J] / std::sqrt(dx * dx + dy * dy + dz * dz);
+        }
+    DevAdj ad = r.ad;
+    ad.vii = vii;
+    ad.pos = r.pos;
+    if (eL) ad.eL = eL;
+    if (lp) ad.lp = lp;
+    if (deL) ad.deL = deL;
+    if (dlp) ad.dlp = dlp;
+    int zero = 0, nbad = 0;
+    HIPCHK(hipMemcpyAsync(r.R_t, R.data(), R.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(r.jas_t, jas.data(), jas.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(r.btab_t, btab.data(), btab.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(r.a_status, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(r.dadj, &ad, sizeof(DevAdj), hipMemcpyHostToDevice, h->stream));
+    hipLaunchKernelGGL(walker_derivs, dim3(r.nw), dim3(kAdjThreads), lds, h->stream,
+                       (const DevAdj*)r.dadj);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&nbad, r.a_status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (nbad) return fail(LRDMC_ERR_SINGULAR, "singular Slater matrix in the adjoint pass");
+    return LRDMC_OK;
+}
+
+int lrdmc_walker_derivs(lrdmc_handle* h, int isys, const double* theta, double* eL, double* logpsi,
+                        double* deL, double* dlogpsi)
+{
+    if (!h || isys < 0 || isys >= (int)h->sys.size()) return fail(LRDMC_ERR_INVALID_ARG, "bad handle/system");
+    return run_derivs(h, isys, theta, eL, logpsi, deL, dlogpsi);
+}
+
 int lrdmc_get_walkers(lrdmc_handle* h, int isys, double* pos, double* lw, double* eL, double* W,
                       int32_t* iters, int32_t* sel, int32_t* trace)
 {
@@ -752,6 +936,18 @@ int lrdmc_get_walkers(lrdmc_handle* h, int isys, double* pos, double* lw, double
         HIPCHK(hipMemcpyAsync(trace, r.trace, nw * (size_t)h->prm.trace_cap * 4, hipMemcpyDeviceToHost,
                               h->stream));
     }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return LRDMC_OK;
+}
+
+int lrdmc_get_precision_report(lrdmc_handle* h, int isys, double* out)
+{
+    if (!h || isys < 0 || isys >= (int)h->sys.size() || !out)
+        return fail(LRDMC_ERR_INVALID_ARG, "bad arguments");
+    const SysRun& r = h->sys[isys];
+    if (r.kind != kKindMixed)
+        return fail(LRDMC_ERR_INVALID_ARG, "the FP64 walker layout has no precision report");
+    HIPCHK(hipMemcpyAsync(out, r.m.diag, (size_t)r.nw * 4 * 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return LRDMC_OK;
 }

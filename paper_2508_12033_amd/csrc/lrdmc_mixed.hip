@@ -48,6 +48,16 @@ __device__ __forceinline__ double block_sum(double v, double* red)
     return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+__device__ __forceinline__ double block_max(double v, double* red)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    const int tid = threadIdx.x;
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
 // exclusive prefix of v over the block (thread order) and the block total
 __device__ __forceinline__ double block_excl_scan(double v, double* red, double& total)
 {
@@ -177,17 +187,27 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
         float4_t acc = {0.f, 0.f, 0.f, 0.f};
         const int col = 16 * t + i16;
         if (s.gemm == kGemmBF16) {
-            // 16x16x32 BF16 tiles: lane holds 8 consecutive inner indices
+            // 16x16x32 BF16 tiles, lane holds 8 consecutive inner indices.  Each
+            // FP32 operand is split into a BF16 high part and a BF16 residual;
+            // hi*hi + hi*lo + lo*hi keeps about 16 significant bits
+            const long plane = (long)((s.ns + 15) / 16) * (s.nb32 / 32) * 64;
             const bf16x8_t* cb = reinterpret_cast<const bf16x8_t*>(s.Cbf) +
                                  (long)t * (s.nb32 / 32) * 64;
             for (int kb = 0; kb < s.nb32 / 32; ++kb) {
-                bf16x8_t av;
+                bf16x8_t ah, alo;
                 const int k0 = 32 * kb + 8 * k4;
 #pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    av[e] = (__bf16)(i16 < 11 ? B[i16 * ldb + k0 + e] : 0.0f);
-                const bf16x8_t bv = cb[(long)kb * 64 + lane];
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+                for (int e = 0; e < 8; ++e) {
+                    const float x = i16 < 11 ? B[i16 * ldb + k0 + e] : 0.0f;
+                    const __bf16 h = (__bf16)x;
+                    ah[e] = h;
+                    alo[e] = (__bf16)(x - (float)h);
+                }
+                const bf16x8_t bh = cb[(long)kb * 64 + lane];
+                const bf16x8_t bl = cb[plane + (long)kb * 64 + lane];
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bh, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
             }
         } else {
             for (int k0 = 0; k0 < Nb; k0 += 4) {
@@ -227,10 +247,12 @@ __device__ __noinline__ void mixed_store_rows(const DevMix* __restrict__ dm, flo
 }
 
 // FP64 Gauss-Jordan (in place, partial pivoting) of the transposed Slater
-// matrix of spin sp; writes AinvT (FP32) and log|det|, sign.
-__device__ __noinline__ bool mixed_refresh_inverse(const DevMix* __restrict__ dm, float* st, int sp)
+// matrix of spin sp read from Arow ([N][ns], FP32 or FP64); writes the
+// transposed inverse AiT[c][k] (FP32 or FP64, row stride ns) and log|det|,
+// sign into the walker scalars.
+template <class TS, class TD>
+__device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
 {
-    const DevMix& s = *dm;
     const int tid = threadIdx.x;
     const int n = mnspin(s, sp);
     if (!n) return true;
@@ -240,7 +262,7 @@ __device__ __noinline__ bool mixed_refresh_inverse(const DevMix* __restrict__ dm
     int* piv = reinterpret_cast<int*>(LDSF(s.l_tmp));
     for (int idx = tid; idx < n * n; idx += kMixThreads) {
         const int r = idx / n, c = idx - r * n;
-        M[idx] = (double)st[s.g_Arow + (long)(off + c) * ns + r];
+        M[idx] = (double)Arow[(long)(off + c) * ns + r];
     }
     __syncthreads();
     double logdet = 0.0, sign = 1.0;
@@ -294,16 +316,21 @@ __device__ __noinline__ bool mixed_refresh_inverse(const DevMix* __restrict__ dm
                 }
             __syncthreads();
         }
-        float* Ai = st + s.g_AinvT + (long)sp * ns * ns;
         for (int idx = tid; idx < n * n; idx += kMixThreads) {
             const int c = idx / n, k = idx - c * n;
-            Ai[(long)c * ns + k] = (float)M[idx];
+            AiT[(long)c * ns + k] = (TD)M[idx];
         }
         if (tid == 0) { sc[kScLogdet0 + sp] = logdet; sc[kScSign0 + sp] = sign; }
     }
     __threadfence_block();
     __syncthreads();
     return ok;
+}
+
+__device__ __noinline__ bool mixed_refresh_inverse(const DevMix* __restrict__ dm, float* st, int sp)
+{
+    const DevMix& s = *dm;
+    return gj_inverse<float, float>(s, st + s.g_Arow, st + s.g_AinvT + (long)sp * s.ns * s.ns, sp);
 }
 
 // determinant gradients / Laplacians of the electrons of spin sp (sp < 0:
@@ -484,6 +511,210 @@ __device__ __noinline__ MLocal mixed_evaluate(const DevMix* __restrict__ dm, dou
     MLocal L;
     L.bbar = bs / (2.0 * a * a);
     L.eL = econt + LDSD(s.l_scal)[kScVee] + s.vii + dnu;
+    L.W = L.eL + L.bbar;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 estimator evaluation: everything recomputed from the positions in FP64
+// (orbital rows, Gauss-Jordan inverses, ratios, Jastrow, local energy), so
+// that e_L and W handed to the reconfiguration and the energy estimate carry
+// no FP32 error.  Basis functions are taken in chunks of kMixChunk.
+// ---------------------------------------------------------------------------
+// orbital rows of electron i in FP64: nrows = 1 (value) or 11 (value, the 6
+// lattice neighbours, gradient, Laplacian) into out[row][ns]
+__device__ void orb_rows64(const DevMix& s, int i, int nrows, double a, double* out)
+{
+    const int tid = threadIdx.x, ns = s.ns, Nb = s.Nb;
+    const int n = mnspin(s, mspin(s, i));
+    double* rb = LDSD(s.l_U);                    // [11][kMixChunk]
+    const double* pos = LDSD(s.l_pos);
+    const int items = nrows * n;                 // <= 11 * 64 < 3 * kMixThreads
+    const int npts = nrows == 1 ? 1 : 7;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int m0 = 0; m0 < Nb; m0 += kMixChunk) {
+        const int cnt = min(kMixChunk, Nb - m0);
+        for (int it = tid; it < npts * kMixChunk; it += kMixThreads) {
+            const int q = it / kMixChunk, m = it - q * kMixChunk, mu = m0 + m;
+            if (m >= cnt) continue;
+            double p[3];
+            point_q(pos + 3 * i, q, a, p);
+            const double* rec = s.btab + 4 * mu;
+            const double dx = p[0] - rec[0], dy = p[1] - rec[1], dz = p[2] - rec[2];
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            const int t = s.btype[mu];
+            if (q == 0 && nrows > 1) {
+                double v, g[3], l;
+                basis_vgl_d(t, rec[3], dx, dy, dz, d2, v, g, l);
+                rb[m] = v;
+                rb[7 * kMixChunk + m] = g[0];
+                rb[8 * kMixChunk + m] = g[1];
+                rb[9 * kMixChunk + m] = g[2];
+                rb[10 * kMixChunk + m] = l;
+            } else {
+                rb[q * kMixChunk + m] = basis_value_d(t, rec[3], dx, dy, dz, d2);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int it = tid + r * kMixThreads;
+            if (it < items) {
+                const int row = it / n, k = it - row * n;
+                double sacc = 0.0;
+                for (int m = 0; m < cnt; ++m)
+                    sacc += rb[row * kMixChunk + m] * s.C64[(long)(m0 + m) * s.Norb + k];
+                acc[r] += sacc;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int it = tid + r * kMixThreads;
+        if (it < items) {
+            const int row = it / n, k = it - row * n;
+            out[row * ns + k] = acc[r];
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, double a, int nu_mode,
+                                                bool& ok)
+{
+    const DevMix& s = *dm;
+    const int tid = threadIdx.x, ns = s.ns, N = s.N, P = s.P;
+    double* g64 = s.s64 + (long)blockIdx.x * s.stride64;
+    double* A64 = g64;                           // [N][ns]    Slater rows
+    double* Ai64 = g64 + (long)N * ns;           // [2][ns][ns] transposed inverses
+    const double* pos = LDSD(s.l_pos);
+    double* F = LDSD(s.l_F);
+    double* R64 = F;                             // [P]
+    double* gD64 = F + P;                        // [N][4]
+    double* dJ64 = gD64 + 4 * N;                 // [P]
+    double* Jg64 = dJ64 + P;                     // [N][3]
+    double* Jl64 = Jg64 + 3 * N;                 // [N]
+    double* rows = Jl64 + N;                     // [11][ns]
+    double* nue = LDSD(s.l_nue);
+    double* nua = LDSD(s.l_nua);
+    double* red = LDSD(s.l_red);
+    // Slater rows and inverses
+    for (int i = 0; i < N; ++i) {
+        orb_rows64(s, i, 1, a, rows);
+        const int n = mnspin(s, mspin(s, i));
+        for (int k = tid; k < n; k += kMixThreads) A64[(long)i * ns + k] = rows[k];
+        __threadfence_block();
+        __syncthreads();
+    }
+    ok = gj_inverse<double, double>(s, A64, Ai64, 0);
+    ok = gj_inverse<double, double>(s, A64, Ai64 + (long)ns * ns, 1) && ok;
+    // determinant ratios of the 6 moves, gradient and Laplacian of each electron
+    for (int i = 0; i < N; ++i) {
+        orb_rows64(s, i, 11, a, rows);
+        const int sp = mspin(s, i), c = mcol(s, i), n = mnspin(s, sp);
+        const double* Ai = Ai64 + (long)sp * ns * ns + (long)c * ns;
+        if (tid < 10) {
+            const int row = tid + 1;
+            double acc = 0.0;
+            for (int k = 0; k < n; ++k) acc += rows[row * ns + k] * Ai[k];
+            if (row <= 6) R64[6 * i + row - 1] = acc;
+            else gD64[4 * i + row - 7] = acc;
+        }
+        __syncthreads();
+    }
+    // Jastrow: exponent changes of the 6N moves, gradients and Laplacians;
+    // potentials and V_ee
+    double* S = LDSD(s.l_U);                     // [N][7]
+    const int K = N + s.M, Kj = s.has_en ? K : N;
+    for (int it = tid; it < 7 * N; it += kMixThreads) {
+        const int j = it / 7, q = it - 7 * j;
+        double pq[3];
+        point_q(pos + 3 * j, q, a, pq);
+        double acc = 0.0;
+        #pragma unroll 1
+        for (int k = 0; k < Kj; ++k) {
+            if (k == j) continue;
+            double pk[3];
+            int jr;
+            mpartner(s, pos, j, k, pk, jr);
+            acc += pade_u(s.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+        }
+        S[it] = acc;
+    }
+    double vee = 0.0;
+    for (int j = tid; j < N; j += kMixThreads) {
+        const double* rj = pos + 3 * j;
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0, nu = 0.0, nv = 0.0;
+        #pragma unroll 1
+        for (int k = 0; k < K; ++k) {
+            if (k == j) continue;
+            const bool isel = k < N;
+            double pk[3];
+            int jr;
+            mpartner(s, pos, j, k, pk, jr);
+            const double d0 = rj[0] - pk[0], d1 = rj[1] - pk[1], d2 = rj[2] - pk[2];
+            const double r = norm3(d0, d1, d2);
+            if (isel || s.has_en) {
+                double u, dur, lp;
+                pade_derivs(s.jas + 3 * jr, r, u, dur, lp);
+                g0 += dur * d0; g1 += dur * d1; g2 += dur * d2;
+                l += lp;
+                if (isel && k > j) vee += 1.0 / r;
+            }
+            if (!isel) {
+                double a1, a2;
+                nuc_pot(s, k - N, r, a, a1, a2);
+                nu += a1; nv += a2;
+            }
+        }
+        Jg64[3 * j] = g0; Jg64[3 * j + 1] = g1; Jg64[3 * j + 2] = g2; Jl64[j] = l;
+        nue[j] = nu; nua[j] = nv;
+    }
+    vee = block_sum(vee, red);
+    for (int p = tid; p < P; p += kMixThreads) {
+        const int j = p / 6, q = p - 6 * j;
+        dJ64[p] = S[7 * j + q + 1] - S[7 * j];
+    }
+    __syncthreads();
+    // ratios, lattice diagonal, local energy (App. D), as in the FP64 kernel
+    double bs = 0.0;
+    int anyneg = 0;
+    for (int p = tid; p < P; p += kMixThreads) {
+        const double r = R64[p] * exp(dJ64[p]);
+        R64[p] = r;
+        if (r > 0) bs += r;
+        else if (r < 0) anyneg = 1;
+    }
+    const bool anynode = block_sum(anyneg ? 1.0 : 0.0, red) > 0.0;
+    bs = block_sum(bs, red);
+    double econt = 0.0, dnu = 0.0;
+    const double ia2 = 1.0 / (a * a);
+    for (int j = tid; j < N; j += kMixThreads) {
+        const double j0 = Jg64[3 * j], j1 = Jg64[3 * j + 1], j2 = Jg64[3 * j + 2];
+        const double lap = gD64[4 * j + 3] +
+                           2.0 * (gD64[4 * j] * j0 + gD64[4 * j + 1] * j1 + gD64[4 * j + 2] * j2) +
+                           Jl64[j] + j0 * j0 + j1 * j1 + j2 * j2;
+        double lapA = 0.0;
+        int nd = 0;
+        for (int q = 0; q < 6; ++q) {
+            const double r = R64[6 * j + q];
+            lapA += (r - 1.0) * ia2;
+            if (r < 0) nd = 1;
+        }
+        if (nu_mode == 1) nd = anynode;
+        if (nu_mode == 2) nd = 1;
+        const double nuzv = nue[j] + 0.5 * (lapA - lap);
+        const double numax = nuzv > nua[j] ? nuzv : nua[j];
+        econt += -0.5 * lap + nue[j];
+        dnu += (nd ? numax : nuzv) - nuzv;
+    }
+    econt = block_sum(econt, red);
+    dnu = block_sum(dnu, red);
+    if (tid == 0) LDSD(s.l_scal)[kScVee] = vee;
+    MLocal L;
+    L.bbar = bs / (2.0 * a * a);
+    L.eL = econt + vee + s.vii + dnu;
     L.W = L.eL + L.bbar;
     return L;
 }
@@ -762,7 +993,28 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(const DevMix* __restr
             }
         }
     }
-    if (pa.scheme == 0) L = mixed_evaluate(&s, a, pa.nu_mode);
+    // estimator values at the final configuration, in FP64; beside them the
+    // values the mixed-precision step computed there, and the largest ratio
+    // error, for the error report
+    {
+        if (pa.scheme == 0) L = mixed_evaluate(&s, a, pa.nu_mode);
+        const MLocal Lm = L;
+        bool ok64 = true;
+        L = mixed_final_fp64(&s, a, pa.nu_mode, ok64);
+        if (!ok64) n_sing++;
+        if (s.diag) {
+            const float* R = LDSF(s.l_R);
+            const double* R64 = LDSD(s.l_F);
+            double e = 0.0;
+            for (int p = tid; p < s.P; p += kMixThreads)
+                e = fmax(e, fabs((double)R[p] - R64[p]) / fmax(1.0, fabs(R64[p])));
+            e = block_max(e, LDSD(s.l_red));
+            if (tid == 0) {
+                double* dg = s.diag + (long)wid * 4;
+                dg[0] = Lm.eL; dg[1] = Lm.W; dg[2] = Lm.bbar; dg[3] = e;
+            }
+        }
+    }
 
     for (int q = tid; q < 3 * s.N; q += kMixThreads) s.pos[(long)wid * 3 * s.N + q] = pos[q];
     if (tid == 0) {

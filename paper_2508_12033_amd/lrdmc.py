@@ -67,7 +67,8 @@ class lrdmc_energy(ct.Structure):
 
 EXPORTS = ["lrdmc_workspace_bytes", "lrdmc_init_system", "lrdmc_step", "lrdmc_branch",
            "lrdmc_energy_forces", "lrdmc_get_walkers", "lrdmc_set_walkers", "lrdmc_get_e0",
-           "lrdmc_set_e0", "lrdmc_get_branch_index", "lrdmc_destroy", "lrdmc_last_error"]
+           "lrdmc_set_e0", "lrdmc_get_branch_index", "lrdmc_destroy", "lrdmc_last_error",
+           "lrdmc_n_theta", "lrdmc_walker_derivs", "lrdmc_get_precision_report"]
 
 _lib = None
 
@@ -97,9 +98,13 @@ def load(path=LIB_PATH):
     L.lrdmc_destroy.argtypes = [vp]
     L.lrdmc_destroy.restype = None
     L.lrdmc_last_error.restype = ct.c_char_p
+    L.lrdmc_n_theta.argtypes = [vp, ct.c_int]
+    L.lrdmc_get_precision_report.argtypes = [vp, ct.c_int, vp]
+    L.lrdmc_walker_derivs.argtypes = [vp, ct.c_int, vp, vp, vp, vp, vp]
     for k in ("lrdmc_init_system", "lrdmc_step", "lrdmc_branch", "lrdmc_energy_forces",
               "lrdmc_get_walkers", "lrdmc_set_walkers", "lrdmc_set_e0",
-              "lrdmc_get_branch_index"):
+              "lrdmc_get_branch_index", "lrdmc_n_theta", "lrdmc_walker_derivs",
+              "lrdmc_get_precision_report"):
         getattr(L, k).restype = ct.c_int
     _lib = L
     return L
@@ -203,6 +208,41 @@ class Handle:
         _check(self.L.lrdmc_energy_forces(self.h, ct.byref(e), None, None))
         return e.energy, e.sigma, e.n_used
 
+    def n_theta(self, isys=0):
+        n = self.L.lrdmc_n_theta(self.h, isys)
+        _check(n)
+        return n
+
+    def forces(self):
+        """(forces [n_atoms][3], Jastrow-table energy gradient) of system 0 from
+        the adjoint pass over the current population."""
+        e = lrdmc_energy()
+        nth = self.n_theta(0)
+        M = self.systems[0]["atom_pos"].shape[0]
+        f = np.zeros(3 * M); jg = np.zeros(nth - 3 * M)
+        _check(self.L.lrdmc_energy_forces(self.h, ct.byref(e), f.ctypes.data, jg.ctypes.data))
+        return f.reshape(M, 3), jg
+
+    def walker_derivs(self, theta=None, isys=0):
+        """Per-walker e_L, log|Psi| [nw] and d/dtheta of both [nw][n_theta]
+        as float64 tensors on the handle's device (adjoint pass)."""
+        import torch
+        nw, nth = self.nw[isys], self.n_theta(isys)
+        dev = self.device
+        eL = torch.empty(nw, dtype=torch.float64, device=dev)
+        lp = torch.empty(nw, dtype=torch.float64, device=dev)
+        deL = torch.empty(nw, nth, dtype=torch.float64, device=dev)
+        dlp = torch.empty(nw, nth, dtype=torch.float64, device=dev)
+        th = None
+        if theta is not None:
+            th = np.ascontiguousarray(np.asarray(theta, np.float64).reshape(-1))
+            if th.size != nth:
+                raise ValueError("theta has %d entries, expected %d" % (th.size, nth))
+        _check(self.L.lrdmc_walker_derivs(self.h, isys, None if th is None else th.ctypes.data,
+                                          eL.data_ptr(), lp.data_ptr(), deL.data_ptr(),
+                                          dlp.data_ptr()))
+        return eL, lp, deL, dlp
+
     def walkers(self, isys=0, trace=False):
         nw, N = self.nw[isys], self.N[isys]
         pos = np.zeros((nw, N, 3)); lw = np.zeros(nw); eL = np.zeros(nw); W = np.zeros(nw)
@@ -214,6 +254,13 @@ class Handle:
         out = dict(pos=pos, lw=lw, eL=eL, W=W, iters=it, sel=sel)
         if trace:
             out["trace"] = tr
+        return out
+
+    def precision_report(self, isys=0):
+        """Mixed precisions: [nw][4] = e_L, W, bbar of the mixed-precision step
+        at the last phase's final configuration and its largest ratio error."""
+        out = np.zeros((self.nw[isys], 4))
+        _check(self.L.lrdmc_get_precision_report(self.h, isys, out.ctypes.data))
         return out
 
     def set_walkers(self, pos, lw=None, isys=0):
@@ -241,3 +288,42 @@ class Handle:
             self.close()
         except Exception:
             pass
+
+
+def _walker_energy_fn():
+    import torch
+
+    class WalkerEnergy(torch.autograd.Function):
+        """theta (float64 CPU tensor [n_theta]: nuclear coordinates, then the
+        Jastrow table) -> per-walker (e_L, log|Psi|) of the handle's current
+        walkers, with the adjoint pass supplying the vector-Jacobian product."""
+
+        @staticmethod
+        def forward(ctx, theta, handle, isys):
+            eL, lp, deL, dlp = handle.walker_derivs(theta.detach().cpu().numpy(), isys)
+            ctx.save_for_backward(deL, dlp)
+            ctx.theta_device = theta.device
+            return eL, lp
+
+        @staticmethod
+        def backward(ctx, g_eL, g_lp):
+            deL, dlp = ctx.saved_tensors
+            g = torch.zeros(deL.shape[1], dtype=torch.float64, device=deL.device)
+            if g_eL is not None:
+                g = g + g_eL.to(torch.float64) @ deL
+            if g_lp is not None:
+                g = g + g_lp.to(torch.float64) @ dlp
+            return g.to(ctx.theta_device), None, None
+
+    return WalkerEnergy
+
+
+_WE = None
+
+
+def walker_energy(theta, handle, isys=0):
+    """Differentiable per-walker (e_L, log|Psi|) as functions of theta."""
+    global _WE
+    if _WE is None:
+        _WE = _walker_energy_fn()
+    return _WE.apply(theta, handle, isys)
