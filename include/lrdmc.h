@@ -146,6 +146,12 @@ typedef struct lrdmc_energy {
     int32_t n_used;          /* branchings used */
 } lrdmc_energy;
 
+typedef struct lrdmc_tune_entry {
+    int32_t threads;          /* workgroup size of the mixed-precision phase kernel */
+    int32_t order_big_first;  /* 1: systems with more electrons first in the launch */
+    float ms;                 /* measured time of the tuning phase */
+} lrdmc_tune_entry;
+
 /* ---- calls ------------------------------------------------------------- */
 
 /* Bytes of device workspace needed for these systems and parameters.  Pure
@@ -171,8 +177,34 @@ int lrdmc_step(struct lrdmc_handle *h, lrdmc_step_stats *st);
 /* Reconfiguration (Sec. II.A): walker-averaged local energy, FP64 prefix sum
  * of the weights, comb with N_w correlated numbers, gather of the selected
  * walkers, weights reset to 1; then appends (log wbar, e_bar) to the history
- * and updates E_0.  Synchronises (one small device-to-host copy). */
+ * and updates E_0 (Algorithm 2), both on the device.  Synchronises and copies
+ * the new history records to the host. */
 int lrdmc_branch(struct lrdmc_handle *h, lrdmc_branch_stats *st);
+
+/* n_branchings cycles of (projection phase, reconfiguration) as by
+ * lrdmc_step + lrdmc_branch, with E_0, the branching index and the history
+ * kept on the device: each cycle is one replay of a HIP graph captured at the
+ * first call (one graph per walker buffer slot), so the host issues one
+ * launch per cycle and synchronises only at the end.  st: counters summed
+ * over all cycles (max/min over all phases), elapsed time of the whole run;
+ * bst: the last reconfiguration.  Either may be NULL. */
+int lrdmc_run(struct lrdmc_handle *h, int n_branchings, lrdmc_step_stats *st,
+              lrdmc_branch_stats *bst);
+
+/* Autotuner of the mixed-precision launch (every mixed-precision system of
+ * the handle advances in one launch): each candidate workgroup size (256 or
+ * 128 threads per walker) and order of the systems in the launch is timed on
+ * a copy of the current walkers for n_steps load-balanced steps; the fastest
+ * is kept for later phases.  The walkers, weights, E_0 and random streams of
+ * the run are not changed.  log (may be NULL) receives up to log_cap timings,
+ * *n_log their number.  Synchronises.  No effect for FP64 handles. */
+int lrdmc_autotune(struct lrdmc_handle *h, int n_steps, lrdmc_tune_entry *log, int log_cap,
+                   int *n_log);
+
+/* Fix the mixed-precision launch instead of tuning it: threads per walker
+ * workgroup (128 or 256) and the order of the systems in the launch (1:
+ * more electrons first).  No effect on results beyond FP32 summation order. */
+int lrdmc_set_launch(struct lrdmc_handle *h, int threads, int order_big_first);
 
 /* Energy estimate from the branching history (Sec. II.A correcting factors,
  * first 10 % of branchings dropped).  When forces ([n_atoms][3], host) or

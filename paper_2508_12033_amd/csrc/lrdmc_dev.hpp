@@ -23,6 +23,8 @@ struct DevSys {
     int M, Nb, Norb, Nup, Ndn, N, P, ns, nspec, nw, has_en;
     double vii;              // ion-ion repulsion (host-computed constant)
     uint64_t sysid;
+    const int *jp;           // branching index (Philox counter word 1), device
+    const double *e0p;       // E_0 of this system, device
     // system arrays (device)
     const double *R, *Z, *rc, *bexp, *C, *jas;
     const double *btab;      // [Nb][4]: centre x, y, z and exponent of each basis function
@@ -46,11 +48,10 @@ struct DevSys {
 struct PhaseArgs {
     int scheme;              // 0 load-balanced, 1 conventional
     int nproj;
-    int j;                   // branching index (Philox counter word 1)
     int refresh_every;
     int nu_mode;
     int conv_cap;            // hard bound on conventional iterations per phase
-    double a, tau, E0;
+    double a, tau;
     uint64_t seed;
     unsigned long long *counters;   // [kCntLen]
     unsigned long long *timers;     // [nw][8] section cycles (instrumentation builds)
@@ -67,6 +68,8 @@ struct DevMix {
     int M, Nb, Norb, Nup, Ndn, N, P, ns, nspec, nw, has_en, gemm;
     double vii;
     uint64_t sysid;
+    const int *jp;               // branching index, device
+    const double *e0p;           // E_0 of this system, device
     const double *R, *Z, *rc, *jas, *btab;
     const int32_t *core, *spec, *btype;
     const float *Cf;             // [Nb][ns] coefficients, FP32
@@ -113,12 +116,27 @@ struct DevAdj {
         o_Glp, o_sc, o_piv, lds_doubles;
 };
 
+// Systems advanced by one launch of the mixed-precision phase kernel.
+constexpr int kMaxBatch = 8;
+struct MixBatch {
+    const DevMix *tab;            // [nsys] descriptors in launch order
+    int nsys;
+    int start[kMaxBatch + 1];     // first workgroup of each system, start[nsys] = total
+};
+
 // What the reconfiguration kernels see of a system (either layout).
 struct BranchView {
     int nw, N;
     uint64_t sysid;
     double *pos, *lw, *eL, *Wd;   // current buffers
+    const int *jp;                // branching index
+    const double *e0p;            // E_0
 };
+
+// device history ring of the branchings: one record per branching
+enum : int { kHistLogW = 0, kHistEbar = 1, kHistE0 = 2, kHistMaxLw = 3, kHistDistinct = 4,
+             kHistLen = 8 };
+constexpr int kHistCap = 4096;
 
 // per-walker scalars stored at o_scal
 enum : int { kScLogdet0 = 0, kScLogdet1 = 1, kScSign0 = 2, kScSign1 = 3, kScVee = 4,

@@ -4,9 +4,12 @@
 // correcting-factor energy estimate and its blocking error bar, Sec. II.A).
 //
 // Two walker layouts: FP64 runs use the LDS-resident one-wavefront-per-walker
-// phase kernel (phase_fp64); mixed-precision runs use the 256-thread
-// workgroup-per-walker kernel with orbital data in HBM (phase_mixed).  Both
-// share the reconfiguration kernels.
+// phase kernel (phase_fp64, one launch per system); mixed-precision runs use
+// the workgroup-per-walker kernel with orbital data in HBM (phase_mixed), one
+// launch for the walkers of every system.  Both share the reconfiguration
+// kernels.  E_0, the branching index and the history of the branchings live
+// on the device, so that a projection phase plus its reconfiguration can be
+// captured once into a graph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,9 +24,9 @@
 
 namespace lrdmc {
 __global__ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa);
-__global__ void phase_mixed(const DevMix* __restrict__ sys, PhaseArgs pa, int build);
-__global__ void branch_scan(BranchView s, int scheme, double E0, double* cum, double* out);
-__global__ void branch_comb(BranchView s, uint64_t seed, int j, const double* cum, const double* out,
+__global__ void phase_mixed(MixBatch b, PhaseArgs pa, int build);
+__global__ void branch_scan(BranchView s, int scheme, double* cum, double* out, int* n_distinct);
+__global__ void branch_comb(BranchView s, uint64_t seed, const double* cum, const double* out,
                             int32_t* sel);
 __global__ void branch_count(const int32_t* sel, int nw, int* n_distinct);
 __global__ void branch_gather(BranchView s, const int32_t* sel, const double* pos_old,
@@ -31,6 +34,10 @@ __global__ void branch_gather(BranchView s, const int32_t* sel, const double* po
 __global__ void branch_gather_mixed(const DevMix* __restrict__ sys, const int32_t* sel,
                                     const float* old_state, const double* pos_old,
                                     const double* eL_old, const double* W_old);
+__global__ void branch_finish(int nw, const double* out, const int* n_distinct, double* hist,
+                              long long* n_hist, double* e0p, int* n_dead, int window, int cap,
+                              int* bump_j);
+__global__ void reset_counters_kernel(unsigned long long* c);
 __global__ void walker_derivs(const DevAdj* __restrict__ sys);
 __global__ void derivs_reduce(int nw, int nth, int scheme, const double* lw, const double* Wd,
                               const double* e0p, const double* eL, const double* deL,
@@ -203,6 +210,8 @@ std::string validate(const lrdmc_system* sys, int n_sys, const lrdmc_params* prm
     if (prm->refresh_every < 1) return "refresh_every must be >= 1";
     if (prm->nu_opt_mode < 0 || prm->nu_opt_mode > 2) return "bad nu_opt_mode";
     if (prm->trace_cap < 0) return "bad trace_cap";
+    if (prm->e0_window < 0 || prm->e0_window > kHistCap) return "e0_window out of range";
+    if (n_sys > kMaxBatch) return "at most 8 systems per handle";
     for (int k = 0; k < n_sys; ++k) {
         const lrdmc_system& s = sys[k];
         if (s.n_atoms < 1 || s.n_basis < 1 || s.n_up < 0 || s.n_dn < 0 || s.n_up + s.n_dn < 1)
@@ -247,31 +256,36 @@ uint16_t to_bf16(float x)
 struct SysRun {
     int kind;
     Layout L;
-    // common buffers (current + alternate)
-    double *pos, *lw, *eL, *Wd, *pos_alt, *eL_alt, *W_alt;
+    int nw, N;
+    uint64_t sysid;
+    // walker buffers by slot; the current slot is the handle's parity, the
+    // other one receives the gather of the next reconfiguration
+    double *pos[2], *eL[2], *Wd[2];
+    float* state[2];                     // mixed layout walker blocks
+    double* lw;
     int32_t *iters, *trace, *sel;
     double *cum, *bout;
     int* ndist;
-    int nw, N;
-    uint64_t sysid;
-    // FP64 layout
-    DevSys d;
-    DevSys* dsys[2];
+    // device control: E_0, history ring of the branchings, dead-population count
+    double* d_e0;
+    double* d_hist;
+    long long* d_nhist;
+    int* d_dead;
+    long long h_nhist;
+    int h_dead;
+    // descriptors per slot
     DevSys hsys[2];
-    // mixed layout
-    DevMix m;
-    DevMix* dmix[2];
+    DevSys* dsys[2];
     DevMix hmix[2];
-    float *state, *state_alt;
+    DevMix* dmix[2];
     bool need_build;
-    int parity;
     double e0;
-    std::vector<double> hist_lwb, hist_e;
+    std::vector<double> hist_lwb, hist_e, hist_e0, hist_mx, hist_nd;
     std::vector<double> btab_host;
     // adjoint pass: theta-dependent copies of the system arrays, outputs
     DevAdj ad;
     DevAdj* dadj;
-    double *R_t, *jas_t, *btab_t, *a_eL, *a_lp, *a_deL, *a_dlp, *a_out, *a_e0;
+    double *R_t, *jas_t, *btab_t, *a_eL, *a_lp, *a_deL, *a_dlp, *a_out;
     int* a_status;
     std::vector<double> h_R, h_Z, h_bexp, h_jas;
     std::vector<int32_t> h_batom;
@@ -279,12 +293,23 @@ struct SysRun {
     std::vector<uint16_t> cbf_host;
 };
 
-BranchView view_of(const SysRun& r)
+BranchView view_of(const SysRun& r, int slot, const int* jp)
 {
     BranchView v;
     v.nw = r.nw; v.N = r.N; v.sysid = r.sysid;
-    v.pos = r.pos; v.lw = r.lw; v.eL = r.eL; v.Wd = r.Wd;
+    v.pos = r.pos[slot]; v.lw = r.lw; v.eL = r.eL[slot]; v.Wd = r.Wd[slot];
+    v.jp = jp; v.e0p = r.d_e0;
     return v;
+}
+
+size_t handle_bytes(int n_sys)
+{
+    return align_up(kCntLen * 8) + align_up(8) + 2 * align_up((size_t)n_sys * sizeof(DevMix));
+}
+
+size_t control_bytes()
+{
+    return align_up(8) + align_up((size_t)kHistCap * kHistLen * 8) + align_up(8) + align_up(8);
 }
 
 }  // namespace
@@ -293,12 +318,242 @@ struct lrdmc_handle {
     std::vector<SysRun> sys;
     lrdmc_params prm;
     hipStream_t stream;
-    int j;
+    int j;                                  // host mirror of the branching index
+    int parity;                             // current walker slot
+    int* d_j;
     unsigned long long* counters;           // [kCntLen] device
-    unsigned long long cnt_init[kCntLen];   // host source of the counter reset
     hipEvent_t ev0, ev1;
     unsigned long long* timers = nullptr;   // instrumentation builds: [nw][8]
+    // one launch advances every mixed-precision system
+    std::vector<int> mix_order;             // system indices in launch order
+    DevMix* mix_tab[2];                     // device descriptor tables per slot
+    int mix_threads = kMixThreads;
+    size_t mix_lds = 0;
+    // captured step + reconfiguration per slot
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    std::vector<lrdmc_tune_entry> tune_log;
 };
+
+namespace {
+
+int upload_mix_tables(lrdmc_handle* h)
+{
+    const int n = (int)h->mix_order.size();
+    if (!n) return LRDMC_OK;
+    for (int p = 0; p < 2; ++p) {
+        std::vector<DevMix> t(n);
+        for (int k = 0; k < n; ++k) t[k] = h->sys[h->mix_order[k]].hmix[p];
+        HIPCHK(hipMemcpyAsync(h->mix_tab[p], t.data(), n * sizeof(DevMix), hipMemcpyHostToDevice,
+                              h->stream));
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return LRDMC_OK;
+}
+
+void drop_graphs(lrdmc_handle* h)
+{
+    for (int p = 0; p < 2; ++p)
+        if (h->gexec[p]) { (void)hipGraphExecDestroy(h->gexec[p]); h->gexec[p] = nullptr; }
+}
+
+// Termination bound of the conventional loop: 1000 times the mean number of
+// moves tau * 3N/a^2 (plus a floor).  Reaching it is counted and reported.
+int conv_cap(const lrdmc_params& p, int N)
+{
+    const double mean = p.tau * 3.0 * N / (p.a * p.a);
+    const double cap = 1000.0 * mean + 10000.0;
+    return cap > 2e9 ? 2000000000 : (int)cap;
+}
+
+PhaseArgs phase_args(const lrdmc_handle* h, int N, int nproj_override)
+{
+    PhaseArgs pa{};
+    pa.scheme = nproj_override >= 0 ? 0 : h->prm.scheme;
+    pa.nproj = nproj_override >= 0 ? nproj_override : h->prm.n_proj;
+    pa.refresh_every = h->prm.refresh_every;
+    pa.nu_mode = h->prm.nu_opt_mode;
+    pa.conv_cap = conv_cap(h->prm, N);
+    pa.a = h->prm.a;
+    pa.tau = h->prm.tau;
+    pa.seed = h->prm.seed;
+    pa.counters = h->counters;
+    pa.timers = h->timers;
+    return pa;
+}
+
+// One projection phase for every system on stream st with walkers in slot p.
+// nproj_override >= 0: a load-balanced phase of that many steps (0 = evaluate
+// only).  FP64 systems: one launch each; mixed systems: one launch for all.
+int launch_phases(lrdmc_handle* h, hipStream_t st, int p, int nproj_override, bool allow_build)
+{
+    int maxN = 1;
+    for (auto& r : h->sys) maxN = std::max(maxN, r.N);
+    for (auto& r : h->sys) {
+        if (r.kind != kKindLds) continue;
+        const PhaseArgs pa = phase_args(h, r.N, nproj_override);
+        hipLaunchKernelGGL(phase_fp64, dim3(r.nw), dim3(kWave), r.L.lds_bytes, st,
+                           (const DevSys*)r.dsys[p], pa);
+        HIPCHK(hipGetLastError());
+    }
+    const int n = (int)h->mix_order.size();
+    if (n) {
+        MixBatch b{};
+        b.tab = h->mix_tab[p];
+        b.nsys = n;
+        int tot = 0, build = 0;
+        for (int k = 0; k < n; ++k) {
+            SysRun& r = h->sys[h->mix_order[k]];
+            b.start[k] = tot;
+            tot += r.nw;
+            if (r.need_build) build = 1;
+        }
+        b.start[n] = tot;
+        if (build && !allow_build) return fail(LRDMC_ERR_INVALID_ARG, "rebuild pending in a capture");
+        const PhaseArgs pa = phase_args(h, maxN, nproj_override);
+        hipLaunchKernelGGL(phase_mixed, dim3(tot), dim3(h->mix_threads), h->mix_lds, st, b, pa, build);
+        HIPCHK(hipGetLastError());
+        for (int k = 0; k < n; ++k) h->sys[h->mix_order[k]].need_build = false;
+    }
+    return LRDMC_OK;
+}
+
+// Reconfiguration of every system on stream st, walkers in slot p gathered
+// into slot p ^ 1; device-side history and E_0 update; branching index + 1.
+int enqueue_branch(lrdmc_handle* h, hipStream_t st, int p)
+{
+    const int nsys = (int)h->sys.size();
+    for (int k = 0; k < nsys; ++k) {
+        SysRun& r = h->sys[k];
+        const int nw = r.nw;
+        const BranchView bv = view_of(r, p, h->d_j);
+        const int nt = std::min(kMaxBranchBlock, std::max(64, 1 << (int)std::ceil(std::log2((double)nw))));
+        hipLaunchKernelGGL(branch_scan, dim3(1), dim3(nt), 0, st, bv, h->prm.scheme, r.cum, r.bout,
+                           r.ndist);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(branch_comb, dim3((nw + 255) / 256), dim3(256), 0, st, bv, h->prm.seed,
+                           (const double*)r.cum, (const double*)r.bout, r.sel);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(branch_count, dim3((nw + 255) / 256), dim3(256), 0, st,
+                           (const int32_t*)r.sel, nw, r.ndist);
+        HIPCHK(hipGetLastError());
+        if (r.kind == kKindLds) {
+            const BranchView dn = view_of(r, p ^ 1, h->d_j);
+            const long tot = (long)nw * 3 * r.N;
+            hipLaunchKernelGGL(branch_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                               dn, (const int32_t*)r.sel, (const double*)r.pos[p],
+                               (const double*)r.eL[p], (const double*)r.Wd[p]);
+        } else {
+            hipLaunchKernelGGL(branch_gather_mixed, dim3(nw), dim3(256), 0, st,
+                               (const DevMix*)r.dmix[p ^ 1], (const int32_t*)r.sel,
+                               (const float*)r.state[p], (const double*)r.pos[p],
+                               (const double*)r.eL[p], (const double*)r.Wd[p]);
+        }
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(branch_finish, dim3(1), dim3(64), 0, st, nw, (const double*)r.bout,
+                           (const int*)r.ndist, r.d_hist, r.d_nhist, r.d_e0, r.d_dead,
+                           std::max(1, h->prm.e0_window), kHistCap, k == nsys - 1 ? h->d_j : nullptr);
+        HIPCHK(hipGetLastError());
+    }
+    return LRDMC_OK;
+}
+
+// Copy the branchings recorded on the device since the last drain into the
+// host history (synchronises).
+int drain(lrdmc_handle* h)
+{
+    HIPCHK(hipStreamSynchronize(h->stream));
+    int rc = LRDMC_OK;
+    for (auto& r : h->sys) {
+        long long n = 0;
+        int dead = 0;
+        HIPCHK(hipMemcpy(&n, r.d_nhist, 8, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(&dead, r.d_dead, 4, hipMemcpyDeviceToHost));
+        if (n - r.h_nhist > kHistCap) rc = fail(LRDMC_ERR_INVALID_ARG, "branching history overflow");
+        const long long q0 = std::max(r.h_nhist, n - kHistCap);
+        std::vector<double> buf((size_t)kHistCap * kHistLen);
+        for (long long q = q0; q < n;) {   // contiguous pieces of the ring
+            const long long at = q % kHistCap, cnt = std::min(n - q, (long long)kHistCap - at);
+            HIPCHK(hipMemcpy(buf.data() + at * kHistLen, r.d_hist + at * kHistLen,
+                             (size_t)cnt * kHistLen * 8, hipMemcpyDeviceToHost));
+            q += cnt;
+        }
+        for (long long q = q0; q < n; ++q) {
+            const double* e = buf.data() + (q % kHistCap) * kHistLen;
+            r.hist_lwb.push_back(e[kHistLogW]);
+            r.hist_e.push_back(e[kHistEbar]);
+            r.hist_e0.push_back(e[kHistE0]);
+            r.hist_mx.push_back(e[kHistMaxLw]);
+            r.hist_nd.push_back(e[kHistDistinct]);
+            r.e0 = e[kHistE0];
+        }
+        r.h_nhist = n;
+        if (dead > r.h_dead) {
+            r.h_dead = dead;
+            rc = fail(LRDMC_ERR_ALL_DEAD, "every walker weight is zero");
+        }
+    }
+    return rc;
+}
+
+int capture_graphs(lrdmc_handle* h)
+{
+    if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    for (int p = 0; p < 2; ++p) {
+        if (h->gexec[p]) continue;
+        hipGraph_t g;
+        HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        int rc = launch_phases(h, h->cap_stream, p, -1, false);
+        if (!rc) rc = enqueue_branch(h, h->cap_stream, p);
+        const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+        if (rc) { if (e == hipSuccess) (void)hipGraphDestroy(g); return rc; }
+        HIPCHK(e);
+        const hipError_t ei = hipGraphInstantiate(&h->gexec[p], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(ei);
+    }
+    return LRDMC_OK;
+}
+
+int reset_counters(lrdmc_handle* h, hipStream_t st)
+{
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, st, h->counters);
+    HIPCHK(hipGetLastError());
+    return LRDMC_OK;
+}
+
+int read_counters(lrdmc_handle* h, lrdmc_step_stats* st, float ms)
+{
+    unsigned long long cnt[kCntLen];
+    HIPCHK(hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    st->walker_iters = (int64_t)cnt[kCntIters];
+    st->max_iters = (int32_t)cnt[kCntMaxIters];
+    st->min_iters = (int32_t)cnt[kCntMinIters];
+    st->n_neg_weight = (int64_t)cnt[kCntNegW];
+    st->n_no_move = (int64_t)cnt[kCntNoMove];
+    st->n_refresh = (int64_t)cnt[kCntRefresh];
+    st->n_small_ratio = (int64_t)cnt[kCntSmallR];
+    st->n_capped = (int64_t)cnt[kCntCapped];
+    st->elapsed_ms = ms;
+    if (cnt[kCntSingular]) return fail(LRDMC_ERR_SINGULAR, "singular Slater matrix in a refresh");
+    return LRDMC_OK;
+}
+
+void fill_branch_stats(const lrdmc_handle* h, lrdmc_branch_stats* st, float ms)
+{
+    const SysRun& r = h->sys[0];
+    const size_t n = r.hist_e.size();
+    st->elapsed_ms = ms;
+    if (!n) { st->log_wbar = NAN; st->e_bar = NAN; st->e0 = r.e0; st->max_lw = NAN; st->n_distinct = 0; return; }
+    st->log_wbar = r.hist_lwb[n - 1];
+    st->e_bar = r.hist_e[n - 1];
+    st->e0 = r.hist_e0[n - 1];
+    st->max_lw = r.hist_mx[n - 1];
+    st->n_distinct = (int)r.hist_nd[n - 1];
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -308,67 +563,16 @@ size_t lrdmc_workspace_bytes(const lrdmc_system* sys, int n_sys, const lrdmc_par
 {
     const std::string v = validate(sys, n_sys, prm);
     if (!v.empty()) { g_err = v; return 0; }
-    size_t tot = align_up(kCntLen * 8);
+    size_t tot = handle_bytes(n_sys);
     for (int k = 0; k < n_sys; ++k) {
         const Layout L = make_layout(sys[k], *prm);
-        tot += L.b_sys + L.b_state + L.b_adj;
+        tot += L.b_sys + L.b_state + L.b_adj + control_bytes();
     }
     return tot;
 }
 
 static int run_derivs(lrdmc_handle* h, int isys, const double* theta, double* eL, double* lp,
                       double* deL, double* dlp);
-
-// Termination bound of the conventional loop: 1000 times the mean number of
-// moves tau * 3N/a^2 (plus a floor).  Reaching it is counted and reported.
-static int conv_cap(const lrdmc_params& p, int N)
-{
-    const double mean = p.tau * 3.0 * N / (p.a * p.a);
-    const double cap = 1000.0 * mean + 10000.0;
-    return cap > 2e9 ? 2000000000 : (int)cap;
-}
-
-static PhaseArgs phase_args(const lrdmc_handle* h, const SysRun& r, int nproj_override)
-{
-    PhaseArgs pa{};
-    pa.scheme = nproj_override >= 0 ? 0 : h->prm.scheme;
-    pa.nproj = nproj_override >= 0 ? nproj_override : h->prm.n_proj;
-    pa.j = h->j;
-    pa.refresh_every = h->prm.refresh_every;
-    pa.nu_mode = h->prm.nu_opt_mode;
-    pa.conv_cap = conv_cap(h->prm, r.N);
-    pa.a = h->prm.a;
-    pa.tau = h->prm.tau;
-    pa.E0 = r.e0;
-    pa.seed = h->prm.seed;
-    pa.counters = h->counters;
-    pa.timers = h->timers;
-    return pa;
-}
-
-// nproj_override >= 0: a load-balanced phase of that many steps (0 = evaluate only)
-static int launch_phase(lrdmc_handle* h, SysRun& r, int nproj_override)
-{
-    const PhaseArgs pa = phase_args(h, r, nproj_override);
-    if (r.kind == kKindLds) {
-        hipLaunchKernelGGL(phase_fp64, dim3(r.nw), dim3(kWave), r.L.lds_bytes, h->stream,
-                           (const DevSys*)r.dsys[r.parity], pa);
-    } else {
-        hipLaunchKernelGGL(phase_mixed, dim3(r.nw), dim3(kMixThreads), r.L.lds_bytes, h->stream,
-                           (const DevMix*)r.dmix[r.parity], pa, r.need_build ? 1 : 0);
-        r.need_build = false;
-    }
-    HIPCHK(hipGetLastError());
-    return LRDMC_OK;
-}
-
-static int reset_counters(lrdmc_handle* h)
-{
-    for (int k = 0; k < kCntLen; ++k) h->cnt_init[k] = (k == kCntMinIters) ? ~0ull : 0ull;
-    HIPCHK(hipMemcpyAsync(h->counters, h->cnt_init, sizeof(h->cnt_init), hipMemcpyHostToDevice,
-                          h->stream));
-    return LRDMC_OK;
-}
 
 int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* prm,
                       const double* init_pos, void* dev_workspace, size_t ws_bytes, void* stream,
@@ -393,19 +597,25 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
     h->prm = *prm;
     h->stream = (hipStream_t)stream;
     h->j = 0;
+    h->parity = 0;
     h->sys.reserve(n_sys);
     char* base = (char*)dev_workspace;
     size_t off = 0;
     auto carve = [&](size_t bytes) { void* p = base + off; off += align_up(bytes); return p; };
     h->counters = (unsigned long long*)carve(kCntLen * 8);
+    h->d_j = (int*)carve(8);
+    h->mix_tab[0] = (DevMix*)carve((size_t)n_sys * sizeof(DevMix));
+    h->mix_tab[1] = (DevMix*)carve((size_t)n_sys * sizeof(DevMix));
     hipError_t e1 = hipEventCreate(&h->ev0), e2 = hipEventCreate(&h->ev1);
     if (e1 != hipSuccess || e2 != hipSuccess) { delete h; return fail(LRDMC_ERR_HIP, "hipEventCreate"); }
 
     auto up = [&](void* dst, const void* src, size_t bytes) {
         return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream);
     };
+    const int zero4[2] = {0, 0};
+    const long long zero8 = 0;
+    int rc = up(h->d_j, zero4, 4) == hipSuccess ? LRDMC_OK : fail(LRDMC_ERR_HIP, "upload failed");
     const double* ip = init_pos;
-    int rc = LRDMC_OK;
     for (int k = 0; k < n_sys && rc == LRDMC_OK; ++k) {
         const lrdmc_system& s = sys[k];
         h->sys.emplace_back();
@@ -491,21 +701,30 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             }
         }
         const size_t nw = s.n_walkers;
-        r.pos = (double*)carve(nw * 3 * L.N * 8);
-        r.pos_alt = (double*)carve(nw * 3 * L.N * 8);
+        for (int p = 0; p < 2; ++p) {
+            r.pos[p] = (double*)carve(nw * 3 * L.N * 8);
+            r.eL[p] = (double*)carve(nw * 8);
+            r.Wd[p] = (double*)carve(nw * 8);
+            r.state[p] = nullptr;
+        }
         r.lw = (double*)carve(nw * 8);
-        r.eL = (double*)carve(nw * 8);
-        r.eL_alt = (double*)carve(nw * 8);
-        r.Wd = (double*)carve(nw * 8);
-        r.W_alt = (double*)carve(nw * 8);
         r.iters = (int32_t*)carve(nw * 4);
         r.sel = (int32_t*)carve(nw * 4);
         r.cum = (double*)carve(nw * 8);
         r.bout = (double*)carve(8 * 8);
         r.ndist = (int*)carve(8);
         r.trace = prm->trace_cap > 0 ? (int32_t*)carve(nw * (size_t)prm->trace_cap * 4) : nullptr;
-        r.parity = 0;
+        r.d_e0 = (double*)carve(8);
+        r.d_hist = (double*)carve((size_t)kHistCap * kHistLen * 8);
+        r.d_nhist = (long long*)carve(8);
+        r.d_dead = (int*)carve(8);
+        r.h_nhist = 0;
+        r.h_dead = 0;
         r.need_build = false;
+        if (up(r.d_nhist, &zero8, 8) || up(r.d_dead, zero4, 4)) {
+            rc = fail(LRDMC_ERR_HIP, "upload failed");
+            break;
+        }
         {   // adjoint pass buffers and descriptor
             const int nth = L.nth, nsp = s.n_species;
             r.R_t = (double*)carve(M * 3 * 8);
@@ -517,7 +736,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             r.a_dlp = (double*)carve(nw * (size_t)nth * 8);
             r.a_status = (int*)carve(8);
             r.a_out = (double*)carve((3 * (size_t)nth + 2) * 8);
-            r.a_e0 = (double*)carve(8);
+            (void)carve(8);
             r.dadj = (DevAdj*)carve(sizeof(DevAdj));
             r.h_R.assign(s.atom_pos, s.atom_pos + 3 * M);
             r.h_Z.assign(s.atom_charge, s.atom_charge + M);
@@ -530,7 +749,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             ad.a = prm->a; ad.vii = vii;
             ad.R = r.R_t; ad.Z = Z; ad.rc = rcs; ad.jas = r.jas_t; ad.btab = r.btab_t; ad.C = C;
             ad.core = core; ad.spec = spec; ad.batom = batom; ad.btype = btype;
-            ad.pos = r.pos;
+            ad.pos = r.pos[0];
             ad.eL = r.a_eL; ad.lp = r.a_lp; ad.deL = r.a_deL; ad.dlp = r.a_dlp;
             ad.status = r.a_status;
             ad.o_pos = L.a_pos; ad.o_phi = L.a_phi; ad.o_dphi = L.a_dphi; ad.o_phi6 = L.a_phi6;
@@ -543,13 +762,14 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             ad.lds_doubles = L.a_doubles;
         }
         if (r.kind == kKindLds) {
-            DevSys& d = r.d;
+            DevSys d{};
             d.M = M; d.Nb = Nb; d.Norb = s.n_orb; d.Nup = s.n_up; d.Ndn = s.n_dn;
             d.N = L.N; d.P = L.P; d.ns = ns; d.nspec = s.n_species; d.nw = r.nw;
             d.has_en = has_en; d.vii = vii; d.sysid = s.system_id;
+            d.jp = h->d_j; d.e0p = r.d_e0;
             d.R = R; d.Z = Z; d.rc = rcs; d.core = core; d.spec = spec; d.batom = batom;
             d.btype = btype; d.bexp = bexp; d.C = C; d.jas = jas; d.btab = btab;
-            d.pos = r.pos; d.lw = r.lw; d.eL = r.eL; d.Wd = r.Wd;
+            d.lw = r.lw;
             d.spill = (double*)carve(nw * L.spill_stride * 8);
             d.spill_stride = L.spill_stride;
             d.iters = r.iters; d.trace = r.trace; d.trace_cap = prm->trace_cap;
@@ -559,16 +779,17 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             d.o_B = L.o_B; d.o_rows = L.o_rows; d.o_tmp = L.o_tmp; d.o_C = L.o_C;
             d.lds_doubles = L.lds_doubles;
             d.s_Phi = L.s_Phi; d.s_dPhi = L.s_dPhi;
-            r.dsys[0] = (DevSys*)carve(sizeof(DevSys));
-            r.dsys[1] = (DevSys*)carve(sizeof(DevSys));
-            r.hsys[0] = d;
-            r.hsys[1] = d;
-            r.hsys[1].pos = r.pos_alt; r.hsys[1].eL = r.eL_alt; r.hsys[1].Wd = r.W_alt;
+            for (int p = 0; p < 2; ++p) {
+                r.dsys[p] = (DevSys*)carve(sizeof(DevSys));
+                r.hsys[p] = d;
+                r.hsys[p].pos = r.pos[p]; r.hsys[p].eL = r.eL[p]; r.hsys[p].Wd = r.Wd[p];
+            }
         } else {
-            DevMix& m = r.m;
+            DevMix m{};
             m.M = M; m.Nb = Nb; m.Norb = s.n_orb; m.Nup = s.n_up; m.Ndn = s.n_dn;
             m.N = L.N; m.P = L.P; m.ns = ns; m.nspec = s.n_species; m.nw = r.nw;
             m.has_en = has_en; m.vii = vii; m.sysid = s.system_id;
+            m.jp = h->d_j; m.e0p = r.d_e0;
             m.gemm = prm->precision == LRDMC_MIXED_BF16 ? kGemmBF16 : kGemmFP32;
             m.R = R; m.Z = Z; m.rc = rcs; m.jas = jas; m.btab = btab;
             m.core = core; m.spec = spec; m.btype = btype;
@@ -577,10 +798,9 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             m.s64 = (double*)carve(nw * L.stride64 * 8);
             m.stride64 = L.stride64;
             m.diag = (double*)carve(nw * 4 * 8);
-            m.pos = r.pos; m.lw = r.lw; m.eL = r.eL; m.Wd = r.Wd;
-            r.state = (float*)carve(nw * L.m_stride * 4);
-            r.state_alt = (float*)carve(nw * L.m_stride * 4);
-            m.state = r.state;
+            m.lw = r.lw;
+            r.state[0] = (float*)carve(nw * L.m_stride * 4);
+            r.state[1] = (float*)carve(nw * L.m_stride * 4);
             m.stride = L.m_stride;
             m.g_Phi = L.g_Phi; m.g_dPhi = L.g_dPhi; m.g_Arow = L.g_Arow; m.g_AinvT = L.g_AinvT;
             m.iters = r.iters; m.trace = r.trace; m.trace_cap = prm->trace_cap;
@@ -588,15 +808,17 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             m.l_red = L.l_red; m.l_U = L.l_U; m.l_R = L.l_R; m.l_Rdet = L.l_Rdet; m.l_dJ = L.l_dJ;
             m.l_gD = L.l_gD; m.l_Jg = L.l_Jg; m.l_Jl = L.l_Jl; m.l_dje = L.l_dje;
             m.l_rows = L.l_rows; m.l_tmp = L.l_tmp; m.l_F = L.l_F; m.l_bytes = L.l_bytes;
-            r.dmix[0] = (DevMix*)carve(sizeof(DevMix));
-            r.dmix[1] = (DevMix*)carve(sizeof(DevMix));
-            r.hmix[0] = m;
-            r.hmix[1] = m;
-            r.hmix[1].pos = r.pos_alt; r.hmix[1].eL = r.eL_alt; r.hmix[1].Wd = r.W_alt;
-            r.hmix[1].state = r.state_alt;
+            for (int p = 0; p < 2; ++p) {
+                r.dmix[p] = (DevMix*)carve(sizeof(DevMix));
+                r.hmix[p] = m;
+                r.hmix[p].pos = r.pos[p]; r.hmix[p].eL = r.eL[p]; r.hmix[p].Wd = r.Wd[p];
+                r.hmix[p].state = r.state[p];
+            }
             r.need_build = true;
+            h->mix_order.push_back(k);
+            h->mix_lds = std::max(h->mix_lds, L.lds_bytes);
         }
-        if (up(r.pos, ip, nw * 3 * L.N * 8) != hipSuccess ||
+        if (up(r.pos[0], ip, nw * 3 * L.N * 8) != hipSuccess ||
             hipMemsetAsync(r.lw, 0, nw * 8, h->stream) != hipSuccess) {
             rc = fail(LRDMC_ERR_HIP, "upload of walkers failed");
             break;
@@ -610,43 +832,45 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
     if (rc == LRDMC_OK && off > ws_bytes) rc = fail(LRDMC_ERR_WORKSPACE, "workspace layout overflow");
     for (auto& r : h->sys) {
         if (rc) break;
-        const bool bad = r.kind == kKindLds
-                             ? (up(r.dsys[0], &r.hsys[0], sizeof(DevSys)) ||
-                                up(r.dsys[1], &r.hsys[1], sizeof(DevSys)))
-                             : (up(r.dmix[0], &r.hmix[0], sizeof(DevMix)) ||
-                                up(r.dmix[1], &r.hmix[1], sizeof(DevMix)));
+        bool bad = false;
+        for (int p = 0; p < 2; ++p)
+            bad = bad || (r.kind == kKindLds ? up(r.dsys[p], &r.hsys[p], sizeof(DevSys))
+                                             : up(r.dmix[p], &r.hmix[p], sizeof(DevMix))) != hipSuccess;
         if (bad) rc = fail(LRDMC_ERR_HIP, "upload of system descriptors failed");
+    }
+    if (rc == LRDMC_OK && !h->mix_order.empty()) {
+        // larger systems first: their walkers take longest
+        std::stable_sort(h->mix_order.begin(), h->mix_order.end(), [&](int x, int y) {
+            return h->sys[x].N > h->sys[y].N;
+        });
+        rc = upload_mix_tables(h);
     }
     if (rc == LRDMC_OK) {
         // allow each phase kernel the LDS that its static allocation leaves free
-        for (auto& r : h->sys) {
-            const void* fn = r.kind == kKindLds ? (const void*)phase_fp64 : (const void*)phase_mixed;
+        for (int kind = 0; kind < 2 && !rc; ++kind) {
+            const void* fn = kind == kKindLds ? (const void*)phase_fp64 : (const void*)phase_mixed;
+            size_t need_lds = 0;
+            for (auto& r : h->sys) if (r.kind == kind) need_lds = std::max(need_lds, r.L.lds_bytes);
+            if (!need_lds) continue;
             hipFuncAttributes fa;
-            if (hipFuncGetAttributes(&fa, fn) != hipSuccess) {
-                rc = fail(LRDMC_ERR_HIP, "hipFuncGetAttributes failed");
-                break;
-            }
+            if (hipFuncGetAttributes(&fa, fn) != hipSuccess) { rc = fail(LRDMC_ERR_HIP, "hipFuncGetAttributes failed"); break; }
             const size_t dyn_max = (size_t)kMaxLdsBytes - fa.sharedSizeBytes;
-            if (r.L.lds_bytes > dyn_max) {
-                rc = fail(LRDMC_ERR_UNSUPPORTED, "system too large for the LDS of one workgroup");
-                break;
-            }
-            if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_max) !=
-                hipSuccess) {
+            if (need_lds > dyn_max) { rc = fail(LRDMC_ERR_UNSUPPORTED, "system too large for the LDS of one workgroup"); break; }
+            if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_max) != hipSuccess)
                 rc = fail(LRDMC_ERR_HIP, "hipFuncSetAttribute failed");
-                break;
-            }
         }
     }
     if (rc == LRDMC_OK) {
-        // initial local energies: a zero-step load-balanced phase
-        rc = reset_counters(h);
+        // initial local energies: a zero-step load-balanced phase (E_0 is not
+        // read by it); E_0 = their unweighted mean
+        for (auto& r : h->sys) r.e0 = 0.0;
+        for (auto& r : h->sys) if (!rc && up(r.d_e0, &r.e0, 8)) rc = fail(LRDMC_ERR_HIP, "upload failed");
+        if (!rc) rc = reset_counters(h, h->stream);
+        if (!rc) rc = launch_phases(h, h->stream, 0, 0, true);
         for (auto& r : h->sys) {
             if (rc) break;
-            r.e0 = 0.0;
-            if ((rc = launch_phase(h, r, 0))) break;
             std::vector<double> eL(r.nw);
-            if (hipMemcpyAsync(eL.data(), r.eL, r.nw * 8, hipMemcpyDeviceToHost, h->stream) ||
+            if (hipMemcpyAsync(eL.data(), r.eL[0], r.nw * 8, hipMemcpyDeviceToHost, h->stream) ||
                 hipStreamSynchronize(h->stream)) {
                 rc = fail(LRDMC_ERR_HIP, "init evaluation failed");
                 break;
@@ -655,6 +879,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             for (double x : eL) acc += x;
             r.e0 = acc / r.nw;
             if (!std::isfinite(r.e0)) rc = fail(LRDMC_ERR_SINGULAR, "non-finite initial local energy");
+            else if (up(r.d_e0, &r.e0, 8)) rc = fail(LRDMC_ERR_HIP, "upload failed");
         }
         unsigned long long cnt[kCntLen];
         if (!rc && (hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, h->stream) !=
@@ -689,28 +914,16 @@ int lrdmc_section_timers(lrdmc_handle* h, unsigned long long* out)
 int lrdmc_step(lrdmc_handle* h, lrdmc_step_stats* st)
 {
     if (!h) return fail(LRDMC_ERR_INVALID_ARG, "null handle");
-    int rc = reset_counters(h);
+    int rc = reset_counters(h, h->stream);
     if (rc) return rc;
     HIPCHK(hipEventRecord(h->ev0, h->stream));
-    for (auto& r : h->sys)
-        if ((rc = launch_phase(h, r, -1))) return rc;
+    if ((rc = launch_phases(h, h->stream, h->parity, -1, true))) return rc;
     HIPCHK(hipEventRecord(h->ev1, h->stream));
     if (st) {
-        unsigned long long cnt[kCntLen];
-        HIPCHK(hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-        st->walker_iters = (int64_t)cnt[kCntIters];
-        st->max_iters = (int32_t)cnt[kCntMaxIters];
-        st->min_iters = (int32_t)cnt[kCntMinIters];
-        st->n_neg_weight = (int64_t)cnt[kCntNegW];
-        st->n_no_move = (int64_t)cnt[kCntNoMove];
-        st->n_refresh = (int64_t)cnt[kCntRefresh];
-        st->n_small_ratio = (int64_t)cnt[kCntSmallR];
-        st->n_capped = (int64_t)cnt[kCntCapped];
-        st->elapsed_ms = ms;
-        if (cnt[kCntSingular]) return fail(LRDMC_ERR_SINGULAR, "singular Slater matrix in a refresh");
+        return read_counters(h, st, ms);
     }
     return LRDMC_OK;
 }
@@ -719,69 +932,152 @@ int lrdmc_branch(lrdmc_handle* h, lrdmc_branch_stats* st)
 {
     if (!h) return fail(LRDMC_ERR_INVALID_ARG, "null handle");
     HIPCHK(hipEventRecord(h->ev0, h->stream));
-    std::vector<std::vector<double>> outs(h->sys.size(), std::vector<double>(5));
-    std::vector<int> nd(h->sys.size());
-    for (size_t k = 0; k < h->sys.size(); ++k) {
-        SysRun& r = h->sys[k];
-        const int nw = r.nw;
-        const BranchView bv = view_of(r);
-        const int nt = std::min(kMaxBranchBlock, std::max(64, 1 << (int)std::ceil(std::log2((double)nw))));
-        hipLaunchKernelGGL(branch_scan, dim3(1), dim3(nt), 0, h->stream, bv, h->prm.scheme, r.e0,
-                           r.cum, r.bout);
-        HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(branch_comb, dim3((nw + 255) / 256), dim3(256), 0, h->stream, bv,
-                           h->prm.seed, h->j, r.cum, r.bout, r.sel);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemsetAsync(r.ndist, 0, sizeof(int), h->stream));
-        hipLaunchKernelGGL(branch_count, dim3((nw + 255) / 256), dim3(256), 0, h->stream, r.sel, nw,
-                           r.ndist);
-        HIPCHK(hipGetLastError());
-        // gather into the alternate buffers, then swap
-        if (r.kind == kKindLds) {
-            BranchView dn = bv;
-            dn.pos = r.pos_alt; dn.eL = r.eL_alt; dn.Wd = r.W_alt;
-            const long tot = (long)nw * 3 * r.N;
-            hipLaunchKernelGGL(branch_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                               h->stream, dn, r.sel, r.pos, r.eL, r.Wd);
-        } else {
-            hipLaunchKernelGGL(branch_gather_mixed, dim3(nw), dim3(256), 0, h->stream,
-                               (const DevMix*)r.dmix[r.parity ^ 1], r.sel, r.state, r.pos, r.eL,
-                               r.Wd);
-            std::swap(r.state, r.state_alt);
-        }
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(outs[k].data(), r.bout, 5 * 8, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipMemcpyAsync(&nd[k], r.ndist, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-        std::swap(r.pos, r.pos_alt);
-        std::swap(r.eL, r.eL_alt);
-        std::swap(r.Wd, r.W_alt);
-        r.parity ^= 1;
-    }
+    int rc = enqueue_branch(h, h->stream, h->parity);
+    if (rc) return rc;
     HIPCHK(hipEventRecord(h->ev1, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
+    h->parity ^= 1;
+    h->j++;
+    rc = drain(h);
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-    int rc = LRDMC_OK;
-    for (size_t k = 0; k < h->sys.size(); ++k) {
-        SysRun& r = h->sys[k];
-        const double mx = outs[k][0], tot = outs[k][1], se = outs[k][2], so = outs[k][3];
-        if (!(mx > -INFINITY) || !(tot > 0)) { rc = fail(LRDMC_ERR_ALL_DEAD, "every walker weight is zero"); continue; }
-        const double lwb = std::log(tot / r.nw) + mx;
-        const double eb = se / so;
-        r.hist_lwb.push_back(lwb);
-        r.hist_e.push_back(eb);
-        const int win = std::max(1, h->prm.e0_window);
-        const size_t n = r.hist_e.size(), k0 = n > (size_t)win ? n - win : 0;
-        double acc = 0.0;
-        for (size_t q = k0; q < n; ++q) acc += r.hist_e[q];
-        r.e0 = acc / (double)(n - k0);
-        if (st && k == 0) {
-            st->log_wbar = lwb; st->e_bar = eb; st->e0 = r.e0; st->max_lw = mx;
-            st->n_distinct = nd[k]; st->elapsed_ms = ms;
-        }
-    }
-    h->j++;
+    if (st) fill_branch_stats(h, st, ms);
     return rc;
+}
+
+int lrdmc_run(lrdmc_handle* h, int n_branchings, lrdmc_step_stats* st, lrdmc_branch_stats* bst)
+{
+    if (!h || n_branchings < 1) return fail(LRDMC_ERR_INVALID_ARG, "bad arguments");
+    bool pending = false;
+    for (auto& r : h->sys) pending = pending || r.need_build;
+    int rc = reset_counters(h, h->stream);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(h->ev0, h->stream));
+    int done = 0;
+    if (pending) {   // a rebuild of the orbital data is not part of the captured cycle
+        if ((rc = launch_phases(h, h->stream, h->parity, -1, true))) return rc;
+        if ((rc = enqueue_branch(h, h->stream, h->parity))) return rc;
+        h->parity ^= 1; h->j++; done = 1;
+    }
+    if (done < n_branchings && (rc = capture_graphs(h))) return rc;
+    for (; done < n_branchings; ++done) {
+        HIPCHK(hipGraphLaunch(h->gexec[h->parity], h->stream));
+        h->parity ^= 1;
+        h->j++;
+        if ((done + 1) % (kHistCap / 2) == 0 && (rc = drain(h))) return rc;
+    }
+    HIPCHK(hipEventRecord(h->ev1, h->stream));
+    rc = drain(h);
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    if (st) { const int rc2 = read_counters(h, st, ms); if (!rc) rc = rc2; }
+    if (bst) fill_branch_stats(h, bst, ms);
+    return rc;
+}
+
+// Autotuner of the mixed-precision launch: workgroup size (threads per
+// walker) x order of the systems in the launch, each candidate timed on a
+// copy of the current walkers (the other slot) for n_steps load-balanced
+// steps; the fastest is kept.  Stream-synchronous.
+int lrdmc_autotune(lrdmc_handle* h, int n_steps, lrdmc_tune_entry* log, int log_cap, int* n_log)
+{
+    if (!h || n_steps < 1) return fail(LRDMC_ERR_INVALID_ARG, "bad arguments");
+    if (n_log) *n_log = 0;
+    if (h->mix_order.empty()) return LRDMC_OK;
+    for (auto& r : h->sys)
+        if (r.need_build) return fail(LRDMC_ERR_INVALID_ARG, "run one phase before tuning");
+    const int p = h->parity, q = p ^ 1;
+    // candidate orders: largest systems first, smallest first
+    std::vector<int> big = h->mix_order, small;
+    std::stable_sort(big.begin(), big.end(), [&](int x, int y) { return h->sys[x].N > h->sys[y].N; });
+    small.assign(big.rbegin(), big.rend());
+    const std::vector<std::vector<int>> orders = big.size() > 1 ? std::vector<std::vector<int>>{big, small}
+                                                                : std::vector<std::vector<int>>{big};
+    const int threads[2] = {256, 128};
+    const std::vector<int> keep_order = h->mix_order;
+    const int keep_threads = h->mix_threads;
+    float best = 1e30f;
+    int best_t = keep_threads;
+    std::vector<int> best_o = keep_order;
+    h->tune_log.clear();
+    int rc = LRDMC_OK;
+    // the tuning phases update the log-weights in place: keep them
+    for (int k : h->mix_order) {
+        SysRun& r = h->sys[k];
+        HIPCHK(hipMemcpyAsync(r.cum, r.lw, (size_t)r.nw * 8, hipMemcpyDeviceToDevice, h->stream));
+    }
+    for (size_t oi = 0; oi < orders.size() && !rc; ++oi)
+        for (int ti = 0; ti < 2 && !rc; ++ti) {
+            h->mix_order = orders[oi];
+            h->mix_threads = threads[ti];
+            if ((rc = upload_mix_tables(h))) break;
+            float ms_best = 1e30f;
+            for (int rep = 0; rep < 2 && !rc; ++rep) {
+                for (int k : h->mix_order) {
+                    SysRun& r = h->sys[k];
+                    const size_t nw = r.nw;
+                    if (hipMemcpyAsync(r.pos[q], r.pos[p], nw * 3 * r.N * 8, hipMemcpyDeviceToDevice, h->stream) ||
+                        hipMemcpyAsync(r.state[q], r.state[p], nw * r.L.m_stride * 4, hipMemcpyDeviceToDevice, h->stream))
+                        rc = fail(LRDMC_ERR_HIP, "tuning copy failed");
+                }
+                if (rc) break;
+                HIPCHK(hipEventRecord(h->ev0, h->stream));
+                // mixed systems only, on the copies
+                MixBatch b{};
+                b.tab = h->mix_tab[q];
+                b.nsys = (int)h->mix_order.size();
+                int tot = 0, maxN = 1;
+                for (int k = 0; k < b.nsys; ++k) {
+                    b.start[k] = tot;
+                    tot += h->sys[h->mix_order[k]].nw;
+                    maxN = std::max(maxN, h->sys[h->mix_order[k]].N);
+                }
+                b.start[b.nsys] = tot;
+                const PhaseArgs pa = phase_args(h, maxN, n_steps);
+                hipLaunchKernelGGL(phase_mixed, dim3(tot), dim3(h->mix_threads), h->mix_lds,
+                                   h->stream, b, pa, 0);
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipEventRecord(h->ev1, h->stream));
+                HIPCHK(hipStreamSynchronize(h->stream));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+                ms_best = std::min(ms_best, ms);
+            }
+            if (rc) break;
+            lrdmc_tune_entry e;
+            e.threads = h->mix_threads;
+            e.order_big_first = (oi == 0) ? 1 : 0;
+            e.ms = ms_best;
+            h->tune_log.push_back(e);
+            if (ms_best < best) { best = ms_best; best_t = h->mix_threads; best_o = h->mix_order; }
+        }
+    for (int k : keep_order) {
+        SysRun& r = h->sys[k];
+        if (hipMemcpyAsync(r.lw, r.cum, (size_t)r.nw * 8, hipMemcpyDeviceToDevice, h->stream) && !rc)
+            rc = fail(LRDMC_ERR_HIP, "restoring the log-weights failed");
+    }
+    h->mix_order = rc ? keep_order : best_o;
+    h->mix_threads = rc ? keep_threads : best_t;
+    const int rc2 = upload_mix_tables(h);
+    drop_graphs(h);
+    (void)reset_counters(h, h->stream);
+    if (log && n_log) {
+        const int n = std::min(log_cap, (int)h->tune_log.size());
+        for (int k = 0; k < n; ++k) log[k] = h->tune_log[k];
+        *n_log = n;
+    }
+    return rc ? rc : rc2;
+}
+
+int lrdmc_set_launch(lrdmc_handle* h, int threads, int order_big_first)
+{
+    if (!h || (threads != 128 && threads != 256))
+        return fail(LRDMC_ERR_INVALID_ARG, "threads must be 128 or 256");
+    std::stable_sort(h->mix_order.begin(), h->mix_order.end(), [&](int x, int y) {
+        return order_big_first ? h->sys[x].N > h->sys[y].N : h->sys[x].N < h->sys[y].N;
+    });
+    h->mix_threads = threads;
+    drop_graphs(h);
+    return upload_mix_tables(h);
 }
 
 int lrdmc_energy_forces(lrdmc_handle* h, lrdmc_energy* e, double* forces, double* jgrad)
@@ -794,11 +1090,11 @@ int lrdmc_energy_forces(lrdmc_handle* h, lrdmc_energy* e, double* forces, double
         int rc = run_derivs(h, 0, nullptr, nullptr, nullptr, nullptr, nullptr);
         if (rc) return rc;
         const int nth = r.L.nth, M = r.ad.M;
-        HIPCHK(hipMemcpyAsync(r.a_e0, &r.e0, 8, hipMemcpyHostToDevice, h->stream));
         hipLaunchKernelGGL(derivs_reduce, dim3(3 * nth + 2), dim3(256), 0, h->stream, r.nw, nth,
                            h->prm.scheme == LRDMC_SCHEME_LB ? 0 : 1, (const double*)r.lw,
-                           (const double*)r.Wd, (const double*)r.a_e0, (const double*)r.a_eL,
-                           (const double*)r.a_deL, (const double*)r.a_dlp, r.a_out);
+                           (const double*)r.Wd[h->parity], (const double*)r.d_e0,
+                           (const double*)r.a_eL, (const double*)r.a_deL, (const double*)r.a_dlp,
+                           r.a_out);
         HIPCHK(hipGetLastError());
         std::vector<double> o(3 * (size_t)nth + 2);
         HIPCHK(hipMemcpyAsync(o.data(), r.a_out, o.size() * 8, hipMemcpyDeviceToHost, h->stream));
@@ -873,10 +1169,10 @@ static int run_derivs(lrdmc_handle* h, int isys, const double* theta, double* eL
     const int M = r.ad.M, Nb = r.ad.Nb, nj = 3 * (2 + r.ad.nspec);
     std::vector<double> R(r.h_R), jas(r.h_jas);
     if (theta) {
-        for (int q = 0; q < 3 * M; ++q) R[q] = theta[q];
-        for (int q = 0; q < nj; ++q) jas[q] = theta[3 * M + q];
         for (int q = 0; q < 3 * M + nj; ++q)
             if (!std::isfinite(theta[q])) return fail(LRDMC_ERR_INVALID_ARG, "non-finite theta");
+        for (int q = 0; q < 3 * M; ++q) R[q] = theta[q];
+        for (int q = 0; q < nj; ++q) jas[q] = theta[3 * M + q];
     }
     std::vector<double> btab((size_t)Nb * 4);
     for (int mu = 0; mu < Nb; ++mu) {
@@ -892,7 +1188,7 @@ static int run_derivs(lrdmc_handle* h, int isys, const double* theta, double* eL
         }
     DevAdj ad = r.ad;
     ad.vii = vii;
-    ad.pos = r.pos;
+    ad.pos = r.pos[h->parity];
     if (eL) ad.eL = eL;
     if (lp) ad.lp = lp;
     if (deL) ad.deL = deL;
@@ -924,12 +1220,13 @@ int lrdmc_get_walkers(lrdmc_handle* h, int isys, double* pos, double* lw, double
 {
     if (!h || isys < 0 || isys >= (int)h->sys.size()) return fail(LRDMC_ERR_INVALID_ARG, "bad handle/system");
     const SysRun& r = h->sys[isys];
+    const int p = h->parity;
     const size_t nw = r.nw;
     auto dn = [&](void* dst, const void* src, size_t b) {
         return dst ? hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToHost, h->stream) : hipSuccess;
     };
-    if (dn(pos, r.pos, nw * 3 * r.N * 8) || dn(lw, r.lw, nw * 8) || dn(eL, r.eL, nw * 8) ||
-        dn(W, r.Wd, nw * 8) || dn(iters, r.iters, nw * 4) || dn(sel, r.sel, nw * 4))
+    if (dn(pos, r.pos[p], nw * 3 * r.N * 8) || dn(lw, r.lw, nw * 8) || dn(eL, r.eL[p], nw * 8) ||
+        dn(W, r.Wd[p], nw * 8) || dn(iters, r.iters, nw * 4) || dn(sel, r.sel, nw * 4))
         return fail(LRDMC_ERR_HIP, "device-to-host copy failed");
     if (trace) {
         if (!r.trace) return fail(LRDMC_ERR_INVALID_ARG, "tracing is off (trace_cap = 0)");
@@ -947,7 +1244,7 @@ int lrdmc_get_precision_report(lrdmc_handle* h, int isys, double* out)
     const SysRun& r = h->sys[isys];
     if (r.kind != kKindMixed)
         return fail(LRDMC_ERR_INVALID_ARG, "the FP64 walker layout has no precision report");
-    HIPCHK(hipMemcpyAsync(out, r.m.diag, (size_t)r.nw * 4 * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(out, r.hmix[0].diag, (size_t)r.nw * 4 * 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return LRDMC_OK;
 }
@@ -958,7 +1255,7 @@ int lrdmc_set_walkers(lrdmc_handle* h, int isys, const double* pos, const double
         return fail(LRDMC_ERR_INVALID_ARG, "bad arguments");
     SysRun& r = h->sys[isys];
     const size_t nw = r.nw;
-    HIPCHK(hipMemcpyAsync(r.pos, pos, nw * 3 * r.N * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(r.pos[h->parity], pos, nw * 3 * r.N * 8, hipMemcpyHostToDevice, h->stream));
     if (lw) HIPCHK(hipMemcpyAsync(r.lw, lw, nw * 8, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     r.need_build = r.kind == kKindMixed;   // mixed layout: orbital data follow the positions
@@ -974,7 +1271,10 @@ double lrdmc_get_e0(lrdmc_handle* h, int isys)
 int lrdmc_set_e0(lrdmc_handle* h, int isys, double e0)
 {
     if (!h || isys < 0 || isys >= (int)h->sys.size()) return fail(LRDMC_ERR_INVALID_ARG, "bad handle/system");
-    h->sys[isys].e0 = e0;
+    SysRun& r = h->sys[isys];
+    r.e0 = e0;
+    HIPCHK(hipMemcpyAsync(r.d_e0, &r.e0, 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
     return LRDMC_OK;
 }
 
@@ -983,6 +1283,9 @@ int lrdmc_get_branch_index(lrdmc_handle* h) { return h ? h->j : -1; }
 void lrdmc_destroy(lrdmc_handle* h)
 {
     if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     (void)hipEventDestroy(h->ev0);
     (void)hipEventDestroy(h->ev1);
     delete h;

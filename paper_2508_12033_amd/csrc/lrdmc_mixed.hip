@@ -36,26 +36,30 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------------------
-// block collectives (4 wavefronts); red is a 4-double LDS scratch
+// block collectives (2 or 4 wavefronts); red is a 4-double LDS scratch
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double block_sum(double v, double* red)
 {
     v = wave_sum(v);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, nwv = blockDim.x >> 6;
     __syncthreads();
     if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
-    return (red[0] + red[1]) + (red[2] + red[3]);
+    double t = red[0];
+    for (int q = 1; q < nwv; ++q) t += red[q];
+    return t;
 }
 
 __device__ __forceinline__ double block_max(double v, double* red)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, nwv = blockDim.x >> 6;
     __syncthreads();
     if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
-    return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    double t = red[0];
+    for (int q = 1; q < nwv; ++q) t = fmax(t, red[q]);
+    return t;
 }
 
 // exclusive prefix of v over the block (thread order) and the block total
@@ -70,7 +74,8 @@ __device__ __forceinline__ double block_excl_scan(double v, double* red, double&
     __syncthreads();
     double off = 0.0;
     for (int q = 0; q < wv; ++q) off += red[q];
-    total = ((red[0] + red[1]) + red[2]) + red[3];
+    total = red[0];
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) total += red[q];
     return off + prev;
 }
 
@@ -138,7 +143,7 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
     float* B = LDSF(s.l_U);                      // [11][nb32] basis rows (zero padded)
     float* rows = LDSF(s.l_rows);
     const int ldb = s.nb32;
-    for (int it = tid; it < items; it += kMixThreads) {
+    for (int it = tid; it < items; it += (int)blockDim.x) {
         const int q = it / Nb, mu = it - q * Nb;
         double p[3];
         point_q(r, q, a, p);
@@ -183,7 +188,7 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
     const int n = mnspin(s, mspin(s, j));
     const int tiles = (n + 15) / 16;
     const int i16 = lane & 15, k4 = lane >> 4;
-    for (int t = wv; t < tiles; t += kMixThreads / kWave) {
+    for (int t = wv; t < tiles; t += (int)(blockDim.x >> 6)) {
         float4_t acc = {0.f, 0.f, 0.f, 0.f};
         const int col = 16 * t + i16;
         if (s.gemm == kGemmBF16) {
@@ -235,7 +240,7 @@ __device__ __noinline__ void mixed_store_rows(const DevMix* __restrict__ dm, flo
     const float* rows = LDSF(s.l_rows);
     float* Phi = st + s.g_Phi + (long)sp * ns * 6 * ns;
     float* dPhi = st + s.g_dPhi + (long)sp * ns * 4 * ns;
-    for (int idx = tid; idx < 11 * n; idx += kMixThreads) {
+    for (int idx = tid; idx < 11 * n; idx += (int)blockDim.x) {
         const int row = idx / n, k = idx - row * n;
         const float v = rows[row * ns + k];
         if (row == 0) { if (arow) st[s.g_Arow + (long)j * ns + k] = v; }
@@ -260,7 +265,7 @@ __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
     double* M = LDSD(s.l_U);                     // [n][n]
     double* sc = LDSD(s.l_scal);
     int* piv = reinterpret_cast<int*>(LDSF(s.l_tmp));
-    for (int idx = tid; idx < n * n; idx += kMixThreads) {
+    for (int idx = tid; idx < n * n; idx += (int)blockDim.x) {
         const int r = idx / n, c = idx - r * n;
         M[idx] = (double)Arow[(long)(off + c) * ns + r];
     }
@@ -277,7 +282,7 @@ __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
         if (!(best > 0.0)) { ok = false; break; }
         if (tid == 0) piv[k] = bi;
         if (bi != k) {
-            for (int c = tid; c < n; c += kMixThreads) {
+            for (int c = tid; c < n; c += (int)blockDim.x) {
                 const double t = M[k * n + c];
                 M[k * n + c] = M[bi * n + c];
                 M[bi * n + c] = t;
@@ -292,11 +297,11 @@ __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
         __syncthreads();
         // row k scaled; column k of the other rows stored before elimination
         double* colk = LDSD(s.l_U) + n * n;          // [n]
-        for (int r = tid; r < n; r += kMixThreads) colk[r] = M[r * n + k];
+        for (int r = tid; r < n; r += (int)blockDim.x) colk[r] = M[r * n + k];
         __syncthreads();
-        for (int c = tid; c < n; c += kMixThreads) M[k * n + c] = (c == k ? 1.0 : M[k * n + c]) * id;
+        for (int c = tid; c < n; c += (int)blockDim.x) M[k * n + c] = (c == k ? 1.0 : M[k * n + c]) * id;
         __syncthreads();
-        for (int idx = tid; idx < n * n; idx += kMixThreads) {
+        for (int idx = tid; idx < n * n; idx += (int)blockDim.x) {
             const int r = idx / n, c = idx - r * n;
             if (r == k) continue;
             const double f = colk[r];
@@ -309,14 +314,14 @@ __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
         for (int k = n - 1; k >= 0; --k) {
             const int p = piv[k];
             if (p != k)
-                for (int r = tid; r < n; r += kMixThreads) {
+                for (int r = tid; r < n; r += (int)blockDim.x) {
                     const double t = M[r * n + k];
                     M[r * n + k] = M[r * n + p];
                     M[r * n + p] = t;
                 }
             __syncthreads();
         }
-        for (int idx = tid; idx < n * n; idx += kMixThreads) {
+        for (int idx = tid; idx < n * n; idx += (int)blockDim.x) {
             const int c = idx / n, k = idx - c * n;
             AiT[(long)c * ns + k] = (TD)M[idx];
         }
@@ -345,7 +350,7 @@ __device__ __noinline__ void mixed_gD(const DevMix* __restrict__ dm, const float
         const int n = mnspin(s, spin), off = spin ? s.Nup : 0;
         const float* dPhi = st + s.g_dPhi + (long)spin * ns * 4 * ns;
         const float* Ai = st + s.g_AinvT + (long)spin * ns * ns;
-        for (int it = tid; it < 4 * n; it += kMixThreads) {
+        for (int it = tid; it < 4 * n; it += (int)blockDim.x) {
             const int c = it >> 2;
             float acc = 0.f;
             for (int k = 0; k < n; ++k) acc += dPhi[(long)k * 4 * ns + it] * Ai[(long)c * ns + k];
@@ -368,7 +373,7 @@ __device__ __noinline__ void mixed_ratios(const DevMix* __restrict__ dm, const f
         const int n = mnspin(s, spin), off = spin ? s.Nup : 0;
         const float* Phi = st + s.g_Phi + (long)spin * ns * 6 * ns;
         const float* Ai = st + s.g_AinvT + (long)spin * ns * ns;
-        for (int q = tid; q < 6 * n; q += kMixThreads) {
+        for (int q = tid; q < 6 * n; q += (int)blockDim.x) {
             const int c = q / 6;
             float acc = 0.f;
             for (int k = 0; k < n; ++k) acc += Phi[(long)k * 6 * ns + q] * Ai[(long)c * ns + k];
@@ -376,7 +381,7 @@ __device__ __noinline__ void mixed_ratios(const DevMix* __restrict__ dm, const f
         }
     }
     __syncthreads();
-    for (int p = tid; p < s.P; p += kMixThreads) R[p] = Rdet[p] * expf(dJ[p]);
+    for (int p = tid; p < s.P; p += (int)blockDim.x) R[p] = Rdet[p] * expf(dJ[p]);
     __syncthreads();
 }
 
@@ -393,7 +398,7 @@ __device__ __noinline__ double mixed_jastrow_all(const DevMix* __restrict__ dm, 
     double* nua = LDSD(s.l_nua);
     float* S = LDSF(s.l_U);                       // [N][7]
     const int K = s.N + s.M, Kj = s.has_en ? K : s.N;
-    for (int it = tid; it < 7 * s.N; it += kMixThreads) {
+    for (int it = tid; it < 7 * s.N; it += (int)blockDim.x) {
         const int j = it / 7, q = it - 7 * j;
         double pq[3];
         point_q(pos + 3 * j, q, a, pq);
@@ -409,7 +414,7 @@ __device__ __noinline__ double mixed_jastrow_all(const DevMix* __restrict__ dm, 
         S[it] = acc;
     }
     double vee = 0.0;
-    for (int j = tid; j < s.N; j += kMixThreads) {
+    for (int j = tid; j < s.N; j += (int)blockDim.x) {
         const double* rj = pos + 3 * j;
         float g0 = 0.f, g1 = 0.f, g2 = 0.f, l = 0.f;
         double nu = 0.0, nv = 0.0;
@@ -439,7 +444,7 @@ __device__ __noinline__ double mixed_jastrow_all(const DevMix* __restrict__ dm, 
         nue[j] = nu; nua[j] = nv;
     }
     vee = block_sum(vee, LDSD(s.l_red));
-    for (int p = tid; p < s.P; p += kMixThreads) {
+    for (int p = tid; p < s.P; p += (int)blockDim.x) {
         const int j = p / 6, q = p - 6 * j;
         dJ[p] = S[7 * j + q + 1] - S[7 * j];
     }
@@ -476,7 +481,7 @@ __device__ __noinline__ MLocal mixed_evaluate(const DevMix* __restrict__ dm, dou
     double* red = LDSD(s.l_red);
     double bs = 0.0;
     int anyneg = 0;
-    for (int p = tid; p < s.P; p += kMixThreads) {
+    for (int p = tid; p < s.P; p += (int)blockDim.x) {
         const double r = (double)R[p];
         if (r > 0) bs += r;
         else if (r < 0) anyneg = 1;
@@ -485,7 +490,7 @@ __device__ __noinline__ MLocal mixed_evaluate(const DevMix* __restrict__ dm, dou
     bs = block_sum(bs, red);
     double econt = 0.0, dnu = 0.0;
     const double ia2 = 1.0 / (a * a);
-    for (int j = tid; j < s.N; j += kMixThreads) {
+    for (int j = tid; j < s.N; j += (int)blockDim.x) {
         const double j0 = Jg[3 * j], j1 = Jg[3 * j + 1], j2 = Jg[3 * j + 2];
         const double lap = (double)gD[4 * j + 3] +
                            2.0 * ((double)gD[4 * j] * j0 + (double)gD[4 * j + 1] * j1 +
@@ -529,12 +534,12 @@ __device__ void orb_rows64(const DevMix& s, int i, int nrows, double a, double* 
     const int n = mnspin(s, mspin(s, i));
     double* rb = LDSD(s.l_U);                    // [11][kMixChunk]
     const double* pos = LDSD(s.l_pos);
-    const int items = nrows * n;                 // <= 11 * 64 < 3 * kMixThreads
+    const int items = nrows * n;                 // <= 11 * 64 < 6 * 128
     const int npts = nrows == 1 ? 1 : 7;
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int m0 = 0; m0 < Nb; m0 += kMixChunk) {
         const int cnt = min(kMixChunk, Nb - m0);
-        for (int it = tid; it < npts * kMixChunk; it += kMixThreads) {
+        for (int it = tid; it < npts * kMixChunk; it += (int)blockDim.x) {
             const int q = it / kMixChunk, m = it - q * kMixChunk, mu = m0 + m;
             if (m >= cnt) continue;
             double p[3];
@@ -557,8 +562,8 @@ __device__ void orb_rows64(const DevMix& s, int i, int nrows, double a, double* 
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const int it = tid + r * kMixThreads;
+        for (int r = 0; r < 6; ++r) {
+            const int it = tid + r * (int)blockDim.x;
             if (it < items) {
                 const int row = it / n, k = it - row * n;
                 double sacc = 0.0;
@@ -570,8 +575,8 @@ __device__ void orb_rows64(const DevMix& s, int i, int nrows, double a, double* 
         __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        const int it = tid + r * kMixThreads;
+    for (int r = 0; r < 6; ++r) {
+        const int it = tid + r * (int)blockDim.x;
         if (it < items) {
             const int row = it / n, k = it - row * n;
             out[row * ns + k] = acc[r];
@@ -580,12 +585,12 @@ __device__ void orb_rows64(const DevMix& s, int i, int nrows, double a, double* 
     __syncthreads();
 }
 
-__device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, double a, int nu_mode,
-                                                bool& ok)
+__device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, int wid, double a,
+                                                int nu_mode, bool& ok)
 {
     const DevMix& s = *dm;
     const int tid = threadIdx.x, ns = s.ns, N = s.N, P = s.P;
-    double* g64 = s.s64 + (long)blockIdx.x * s.stride64;
+    double* g64 = s.s64 + (long)wid * s.stride64;
     double* A64 = g64;                           // [N][ns]    Slater rows
     double* Ai64 = g64 + (long)N * ns;           // [2][ns][ns] transposed inverses
     const double* pos = LDSD(s.l_pos);
@@ -603,7 +608,7 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, d
     for (int i = 0; i < N; ++i) {
         orb_rows64(s, i, 1, a, rows);
         const int n = mnspin(s, mspin(s, i));
-        for (int k = tid; k < n; k += kMixThreads) A64[(long)i * ns + k] = rows[k];
+        for (int k = tid; k < n; k += (int)blockDim.x) A64[(long)i * ns + k] = rows[k];
         __threadfence_block();
         __syncthreads();
     }
@@ -627,7 +632,7 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, d
     // potentials and V_ee
     double* S = LDSD(s.l_U);                     // [N][7]
     const int K = N + s.M, Kj = s.has_en ? K : N;
-    for (int it = tid; it < 7 * N; it += kMixThreads) {
+    for (int it = tid; it < 7 * N; it += (int)blockDim.x) {
         const int j = it / 7, q = it - 7 * j;
         double pq[3];
         point_q(pos + 3 * j, q, a, pq);
@@ -643,7 +648,7 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, d
         S[it] = acc;
     }
     double vee = 0.0;
-    for (int j = tid; j < N; j += kMixThreads) {
+    for (int j = tid; j < N; j += (int)blockDim.x) {
         const double* rj = pos + 3 * j;
         double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0, nu = 0.0, nv = 0.0;
         #pragma unroll 1
@@ -672,7 +677,7 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, d
         nue[j] = nu; nua[j] = nv;
     }
     vee = block_sum(vee, red);
-    for (int p = tid; p < P; p += kMixThreads) {
+    for (int p = tid; p < P; p += (int)blockDim.x) {
         const int j = p / 6, q = p - 6 * j;
         dJ64[p] = S[7 * j + q + 1] - S[7 * j];
     }
@@ -680,7 +685,7 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, d
     // ratios, lattice diagonal, local energy (App. D), as in the FP64 kernel
     double bs = 0.0;
     int anyneg = 0;
-    for (int p = tid; p < P; p += kMixThreads) {
+    for (int p = tid; p < P; p += (int)blockDim.x) {
         const double r = R64[p] * exp(dJ64[p]);
         R64[p] = r;
         if (r > 0) bs += r;
@@ -690,7 +695,7 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, d
     bs = block_sum(bs, red);
     double econt = 0.0, dnu = 0.0;
     const double ia2 = 1.0 / (a * a);
-    for (int j = tid; j < N; j += kMixThreads) {
+    for (int j = tid; j < N; j += (int)blockDim.x) {
         const double j0 = Jg64[3 * j], j1 = Jg64[3 * j + 1], j2 = Jg64[3 * j + 2];
         const double lap = gD64[4 * j + 3] +
                            2.0 * (gD64[4 * j] * j0 + gD64[4 * j + 1] * j1 + gD64[4 * j + 2] * j2) +
@@ -727,7 +732,7 @@ __device__ __noinline__ int mixed_heat_bath(const DevMix* __restrict__ dm, doubl
     const float* R = LDSF(s.l_R);
     double* red = LDSD(s.l_red);
     int* pick = reinterpret_cast<int*>(LDSD(s.l_red) + 4);
-    const int per = (s.P + kMixThreads - 1) / kMixThreads;
+    const int per = (s.P + (int)blockDim.x - 1) / (int)blockDim.x;
     const int p0 = tid * per, p1 = min(p0 + per, s.P);
     double loc = 0.0;
     for (int p = p0; p < p1; ++p) {
@@ -780,24 +785,24 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
     float* rowc = tmp + ns;       // [ns] column c of the inverse
     float* beta = tmp + 2 * ns;   // [ns]
     const int q = 6 * c + (p - 6 * i);
-    for (int k = tid; k < n; k += kMixThreads) {
+    for (int k = tid; k < n; k += (int)blockDim.x) {
         u[k] = Phi[(long)k * 6 * ns + q];
         rowc[k] = Ai[(long)c * ns + k];
     }
     __syncthreads();
-    for (int cc = tid; cc < n; cc += kMixThreads) {
+    for (int cc = tid; cc < n; cc += (int)blockDim.x) {
         float acc = 0.f;
         for (int k = 0; k < n; ++k) acc += u[k] * Ai[(long)cc * ns + k];
         beta[cc] = acc;
     }
     __syncthreads();
     const float iR = 1.0f / Rd;
-    for (int idx = tid; idx < n * n; idx += kMixThreads) {
+    for (int idx = tid; idx < n * n; idx += (int)blockDim.x) {
         const int cc = idx / n, k = idx - cc * n;
         if (cc == c) Ai[(long)cc * ns + k] = rowc[k] * iR;
         else Ai[(long)cc * ns + k] -= rowc[k] * (beta[cc] * iR);
     }
-    for (int k = tid; k < n; k += kMixThreads) st[s.g_Arow + (long)i * ns + k] = u[k];
+    for (int k = tid; k < n; k += (int)blockDim.x) st[s.g_Arow + (long)i * ns + k] = u[k];
     if (tid == 0) {
         double* sc = LDSD(s.l_scal);
         sc[kScLogdet0 + sp] += log(fabs((double)Rd));
@@ -826,7 +831,7 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
         point_q(rnew, qq, a, pq);
         double acc = 0.0;
         #pragma unroll 1
-        for (int k = tid; k < Kj; k += kMixThreads) {
+        for (int k = tid; k < Kj; k += (int)blockDim.x) {
             if (k == i) continue;
             double pk[3];
             int jr;
@@ -840,7 +845,7 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
     }
     double g0 = 0, g1 = 0, g2 = 0, l = 0, dvee = 0, nu = 0, nua = 0;
     #pragma unroll 1
-    for (int k = tid; k < K; k += kMixThreads) {
+    for (int k = tid; k < K; k += (int)blockDim.x) {
         if (k == i) continue;
         const bool isel = k < s.N;
         double pk[3];
@@ -877,7 +882,7 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
     l = block_sum(l, red); dvee = block_sum(dvee, red);
     nu = block_sum(nu, red); nua = block_sum(nua, red);
     // Jastrow exponent changes of the other electrons' moves
-    for (int qp = tid; qp < s.P; qp += kMixThreads) {
+    for (int qp = tid; qp < s.P; qp += (int)blockDim.x) {
         const int j = qp / 6;
         if (j == i) continue;
         const int dd = (qp / 2) % 3, s2 = qp % 2;
@@ -903,22 +908,27 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
 }
 
 // ---------------------------------------------------------------------------
-// the phase kernel: one 256-thread workgroup per walker.  build != 0 first
-// evaluates every electron's orbital rows from its position.
+// the phase kernel: one workgroup (128 or 256 threads) per walker, the walkers
+// of every system of the batch in one launch (workgroups of system k are
+// start[k] .. start[k+1]-1).  build != 0 first evaluates every electron's
+// orbital rows from its position.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kMixThreads) void phase_mixed(const DevMix* __restrict__ sys,
-                                                           PhaseArgs pa, int build)
+__global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs pa, int build)
 {
-    const DevMix& s = *sys;
-    const int wid = blockIdx.x;
+    int k = 0;
+    while (k + 1 < b.nsys && (int)blockIdx.x >= b.start[k + 1]) ++k;
+    const DevMix& s = b.tab[k];
+    const int wid = (int)blockIdx.x - b.start[k];
     if (wid >= s.nw) return;
+    const int jb = *s.jp;
+    const double E0 = *s.e0p;
     const int tid = threadIdx.x;
     float* st = s.state + (long)wid * s.stride;
     double* pos = LDSD(s.l_pos);
-    for (int q = tid; q < 3 * s.N; q += kMixThreads) pos[q] = s.pos[(long)wid * 3 * s.N + q];
+    for (int q = tid; q < 3 * s.N; q += (int)blockDim.x) pos[q] = s.pos[(long)wid * 3 * s.N + q];
     {
         float* B = LDSF(s.l_U);   // zero the padding of the basis rows once
-        for (int q = tid; q < 11 * s.nb32; q += kMixThreads) B[q] = 0.0f;
+        for (int q = tid; q < 11 * s.nb32; q += (int)blockDim.x) B[q] = 0.0f;
     }
     __syncthreads();
     const double a = pa.a;
@@ -935,7 +945,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(const DevMix* __restr
     // the Gauss-Jordan scratch overlaps the basis rows: restore their padding
     {
         float* B = LDSF(s.l_U);
-        for (int q = tid; q < 11 * s.nb32; q += kMixThreads) B[q] = 0.0f;
+        for (int q = tid; q < 11 * s.nb32; q += (int)blockDim.x) B[q] = 0.0f;
         __syncthreads();
     }
 
@@ -949,17 +959,17 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(const DevMix* __restr
         L = mixed_evaluate(&s, a, pa.nu_mode);
         int q;
         if (pa.scheme == 0) {
-            const double den = L.W - pa.E0;
+            const double den = L.W - E0;
             if (!(den > 0)) { lw = -INFINITY; n_neg++; }
             else if (!(L.bbar > 0)) { lw = -INFINITY; n_nomove++; }
             else lw += log(L.bbar) - log(den);
-            const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)pa.j,
+            const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb,
                                              (uint64_t)it, kMove);
             q = mixed_heat_bath(&s, xi);
             if (tr && it < s.trace_cap && tid == 0) tr[it] = q;
             ++it;
         } else {
-            const double xt = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)pa.j,
+            const double xt = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb,
                                              (uint64_t)it, kPersist);
             const double t = (L.bbar > 0) ? -log1p(-xt) / L.bbar : INFINITY;
             if (!(L.bbar > 0)) n_nomove++;
@@ -974,7 +984,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(const DevMix* __restr
                 if (tr && it - 1 < s.trace_cap && tid == 0) tr[it - 1] = -1;
                 break;
             }
-            const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)pa.j,
+            const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb,
                                              (uint64_t)(it - 1), kMove);
             q = mixed_heat_bath(&s, xi);
             if (tr && it - 1 < s.trace_cap && tid == 0) tr[it - 1] = q;
@@ -986,7 +996,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(const DevMix* __restr
             if (small || since >= pa.refresh_every) {
                 if (!mixed_refresh(&s, st, a)) n_sing++;
                 float* B = LDSF(s.l_U);
-                for (int z = tid; z < 11 * s.nb32; z += kMixThreads) B[z] = 0.0f;
+                for (int z = tid; z < 11 * s.nb32; z += (int)blockDim.x) B[z] = 0.0f;
                 __syncthreads();
                 n_refresh++;
                 since = 0;
@@ -1000,13 +1010,13 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(const DevMix* __restr
         if (pa.scheme == 0) L = mixed_evaluate(&s, a, pa.nu_mode);
         const MLocal Lm = L;
         bool ok64 = true;
-        L = mixed_final_fp64(&s, a, pa.nu_mode, ok64);
+        L = mixed_final_fp64(&s, wid, a, pa.nu_mode, ok64);
         if (!ok64) n_sing++;
         if (s.diag) {
             const float* R = LDSF(s.l_R);
             const double* R64 = LDSD(s.l_F);
             double e = 0.0;
-            for (int p = tid; p < s.P; p += kMixThreads)
+            for (int p = tid; p < s.P; p += (int)blockDim.x)
                 e = fmax(e, fabs((double)R[p] - R64[p]) / fmax(1.0, fabs(R64[p])));
             e = block_max(e, LDSD(s.l_red));
             if (tid == 0) {
@@ -1016,7 +1026,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(const DevMix* __restr
         }
     }
 
-    for (int q = tid; q < 3 * s.N; q += kMixThreads) s.pos[(long)wid * 3 * s.N + q] = pos[q];
+    for (int q = tid; q < 3 * s.N; q += (int)blockDim.x) s.pos[(long)wid * 3 * s.N + q] = pos[q];
     if (tid == 0) {
         s.lw[wid] = lw;
         s.eL[wid] = L.eL;

@@ -608,6 +608,8 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
     if (wid >= s.nw) return;
     const int lane = threadIdx.x;
     const Walker w = walker_view(s);
+    const int jb = *s.jp;
+    const double E0 = *s.e0p;
 
     for (int q = lane; q < 3 * s.N; q += kWave) lds[w.pos + q] = s.pos[(long)wid * 3 * s.N + q];
     for (int q = lane; q < s.Nb * s.ns; q += kWave) {
@@ -641,17 +643,17 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
         LRDMC_T(0);
         int q;
         if (pa.scheme == 0) {
-            const double den = L.W - pa.E0;
+            const double den = L.W - E0;
             if (!(den > 0)) { lw = -INFINITY; n_neg++; }
             else if (!(L.bbar > 0)) { lw = -INFINITY; n_nomove++; }
             else lw += log(L.bbar) - log(den);
-            const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)pa.j,
+            const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb,
                                              (uint64_t)it, kMove);
             q = heat_bath(s, w, xi, lane);
             if (tr && it < s.trace_cap && lane == 0) tr[it] = q;
             ++it;
         } else {
-            const double xt = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)pa.j,
+            const double xt = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb,
                                              (uint64_t)it, kPersist);
             const double t = (L.bbar > 0) ? -log1p(-xt) / L.bbar : INFINITY;
             if (!(L.bbar > 0)) n_nomove++;
@@ -668,7 +670,7 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
                 if (tr && it - 1 < s.trace_cap && lane == 0) tr[it - 1] = -1;
                 break;
             }
-            const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)pa.j,
+            const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb,
                                              (uint64_t)(it - 1), kMove);
             q = heat_bath(s, w, xi, lane);
             if (tr && it - 1 < s.trace_cap && lane == 0) tr[it - 1] = q;
@@ -720,12 +722,15 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
 // FP64 inclusive prefix of exp(lw - max) in slot order, and the weighted
 // local-energy sums; then one thread per new walker runs the comb search
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kMaxBranchBlock) void branch_scan(BranchView s, int scheme, double E0,
-                                                               double* cum, double* out)
+__global__ __launch_bounds__(kMaxBranchBlock) void branch_scan(BranchView s, int scheme,
+                                                               double* cum, double* out,
+                                                               int* n_distinct)
 {
     __shared__ double sh[kMaxBranchBlock];
     __shared__ int shi[kMaxBranchBlock];
     const int t = threadIdx.x, nt = blockDim.x, nw = s.nw;
+    const double E0 = *s.e0p;
+    if (t == 0) *n_distinct = 0;
     const int per = (nw + nt - 1) / nt, b0 = t * per, b1 = min(b0 + per, nw);
     double mx = -INFINITY;
     int last = -1;
@@ -787,13 +792,13 @@ __global__ __launch_bounds__(kMaxBranchBlock) void branch_scan(BranchView s, int
     }
 }
 
-__global__ void branch_comb(BranchView s, uint64_t seed, int j, const double* cum, const double* out,
+__global__ void branch_comb(BranchView s, uint64_t seed, const double* cum, const double* out,
                             int32_t* sel)
 {
     const int al = blockIdx.x * blockDim.x + threadIdx.x;
     const int nw = s.nw;
     if (al >= nw) return;
-    const double xi = philox_uniform(seed, s.sysid, 0, (uint64_t)j, 0, kComb);
+    const double xi = philox_uniform(seed, s.sysid, 0, (uint64_t)*s.jp, 0, kComb);
     const double tot = out[1];
     const double target = (xi + (double)al) * tot / (double)nw;
     int lo = 0, hi = nw;          // first index with cum > target
@@ -827,6 +832,45 @@ __global__ void branch_gather(BranchView s, const int32_t* sel, const double* po
         s.eL[al] = eL_old[b];
         s.Wd[al] = W_old[b];
     }
+}
+
+// After the gather: the walker-averaged local energy and log wbar of this
+// branching appended to the device history ring, and E_0 updated to the mean
+// of the last `window` e_bar (Algorithm 2).  A branching in which every
+// weight is zero appends nothing and is counted in *n_dead.  bump_j (non-null
+// for the last system of a handle) advances the branching index.
+__global__ void branch_finish(int nw, const double* out, const int* n_distinct, double* hist,
+                              long long* n_hist, double* e0p, int* n_dead, int window, int cap,
+                              int* bump_j)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double mx = out[0], tot = out[1], se = out[2], so = out[3];
+    if (!(mx > -INFINITY) || !(tot > 0.0)) {
+        *n_dead += 1;
+    } else {
+        const long long n = *n_hist;
+        double* e = hist + (n % cap) * kHistLen;
+        e[kHistLogW] = log(tot / (double)nw) + mx;
+        e[kHistEbar] = se / so;
+        e[kHistMaxLw] = mx;
+        e[kHistDistinct] = (double)*n_distinct;
+        const long long n1 = n + 1, k0 = n1 > window ? n1 - window : 0;
+        double acc = 0.0;
+        for (long long q = k0; q < n1; ++q) acc += hist[(q % cap) * kHistLen + kHistEbar];
+        const double e0 = acc / (double)(n1 - k0);
+        e[kHistE0] = e0;
+        *e0p = e0;
+        *n_hist = n1;
+    }
+    if (bump_j) *bump_j += 1;
+}
+
+// counters of a phase to their initial values (a kernel, so that it can sit
+// inside a captured graph)
+__global__ void reset_counters_kernel(unsigned long long* c)
+{
+    const int k = threadIdx.x;
+    if (k < kCntLen) c[k] = (k == kCntMinIters) ? ~0ull : 0ull;
 }
 
 }  // namespace lrdmc

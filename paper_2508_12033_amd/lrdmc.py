@@ -61,6 +61,10 @@ class lrdmc_branch_stats(ct.Structure):
                 ("max_lw", ct.c_double), ("n_distinct", ct.c_int32), ("elapsed_ms", ct.c_double)]
 
 
+class lrdmc_tune_entry(ct.Structure):
+    _fields_ = [("threads", ct.c_int32), ("order_big_first", ct.c_int32), ("ms", ct.c_float)]
+
+
 class lrdmc_energy(ct.Structure):
     _fields_ = [("energy", ct.c_double), ("sigma", ct.c_double), ("n_used", ct.c_int32)]
 
@@ -68,7 +72,8 @@ class lrdmc_energy(ct.Structure):
 EXPORTS = ["lrdmc_workspace_bytes", "lrdmc_init_system", "lrdmc_step", "lrdmc_branch",
            "lrdmc_energy_forces", "lrdmc_get_walkers", "lrdmc_set_walkers", "lrdmc_get_e0",
            "lrdmc_set_e0", "lrdmc_get_branch_index", "lrdmc_destroy", "lrdmc_last_error",
-           "lrdmc_n_theta", "lrdmc_walker_derivs", "lrdmc_get_precision_report"]
+           "lrdmc_n_theta", "lrdmc_walker_derivs", "lrdmc_get_precision_report",
+           "lrdmc_run", "lrdmc_autotune", "lrdmc_set_launch"]
 
 _lib = None
 
@@ -100,11 +105,15 @@ def load(path=LIB_PATH):
     L.lrdmc_last_error.restype = ct.c_char_p
     L.lrdmc_n_theta.argtypes = [vp, ct.c_int]
     L.lrdmc_get_precision_report.argtypes = [vp, ct.c_int, vp]
+    L.lrdmc_run.argtypes = [vp, ct.c_int, vp, vp]
+    L.lrdmc_autotune.argtypes = [vp, ct.c_int, vp, ct.c_int, vp]
+    L.lrdmc_set_launch.argtypes = [vp, ct.c_int, ct.c_int]
     L.lrdmc_walker_derivs.argtypes = [vp, ct.c_int, vp, vp, vp, vp, vp]
     for k in ("lrdmc_init_system", "lrdmc_step", "lrdmc_branch", "lrdmc_energy_forces",
               "lrdmc_get_walkers", "lrdmc_set_walkers", "lrdmc_set_e0",
               "lrdmc_get_branch_index", "lrdmc_n_theta", "lrdmc_walker_derivs",
-              "lrdmc_get_precision_report"):
+              "lrdmc_get_precision_report", "lrdmc_run", "lrdmc_autotune",
+              "lrdmc_set_launch"):
         getattr(L, k).restype = ct.c_int
     _lib = L
     return L
@@ -202,6 +211,25 @@ class Handle:
         st = lrdmc_branch_stats()
         _check(self.L.lrdmc_branch(self.h, ct.byref(st)))
         return st
+
+    def run(self, n_branchings):
+        """n_branchings graph-replayed cycles of phase + reconfiguration;
+        returns (summed step stats, last branch stats)."""
+        st = lrdmc_step_stats()
+        bs = lrdmc_branch_stats()
+        _check(self.L.lrdmc_run(self.h, int(n_branchings), ct.byref(st), ct.byref(bs)))
+        return st, bs
+
+    def autotune(self, n_steps=8):
+        """Time the launch candidates of the mixed-precision phase; returns the
+        list of (threads, big_first, ms) and keeps the fastest."""
+        log = (lrdmc_tune_entry * 16)()
+        n = ct.c_int(0)
+        _check(self.L.lrdmc_autotune(self.h, int(n_steps), log, 16, ct.byref(n)))
+        return [(log[k].threads, log[k].order_big_first, log[k].ms) for k in range(n.value)]
+
+    def set_launch(self, threads, big_first=True):
+        _check(self.L.lrdmc_set_launch(self.h, int(threads), 1 if big_first else 0))
 
     def energy(self):
         e = lrdmc_energy()
