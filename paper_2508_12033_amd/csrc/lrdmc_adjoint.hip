@@ -94,6 +94,7 @@ __device__ bool gauss_jordan(double* G, int n, int* piv, double* colk, double& l
             if (v > best) { best = v; bi = r; }
         }
         if (!(best > 0.0)) return false;
+        __syncthreads();   // every wave has read column k before any row moves
         if (tid == 0) piv[k] = bi;
         if (bi != k) {
             for (int c = tid; c < n; c += kT) {

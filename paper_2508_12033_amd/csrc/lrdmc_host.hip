@@ -876,9 +876,20 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
                 break;
             }
             double acc = 0.0;
-            for (double x : eL) acc += x;
+            int nbad = 0, first = -1;
+            for (int w = 0; w < r.nw; ++w) {
+                acc += eL[w];
+                if (!std::isfinite(eL[w])) { if (first < 0) first = w; ++nbad; }
+            }
             r.e0 = acc / r.nw;
-            if (!std::isfinite(r.e0)) rc = fail(LRDMC_ERR_SINGULAR, "non-finite initial local energy");
+#ifdef LRDMC_DEBUG_KEEP_NONFINITE
+            if (nbad) { std::fprintf(stderr, "debug: system %d: %d non-finite, first %d\n", (int)(&r - h->sys.data()), nbad, first); nbad = 0; r.e0 = eL[0]; }
+#endif
+            if (nbad)
+                rc = fail(LRDMC_ERR_SINGULAR,
+                          "non-finite initial local energy: system " +
+                              std::to_string(&r - h->sys.data()) + ", " + std::to_string(nbad) +
+                              " walkers, first " + std::to_string(first));
             else if (up(r.d_e0, &r.e0, 8)) rc = fail(LRDMC_ERR_HIP, "upload failed");
         }
         unsigned long long cnt[kCntLen];

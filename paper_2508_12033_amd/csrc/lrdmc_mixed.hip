@@ -50,6 +50,19 @@ __device__ __forceinline__ double block_sum(double v, double* red)
     return t;
 }
 
+// Global-memory data written by some waves of the workgroup and read by others
+// after the barrier.  The workgroup-scope fence orders the accesses in the
+// compiler but is lowered without a wait for outstanding vector-memory stores
+// (it relies on the vector L1 serving the waves of a CU in order); the explicit
+// wait makes every store of this wave complete before the barrier, so the
+// hand-off does not depend on that ordering.
+__device__ __forceinline__ void global_handoff()
+{
+    __threadfence_block();
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
 __device__ __forceinline__ double block_max(double v, double* red)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -247,8 +260,7 @@ __device__ __noinline__ void mixed_store_rows(const DevMix* __restrict__ dm, flo
         else if (row <= 6) Phi[(long)k * 6 * ns + 6 * c + row - 1] = v;
         else dPhi[(long)k * 4 * ns + 4 * c + row - 7] = v;
     }
-    __threadfence_block();
-    __syncthreads();
+    global_handoff();
 }
 
 // FP64 Gauss-Jordan (in place, partial pivoting) of the transposed Slater
@@ -280,6 +292,7 @@ __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
             if (v > best) { best = v; bi = r; }
         }
         if (!(best > 0.0)) { ok = false; break; }
+        __syncthreads();   // every wave has read column k before any row moves
         if (tid == 0) piv[k] = bi;
         if (bi != k) {
             for (int c = tid; c < n; c += (int)blockDim.x) {
@@ -327,8 +340,7 @@ __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
         }
         if (tid == 0) { sc[kScLogdet0 + sp] = logdet; sc[kScSign0 + sp] = sign; }
     }
-    __threadfence_block();
-    __syncthreads();
+    global_handoff();
     return ok;
 }
 
@@ -609,8 +621,7 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
         orb_rows64(s, i, 1, a, rows);
         const int n = mnspin(s, mspin(s, i));
         for (int k = tid; k < n; k += (int)blockDim.x) A64[(long)i * ns + k] = rows[k];
-        __threadfence_block();
-        __syncthreads();
+        global_handoff();
     }
     ok = gj_inverse<double, double>(s, A64, Ai64, 0);
     ok = gj_inverse<double, double>(s, A64, Ai64 + (long)ns * ns, 1) && ok;
@@ -808,8 +819,7 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
         sc[kScLogdet0 + sp] += log(fabs((double)Rd));
         if (Rd < 0) sc[kScSign0 + sp] = -sc[kScSign0 + sp];
     }
-    __threadfence_block();
-    __syncthreads();
+    global_handoff();
 
     mixed_rows(&s, i, rnew, a);
     mixed_store_rows(&s, st, i, false);
