@@ -148,7 +148,7 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.l_nua = take(N * 8);
         L.l_scal = take(kScLen * 8);
         L.l_red = take(8 * 8);
-        L.l_U = take(std::max(std::max(std::max((size_t)11 * L.nb32 * 4, (size_t)(ns * ns + ns) * 8),
+        L.l_U = take(std::max(std::max(std::max((size_t)11 * (L.nb32 + 4) * 4, (size_t)(ns * ns + ns) * 8),
                                        (size_t)7 * N * 8),
                               (size_t)11 * kMixChunk * 8));
         L.l_R = take(P * 4);
@@ -160,7 +160,7 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.l_dje = take(N * 4);
         L.l_rows = take(11 * ns * 4);
         L.l_tmp = take((3 * ns + 8) * 4);
-        L.l_F = take((size_t)(2 * P + 8 * N + 11 * ns) * 8);
+        L.l_F = take((size_t)(2 * P + 8 * N) * 8);
         L.l_bytes = o;
         L.lds_bytes = o;
         L.g_Phi = 0;
@@ -168,7 +168,7 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.g_Arow = L.g_dPhi + 2L * ns * 4 * ns;
         L.g_AinvT = L.g_Arow + (long)N * ns;
         L.m_stride = (L.g_AinvT + 2L * ns * ns + 63) / 64 * 64;
-        L.stride64 = (long)N * ns + 2L * ns * ns;
+        L.stride64 = (long)N * ns + 2L * ns * ns + 2L * Nb * ns;
         L.b_sys += align_up((size_t)Nb * ns * 4) +
                    align_up((size_t)2 * L.tiles * (L.nb32 / 32) * 64 * 8 * 2);
         L.b_state = common + 2 * align_up(nw * L.m_stride * 4) + align_up(nw * L.stride64 * 8) +

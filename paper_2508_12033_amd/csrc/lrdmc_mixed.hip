@@ -153,9 +153,10 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
     const DevMix& s = *dm;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int Nb = s.Nb, items = 7 * Nb;
-    float* B = LDSF(s.l_U);                      // [11][nb32] basis rows (zero padded)
+    float* B = LDSF(s.l_U);                      // [11][nb32 + 4] basis rows (zero padded; the
+                                                 // extra 4 floats spread the rows over the banks)
     float* rows = LDSF(s.l_rows);
-    const int ldb = s.nb32;
+    const int ldb = s.nb32 + 4;
     for (int it = tid; it < items; it += (int)blockDim.x) {
         const int q = it / Nb, mu = it - q * Nb;
         double p[3];
@@ -214,12 +215,21 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
             for (int kb = 0; kb < s.nb32 / 32; ++kb) {
                 bf16x8_t ah, alo;
                 const int k0 = 32 * kb + 8 * k4;
+                float xa[8];
+                if (i16 < 11) {
+                    const float4_t* src = reinterpret_cast<const float4_t*>(B + i16 * ldb + k0);
+                    const float4_t v0 = src[0], v1 = src[1];
+                    xa[0] = v0[0]; xa[1] = v0[1]; xa[2] = v0[2]; xa[3] = v0[3];
+                    xa[4] = v1[0]; xa[5] = v1[1]; xa[6] = v1[2]; xa[7] = v1[3];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) xa[e] = 0.0f;
+                }
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const float x = i16 < 11 ? B[i16 * ldb + k0 + e] : 0.0f;
-                    const __bf16 h = (__bf16)x;
+                    const __bf16 h = (__bf16)xa[e];
                     ah[e] = h;
-                    alo[e] = (__bf16)(x - (float)h);
+                    alo[e] = (__bf16)(xa[e] - (float)h);
                 }
                 const bf16x8_t bh = cb[(long)kb * 64 + lane];
                 const bf16x8_t bl = cb[plane + (long)kb * 64 + lane];
@@ -284,12 +294,18 @@ __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
     __syncthreads();
     double logdet = 0.0, sign = 1.0;
     bool ok = true;
+    const int lane = tid & 63;
     for (int k = 0; k < n; ++k) {
-        double best = -1.0;
-        int bi = k;
-        for (int r = k; r < n; ++r) {
-            const double v = fabs(M[r * n + k]);
-            if (v > best) { best = v; bi = r; }
+        // pivot: largest |M[r][k]|, r >= k, first index among equals; every
+        // wave finds it with a butterfly over its lanes (n <= 64)
+        const int r0 = k + lane;
+        double best = r0 < n ? fabs(M[r0 * n + k]) : -1.0;
+        int bi = r0 < n ? r0 : n;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o);
+            const int oi = __shfl_xor(bi, o);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
         }
         if (!(best > 0.0)) { ok = false; break; }
         __syncthreads();   // every wave has read column k before any row moves
@@ -534,77 +550,23 @@ __device__ __noinline__ MLocal mixed_evaluate(const DevMix* __restrict__ dm, dou
 
 // ---------------------------------------------------------------------------
 // FP64 estimator evaluation: everything recomputed from the positions in FP64
-// (orbital rows, Gauss-Jordan inverses, ratios, Jastrow, local energy), so
-// that e_L and W handed to the reconfiguration and the energy estimate carry
-// no FP32 error.  Basis functions are taken in chunks of kMixChunk.
+// (Slater rows, Gauss-Jordan inverses, ratios, Jastrow, local energy), so that
+// e_L and W handed to the reconfiguration and the energy estimate carry no
+// FP32 error.  The determinant ratios and derivatives are contracted as
+// chi(r') . (C Ainv)[:, c]: Z = C Ainv is formed once per spin, after which each
+// of the 6 moves, the gradient and the Laplacian of an electron is one dot
+// product over the basis instead of an orbital row times a column.
 // ---------------------------------------------------------------------------
-// orbital rows of electron i in FP64: nrows = 1 (value) or 11 (value, the 6
-// lattice neighbours, gradient, Laplacian) into out[row][ns]
-__device__ void orb_rows64(const DevMix& s, int i, int nrows, double a, double* out)
-{
-    const int tid = threadIdx.x, ns = s.ns, Nb = s.Nb;
-    const int n = mnspin(s, mspin(s, i));
-    double* rb = LDSD(s.l_U);                    // [11][kMixChunk]
-    const double* pos = LDSD(s.l_pos);
-    const int items = nrows * n;                 // <= 11 * 64 < 6 * 128
-    const int npts = nrows == 1 ? 1 : 7;
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int m0 = 0; m0 < Nb; m0 += kMixChunk) {
-        const int cnt = min(kMixChunk, Nb - m0);
-        for (int it = tid; it < npts * kMixChunk; it += (int)blockDim.x) {
-            const int q = it / kMixChunk, m = it - q * kMixChunk, mu = m0 + m;
-            if (m >= cnt) continue;
-            double p[3];
-            point_q(pos + 3 * i, q, a, p);
-            const double* rec = s.btab + 4 * mu;
-            const double dx = p[0] - rec[0], dy = p[1] - rec[1], dz = p[2] - rec[2];
-            const double d2 = dx * dx + dy * dy + dz * dz;
-            const int t = s.btype[mu];
-            if (q == 0 && nrows > 1) {
-                double v, g[3], l;
-                basis_vgl_d(t, rec[3], dx, dy, dz, d2, v, g, l);
-                rb[m] = v;
-                rb[7 * kMixChunk + m] = g[0];
-                rb[8 * kMixChunk + m] = g[1];
-                rb[9 * kMixChunk + m] = g[2];
-                rb[10 * kMixChunk + m] = l;
-            } else {
-                rb[q * kMixChunk + m] = basis_value_d(t, rec[3], dx, dy, dz, d2);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 6; ++r) {
-            const int it = tid + r * (int)blockDim.x;
-            if (it < items) {
-                const int row = it / n, k = it - row * n;
-                double sacc = 0.0;
-                for (int m = 0; m < cnt; ++m)
-                    sacc += rb[row * kMixChunk + m] * s.C64[(long)(m0 + m) * s.Norb + k];
-                acc[r] += sacc;
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int r = 0; r < 6; ++r) {
-        const int it = tid + r * (int)blockDim.x;
-        if (it < items) {
-            const int row = it / n, k = it - row * n;
-            out[row * ns + k] = acc[r];
-        }
-    }
-    __syncthreads();
-}
-
 __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, int wid, double a,
                                                 int nu_mode, bool& ok)
 {
     const DevMix& s = *dm;
-    const int tid = threadIdx.x, ns = s.ns, N = s.N, P = s.P;
+    const int tid = threadIdx.x, nt = blockDim.x, ns = s.ns, N = s.N, P = s.P, Nb = s.Nb;
+    const int lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
     double* g64 = s.s64 + (long)wid * s.stride64;
-    double* A64 = g64;                           // [N][ns]    Slater rows
-    double* Ai64 = g64 + (long)N * ns;           // [2][ns][ns] transposed inverses
+    double* A64 = g64;                           // [N][ns]       Slater rows
+    double* Ai64 = g64 + (long)N * ns;           // [2][ns][ns]   transposed inverses AiT[c][k]
+    double* Z64 = Ai64 + 2L * ns * ns;           // [2][Nb][ns]   Z[mu][c] = sum_k C[mu][k] Ainv[k][c]
     const double* pos = LDSD(s.l_pos);
     double* F = LDSD(s.l_F);
     double* R64 = F;                             // [P]
@@ -612,30 +574,92 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
     double* dJ64 = gD64 + 4 * N;                 // [P]
     double* Jg64 = dJ64 + P;                     // [N][3]
     double* Jl64 = Jg64 + 3 * N;                 // [N]
-    double* rows = Jl64 + N;                     // [11][ns]
     double* nue = LDSD(s.l_nue);
     double* nua = LDSD(s.l_nua);
     double* red = LDSD(s.l_red);
-    // Slater rows and inverses
-    for (int i = 0; i < N; ++i) {
-        orb_rows64(s, i, 1, a, rows);
-        const int n = mnspin(s, mspin(s, i));
-        for (int k = tid; k < n; k += (int)blockDim.x) A64[(long)i * ns + k] = rows[k];
-        global_handoff();
+    double* U = LDSD(s.l_U);
+    // Slater rows, G electrons at a time (G ns <= threads: one item per thread)
+    const int G = min(11, max(1, nt / ns));
+    for (int i0 = 0; i0 < N; i0 += G) {
+        const int g = min(G, N - i0);
+        const int e_it = tid / ns, k_it = tid - e_it * ns;
+        const bool mine = e_it < g && k_it < mnspin(s, mspin(s, i0 + e_it));
+        double acc = 0.0;
+        for (int m0 = 0; m0 < Nb; m0 += kMixChunk) {
+            const int cnt = min(kMixChunk, Nb - m0);
+            for (int it = tid; it < g * kMixChunk; it += nt) {
+                const int e = it / kMixChunk, m = it - e * kMixChunk;
+                if (m >= cnt) continue;
+                const double* r = pos + 3 * (i0 + e);
+                const double* rec = s.btab + 4 * (m0 + m);
+                const double dx = r[0] - rec[0], dy = r[1] - rec[1], dz = r[2] - rec[2];
+                U[e * kMixChunk + m] =
+                    basis_value_d(s.btype[m0 + m], rec[3], dx, dy, dz, dx * dx + dy * dy + dz * dz);
+            }
+            __syncthreads();
+            if (mine)
+                for (int m = 0; m < cnt; ++m)
+                    acc += U[e_it * kMixChunk + m] * s.C64[(long)(m0 + m) * s.Norb + k_it];
+            __syncthreads();
+        }
+        if (mine) A64[(long)(i0 + e_it) * ns + k_it] = acc;
     }
+    global_handoff();
     ok = gj_inverse<double, double>(s, A64, Ai64, 0);
     ok = gj_inverse<double, double>(s, A64, Ai64 + (long)ns * ns, 1) && ok;
-    // determinant ratios of the 6 moves, gradient and Laplacian of each electron
-    for (int i = 0; i < N; ++i) {
-        orb_rows64(s, i, 11, a, rows);
-        const int sp = mspin(s, i), c = mcol(s, i), n = mnspin(s, sp);
-        const double* Ai = Ai64 + (long)sp * ns * ns + (long)c * ns;
-        if (tid < 10) {
-            const int row = tid + 1;
+    // Z = C Ainv per spin, with the inverse staged in LDS
+    for (int sp = 0; sp < 2; ++sp) {
+        const int n = mnspin(s, sp);
+        if (!n) continue;
+        for (int idx = tid; idx < n * n; idx += nt) {
+            const int c = idx / n, k = idx - c * n;
+            U[idx] = Ai64[(long)sp * ns * ns + (long)c * ns + k];
+        }
+        __syncthreads();
+        for (int idx = tid; idx < Nb * n; idx += nt) {
+            const int mu = idx / n, c = idx - mu * n;
+            const double* Cm = s.C64 + (long)mu * s.Norb;
             double acc = 0.0;
-            for (int k = 0; k < n; ++k) acc += rows[row * ns + k] * Ai[k];
-            if (row <= 6) R64[6 * i + row - 1] = acc;
-            else gD64[4 * i + row - 7] = acc;
+            for (int k = 0; k < n; ++k) acc += Cm[k] * U[c * n + k];
+            Z64[((long)sp * Nb + mu) * ns + c] = acc;
+        }
+        __syncthreads();
+    }
+    global_handoff();
+    // per electron: the 6 neighbour values, gradient and Laplacian of the
+    // basis, each contracted with Z[:, c]; partial sums over the basis reduced
+    // across the workgroup (U holds [waves][10])
+    for (int i = 0; i < N; ++i) {
+        const int sp = mspin(s, i), c = mcol(s, i);
+        const double* Zc = Z64 + (long)sp * Nb * ns + c;
+        double t[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int mu = tid; mu < Nb; mu += nt) {
+            const double z = Zc[(long)mu * ns];
+            const double* rec = s.btab + 4 * mu;
+            const int ty = s.btype[mu];
+            for (int q = 1; q <= 6; ++q) {
+                double p[3];
+                point_q(pos + 3 * i, q, a, p);
+                const double dx = p[0] - rec[0], dy = p[1] - rec[1], dz = p[2] - rec[2];
+                t[q - 1] += z * basis_value_d(ty, rec[3], dx, dy, dz, dx * dx + dy * dy + dz * dz);
+            }
+            const double* r = pos + 3 * i;
+            const double dx = r[0] - rec[0], dy = r[1] - rec[1], dz = r[2] - rec[2];
+            double v, gg[3], l;
+            basis_vgl_d(ty, rec[3], dx, dy, dz, dx * dx + dy * dy + dz * dz, v, gg, l);
+            t[6] += z * gg[0]; t[7] += z * gg[1]; t[8] += z * gg[2]; t[9] += z * l;
+        }
+#pragma unroll
+        for (int q = 0; q < 10; ++q) {
+            const double w = wave_sum(t[q]);
+            if (lane == 0) U[wv * 10 + q] = w;
+        }
+        __syncthreads();
+        if (tid < 10) {
+            double v = U[tid];
+            for (int w = 1; w < nwv; ++w) v += U[w * 10 + tid];
+            if (tid < 6) R64[6 * i + tid] = v;
+            else gD64[4 * i + tid - 6] = v;
         }
         __syncthreads();
     }
@@ -938,7 +962,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
     for (int q = tid; q < 3 * s.N; q += (int)blockDim.x) pos[q] = s.pos[(long)wid * 3 * s.N + q];
     {
         float* B = LDSF(s.l_U);   // zero the padding of the basis rows once
-        for (int q = tid; q < 11 * s.nb32; q += (int)blockDim.x) B[q] = 0.0f;
+        for (int q = tid; q < 11 * (s.nb32 + 4); q += (int)blockDim.x) B[q] = 0.0f;
     }
     __syncthreads();
     const double a = pa.a;
@@ -955,7 +979,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
     // the Gauss-Jordan scratch overlaps the basis rows: restore their padding
     {
         float* B = LDSF(s.l_U);
-        for (int q = tid; q < 11 * s.nb32; q += (int)blockDim.x) B[q] = 0.0f;
+        for (int q = tid; q < 11 * (s.nb32 + 4); q += (int)blockDim.x) B[q] = 0.0f;
         __syncthreads();
     }
 
@@ -1006,7 +1030,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
             if (small || since >= pa.refresh_every) {
                 if (!mixed_refresh(&s, st, a)) n_sing++;
                 float* B = LDSF(s.l_U);
-                for (int z = tid; z < 11 * s.nb32; z += (int)blockDim.x) B[z] = 0.0f;
+                for (int z = tid; z < 11 * (s.nb32 + 4); z += (int)blockDim.x) B[z] = 0.0f;
                 __syncthreads();
                 n_refresh++;
                 since = 0;
