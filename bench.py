@@ -1,19 +1,26 @@
 """Benchmark of the lattice-regularized DMC hot path on one MI355X.
 
-Workload (one step = one pass of the hot path): one load-balanced projection
-phase of N_proj = 300 lattice moves for every walker (ratios of all 6N moves,
-local energy, weight update, heat-bath move, Sherman-Morrison update, FP64
-refreshes) followed by the reconfiguration, on the 16-electron / 8-atom
-synthetic molecule with 4096 walkers in FP64.  Inputs are resident in HBM
-before the timed region.
+Headline workload (one step = one pass of the hot path): one load-balanced
+projection phase of N_proj = 300 lattice moves for every walker (ratios of all
+6N moves, local energy, weight update, heat-bath move, Sherman-Morrison
+update, FP64 refreshes) followed by the reconfiguration, on the 16-electron /
+8-atom synthetic molecule with 4096 walkers in FP64.  Inputs are resident in
+HBM before the timed region; the timed cycles are graph replays of
+(phase, reconfiguration) with E_0 and the history kept on the device.
 
 Metric: electron-move proposals per second = walker-iterations that evaluated
-all 6N move ratios x 6N / wall time.  Printed beside it: the conventional
-(continuous-time) scheme on the same system at matched mean iterations, the
-load-balanced-over-conventional speedup, the roofline of the phase kernel and
-the CPU oracle's throughput on a bounded sample.
+all 6N move ratios x 6N / wall time.  Printed beside it:
+  - conventional (continuous-time) scheme on the same system at matched mean
+    iterations, its lane occupancy, and the load-balanced speedup;
+  - the mixed-precision paths with their stated errors: the same 16-electron
+    workload in FP32, the 128-electron / 2048-walker system with the BF16
+    orbital product (and FP32), the three uneven systems in one launch;
+  - the adjoint pass (per-walker parameter derivatives) on the 16-electron
+    system with electron-nucleus Jastrow terms;
+  - the roofline of the phase kernel and the CPU oracle on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-conv]
+                       [--no-extra] [--copy-calibration]
 """
 import argparse
 import hashlib
@@ -30,20 +37,22 @@ import numpy as np  # noqa: E402
 METRIC = ("electron-move proposals/sec on 1 GPU, mixed vs FP64 at stated error; "
           "speedup vs conventional")
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector
 KERNEL_SOURCES = ["paper_2508_12033_amd/csrc/lrdmc_phase.hip",
-                  "paper_2508_12033_amd/csrc/lrdmc_dev.hpp"]
+                  "paper_2508_12033_amd/csrc/lrdmc_dev.hpp",
+                  "paper_2508_12033_amd/csrc/lrdmc_devfn.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phase_fp64_c1_traffic.json")
 
 
 def flops_per_walker_step(N, n, Nb, M, has_en, refresh_every):
-    """Algorithmic FP64 operations of one incremental walker-step (exp, log,
-    sqrt and division count as one operation each):
+    """Algorithmic floating-point operations of one incremental walker-step
+    (exp, log, sqrt and division count as one operation each):
       basis functions of the moved electron at its position and 6 neighbours
       (+ gradient, Laplacian) ~ 85 Nb; orbital rows 2*11*Nb*n; Sherman-Morrison
       4 n^2; determinant ratios of the moved spin 12 n^2; ratios of all moves
       2P; Jastrow pair differences (N-1)*166 + (P-6)*35 (+ nuclei); local
-      energy N(8n+20) + 2P; heat bath 2P; the FP64 refresh (Gauss-Jordan 8 n^3
-      over both spins and the full Jastrow N(N-1)*137) divided by its cadence."""
+      energy N(8n+20) + 2P; heat bath 2P; the refresh (Gauss-Jordan 8 n^3 over
+      both spins and the full Jastrow N(N-1)*137) divided by its cadence."""
     P = 6 * N
     f = 85 * Nb + 2 * 11 * Nb * n + 4 * n * n + 12 * n * n + 2 * P
     f += (N - 1) * 166 + (P - 6) * 35 + M * (145 if has_en else 8)
@@ -71,7 +80,7 @@ def traffic_per_launch():
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(d, n_walk=2048, n_steps=100):
+def cpu_baseline(d, n_walk=4096, n_steps=600):
     """The FP64 oracle as it stands, all host cores, on a bounded sample: the
     first n_walk walkers of the same system for n_steps load-balanced steps."""
     import oracle as O
@@ -86,36 +95,88 @@ def cpu_baseline(d, n_walk=2048, n_steps=100):
     dt = time.perf_counter() - t0
     return dict(value=n_walk * n_steps * S.P / dt, unit="proposals/s", cores=nt, kind="oracle",
                 sample="%d walkers x %d load-balanced steps of the 16-electron system "
-                       "(%.1f s wall)" % (n_walk, n_steps, dt))
+                       "(%.1f s wall, %d threads)" % (n_walk, n_steps, dt, nt))
 
 
-def run_scheme(B, d, scheme, steps, warmup, **kw):
+def proposals_of(systems, prm, st, scheme):
+    """Proposals evaluated: load-balanced N_proj x walkers x 6N per system per
+    cycle; conventional: the active walker-iterations (one system) x 6N."""
+    if scheme == "conv":
+        return st.walker_iters * 6 * int(systems[0]["n_elec"])
+    return sum(int(d["n_elec"]) * 6 * int(d.get("n_walkers_run", d["init_pos"].shape[0]))
+               for d in systems) * prm.n_proj
+
+
+def run_cycles(B, systems, scheme, steps, warmup, precision="fp64", tune=False, threads=None, **kw):
+    """Init, warm up, then time `steps` graph-replayed (phase, reconfiguration)
+    cycles with one synchronisation at each end."""
     import torch
-    prm = B.params_for(d, scheme, **kw)
-    h = B.Handle(d, prm)
-    N = d["n_elec"]
-    for _ in range(warmup):
-        h.step(stats=False)
-        h.branch()
+    if isinstance(systems, dict):
+        systems = [systems]
+    prm = B.params_for(systems[0], scheme, precision=precision, **kw)
+    h = B.Handle(systems, prm)
+    h.step(stats=False)
+    h.branch()
+    log = None
+    if threads:
+        h.set_launch(threads)
+    if tune:
+        log = h.autotune(n_steps=8)
+    if warmup > 0:
+        h.run(warmup)
     torch.cuda.synchronize()
-    iters, kms, maxit, bms = 0, [], [], []
     t0 = time.perf_counter()
-    for _ in range(steps):
-        st = h.step(stats=True)
-        bs = h.branch()
-        iters += st.walker_iters
-        kms.append(st.elapsed_ms)
-        maxit.append(st.max_iters)
-        bms.append(bs.elapsed_ms)
+    st, bs = h.run(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    nw = d["init_pos"].shape[0]
-    out = dict(proposals=iters * 6 * N, seconds=dt, walker_iters=iters,
-               kernel_ms=float(np.mean(kms)), branch_ms=float(np.mean(bms)),
-               max_iters=float(np.mean(maxit)), mean_iters=iters / (steps * nw),
-               occupancy=iters / (steps * nw * float(np.mean(maxit))), e0=h.e0())
-    h.close()
-    return out
+    nw = sum(int(d.get("n_walkers_run", d["init_pos"].shape[0])) for d in systems)
+    props = proposals_of(systems, prm, st, scheme) * (steps if scheme == "lb" else 1)
+    out = dict(proposals=props, seconds=dt, walker_iters=st.walker_iters,
+               ms_per_cycle=1e3 * dt / steps, max_iters=st.max_iters,
+               mean_iters=st.walker_iters / (steps * nw),
+               occupancy=st.walker_iters / (steps * nw * max(1, st.max_iters)) if scheme == "conv"
+               else 1.0, e0=h.e0(), tune=log)
+    return h, prm, out
+
+
+def phase_kernel_ms(h, n=3):
+    """Average duration of the phase launch(es) of one step, HIP events on the
+    handle's stream."""
+    ms = []
+    for _ in range(n):
+        st = h.step(stats=True)
+        ms.append(st.elapsed_ms)
+        h.branch()
+    return float(np.mean(ms))
+
+
+def precision_summary(h, isys=0):
+    """Stated error of a mixed-precision run at its last phase: the mixed
+    step's own e_L and W against the FP64 estimator values at the same
+    configurations, and the largest ratio error against FP64.  (Read after a
+    phase and before the next reconfiguration, which reorders the walkers.)"""
+    rep = h.precision_report(isys)
+    g = h.walkers(isys)
+    e = np.abs(rep[:, 0] - g["eL"]) / np.abs(g["eL"])
+    w = np.abs(rep[:, 1] - g["W"]) / np.abs(g["W"])
+    return dict(step_eL_rel_err_max=float(e.max()), step_eL_rel_err_median=float(np.median(e)),
+                step_W_rel_err_max=float(w.max()), ratio_err_max=float(rep[:, 3].max()),
+                ratio_err_median=float(np.median(rep[:, 3])),
+                reported_eL="FP64 evaluation at the phase's final configuration")
+
+
+def copy_calibration():
+    """A plain 256 MiB device-to-device copy, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters to bytes."""
+    import torch
+    a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_bytes=256 << 20, copies=3)), flush=True)
 
 
 def main():
@@ -125,6 +186,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-conv", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="headline only (no mixed, batched or adjoint lines)")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
@@ -132,55 +196,103 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_2508_12033_amd import inputs as I
-    from paper_2508_12033_amd import lrdmc as B
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    from paper_2508_12033_amd import inputs as I
+    from paper_2508_12033_amd import lrdmc as B
+
     d = I.c1_system(n_walkers=4096)
     nw, N, n_proj = 4096, d["n_elec"], d["n_proj"]
 
-    lb = run_scheme(B, d, "lb", args.steps, args.warmup)
+    h, prm, lb = run_cycles(B, d, "lb", args.steps, args.warmup)
     value = lb["proposals"] / lb["seconds"]
-    ms_per_step = 1e3 * lb["seconds"] / args.steps
+    kms = phase_kernel_ms(h)
+    h.close()
 
     fl = flops_per_walker_step(N, d["n_up"], d["n_basis"], d["n_atoms"], 0, 16)
-    achieved = fl * nw * n_proj / (lb["kernel_ms"] * 1e-3) / 1e12
+    achieved = fl * nw * n_proj / (kms * 1e-3) / 1e12
     tr = traffic_per_launch()
     roof = dict(bound="alu", kernel="phase_fp64", achieved=achieved, peak=FP64_PEAK_TFLOPS,
                 unit="TFLOP/s", frac=achieved / FP64_PEAK_TFLOPS, traffic=tr,
-                flops_per_walker_step=fl, launch_ms=lb["kernel_ms"])
+                flops_per_walker_step=fl, walker_steps_per_launch=nw * n_proj, launch_ms=kms)
 
     res = dict(metric=METRIC, value=value, unit="proposals/s", n_gpus=1, steps=args.steps,
-               warmup=args.warmup, ms_per_step=ms_per_step, higher_is_better=True,
+               warmup=args.warmup, ms_per_step=lb["ms_per_cycle"], higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
                config=dict(workload="16-electron 8-atom synthetic molecule (1 C-like and 1 "
                                     "O-like soft core, 6 protons, 80 s/p Gaussians), 4096 "
                                     "walkers, a=0.2 bohr, load-balanced N_proj=300, FP64",
                            walkers=nw, electrons=N, n_proj=n_proj, precision="fp64",
-                           scheme="load-balanced"),
-               roofline=roof,
-               branch_ms=lb["branch_ms"])
+                           scheme="load-balanced", step="one projection phase + reconfiguration"),
+               roofline=roof)
 
     if not args.no_conv:
-        cv = run_scheme(B, d, "conv", args.steps, args.warmup)
+        hc, _, cv = run_cycles(B, d, "conv", args.steps, args.warmup)
+        hc.close()
         nbar = cv["mean_iters"]
-        lbm = run_scheme(B, d, "lb", args.steps, 1, n_proj=int(round(nbar)))
-        t_conv = cv["seconds"] / args.steps
-        t_lbm = lbm["seconds"] / args.steps
-        # Poisson model of the lockstep maximum (iterations ~ 1 + Poisson(nbar - 1))
+        hm, _, lbm = run_cycles(B, d, "lb", args.steps, 1, n_proj=int(round(nbar)))
+        hm.close()
         from scipy.stats import poisson
         mu = nbar - 1.0
         k = np.arange(0, int(mu + 40 * np.sqrt(mu) + 100))
         emax = float(np.sum(1.0 - poisson.cdf(k, mu) ** nw)) + 1.0
         res["conventional"] = dict(
             tau=d["tau"], mean_iters=nbar, max_iters=cv["max_iters"], lane_occupancy=cv["occupancy"],
-            proposals_per_s=cv["proposals"] / cv["seconds"], ms_per_branching=1e3 * t_conv,
-            kernel_ms=cv["kernel_ms"], poisson_model_max_iters=emax,
-            poisson_model_time_ratio=emax / nbar)
-        res["lb_matched"] = dict(n_proj=int(round(nbar)), ms_per_branching=1e3 * t_lbm,
-                                 kernel_ms=lbm["kernel_ms"])
-        res["speedup_vs_conventional"] = t_conv / t_lbm
+            proposals_per_s=cv["proposals"] / cv["seconds"], ms_per_branching=cv["ms_per_cycle"],
+            poisson_model_max_iters=emax, poisson_model_time_ratio=emax / nbar)
+        res["lb_matched"] = dict(n_proj=int(round(nbar)), ms_per_branching=lbm["ms_per_cycle"])
+        res["speedup_vs_conventional"] = cv["ms_per_cycle"] / lbm["ms_per_cycle"]
+
+    if not args.no_extra:
+        extra = {}
+        steps_x = max(2, args.steps // 3)
+        # the same 16-electron workload on the mixed-precision path
+        hx, _, r = run_cycles(B, d, "lb", steps_x, 1, precision="fp32", tune=True)
+        hx.step(stats=False)
+        extra["c1_mixed_fp32"] = dict(proposals_per_s=r["proposals"] / r["seconds"],
+                                      ms_per_branching=r["ms_per_cycle"], tune=r["tune"],
+                                      vs_fp64=(r["proposals"] / r["seconds"]) / value,
+                                      error=precision_summary(hx))
+        hx.close()
+        # 128 electrons, 640 basis functions, 2048 walkers
+        c3 = I.c3_system(n_walkers=2048)
+        for prec in ("bf16", "fp32"):
+            hx, _, r = run_cycles(B, c3, "lb", 2, 0, precision=prec)
+            hx.step(stats=False)
+            extra["c3_mixed_" + prec] = dict(
+                workload="128 electrons (64+64), 32 atoms, 640 basis functions, 2048 walkers, "
+                         "a=0.15, N_proj=300, refresh every 16",
+                proposals_per_s=r["proposals"] / r["seconds"], ms_per_branching=r["ms_per_cycle"],
+                error=precision_summary(hx))
+            hx.close()
+        # three uneven systems in one launch, graph-replayed cycles, tuned launch
+        c2 = I.c2_systems()
+        hx, _, r = run_cycles(B, c2, "lb", 2, 0, precision="fp32", tune=True)
+        hx.step(stats=False)
+        extra["c2_batched_fp32"] = dict(
+            workload="16e/8 atoms x 8192, 32e/16 atoms x 4096, 64e/32 atoms x 2048 walkers "
+                     "in one launch, N_proj=300",
+            proposals_per_s=r["proposals"] / r["seconds"], ms_per_branching=r["ms_per_cycle"],
+            tune=r["tune"], error=[precision_summary(hx, k) for k in range(3)])
+        hx.close()
+        # adjoint pass: 4096 walkers, 24 nuclear coordinates + 15 Jastrow parameters
+        c4 = I.c4_system(n_walkers=4096)
+        ha = B.Handle(c4, B.params_for(c4, "lb", n_proj=10))
+        ha.walker_derivs()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            ha.walker_derivs()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / 5
+        extra["c4_adjoint"] = dict(walkers=4096, n_theta=ha.n_theta(), ms_per_call=ms,
+                                   walker_gradients_per_s=4096 / (ms * 1e-3), precision="fp64")
+        ha.close()
+        res["extra"] = extra
 
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(d)

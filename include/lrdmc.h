@@ -192,8 +192,8 @@ int lrdmc_run(struct lrdmc_handle *h, int n_branchings, lrdmc_step_stats *st,
               lrdmc_branch_stats *bst);
 
 /* Autotuner of the mixed-precision launch (every mixed-precision system of
- * the handle advances in one launch): each candidate workgroup size (256 or
- * 128 threads per walker) and order of the systems in the launch is timed on
+ * the handle advances in one launch): each candidate workgroup size (256, 128
+ * or 64 threads per walker) and order of the systems in the launch is timed on
  * a copy of the current walkers for n_steps load-balanced steps; the fastest
  * is kept for later phases.  The walkers, weights, E_0 and random streams of
  * the run are not changed.  log (may be NULL) receives up to log_cap timings,
@@ -202,7 +202,7 @@ int lrdmc_autotune(struct lrdmc_handle *h, int n_steps, lrdmc_tune_entry *log, i
                    int *n_log);
 
 /* Fix the mixed-precision launch instead of tuning it: threads per walker
- * workgroup (128 or 256) and the order of the systems in the launch (1:
+ * workgroup (64, 128 or 256) and the order of the systems in the launch (1:
  * more electrons first).  No effect on results beyond FP32 summation order. */
 int lrdmc_set_launch(struct lrdmc_handle *h, int threads, int order_big_first);
 
@@ -248,7 +248,8 @@ int lrdmc_get_walkers(struct lrdmc_handle *h, int isys, double *pos, double *lw,
  * the mixed-precision step computed them, and the largest ratio error
  * max_p |R_p - R_p(FP64)| / max(1, |R_p(FP64)|).  The e_L and W that the
  * library reports (lrdmc_get_walkers) and uses for the reconfiguration are
- * the FP64 evaluation of the same configuration.  Synchronises. */
+ * the FP64 evaluation of the same configuration.  Valid until the next
+ * reconfiguration, which reorders the walkers.  Synchronises. */
 int lrdmc_get_precision_report(struct lrdmc_handle *h, int isys, double *out);
 
 /* Overwrite positions (and log-weights if lw != NULL) of system `isys`. */

@@ -985,8 +985,8 @@ int lrdmc_run(lrdmc_handle* h, int n_branchings, lrdmc_step_stats* st, lrdmc_bra
     return rc;
 }
 
-// Autotuner of the mixed-precision launch: workgroup size (threads per
-// walker) x order of the systems in the launch, each candidate timed on a
+// Autotuner of the mixed-precision launch: workgroup size (64, 128 or 256
+// threads per walker) x order of the systems in the launch, each candidate timed on a
 // copy of the current walkers (the other slot) for n_steps load-balanced
 // steps; the fastest is kept.  Stream-synchronous.
 int lrdmc_autotune(lrdmc_handle* h, int n_steps, lrdmc_tune_entry* log, int log_cap, int* n_log)
@@ -1003,7 +1003,7 @@ int lrdmc_autotune(lrdmc_handle* h, int n_steps, lrdmc_tune_entry* log, int log_
     small.assign(big.rbegin(), big.rend());
     const std::vector<std::vector<int>> orders = big.size() > 1 ? std::vector<std::vector<int>>{big, small}
                                                                 : std::vector<std::vector<int>>{big};
-    const int threads[2] = {256, 128};
+    const int threads[3] = {256, 128, 64};
     const std::vector<int> keep_order = h->mix_order;
     const int keep_threads = h->mix_threads;
     float best = 1e30f;
@@ -1017,7 +1017,7 @@ int lrdmc_autotune(lrdmc_handle* h, int n_steps, lrdmc_tune_entry* log, int log_
         HIPCHK(hipMemcpyAsync(r.cum, r.lw, (size_t)r.nw * 8, hipMemcpyDeviceToDevice, h->stream));
     }
     for (size_t oi = 0; oi < orders.size() && !rc; ++oi)
-        for (int ti = 0; ti < 2 && !rc; ++ti) {
+        for (int ti = 0; ti < 3 && !rc; ++ti) {
             h->mix_order = orders[oi];
             h->mix_threads = threads[ti];
             if ((rc = upload_mix_tables(h))) break;
@@ -1081,8 +1081,8 @@ int lrdmc_autotune(lrdmc_handle* h, int n_steps, lrdmc_tune_entry* log, int log_
 
 int lrdmc_set_launch(lrdmc_handle* h, int threads, int order_big_first)
 {
-    if (!h || (threads != 128 && threads != 256))
-        return fail(LRDMC_ERR_INVALID_ARG, "threads must be 128 or 256");
+    if (!h || (threads != 64 && threads != 128 && threads != 256))
+        return fail(LRDMC_ERR_INVALID_ARG, "threads must be 64, 128 or 256");
     std::stable_sort(h->mix_order.begin(), h->mix_order.end(), [&](int x, int y) {
         return order_big_first ? h->sys[x].N > h->sys[y].N : h->sys[x].N < h->sys[y].N;
     });

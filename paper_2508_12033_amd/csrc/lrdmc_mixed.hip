@@ -36,7 +36,7 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------------------
-// block collectives (2 or 4 wavefronts); red is a 4-double LDS scratch
+// block collectives (1, 2 or 4 wavefronts); red is a 4-double LDS scratch
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double block_sum(double v, double* red)
 {

@@ -102,8 +102,8 @@ def test_autotune_keeps_state_and_parity():
     e0s = [h.e0(k) for k in range(3)]
     log = h.autotune(n_steps=4)
     say("tuning log", log)
-    assert len(log) == 4
-    assert {t for t, _, _ in log} == {128, 256}
+    assert len(log) == 6
+    assert {t for t, _, _ in log} == {64, 128, 256}
     after = [h.walkers(k) for k in range(3)]
     for a, b in zip(before, after):
         assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["lw"], b["lw"])
@@ -118,13 +118,14 @@ def test_autotune_keeps_state_and_parity():
     h.close()
 
 
-def test_small_blocks_match_oracle():
-    """The 128-thread workgroup variant of the mixed kernel, smallest system
-    first in the launch."""
+@pytest.mark.parametrize("threads", [64, 128])
+def test_small_blocks_match_oracle(threads):
+    """The 64- and 128-thread workgroup variants of the mixed kernel, smallest
+    system first in the launch."""
     ds = _systems((24, 12, 6))
-    say("case batched 128 threads")
+    say("case batched", threads, "threads")
     h, prm = _handle(ds, nproj=20)
-    h.set_launch(128, big_first=False)
+    h.set_launch(threads, big_first=False)
     e0s = [h.e0(k) for k in range(3)]
     pos0 = [d["init_pos"][:d["n_walkers_run"]].copy() for d in ds]
     h.step()
