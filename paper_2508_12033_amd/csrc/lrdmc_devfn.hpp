@@ -61,6 +61,31 @@ __device__ __forceinline__ double wave_sum(double v)
     return lane63(v);
 }
 
+// sums over each row of 16 lanes (result in the row's last lane), and over
+// pairs of rows (result in lanes 31 and 63)
+__device__ __forceinline__ double row16_sum(double v)
+{
+    v += dpp_mov<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_mov<0x118, 0xf>(v);   // row_shr:8
+    return v;
+}
+
+__device__ __forceinline__ double row32_sum(double v)
+{
+    v = row16_sum(v);
+    v += dpp_mov<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    return v;
+}
+
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
 // inclusive prefix sum over the 64 lanes (Hillis-Steele inside 16-lane rows,
 // then row broadcasts)
 __device__ __forceinline__ double wave_incl_scan(double v, int)

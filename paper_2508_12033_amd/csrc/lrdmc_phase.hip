@@ -499,28 +499,53 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     LRDMC_T(3);
 
     // Jastrow and potential caches: pairs (i, k) change from rold to rnew.
-    // Points of the moved electron one at a time, partners over the lanes.
+    // The 7 points of the moved electron (its new position and neighbours):
+    // with at most 32 partners, each point takes one or two rows of 16 lanes,
+    // so 4 or 2 points share a pass and a row reduction; otherwise one point
+    // per pass with a wave reduction.
     const int K = s.N + s.M;
     const int Kj = s.has_en ? K : s.N;
     const int dJi = w.tmp + 3 * s.ns;            // 6 new exponent changes of electron i
-    double S0 = 0.0;
-#pragma unroll 1
-    for (int q = 0; q < 7; ++q) {
-        double pq[3];
-        point_q(rnew, q, a, pq);
-        double acc = 0.0;
-        #pragma unroll 1
-        for (int k = lane; k < Kj; k += kWave) {
-            if (k == i) continue;
-            double pk[3];
-            int jr;
-            partner(s, w, i, k, pk, jr);
-            acc += pade_u(s.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+    double Sq[7];
+    const int rpp = (Kj + 15) >> 4;              // rows of 16 lanes per point
+    if (rpp <= 2) {
+        const int ppp = 4 / rpp, row = lane >> 4;
+        const int qoff = row / rpp, k = (row % rpp) * 16 + (lane & 15);
+        double pk[3] = {0.0, 0.0, 0.0};
+        int jr = 0;
+        const bool kval = k < Kj && k != i;
+        if (kval) partner(s, w, i, k, pk, jr);
+        for (int q0 = 0; q0 < 7; q0 += ppp) {
+            const int q = q0 + qoff;
+            double v = 0.0;
+            if (kval && q < 7) {
+                double pq[3];
+                point_q(rnew, q, a, pq);
+                v = pade_u(s.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+            }
+            v = rpp == 1 ? row16_sum(v) : row32_sum(v);
+            for (int t = 0; t < ppp; ++t)
+                if (q0 + t < 7) Sq[q0 + t] = lane_value(v, 16 * rpp * (t + 1) - 1);
         }
-        acc = wave_sum(acc);
-        if (q == 0) S0 = acc;
-        else if (lane == 0) lds[dJi + q - 1] = acc - S0;
+    } else {
+#pragma unroll 1
+        for (int q = 0; q < 7; ++q) {
+            double pq[3];
+            point_q(rnew, q, a, pq);
+            double acc = 0.0;
+            #pragma unroll 1
+            for (int k = lane; k < Kj; k += kWave) {
+                if (k == i) continue;
+                double pk[3];
+                int jr;
+                partner(s, w, i, k, pk, jr);
+                acc += pade_u(s.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+            }
+            Sq[q] = wave_sum(acc);
+        }
     }
+    if (lane == 0)
+        for (int q = 1; q < 7; ++q) lds[dJi + q - 1] = Sq[q] - Sq[0];
     double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0, dvee = 0.0, nu = 0.0, nua = 0.0;
     #pragma unroll 1
     for (int k = lane; k < K; k += kWave) {
