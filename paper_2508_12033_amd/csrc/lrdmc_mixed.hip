@@ -856,26 +856,39 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
     float* Jl = LDSF(s.l_Jl);
     float* dje = LDSF(s.l_dje);
     double* red = LDSD(s.l_red);
-    // the 7 points of the moved electron, one block sum each
-    double S0 = 0.0;
+    // the 7 points of the moved electron: (point, partner) pairs spread over
+    // the workgroup, one 7-way block reduction
     float* dJi = tmp + 3 * ns;                   // [6] new exponent changes of electron i
-#pragma unroll 1
-    for (int qq = 0; qq < 7; ++qq) {
-        double pq[3];
-        point_q(rnew, qq, a, pq);
-        double acc = 0.0;
+    {
+        double acc7[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         #pragma unroll 1
-        for (int k = tid; k < Kj; k += (int)blockDim.x) {
+        for (int it = tid; it < 7 * Kj; it += (int)blockDim.x) {
+            const int qq = it / Kj, k = it - qq * Kj;
             if (k == i) continue;
-            double pk[3];
+            double pq[3], pk[3];
             int jr;
+            point_q(rnew, qq, a, pq);
             mpartner(s, pos, i, k, pk, jr);
-            acc += (double)pade_uf(s.jas + 3 * jr,
-                                   (float)norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+            const double u = (double)pade_uf(s.jas + 3 * jr,
+                                             (float)norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+#pragma unroll
+            for (int t = 0; t < 7; ++t) acc7[t] += (t == qq) ? u : 0.0;
         }
-        acc = block_sum(acc, red);
-        if (qq == 0) S0 = acc;
-        else if (tid == 0) dJi[qq - 1] = (float)(acc - S0);
+        double* red7 = red + 8;                  // [waves][7]
+        const int lane = tid & 63, wv = tid >> 6, nwv = (int)blockDim.x >> 6;
+#pragma unroll
+        for (int t = 0; t < 7; ++t) {
+            const double v = wave_sum(acc7[t]);
+            if (lane == 0) red7[wv * 7 + t] = v;
+        }
+        __syncthreads();
+        if (tid < 7) {
+            double v = red7[tid];
+            for (int q = 1; q < nwv; ++q) v += red7[q * 7 + tid];
+            red7[28 + tid] = v;
+        }
+        __syncthreads();
+        if (tid > 0 && tid < 7) dJi[tid - 1] = (float)(red7[28 + tid] - red7[28]);
     }
     double g0 = 0, g1 = 0, g2 = 0, l = 0, dvee = 0, nu = 0, nua = 0;
     #pragma unroll 1
