@@ -157,6 +157,11 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
                                                  // extra 4 floats spread the rows over the banks)
     float* rows = LDSF(s.l_rows);
     const int ldb = s.nb32 + 4;
+    // the padding columns [Nb, ldb) of the 11 rows are read by the BF16 path
+    for (int z = tid; z < 11 * (ldb - Nb); z += (int)blockDim.x) {
+        const int row = z / (ldb - Nb);
+        B[row * ldb + Nb + (z - row * (ldb - Nb))] = 0.0f;
+    }
     for (int it = tid; it < items; it += (int)blockDim.x) {
         const int q = it / Nb, mu = it - q * Nb;
         double p[3];
@@ -287,10 +292,11 @@ __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
     double* M = LDSD(s.l_U);                     // [n][n]
     double* sc = LDSD(s.l_scal);
     int* piv = reinterpret_cast<int*>(LDSF(s.l_tmp));
-    for (int idx = tid; idx < n * n; idx += (int)blockDim.x) {
-        const int r = idx / n, c = idx - r * n;
-        M[idx] = (double)Arow[(long)(off + c) * ns + r];
-    }
+    // fixed column per thread, rows strided: no division in the n^2 loops
+    const int rs = (int)blockDim.x / n, c0 = tid % n, r0 = tid / n;
+    const bool act = tid < rs * n;
+    if (act)
+        for (int r = r0; r < n; r += rs) M[r * n + c0] = (double)Arow[(long)(off + c0) * ns + r];
     __syncthreads();
     double logdet = 0.0, sign = 1.0;
     bool ok = true;
@@ -298,9 +304,9 @@ __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
     for (int k = 0; k < n; ++k) {
         // pivot: largest |M[r][k]|, r >= k, first index among equals; every
         // wave finds it with a butterfly over its lanes (n <= 64)
-        const int r0 = k + lane;
-        double best = r0 < n ? fabs(M[r0 * n + k]) : -1.0;
-        int bi = r0 < n ? r0 : n;
+        const int rp = k + lane;
+        double best = rp < n ? fabs(M[rp * n + k]) : -1.0;
+        int bi = rp < n ? rp : n;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             const double ob = __shfl_xor(best, o);
@@ -330,11 +336,12 @@ __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
         __syncthreads();
         for (int c = tid; c < n; c += (int)blockDim.x) M[k * n + c] = (c == k ? 1.0 : M[k * n + c]) * id;
         __syncthreads();
-        for (int idx = tid; idx < n * n; idx += (int)blockDim.x) {
-            const int r = idx / n, c = idx - r * n;
-            if (r == k) continue;
-            const double f = colk[r];
-            M[idx] = (c == k ? 0.0 : M[idx]) - f * M[k * n + c];
+        if (act) {
+            const double mk = M[k * n + c0];
+            for (int r = r0; r < n; r += rs) {
+                if (r == k) continue;
+                M[r * n + c0] = (c0 == k ? 0.0 : M[r * n + c0]) - colk[r] * mk;
+            }
         }
         __syncthreads();
     }
@@ -350,10 +357,8 @@ __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
                 }
             __syncthreads();
         }
-        for (int idx = tid; idx < n * n; idx += (int)blockDim.x) {
-            const int c = idx / n, k = idx - c * n;
-            AiT[(long)c * ns + k] = (TD)M[idx];
-        }
+        if (act)
+            for (int r = r0; r < n; r += rs) AiT[(long)r * ns + c0] = (TD)M[r * n + c0];
         if (tid == 0) { sc[kScLogdet0 + sp] = logdet; sc[kScSign0 + sp] = sign; }
     }
     global_handoff();
@@ -366,50 +371,55 @@ __device__ __noinline__ bool mixed_refresh_inverse(const DevMix* __restrict__ dm
     return gj_inverse<float, float>(s, st + s.g_Arow, st + s.g_AinvT + (long)sp * s.ns * s.ns, sp);
 }
 
-// determinant gradients / Laplacians of the electrons of spin sp (sp < 0:
-// both spins): gD[j][q] = dPhi_j[q] . AinvT[c_j]
-__device__ __noinline__ void mixed_gD(const DevMix* __restrict__ dm, const float* st, int sp)
+// Determinant gradients / Laplacians gD[j][0..3] = dPhi_j . AinvT[c_j] and
+// determinant ratios Rdet_p = Phi_p . AinvT[c] of every move of the electrons
+// of spin sp, with the inverse staged in LDS (the basis-row block is free
+// here; mixed_rows restores its zero padding).
+__device__ __noinline__ void mixed_spin_update(const DevMix* __restrict__ dm, const float* st, int sp)
 {
     const DevMix& s = *dm;
-    const int tid = threadIdx.x, ns = s.ns;
+    const int tid = threadIdx.x, nt = blockDim.x, ns = s.ns;
+    const int n = mnspin(s, sp), off = sp ? s.Nup : 0;
+    if (!n) return;
+    float* AiL = LDSF(s.l_U);                    // [n][ns]
+    const float* Ai = st + s.g_AinvT + (long)sp * ns * ns;
+    for (int idx = tid; idx < n * ns; idx += nt) AiL[idx] = Ai[idx];
+    __syncthreads();
     float* gD = LDSF(s.l_gD);
-    for (int spin = 0; spin < 2; ++spin) {
-        if (sp >= 0 && spin != sp) continue;
-        const int n = mnspin(s, spin), off = spin ? s.Nup : 0;
-        const float* dPhi = st + s.g_dPhi + (long)spin * ns * 4 * ns;
-        const float* Ai = st + s.g_AinvT + (long)spin * ns * ns;
-        for (int it = tid; it < 4 * n; it += (int)blockDim.x) {
-            const int c = it >> 2;
-            float acc = 0.f;
-            for (int k = 0; k < n; ++k) acc += dPhi[(long)k * 4 * ns + it] * Ai[(long)c * ns + k];
-            gD[4 * (off + c) + (it & 3)] = acc;
+    float* Rdet = LDSF(s.l_Rdet);
+    const float* dPhi = st + s.g_dPhi + (long)sp * ns * 4 * ns;
+    const float* Phi = st + s.g_Phi + (long)sp * ns * 6 * ns;
+    // 4n gradient items then 6n ratio items
+    for (int it = tid; it < 10 * n; it += nt) {
+        const bool isg = it < 4 * n;
+        const int q = isg ? it : it - 4 * n;
+        const int c = isg ? (q >> 2) : q / 6;
+        const float* col = isg ? dPhi + q : Phi + q;
+        const long stride = isg ? 4L * ns : 6L * ns;
+        const float* a = AiL + c * ns;
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        int k = 0;
+        for (; k + 4 <= n; k += 4) {
+            s0 += col[(long)k * stride] * a[k];
+            s1 += col[(long)(k + 1) * stride] * a[k + 1];
+            s2 += col[(long)(k + 2) * stride] * a[k + 2];
+            s3 += col[(long)(k + 3) * stride] * a[k + 3];
         }
+        for (; k < n; ++k) s0 += col[(long)k * stride] * a[k];
+        const float v = (s0 + s1) + (s2 + s3);
+        if (isg) gD[4 * (off + c) + (q & 3)] = v;
+        else Rdet[6 * off + q] = v;
     }
     __syncthreads();
 }
 
-// ratios of the moves of spin sp (sp < 0: both); R = Rdet * exp(dJ) for all
-__device__ __noinline__ void mixed_ratios(const DevMix* __restrict__ dm, const float* st, int sp)
+// R = Rdet * exp(dJ) for every move
+__device__ __forceinline__ void mixed_full_ratios(const DevMix& s)
 {
-    const DevMix& s = *dm;
-    const int tid = threadIdx.x, ns = s.ns;
     float* R = LDSF(s.l_R);
-    float* Rdet = LDSF(s.l_Rdet);
+    const float* Rdet = LDSF(s.l_Rdet);
     const float* dJ = LDSF(s.l_dJ);
-    for (int spin = 0; spin < 2; ++spin) {
-        if (sp >= 0 && spin != sp) continue;
-        const int n = mnspin(s, spin), off = spin ? s.Nup : 0;
-        const float* Phi = st + s.g_Phi + (long)spin * ns * 6 * ns;
-        const float* Ai = st + s.g_AinvT + (long)spin * ns * ns;
-        for (int q = tid; q < 6 * n; q += (int)blockDim.x) {
-            const int c = q / 6;
-            float acc = 0.f;
-            for (int k = 0; k < n; ++k) acc += Phi[(long)k * 6 * ns + q] * Ai[(long)c * ns + k];
-            Rdet[6 * off + q] = acc;
-        }
-    }
-    __syncthreads();
-    for (int p = tid; p < s.P; p += (int)blockDim.x) R[p] = Rdet[p] * expf(dJ[p]);
+    for (int p = threadIdx.x; p < s.P; p += (int)blockDim.x) R[p] = Rdet[p] * expf(dJ[p]);
     __syncthreads();
 }
 
@@ -487,8 +497,9 @@ __device__ __noinline__ bool mixed_refresh(const DevMix* __restrict__ dm, float*
     ok = mixed_refresh_inverse(&s, st, 1) && ok;
     const double vee = mixed_jastrow_all(&s, a);
     if (threadIdx.x == 0) LDSD(s.l_scal)[kScVee] = vee;
-    mixed_gD(&s, st, -1);
-    mixed_ratios(&s, st, -1);
+    mixed_spin_update(&s, st, 0);
+    mixed_spin_update(&s, st, 1);
+    mixed_full_ratios(s);
     return ok;
 }
 
@@ -847,7 +858,7 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
 
     mixed_rows(&s, i, rnew, a);
     mixed_store_rows(&s, st, i, false);
-    mixed_gD(&s, st, sp);
+    mixed_spin_update(&s, st, sp);
 
     // Jastrow caches of the moved electron (7 points) and of its partners
     const int K = s.N + s.M, Kj = s.has_en ? K : s.N;
@@ -950,7 +961,7 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
         pos[3 * i + d] = rnew[d];
     }
     __syncthreads();
-    mixed_ratios(&s, st, sp);
+    mixed_full_ratios(s);
     return fabsf(Rd) < 1e-6f;
 }
 
@@ -973,10 +984,6 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
     float* st = s.state + (long)wid * s.stride;
     double* pos = LDSD(s.l_pos);
     for (int q = tid; q < 3 * s.N; q += (int)blockDim.x) pos[q] = s.pos[(long)wid * 3 * s.N + q];
-    {
-        float* B = LDSF(s.l_U);   // zero the padding of the basis rows once
-        for (int q = tid; q < 11 * (s.nb32 + 4); q += (int)blockDim.x) B[q] = 0.0f;
-    }
     __syncthreads();
     const double a = pa.a;
     if (build) {
@@ -989,12 +996,6 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
     unsigned long long n_neg = 0, n_nomove = 0, n_refresh = 1, n_small = 0, n_sing = 0,
                        n_capped = 0;
     if (!mixed_refresh(&s, st, a)) n_sing++;
-    // the Gauss-Jordan scratch overlaps the basis rows: restore their padding
-    {
-        float* B = LDSF(s.l_U);
-        for (int q = tid; q < 11 * (s.nb32 + 4); q += (int)blockDim.x) B[q] = 0.0f;
-        __syncthreads();
-    }
 
     double lw = s.lw[wid];
     double tau_left = pa.tau;
@@ -1042,9 +1043,6 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
             if (small) n_small++;
             if (small || since >= pa.refresh_every) {
                 if (!mixed_refresh(&s, st, a)) n_sing++;
-                float* B = LDSF(s.l_U);
-                for (int z = tid; z < 11 * (s.nb32 + 4); z += (int)blockDim.x) B[z] = 0.0f;
-                __syncthreads();
                 n_refresh++;
                 since = 0;
             }
