@@ -149,7 +149,7 @@ typedef struct lrdmc_energy {
 typedef struct lrdmc_tune_entry {
     int32_t threads;          /* workgroup size of the mixed-precision phase kernel */
     int32_t order_big_first;  /* 1: systems with more electrons first in the launch */
-    float ms;                 /* measured time of the tuning phase */
+    float ms;                 /* projected time of a full phase */
 } lrdmc_tune_entry;
 
 /* ---- calls ------------------------------------------------------------- */
@@ -194,8 +194,9 @@ int lrdmc_run(struct lrdmc_handle *h, int n_branchings, lrdmc_step_stats *st,
 /* Autotuner of the mixed-precision launch (every mixed-precision system of
  * the handle advances in one launch): each candidate workgroup size (256, 128
  * or 64 threads per walker) and order of the systems in the launch is timed on
- * a copy of the current walkers for n_steps load-balanced steps; the fastest
- * is kept for later phases.  The walkers, weights, E_0 and random streams of
+ * a copy of the current walkers for n_steps and 2 n_steps load-balanced
+ * steps, and the one with the shortest projected full phase (fixed cost plus
+ * N_proj times the per-step cost) is kept for later phases.  The walkers, weights, E_0 and random streams of
  * the run are not changed.  log (may be NULL) receives up to log_cap timings,
  * *n_log their number.  Synchronises.  No effect for FP64 handles. */
 int lrdmc_autotune(struct lrdmc_handle *h, int n_steps, lrdmc_tune_entry *log, int log_cap,

@@ -337,6 +337,13 @@ struct lrdmc_handle {
 
 namespace {
 
+int maxN_all(const lrdmc_handle* h)
+{
+    int m = 1;
+    for (int k : h->mix_order) m = std::max(m, h->sys[k].N);
+    return m;
+}
+
 int upload_mix_tables(lrdmc_handle* h)
 {
     const int n = (int)h->mix_order.size();
@@ -987,8 +994,9 @@ int lrdmc_run(lrdmc_handle* h, int n_branchings, lrdmc_step_stats* st, lrdmc_bra
 
 // Autotuner of the mixed-precision launch: workgroup size (64, 128 or 256
 // threads per walker) x order of the systems in the launch, each candidate timed on a
-// copy of the current walkers (the other slot) for n_steps load-balanced
-// steps; the fastest is kept.  Stream-synchronous.
+// copy of the current walkers (the other slot) for n_steps and 2 n_steps
+// load-balanced steps; the one with the shortest projected full phase is
+// kept.  Stream-synchronous.
 int lrdmc_autotune(lrdmc_handle* h, int n_steps, lrdmc_tune_entry* log, int log_cap, int* n_log)
 {
     if (!h || n_steps < 1) return fail(LRDMC_ERR_INVALID_ARG, "bad arguments");
@@ -1021,7 +1029,11 @@ int lrdmc_autotune(lrdmc_handle* h, int n_steps, lrdmc_tune_entry* log, int log_
             h->mix_order = orders[oi];
             h->mix_threads = threads[ti];
             if ((rc = upload_mix_tables(h))) break;
-            float ms_best = 1e30f;
+            // two tuning phases of n_steps and 2 n_steps: the difference is the
+            // per-step cost, the rest the fixed cost of a phase (refresh, FP64
+            // estimator evaluation); the candidate is ranked by the projected
+            // time of a full phase
+            float tms[2] = {0.f, 0.f};
             for (int rep = 0; rep < 2 && !rc; ++rep) {
                 for (int k : h->mix_order) {
                     SysRun& r = h->sys[k];
@@ -1043,16 +1055,21 @@ int lrdmc_autotune(lrdmc_handle* h, int n_steps, lrdmc_tune_entry* log, int log_
                     maxN = std::max(maxN, h->sys[h->mix_order[k]].N);
                 }
                 b.start[b.nsys] = tot;
-                const PhaseArgs pa = phase_args(h, maxN, n_steps);
+                const PhaseArgs pa = phase_args(h, maxN, n_steps * (rep + 1));
                 hipLaunchKernelGGL(phase_mixed, dim3(tot), dim3(h->mix_threads), h->mix_lds,
                                    h->stream, b, pa, 0);
                 HIPCHK(hipGetLastError());
                 HIPCHK(hipEventRecord(h->ev1, h->stream));
                 HIPCHK(hipStreamSynchronize(h->stream));
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-                ms_best = std::min(ms_best, ms);
+                HIPCHK(hipEventElapsedTime(&tms[rep], h->ev0, h->ev1));
             }
+            const float per_step = std::max(0.f, (tms[1] - tms[0]) / n_steps);
+            const float fixed = std::max(0.f, tms[0] - per_step * n_steps);
+            const int steps_full = h->prm.scheme == LRDMC_SCHEME_LB
+                                       ? h->prm.n_proj
+                                       : std::max(1, (int)(h->prm.tau * 3.0 * maxN_all(h) /
+                                                           (h->prm.a * h->prm.a)));
+            const float ms_best = fixed + per_step * steps_full;
             if (rc) break;
             lrdmc_tune_entry e;
             e.threads = h->mix_threads;
