@@ -40,7 +40,7 @@ struct DevSys {
     int trace_cap;
     // LDS layout of one walker (offsets in doubles)
     int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje,
-        o_scal, o_B, o_rows, o_tmp, o_C, lds_doubles;
+        o_scal, o_B, o_rows, o_tmp, o_C, o_bK, lds_doubles;
     // spill layout (offsets in doubles inside a walker's spill block)
     int s_Phi, s_dPhi;
 };

@@ -198,14 +198,17 @@ __device__ __forceinline__ void basis_vgl_d(int t, double al, double dx, double 
         v = e;
         for (int c = 0; c < 3; ++c) g[c] = -al * d[c] * id * e;
         l = (al * al - 2.0 * al * id) * e;
-    } else if (t == 0) {
-        const double e = exp(-al * d2);
+        return;
+    }
+    // s and p Gaussians share one exponential
+    const double e = exp(-al * d2);
+    if (t == 0) {
         v = e;
         for (int c = 0; c < 3; ++c) g[c] = -2.0 * al * d[c] * e;
         l = (4.0 * al * al * d2 - 6.0 * al) * e;
     } else {
         const int q = t - 1;
-        const double e = exp(-al * d2), dq = d[q];
+        const double dq = d[q];
         v = dq * e;
         for (int c = 0; c < 3; ++c) g[c] = ((c == q) ? e : 0.0) - 2.0 * al * dq * d[c] * e;
         l = dq * e * (4.0 * al * al * d2 - 10.0 * al);

@@ -75,7 +75,7 @@ struct Layout {
     int kind, N, P, ns;
     // FP64 kernel: LDS offsets (doubles), spill layout
     int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje, o_scal, o_B,
-        o_rows, o_tmp, o_C, lds_doubles;
+        o_rows, o_tmp, o_C, o_bK, lds_doubles;
     int s_Phi, s_dPhi;
     long spill_stride;
     // mixed kernel: LDS byte offsets, walker block (floats)
@@ -132,6 +132,7 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.o_rows = take(11 * ns);
         L.o_tmp = take(3 * ns + 8);
         L.o_C = take(Nb * ns);
+        L.o_bK = take(Nb);
         L.lds_doubles = o;
         L.lds_bytes = (size_t)o * 8;
         L.s_Phi = 0;
@@ -784,6 +785,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             d.o_Arow = L.o_Arow; d.o_AinvT = L.o_AinvT; d.o_Jg = L.o_Jg; d.o_Jl = L.o_Jl;
             d.o_nue = L.o_nue; d.o_nua = L.o_nua; d.o_dje = L.o_dje; d.o_scal = L.o_scal;
             d.o_B = L.o_B; d.o_rows = L.o_rows; d.o_tmp = L.o_tmp; d.o_C = L.o_C;
+            d.o_bK = L.o_bK;
             d.lds_doubles = L.lds_doubles;
             d.s_Phi = L.s_Phi; d.s_dPhi = L.s_dPhi;
             for (int p = 0; p < 2; ++p) {

@@ -60,7 +60,7 @@ __device__ __forceinline__ void block_visible()
 extern __shared__ double lds[];
 
 struct Walker {
-    int pos, R, Rdet, dJ, Arow, AinvT, Jg, Jl, nue, nua, dje, scal, B, rows, tmp, C;
+    int pos, R, Rdet, dJ, Arow, AinvT, Jg, Jl, nue, nua, dje, scal, B, rows, tmp, C, bK;
     double* Phi;
     double* dPhi;
 };
@@ -72,6 +72,7 @@ __device__ __forceinline__ Walker walker_view(const DevSys& s)
     w.AinvT = s.o_AinvT; w.Jg = s.o_Jg; w.Jl = s.o_Jl; w.nue = s.o_nue; w.nua = s.o_nua;
     w.dje = s.o_dje; w.scal = s.o_scal; w.B = s.o_B; w.rows = s.o_rows; w.tmp = s.o_tmp;
     w.C = s.o_C;
+    w.bK = s.o_bK;
     double* base = s.spill + (long)blockIdx.x * s.spill_stride;
     w.Phi = base + s.s_Phi;
     w.dPhi = base + s.s_dPhi;
@@ -101,50 +102,80 @@ __device__ __forceinline__ void partner(const DevSys& s, const Walker& w, int i,
     }
 }
 
+// 1/x to about one ulp: hardware reciprocal estimate and two Newton steps.
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 // Orbital rows of electron j at position r (11 rows, columns k < n_j):
 // row 0 the value at r, rows 1..6 the values at the six lattice neighbours
 // r +- a e_d (move order), rows 7..9 the gradient, row 10 the Laplacian.
-// Basis functions: one lane per (point, function).  Orbitals: the 11 x Nb
-// basis block times the Nb x n coefficient block on FP64 MFMA (16x16x4
-// tiles; rows 11..15 and columns >= n are padding).
+//
+// Basis values: one lane per function.  A Gaussian factorizes over the
+// coordinates, so at the neighbour r + s a e_c (s = +-1)
+//   exp(-alpha |d + s a e_c|^2) = exp(-alpha d^2) exp(-alpha a^2) exp(-2 s alpha a d_c),
+// with d = r - centre: four exponentials (the per-function constant
+// exp(-alpha a^2) is tabulated once per phase) and three reciprocals give all
+// seven values, and the value at r gives the gradient and Laplacian.  Slater
+// functions take the seven points directly.  Orbitals: the 11 x Nb basis
+// block times the Nb x n coefficient block on FP64 MFMA (16x16x4 tiles; rows
+// 11..15 and columns >= n are padding).
 __device__ void electron_rows(const DevSys& s, const Walker& w, int j, const double* r, double a,
                               int lane)
 {
-    const int Nb = s.Nb, items = 7 * Nb;
-    // basis records of the next item are fetched one iteration ahead
-    int it = lane;
-    double4_t rec = {0.0, 0.0, 0.0, 0.0};
-    int typ = 0;
-    if (it < items) {
-        const int mu = it % Nb;
-        rec = *(const double4_t*)(s.btab + 4 * mu);
-        typ = s.btype[mu];
-    }
-    for (; it < items; it += kWave) {
-        const int q = it / Nb, mu = it - q * Nb;
-        const double4_t cur = rec;
-        const int ct = typ;
-        const int nx = it + kWave;
-        if (nx < items) {
-            const int mun = nx % Nb;
-            rec = *(const double4_t*)(s.btab + 4 * mun);
-            typ = s.btype[mun];
-        }
-        double p[3];
-        point_q(r, q, a, p);
-        const double dx = p[0] - cur[0], dy = p[1] - cur[1], dz = p[2] - cur[2];
-        const double d2 = dx * dx + dy * dy + dz * dz, al = cur[3];
-        if (q == 0) {
-            double v, g[3], l;
-            basis_vgl_d(ct, al, dx, dy, dz, d2, v, g, l);
-            lds[w.B + mu] = v;
-            lds[w.B + 7 * Nb + mu] = g[0];
-            lds[w.B + 8 * Nb + mu] = g[1];
-            lds[w.B + 9 * Nb + mu] = g[2];
-            lds[w.B + 10 * Nb + mu] = l;
+    const int Nb = s.Nb;
+    for (int mu = lane; mu < Nb; mu += kWave) {
+        const double4_t c = *(const double4_t*)(s.btab + 4 * mu);
+        const int t = s.btype[mu];
+        const double al = c[3];
+        const double d[3] = {r[0] - c[0], r[1] - c[1], r[2] - c[2]};
+        const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        double* Bm = lds + w.B + mu;
+        double v, g[3], l;
+        if (t == 4) {
+            for (int q = 1; q < 7; ++q) {
+                double pq[3];
+                point_q(r, q, a, pq);
+                const double dx = pq[0] - c[0], dy = pq[1] - c[1], dz = pq[2] - c[2];
+                Bm[q * Nb] = basis_value_d(t, al, dx, dy, dz, dx * dx + dy * dy + dz * dz);
+            }
+            basis_vgl_d(t, al, d[0], d[1], d[2], d2, v, g, l);
         } else {
-            lds[w.B + q * Nb + mu] = basis_value_d(ct, al, dx, dy, dz, d2);
+            const double e = exp(-al * d2);
+            const double K = lds[w.bK + mu];
+            const double s2a = 2.0 * al * a;
+            // polynomial factor: 1 (s) or the displacement along the p axis
+            const int ax = t - 1;
+            const double f0 = t == 0 ? 1.0 : (ax == 0 ? d[0] : (ax == 1 ? d[1] : d[2]));
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                // exponent clamped: beyond +-700 the value at r has underflowed
+                const double x = fmin(fmax(-s2a * d[cc], -700.0), 700.0);
+                const double tc = exp(x);
+                const double ep = e * (K * tc), em = e * (K * recip(tc));
+                const double fp = (t != 0 && ax == cc) ? f0 + a : f0;
+                const double fm = (t != 0 && ax == cc) ? f0 - a : f0;
+                Bm[(2 * cc + 1) * Nb] = fp * ep;
+                Bm[(2 * cc + 2) * Nb] = fm * em;
+            }
+            if (t == 0) {
+                v = e;
+                for (int cc = 0; cc < 3; ++cc) g[cc] = -2.0 * al * d[cc] * e;
+                l = (4.0 * al * al * d2 - 6.0 * al) * e;
+            } else {
+                v = f0 * e;
+                for (int cc = 0; cc < 3; ++cc) g[cc] = ((cc == ax) ? e : 0.0) - 2.0 * al * f0 * d[cc] * e;
+                l = f0 * e * (4.0 * al * al * d2 - 10.0 * al);
+            }
         }
+        Bm[0] = v;
+        Bm[7 * Nb] = g[0];
+        Bm[8 * Nb] = g[1];
+        Bm[9 * Nb] = g[2];
+        Bm[10 * Nb] = l;
     }
     wave_sync();
     const int n = nspin(s, spin_of(s, j));
@@ -192,8 +223,8 @@ __device__ void store_rows(const DevSys& s, const Walker& w, int j, int lane, bo
         const int row = idx / n, k = idx - row * n;
         const double v = lds[w.rows + row * s.ns + k];
         if (row == 0) { if (arow) lds[w.Arow + j * s.ns + k] = v; }
-        else if (row <= 6) w.Phi[(6 * j + row - 1) * s.ns + k] = v;
-        else w.dPhi[(4 * j + row - 7) * s.ns + k] = v;
+        else if (row <= 6) w.Phi[k * s.P + 6 * j + row - 1] = v;
+        else w.dPhi[k * 4 * s.N + 4 * j + row - 7] = v;
     }
     block_visible();
 }
@@ -270,9 +301,9 @@ __device__ void recompute_ratios(const DevSys& s, const Walker& w, int sp, int l
         if (sp < 0 || spj == sp) {
             const int n = nspin(s, spj), c = col_of(s, j);
             const int ai = w.AinvT + spj * s.ns * s.ns + c * s.ns;
-            const double* ph = w.Phi + p * s.ns;
+            const double* ph = w.Phi + p;
             double rd = 0.0;
-            for (int k = 0; k < n; ++k) rd += ph[k] * lds[ai + k];
+            for (int k = 0; k < n; ++k) rd += ph[k * s.P] * lds[ai + k];
             lds[w.Rdet + p] = rd;
         }
         lds[w.R + p] = lds[w.Rdet + p] * exp(lds[w.dJ + p]);
@@ -379,35 +410,43 @@ __device__ Local evaluate(const DevSys& s, const Walker& w, double a, int nu_mod
     bs = wave_sum(bs);
     vs = wave_sum(vs);
     const bool anynode = __ballot(anyneg) != 0;
+    // determinant gradient and Laplacian of electron j: lane 4j + c computes
+    // component c (x, y, z, Laplacian) from the k-major spill, and the quad's
+    // first lane gathers the four
     double sum_opt = 0.0;
-    for (int j = lane; j < s.N; j += kWave) {
-        const int sp = spin_of(s, j), n = nspin(s, sp), c = col_of(s, j);
-        const int ai = w.AinvT + sp * s.ns * s.ns + c * s.ns;
-        const double* dp = w.dPhi + 4 * j * s.ns;
-        double g0 = 0, g1 = 0, g2 = 0, ld = 0;
-        for (int k = 0; k < n; ++k) {
-            const double x = lds[ai + k];
-            g0 += dp[k] * x;
-            g1 += dp[s.ns + k] * x;
-            g2 += dp[2 * s.ns + k] * x;
-            ld += dp[3 * s.ns + k] * x;
+    const int N4 = 4 * s.N;
+    for (int base = 0; base < N4; base += kWave) {
+        const int it = base + lane, j = it >> 2;
+        const bool act = it < N4;
+        double val = 0.0;
+        if (act) {
+            const int sp = spin_of(s, j), n = nspin(s, sp), c = col_of(s, j);
+            const int ai = w.AinvT + sp * s.ns * s.ns + c * s.ns;
+            const double* dp = w.dPhi + it;
+            for (int k = 0; k < n; ++k) val += dp[k * N4] * lds[ai + k];
         }
-        const double j0 = lds[w.Jg + 3 * j], j1 = lds[w.Jg + 3 * j + 1], j2 = lds[w.Jg + 3 * j + 2];
-        const double lap = ld + 2.0 * (g0 * j0 + g1 * j1 + g2 * j2) + lds[w.Jl + j] +
-                           j0 * j0 + j1 * j1 + j2 * j2;
-        double lapA = 0.0;
-        int nd = 0;
-        for (int q = 0; q < 6; ++q) {
-            const double r = lds[w.R + 6 * j + q];
-            lapA += (r - 1.0) / (a * a);
-            if (r < 0) nd = 1;
+        const double v1 = dpp_mov<0x55, 0xf>(val);   // quad_perm [1,1,1,1]
+        const double v2 = dpp_mov<0xaa, 0xf>(val);   // quad_perm [2,2,2,2]
+        const double v3 = dpp_mov<0xff, 0xf>(val);   // quad_perm [3,3,3,3]
+        if (act && (lane & 3) == 0) {
+            const double g0 = val, g1 = v1, g2 = v2, ld = v3;
+            const double j0 = lds[w.Jg + 3 * j], j1 = lds[w.Jg + 3 * j + 1], j2 = lds[w.Jg + 3 * j + 2];
+            const double lap = ld + 2.0 * (g0 * j0 + g1 * j1 + g2 * j2) + lds[w.Jl + j] +
+                               j0 * j0 + j1 * j1 + j2 * j2;
+            double lapA = 0.0;
+            int nd = 0;
+            for (int q = 0; q < 6; ++q) {
+                const double r = lds[w.R + 6 * j + q];
+                lapA += (r - 1.0) / (a * a);
+                if (r < 0) nd = 1;
+            }
+            if (nu_mode == 1) nd = anynode;
+            if (nu_mode == 2) nd = 1;
+            const double nuzv = lds[w.nue + j] + 0.5 * (lapA - lap);
+            const double nua = lds[w.nua + j];
+            const double numax = nuzv > nua ? nuzv : nua;
+            sum_opt += nd ? numax : nuzv;
         }
-        if (nu_mode == 1) nd = anynode;
-        if (nu_mode == 2) nd = 1;
-        const double nuzv = lds[w.nue + j] + 0.5 * (lapA - lap);
-        const double nua = lds[w.nua + j];
-        const double numax = nuzv > nua ? nuzv : nua;
-        sum_opt += nd ? numax : nuzv;
     }
     sum_opt = wave_sum(sum_opt);
     Local L;
@@ -461,7 +500,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
 {
     const int i = p / 6, d = (p / 2) % 3, sg = p % 2;
     const int sp = spin_of(s, i), c = col_of(s, i), n = nspin(s, sp);
-    const double Rd = lds[w.Rdet + p];
+    const double Rd = lds[w.Rdet + p], iRd = 1.0 / Rd;
     const double rold[3] = {lds[w.pos + 3 * i], lds[w.pos + 3 * i + 1], lds[w.pos + 3 * i + 2]};
     double rnew[3] = {rold[0], rold[1], rold[2]};
     rnew[d] = rnew[d] + (sg ? -a : a);
@@ -470,7 +509,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     const int Ai = w.AinvT + sp * s.ns * s.ns;
     const int u = w.tmp, rowc = w.tmp + s.ns, beta = w.tmp + 2 * s.ns;
     for (int k = lane; k < n; k += kWave) {
-        lds[u + k] = w.Phi[p * s.ns + k];
+        lds[u + k] = w.Phi[k * s.P + p];
         lds[rowc + k] = lds[Ai + c * s.ns + k];
     }
     wave_sync();
@@ -482,8 +521,8 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     wave_sync();
     for (int idx = lane; idx < n * n; idx += kWave) {
         const int cc = idx / n, k = idx - cc * n;
-        if (cc == c) lds[Ai + cc * s.ns + k] = lds[rowc + k] / Rd;
-        else lds[Ai + cc * s.ns + k] -= lds[rowc + k] * (lds[beta + cc] / Rd);
+        if (cc == c) lds[Ai + cc * s.ns + k] = lds[rowc + k] * iRd;
+        else lds[Ai + cc * s.ns + k] -= lds[rowc + k] * (lds[beta + cc] * iRd);
     }
     for (int k = lane; k < n; k += kWave) lds[w.Arow + i * s.ns + k] = lds[u + k];
     if (lane == 0) {
@@ -641,8 +680,10 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
         const int mu = q / s.ns, k = q - mu * s.ns;
         lds[w.C + q] = s.C[mu * s.Norb + k];
     }
-    wave_sync();
     const double a = pa.a;
+    // per-function Gaussian factor exp(-alpha a^2) of a lattice step
+    for (int mu = lane; mu < s.Nb; mu += kWave) lds[w.bK + mu] = exp(-s.btab[4 * mu + 3] * a * a);
+    wave_sync();
     // orbital rows of every electron, then the FP64 refresh
     for (int j = 0; j < s.N; ++j) {
         const double r[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
@@ -661,9 +702,20 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
 #ifdef LRDMC_SECTION_TIMERS
     unsigned long long sect[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #endif
+    // uniforms of 64 consecutive iterations, lane l holding iteration m0 + l
+    // (the draws are counter-based, so drawing ahead changes nothing)
+    double xmove = 0.0, xpers = 0.0;
     LRDMC_T0();
     for (;;) {
         if (pa.scheme == 0 && it >= pa.nproj) break;
+        if ((it & (kWave - 1)) == 0) {
+            xmove = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb,
+                                   (uint64_t)(it + lane), kMove);
+            if (pa.scheme == 1)
+                xpers = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb,
+                                       (uint64_t)(it + lane), kPersist);
+        }
+        const int slot = it & (kWave - 1);
         L = evaluate(s, w, a, pa.nu_mode, lane);
         LRDMC_T(0);
         int q;
@@ -672,14 +724,11 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
             if (!(den > 0)) { lw = -INFINITY; n_neg++; }
             else if (!(L.bbar > 0)) { lw = -INFINITY; n_nomove++; }
             else lw += log(L.bbar) - log(den);
-            const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb,
-                                             (uint64_t)it, kMove);
-            q = heat_bath(s, w, xi, lane);
+            q = heat_bath(s, w, lane_value(xmove, slot), lane);
             if (tr && it < s.trace_cap && lane == 0) tr[it] = q;
             ++it;
         } else {
-            const double xt = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb,
-                                             (uint64_t)it, kPersist);
+            const double xt = lane_value(xpers, slot);
             const double t = (L.bbar > 0) ? -log1p(-xt) / L.bbar : INFINITY;
             if (!(L.bbar > 0)) n_nomove++;
             // the iteration cap only guarantees termination; it is never
@@ -695,9 +744,7 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
                 if (tr && it - 1 < s.trace_cap && lane == 0) tr[it - 1] = -1;
                 break;
             }
-            const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb,
-                                             (uint64_t)(it - 1), kMove);
-            q = heat_bath(s, w, xi, lane);
+            q = heat_bath(s, w, lane_value(xmove, slot), lane);
             if (tr && it - 1 < s.trace_cap && lane == 0) tr[it - 1] = q;
         }
         LRDMC_T(1);
