@@ -28,6 +28,7 @@ struct DevSys {
     // system arrays (device)
     const double *R, *Z, *rc, *bexp, *C, *jas;
     const double *btab;      // [Nb][4]: centre x, y, z and exponent of each basis function
+    const double *bK;        // [Nb]: exp(-alpha a^2), the Gaussian factor of one lattice step
     const int32_t *core, *spec, *batom, *btype;
     // walker arrays (device)
     double *pos;             // [nw][N][3]
@@ -40,7 +41,7 @@ struct DevSys {
     int trace_cap;
     // LDS layout of one walker (offsets in doubles)
     int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje,
-        o_scal, o_B, o_rows, o_tmp, o_C, o_bK, lds_doubles;
+        o_scal, o_B, o_rows, o_tmp, o_C, o_nuc, o_jas, o_gd, lds_doubles;
     // spill layout (offsets in doubles inside a walker's spill block)
     int s_Phi, s_dPhi;
 };

@@ -75,7 +75,7 @@ struct Layout {
     int kind, N, P, ns;
     // FP64 kernel: LDS offsets (doubles), spill layout
     int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje, o_scal, o_B,
-        o_rows, o_tmp, o_C, o_bK, lds_doubles;
+        o_rows, o_tmp, o_C, o_nuc, o_jas, o_gd, lds_doubles;
     int s_Phi, s_dPhi;
     long spill_stride;
     // mixed kernel: LDS byte offsets, walker block (floats)
@@ -104,7 +104,7 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
     const size_t nw = s.n_walkers;
     L.b_sys = align_up(M * 3 * 8) + 2 * align_up(M * 8) + 2 * align_up(M * 4) +
               2 * align_up(Nb * 4) + align_up(Nb * 8) + align_up((size_t)Nb * s.n_orb * 8) +
-              align_up((2 + s.n_species) * 3 * 8) + align_up((size_t)Nb * 4 * 8);
+              align_up((2 + s.n_species) * 3 * 8) + align_up((size_t)Nb * 4 * 8) + align_up(Nb * 8);
     size_t common = 2 * align_up(nw * 3 * N * 8)    // positions, double-buffered
                     + align_up(nw * 8)              // lw
                     + 4 * align_up(nw * 8)          // eL, W double-buffered
@@ -132,7 +132,9 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.o_rows = take(11 * ns);
         L.o_tmp = take(3 * ns + 8);
         L.o_C = take(Nb * ns);
-        L.o_bK = take(Nb);
+        L.o_nuc = take(8 * M);
+        L.o_jas = take(3 * (2 + s.n_species));
+        L.o_gd = take(4 * N);
         L.lds_doubles = o;
         L.lds_bytes = (size_t)o * 8;
         L.s_Phi = 0;
@@ -657,6 +659,9 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
         double* C = (double*)carve((size_t)Nb * s.n_orb * 8);
         double* jas = (double*)carve((2 + s.n_species) * 3 * 8);
         double* btab = (double*)carve((size_t)Nb * 4 * 8);
+        double* bK = (double*)carve(Nb * 8);
+        std::vector<double> bK_host(Nb);
+        for (int mu = 0; mu < Nb; ++mu) bK_host[mu] = std::exp(-s.basis_exp[mu] * prm->a * prm->a);
         r.btab_host.resize((size_t)Nb * 4);
         for (int mu = 0; mu < Nb; ++mu) {
             const int at = s.basis_atom[mu];
@@ -668,7 +673,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             up(batom, s.basis_atom, Nb * 4) || up(btype, s.basis_type, Nb * 4) ||
             up(bexp, s.basis_exp, Nb * 8) || up(C, s.mo_coeff, (size_t)Nb * s.n_orb * 8) ||
             up(jas, s.jastrow, (2 + s.n_species) * 24) ||
-            up(btab, r.btab_host.data(), (size_t)Nb * 32)) {
+            up(btab, r.btab_host.data(), (size_t)Nb * 32) || up(bK, bK_host.data(), Nb * 8)) {
             rc = fail(LRDMC_ERR_HIP, "upload of system arrays failed");
             break;
         }
@@ -785,7 +790,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             d.o_Arow = L.o_Arow; d.o_AinvT = L.o_AinvT; d.o_Jg = L.o_Jg; d.o_Jl = L.o_Jl;
             d.o_nue = L.o_nue; d.o_nua = L.o_nua; d.o_dje = L.o_dje; d.o_scal = L.o_scal;
             d.o_B = L.o_B; d.o_rows = L.o_rows; d.o_tmp = L.o_tmp; d.o_C = L.o_C;
-            d.o_bK = L.o_bK;
+            d.bK = bK; d.o_nuc = L.o_nuc; d.o_jas = L.o_jas; d.o_gd = L.o_gd;
             d.lds_doubles = L.lds_doubles;
             d.s_Phi = L.s_Phi; d.s_dPhi = L.s_dPhi;
             for (int p = 0; p < 2; ++p) {

@@ -59,8 +59,28 @@ __device__ __forceinline__ void block_visible()
 // spill area (orbital rows at the 6N moves, orbital derivatives).
 extern __shared__ double lds[];
 
+// Loads and stores through pointers known to address global memory (the
+// descriptor's pointers are otherwise generic, and generic accesses also wait
+// on the LDS counter).
+template <class T>
+__device__ __forceinline__ T gld(const T* p)
+{
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ void gst(T* p, T v)
+{
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+
+// Nucleus record staged in LDS per walker: x, y, z, charge, core radius,
+// soft-core flag, Jastrow parameter row, padding.
+constexpr int kNucLen = 8;
+// orbital values per lane fetched ahead of the ratio and derivative updates
+constexpr int kPre = 8;
+
 struct Walker {
-    int pos, R, Rdet, dJ, Arow, AinvT, Jg, Jl, nue, nua, dje, scal, B, rows, tmp, C, bK;
+    int pos, R, Rdet, dJ, Arow, AinvT, Jg, Jl, nue, nua, dje, scal, B, rows, tmp, C, nuc, jas, gd;
     double* Phi;
     double* dPhi;
 };
@@ -72,7 +92,9 @@ __device__ __forceinline__ Walker walker_view(const DevSys& s)
     w.AinvT = s.o_AinvT; w.Jg = s.o_Jg; w.Jl = s.o_Jl; w.nue = s.o_nue; w.nua = s.o_nua;
     w.dje = s.o_dje; w.scal = s.o_scal; w.B = s.o_B; w.rows = s.o_rows; w.tmp = s.o_tmp;
     w.C = s.o_C;
-    w.bK = s.o_bK;
+    w.nuc = s.o_nuc;
+    w.jas = s.o_jas;
+    w.gd = s.o_gd;
     double* base = s.spill + (long)blockIdx.x * s.spill_stride;
     w.Phi = base + s.s_Phi;
     w.dPhi = base + s.s_dPhi;
@@ -96,9 +118,9 @@ __device__ __forceinline__ void partner(const DevSys& s, const Walker& w, int i,
         pk[0] = lds[w.pos + 3 * k]; pk[1] = lds[w.pos + 3 * k + 1]; pk[2] = lds[w.pos + 3 * k + 2];
         jrow = ee_row(s, i, k);
     } else {
-        const int I = k - s.N;
-        pk[0] = s.R[3 * I]; pk[1] = s.R[3 * I + 1]; pk[2] = s.R[3 * I + 2];
-        jrow = 2 + s.spec[I];
+        const double* nr = lds + w.nuc + kNucLen * (k - s.N);
+        pk[0] = nr[0]; pk[1] = nr[1]; pk[2] = nr[2];
+        jrow = (int)nr[6];
     }
 }
 
@@ -110,6 +132,22 @@ __device__ __forceinline__ double recip(double x)
     return fma(r, fma(-x, r, 1.0), r);
 }
 
+// Bare (-Z/r, and its value capped at r = a) or soft-core (-Z/sqrt(r^2 + rc^2))
+// electron-nucleus potential of nucleus k at distance r (App. D potentials).
+__device__ __forceinline__ void nucleus_potential(const DevSys& s, const Walker& w, int k, double r,
+                                                  double a, double& nu, double& nua)
+{
+    const double* nr = lds + w.nuc + kNucLen * (k - s.N);
+    const double Z = nr[3];
+    if (nr[5] == 0.0) {
+        nu += -Z / r;
+        nua += -Z / (r > a ? r : a);
+    } else {
+        const double t = -Z / sqrt(r * r + nr[4] * nr[4]);
+        nu += t; nua += t;
+    }
+}
+
 // Orbital rows of electron j at position r (11 rows, columns k < n_j):
 // row 0 the value at r, rows 1..6 the values at the six lattice neighbours
 // r +- a e_d (move order), rows 7..9 the gradient, row 10 the Laplacian.
@@ -118,18 +156,17 @@ __device__ __forceinline__ double recip(double x)
 // coordinates, so at the neighbour r + s a e_c (s = +-1)
 //   exp(-alpha |d + s a e_c|^2) = exp(-alpha d^2) exp(-alpha a^2) exp(-2 s alpha a d_c),
 // with d = r - centre: four exponentials (the per-function constant
-// exp(-alpha a^2) is tabulated once per phase) and three reciprocals give all
+// exp(-alpha a^2) is tabulated with the system) and three reciprocals give all
 // seven values, and the value at r gives the gradient and Laplacian.  Slater
 // functions take the seven points directly.  Orbitals: the 11 x Nb basis
 // block times the Nb x n coefficient block on FP64 MFMA (16x16x4 tiles; rows
 // 11..15 and columns >= n are padding).
-__device__ void electron_rows(const DevSys& s, const Walker& w, int j, const double* r, double a,
-                              int lane)
+__device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, double a, int lane)
 {
     const int Nb = s.Nb;
     for (int mu = lane; mu < Nb; mu += kWave) {
-        const double4_t c = *(const double4_t*)(s.btab + 4 * mu);
-        const int t = s.btype[mu];
+        const double4_t c = gld((const double4_t*)(s.btab + 4 * mu));
+        const int t = gld(s.btype + mu);
         const double al = c[3];
         const double d[3] = {r[0] - c[0], r[1] - c[1], r[2] - c[2]};
         const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
@@ -145,7 +182,7 @@ __device__ void electron_rows(const DevSys& s, const Walker& w, int j, const dou
             basis_vgl_d(t, al, d[0], d[1], d[2], d2, v, g, l);
         } else {
             const double e = exp(-al * d2);
-            const double K = lds[w.bK + mu];
+            const double K = gld(s.bK + mu);
             const double s2a = 2.0 * al * a;
             // polynomial factor: 1 (s) or the displacement along the p axis
             const int ax = t - 1;
@@ -177,7 +214,12 @@ __device__ void electron_rows(const DevSys& s, const Walker& w, int j, const dou
         Bm[9 * Nb] = g[2];
         Bm[10 * Nb] = l;
     }
+}
+
+__device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
+{
     wave_sync();
+    const int Nb = s.Nb;
     const int n = nspin(s, spin_of(s, j));
     const int i16 = lane & 15, k4 = lane >> 4;
     const bool arow_ok = i16 < 11;
@@ -215,6 +257,13 @@ __device__ void electron_rows(const DevSys& s, const Walker& w, int j, const dou
     wave_sync();
 }
 
+__device__ void electron_rows(const DevSys& s, const Walker& w, int j, const double* r, double a,
+                              int lane)
+{
+    basis_rows(s, w, r, a, lane);
+    orbital_rows(s, w, j, lane);
+}
+
 // Store electron j's rows: Slater row, the 6 neighbour rows, derivatives.
 __device__ void store_rows(const DevSys& s, const Walker& w, int j, int lane, bool arow)
 {
@@ -223,8 +272,8 @@ __device__ void store_rows(const DevSys& s, const Walker& w, int j, int lane, bo
         const int row = idx / n, k = idx - row * n;
         const double v = lds[w.rows + row * s.ns + k];
         if (row == 0) { if (arow) lds[w.Arow + j * s.ns + k] = v; }
-        else if (row <= 6) w.Phi[k * s.P + 6 * j + row - 1] = v;
-        else w.dPhi[k * 4 * s.N + 4 * j + row - 7] = v;
+        else if (row <= 6) gst(w.Phi + k * s.P + 6 * j + row - 1, v);
+        else gst(w.dPhi + k * 4 * s.N + 4 * j + row - 7, v);
     }
     block_visible();
 }
@@ -303,10 +352,27 @@ __device__ void recompute_ratios(const DevSys& s, const Walker& w, int sp, int l
             const int ai = w.AinvT + spj * s.ns * s.ns + c * s.ns;
             const double* ph = w.Phi + p;
             double rd = 0.0;
-            for (int k = 0; k < n; ++k) rd += ph[k * s.P] * lds[ai + k];
+            for (int k = 0; k < n; ++k) rd += gld(ph + k * s.P) * lds[ai + k];
             lds[w.Rdet + p] = rd;
         }
         lds[w.R + p] = lds[w.Rdet + p] * exp(lds[w.dJ + p]);
+    }
+    wave_sync();
+}
+
+// Determinant gradient and Laplacian of the electrons of spin sp (every spin
+// when sp < 0): gd[4j + c] = sum_k dPhi_c[j][k] (A^-1)[k][col j], component c
+// = x, y, z, Laplacian; one lane per (electron, component).
+__device__ void recompute_gd(const DevSys& s, const Walker& w, int sp, int lane)
+{
+    const int N4 = 4 * s.N;
+    const int it0 = sp == 1 ? 4 * s.Nup : 0, it1 = sp == 0 ? 4 * s.Nup : N4;
+    for (int it = it0 + lane; it < it1; it += kWave) {
+        const int j = it >> 2, spj = spin_of(s, j), n = nspin(s, spj), c = col_of(s, j);
+        const int ai = w.AinvT + spj * s.ns * s.ns + c * s.ns;
+        double val = 0.0;
+        for (int k = 0; k < n; ++k) val += gld(w.dPhi + k * N4 + it) * lds[ai + k];
+        lds[w.gd + it] = val;
     }
     wave_sync();
 }
@@ -332,7 +398,7 @@ __device__ double jastrow_all(const DevSys& s, const Walker& w, double a, int la
             double pk[3];
             int jr;
             partner(s, w, j, k, pk, jr);
-            acc += pade_u(s.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+            acc += pade_u(lds + w.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
         }
         lds[S + it] = acc;
     }
@@ -351,21 +417,12 @@ __device__ double jastrow_all(const DevSys& s, const Walker& w, double a, int la
             const double r = norm3(d0, d1, d2);
             if (isel || s.has_en) {
                 double u, dur, lp;
-                pade_derivs(s.jas + 3 * jr, r, u, dur, lp);
+                pade_derivs(lds + w.jas + 3 * jr, r, u, dur, lp);
                 g0 += dur * d0; g1 += dur * d1; g2 += dur * d2;
                 l += lp;
                 if (isel && k > j) vee += 1.0 / r;
             }
-            if (!isel) {
-                const int I = k - s.N;
-                if (s.core[I] == 0) {
-                    nu += -s.Z[I] / r;
-                    nua += -s.Z[I] / (r > a ? r : a);
-                } else {
-                    const double t = -s.Z[I] / sqrt(r * r + s.rc[I] * s.rc[I]);
-                    nu += t; nua += t;
-                }
-            }
+            if (!isel) nucleus_potential(s, w, k, r, a, nu, nua);
         }
         lds[w.Jg + 3 * j] = g0; lds[w.Jg + 3 * j + 1] = g1; lds[w.Jg + 3 * j + 2] = g2;
         lds[w.Jl + j] = l; lds[w.nue + j] = nu; lds[w.nua + j] = nua;
@@ -390,6 +447,7 @@ __device__ bool refresh_all(const DevSys& s, const Walker& w, double a, int lane
     if (lane == 0) lds[w.scal + kScVee] = vee;
     wave_sync();
     recompute_ratios(s, w, -1, lane);
+    recompute_gd(s, w, -1, lane);
     return ok;
 }
 
@@ -410,43 +468,26 @@ __device__ Local evaluate(const DevSys& s, const Walker& w, double a, int nu_mod
     bs = wave_sum(bs);
     vs = wave_sum(vs);
     const bool anynode = __ballot(anyneg) != 0;
-    // determinant gradient and Laplacian of electron j: lane 4j + c computes
-    // component c (x, y, z, Laplacian) from the k-major spill, and the quad's
-    // first lane gathers the four
     double sum_opt = 0.0;
-    const int N4 = 4 * s.N;
-    for (int base = 0; base < N4; base += kWave) {
-        const int it = base + lane, j = it >> 2;
-        const bool act = it < N4;
-        double val = 0.0;
-        if (act) {
-            const int sp = spin_of(s, j), n = nspin(s, sp), c = col_of(s, j);
-            const int ai = w.AinvT + sp * s.ns * s.ns + c * s.ns;
-            const double* dp = w.dPhi + it;
-            for (int k = 0; k < n; ++k) val += dp[k * N4] * lds[ai + k];
+    for (int j = lane; j < s.N; j += kWave) {
+        const double g0 = lds[w.gd + 4 * j], g1 = lds[w.gd + 4 * j + 1];
+        const double g2 = lds[w.gd + 4 * j + 2], ld = lds[w.gd + 4 * j + 3];
+        const double j0 = lds[w.Jg + 3 * j], j1 = lds[w.Jg + 3 * j + 1], j2 = lds[w.Jg + 3 * j + 2];
+        const double lap = ld + 2.0 * (g0 * j0 + g1 * j1 + g2 * j2) + lds[w.Jl + j] +
+                           j0 * j0 + j1 * j1 + j2 * j2;
+        double lapA = 0.0;
+        int nd = 0;
+        for (int q = 0; q < 6; ++q) {
+            const double r = lds[w.R + 6 * j + q];
+            lapA += (r - 1.0) / (a * a);
+            if (r < 0) nd = 1;
         }
-        const double v1 = dpp_mov<0x55, 0xf>(val);   // quad_perm [1,1,1,1]
-        const double v2 = dpp_mov<0xaa, 0xf>(val);   // quad_perm [2,2,2,2]
-        const double v3 = dpp_mov<0xff, 0xf>(val);   // quad_perm [3,3,3,3]
-        if (act && (lane & 3) == 0) {
-            const double g0 = val, g1 = v1, g2 = v2, ld = v3;
-            const double j0 = lds[w.Jg + 3 * j], j1 = lds[w.Jg + 3 * j + 1], j2 = lds[w.Jg + 3 * j + 2];
-            const double lap = ld + 2.0 * (g0 * j0 + g1 * j1 + g2 * j2) + lds[w.Jl + j] +
-                               j0 * j0 + j1 * j1 + j2 * j2;
-            double lapA = 0.0;
-            int nd = 0;
-            for (int q = 0; q < 6; ++q) {
-                const double r = lds[w.R + 6 * j + q];
-                lapA += (r - 1.0) / (a * a);
-                if (r < 0) nd = 1;
-            }
-            if (nu_mode == 1) nd = anynode;
-            if (nu_mode == 2) nd = 1;
-            const double nuzv = lds[w.nue + j] + 0.5 * (lapA - lap);
-            const double nua = lds[w.nua + j];
-            const double numax = nuzv > nua ? nuzv : nua;
-            sum_opt += nd ? numax : nuzv;
-        }
+        if (nu_mode == 1) nd = anynode;
+        if (nu_mode == 2) nd = 1;
+        const double nuzv = lds[w.nue + j] + 0.5 * (lapA - lap);
+        const double nua = lds[w.nua + j];
+        const double numax = nuzv > nua ? nuzv : nua;
+        sum_opt += nd ? numax : nuzv;
     }
     sum_opt = wave_sum(sum_opt);
     Local L;
@@ -505,11 +546,18 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     double rnew[3] = {rold[0], rold[1], rold[2]};
     rnew[d] = rnew[d] + (sg ? -a : a);
 
+    // The accepted orbital row u is fetched first and the basis values at
+    // the new position are computed while it is in flight.
+    double u0 = 0.0;
+    if (lane < n) u0 = gld(w.Phi + lane * s.P + p);
+    basis_rows(s, w, rnew, a, lane);
+    LRDMC_T(3);
+
     // Sherman-Morrison on AinvT of spin sp with the accepted orbital row u
     const int Ai = w.AinvT + sp * s.ns * s.ns;
     const int u = w.tmp, rowc = w.tmp + s.ns, beta = w.tmp + 2 * s.ns;
     for (int k = lane; k < n; k += kWave) {
-        lds[u + k] = w.Phi[k * s.P + p];
+        lds[u + k] = k < kWave ? u0 : gld(w.Phi + k * s.P + p);
         lds[rowc + k] = lds[Ai + c * s.ns + k];
     }
     wave_sync();
@@ -533,9 +581,21 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
 
     LRDMC_T(2);
     // new orbital rows of electron i at rnew
-    electron_rows(s, w, i, rnew, a, lane);
+    orbital_rows(s, w, i, lane);
     store_rows(s, w, i, lane, false);
-    LRDMC_T(3);
+    LRDMC_T(4);
+
+    // Orbital rows of the moves of spin sp and orbital derivatives of its
+    // electrons (first kPre values of the first pass) are fetched now; the
+    // Jastrow updates run while they are in flight.
+    const int off = sp ? s.Nup : 0;
+    double pre_r[kPre], pre_g[kPre];
+    const bool rv = lane < 6 * n, gv = lane < 4 * n;
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+        pre_r[k] = (rv && k < n) ? gld(w.Phi + k * s.P + 6 * off + lane) : 0.0;
+        pre_g[k] = (gv && k < n) ? gld(w.dPhi + k * 4 * s.N + 4 * off + lane) : 0.0;
+    }
 
     // Jastrow and potential caches: pairs (i, k) change from rold to rnew.
     // The 7 points of the moved electron (its new position and neighbours):
@@ -560,7 +620,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
             if (kval && q < 7) {
                 double pq[3];
                 point_q(rnew, q, a, pq);
-                v = pade_u(s.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+                v = pade_u(lds + w.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
             }
             v = rpp == 1 ? row16_sum(v) : row32_sum(v);
             for (int t = 0; t < ppp; ++t)
@@ -578,7 +638,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
                 double pk[3];
                 int jr;
                 partner(s, w, i, k, pk, jr);
-                acc += pade_u(s.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+                acc += pade_u(lds + w.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
             }
             Sq[q] = wave_sum(acc);
         }
@@ -597,14 +657,14 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
         const double rn = norm3(n0, n1, n2);
         if (isel || s.has_en) {
             double un, dnr, lpn;
-            pade_derivs(s.jas + 3 * jr, rn, un, dnr, lpn);
+            pade_derivs(lds + w.jas + 3 * jr, rn, un, dnr, lpn);
             g0 += dnr * n0; g1 += dnr * n1; g2 += dnr * n2;
             l += lpn;
             if (isel) {
                 const double o0 = rold[0] - pk[0], o1 = rold[1] - pk[1], o2 = rold[2] - pk[2];
                 const double ro = norm3(o0, o1, o2);
                 double uo, dor, lpo;
-                pade_derivs(s.jas + 3 * jr, ro, uo, dor, lpo);
+                pade_derivs(lds + w.jas + 3 * jr, ro, uo, dor, lpo);
                 lds[w.dje + k] = un - uo;
                 // electron k sees the pair through r_k - r_i = -(r_i - r_k)
                 lds[w.Jg + 3 * k] += -(dnr * n0) + dor * o0;
@@ -614,16 +674,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
                 dvee += 1.0 / rn - 1.0 / ro;
             }
         }
-        if (!isel) {
-            const int I = k - s.N;
-            if (s.core[I] == 0) {
-                nu += -s.Z[I] / rn;
-                nua += -s.Z[I] / (rn > a ? rn : a);
-            } else {
-                const double t = -s.Z[I] / sqrt(rn * rn + s.rc[I] * s.rc[I]);
-                nu += t; nua += t;
-            }
-        }
+        if (!isel) nucleus_potential(s, w, k, rn, a, nu, nua);
     }
     g0 = wave_sum(g0); g1 = wave_sum(g1); g2 = wave_sum(g2);
     l = wave_sum(l); dvee = wave_sum(dvee); nu = wave_sum(nu); nua = wave_sum(nua);
@@ -634,7 +685,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
         const int j = q / 6;
         if (j == i) continue;
         const int dd = (q / 2) % 3, s2 = q % 2;
-        const double* prm = s.jas + 3 * ee_row(s, i, j);
+        const double* prm = lds + w.jas + 3 * ee_row(s, i, j);
         double r2[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
         r2[dd] = r2[dd] + (s2 ? -a : a);
         const double un = pade_u(prm, norm3(r2[0] - rnew[0], r2[1] - rnew[1], r2[2] - rnew[2]));
@@ -650,7 +701,38 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     }
     wave_sync();
     LRDMC_T(5);
-    recompute_ratios(s, w, sp, lane);
+    // ratios of the moves of spin sp, derivatives of its electrons
+    for (int pp = lane; pp < 6 * n; pp += kWave) {
+        const int q = 6 * off + pp, cj = col_of(s, q / 6);
+        const int ai = Ai + cj * s.ns;
+        double rd = 0.0;
+        if (pp < kWave) {
+#pragma unroll
+            for (int k = 0; k < kPre; ++k)
+                if (k < n) rd += pre_r[k] * lds[ai + k];
+            for (int k = kPre; k < n; ++k) rd += gld(w.Phi + k * s.P + q) * lds[ai + k];
+        } else {
+            for (int k = 0; k < n; ++k) rd += gld(w.Phi + k * s.P + q) * lds[ai + k];
+        }
+        lds[w.Rdet + q] = rd;
+    }
+    for (int gg = lane; gg < 4 * n; gg += kWave) {
+        const int it = 4 * off + gg, cj = col_of(s, it >> 2);
+        const int ai = Ai + cj * s.ns;
+        double val = 0.0;
+        if (gg < kWave) {
+#pragma unroll
+            for (int k = 0; k < kPre; ++k)
+                if (k < n) val += pre_g[k] * lds[ai + k];
+            for (int k = kPre; k < n; ++k) val += gld(w.dPhi + k * 4 * s.N + it) * lds[ai + k];
+        } else {
+            for (int k = 0; k < n; ++k) val += gld(w.dPhi + k * 4 * s.N + it) * lds[ai + k];
+        }
+        lds[w.gd + it] = val;
+    }
+    wave_sync();
+    for (int q = lane; q < s.P; q += kWave) lds[w.R + q] = lds[w.Rdet + q] * exp(lds[w.dJ + q]);
+    wave_sync();
     LRDMC_T(6);
     return fabs(Rd) < 1e-6;
 }
@@ -678,11 +760,20 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
     for (int q = lane; q < 3 * s.N; q += kWave) lds[w.pos + q] = s.pos[(long)wid * 3 * s.N + q];
     for (int q = lane; q < s.Nb * s.ns; q += kWave) {
         const int mu = q / s.ns, k = q - mu * s.ns;
-        lds[w.C + q] = s.C[mu * s.Norb + k];
+        lds[w.C + q] = gld(s.C + mu * s.Norb + k);
     }
     const double a = pa.a;
-    // per-function Gaussian factor exp(-alpha a^2) of a lattice step
-    for (int mu = lane; mu < s.Nb; mu += kWave) lds[w.bK + mu] = exp(-s.btab[4 * mu + 3] * a * a);
+    // nucleus records and Pade parameter rows
+    for (int I = lane; I < s.M; I += kWave) {
+        double* nr = lds + w.nuc + kNucLen * I;
+        nr[0] = gld(s.R + 3 * I); nr[1] = gld(s.R + 3 * I + 1); nr[2] = gld(s.R + 3 * I + 2);
+        nr[3] = gld(s.Z + I);
+        nr[4] = gld(s.rc + I);
+        nr[5] = gld(s.core + I) == 0 ? 0.0 : 1.0;
+        nr[6] = (double)(2 + gld(s.spec + I));
+        nr[7] = 0.0;
+    }
+    for (int q = lane; q < 3 * (2 + s.nspec); q += kWave) lds[w.jas + q] = gld(s.jas + q);
     wave_sync();
     // orbital rows of every electron, then the FP64 refresh
     for (int j = 0; j < s.N; ++j) {
