@@ -61,6 +61,19 @@ __device__ __forceinline__ double wave_sum(double v)
     return lane63(v);
 }
 
+// maximum over the 64 lanes (every lane receives it); lanes without a DPP
+// source contribute 0, so it serves non-negative data
+__device__ __forceinline__ double wave_max(double v)
+{
+    v = fmax(v, dpp_mov<0xb1, 0xf>(v));
+    v = fmax(v, dpp_mov<0x4e, 0xf>(v));
+    v = fmax(v, dpp_mov<0x114, 0xf>(v));
+    v = fmax(v, dpp_mov<0x118, 0xf>(v));
+    v = fmax(v, dpp_mov<0x142, 0xa>(v));
+    v = fmax(v, dpp_mov<0x143, 0xc>(v));
+    return lane63(v);
+}
+
 // sums over each row of 16 lanes (result in the row's last lane), and over
 // pairs of rows (result in lanes 31 and 63)
 __device__ __forceinline__ double row16_sum(double v)

@@ -130,7 +130,7 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.o_scal = take(kScLen);
         L.o_B = take(std::max(std::max(11 * Nb, 2 * ns * ns), 7 * N));
         L.o_rows = take(11 * ns);
-        L.o_tmp = take(3 * ns + 8);
+        L.o_tmp = take(3 * ns + 16);
         L.o_C = take(Nb * ns);
         L.o_nuc = take(8 * M);
         L.o_jas = take(3 * (2 + s.n_species));

@@ -132,18 +132,48 @@ __device__ __forceinline__ double recip(double x)
     return fma(r, fma(-x, r, 1.0), r);
 }
 
+// 1/sqrt(x) to about one ulp: hardware estimate and two Newton steps.
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
+// Pade pair function u(r) = (A r + B r^2)/(1 + b r) from the squared distance.
+__device__ __forceinline__ double pade_u2(const double* p, double r2)
+{
+    const double r = r2 * rsqrt_nr(r2);
+    return r * (p[0] + p[1] * r) * recip(1.0 + p[2] * r);
+}
+
+// u, u'/r and u'' + 2u'/r from the squared distance r2 and ir = 1/r.
+__device__ __forceinline__ void pade_derivs2(const double* p, double r2, double ir, double& u,
+                                             double& du_r, double& lap)
+{
+    const double A = p[0], B = p[1], b = p[2];
+    const double r = r2 * ir;
+    const double iden = recip(1.0 + b * r);
+    const double i2 = iden * iden;
+    u = (A * r + B * r * r) * iden;
+    const double du = (A + 2.0 * B * r + B * b * r * r) * i2;
+    du_r = du * ir;
+    lap = 2.0 * (B - A * b) * i2 * iden + 2.0 * du_r;
+}
+
 // Bare (-Z/r, and its value capped at r = a) or soft-core (-Z/sqrt(r^2 + rc^2))
 // electron-nucleus potential of nucleus k at distance r (App. D potentials).
-__device__ __forceinline__ void nucleus_potential(const DevSys& s, const Walker& w, int k, double r,
-                                                  double a, double& nu, double& nua)
+// From the squared distance r2, 1/r and 1/a.
+__device__ __forceinline__ void nucleus_potential(const DevSys& s, const Walker& w, int k, double r2,
+                                                  double ir, double ia, double& nu, double& nua)
 {
     const double* nr = lds + w.nuc + kNucLen * (k - s.N);
     const double Z = nr[3];
     if (nr[5] == 0.0) {
-        nu += -Z / r;
-        nua += -Z / (r > a ? r : a);
+        nu += -Z * ir;
+        nua += -Z * (ir < ia ? ir : ia);
     } else {
-        const double t = -Z / sqrt(r * r + nr[4] * nr[4]);
+        const double t = -Z * rsqrt_nr(r2 + nr[4] * nr[4]);
         nu += t; nua += t;
     }
 }
@@ -279,50 +309,53 @@ __device__ void store_rows(const DevSys& s, const Walker& w, int j, int lane, bo
 }
 
 // FP64 Gauss-Jordan inverse with partial pivoting of the transposed Slater
-// matrix of spin sp: AinvT[c][k] = (A^-1)[k][c].  Sets log|det| and sign.
-// Returns false for an exactly singular matrix.
+// matrix of spin sp: AinvT[c][k] = (A^-1)[k][c].  Returns false for an
+// exactly singular matrix.  The pivot of column j is the largest |M[r][j]|,
+// r >= j, the first such row on ties: one lane per row and a wavefront
+// maximum (n <= 64 rows).
 __device__ bool refresh_inverse(const DevSys& s, const Walker& w, int sp, int lane)
 {
     const int n = nspin(s, sp);
     if (!n) return true;
-    const int off = sp ? s.Nup : 0, n2 = 2 * n;
+    const int off = sp ? s.Nup : 0, n2 = 2 * n, nn = n * n2;
     const int M = w.B;                   // [n][2n] scratch
-    for (int idx = lane; idx < n * n2; idx += kWave) {
-        const int r = idx / n2, c = idx - r * n2;
-        lds[M + idx] = c < n ? lds[w.Arow + (off + c) * s.ns + r] : (c - n == r ? 1.0 : 0.0);
+    // (row, column) of the lane's first element of [n][2n] and the stride
+    const int r0 = lane / n2, c0 = lane - r0 * n2;
+    const int dr = kWave / n2, dc = kWave - dr * n2;
+    {
+        int r = r0, c = c0;
+        for (int idx = lane; idx < nn; idx += kWave) {
+            lds[M + idx] = c < n ? lds[w.Arow + (off + c) * s.ns + r] : (c - n == r ? 1.0 : 0.0);
+            r += dr; c += dc;
+            if (c >= n2) { c -= n2; ++r; }
+        }
     }
     wave_sync();
-    double logdet = 0.0, sign = 1.0;
     bool ok = true;
     for (int j = 0; j < n; ++j) {
-        // pivot: largest |M[r][j]| for r >= j, first one on ties (every lane
-        // scans the same LDS column, so the choice is uniform)
-        double best = -1.0;
-        int bi = n;
-        for (int r = j; r < n; ++r) {
-            const double v = fabs(lds[M + r * n2 + j]);
-            if (v > best) { best = v; bi = r; }
-        }
+        const double v = (lane >= j && lane < n) ? fabs(lds[M + lane * n2 + j]) : -1.0;
+        const double best = wave_max(v);
         if (!(best > 0.0)) { ok = false; break; }
+        const unsigned long long hit = __ballot(v == best);
+        const int bi = __ffsll((long long)hit) - 1;
         if (bi != j) {
             for (int c = lane; c < n2; c += kWave) {
                 const double t = lds[M + j * n2 + c];
                 lds[M + j * n2 + c] = lds[M + bi * n2 + c];
                 lds[M + bi * n2 + c] = t;
             }
-            sign = -sign;
             wave_sync();
         }
         const double pv = lds[M + j * n2 + j];
-        logdet += log(fabs(pv));
-        if (pv < 0) sign = -sign;
         wave_sync();
         for (int c = lane; c < n2; c += kWave) lds[M + j * n2 + c] = lds[M + j * n2 + c] / pv;
         for (int r = lane; r < n; r += kWave) lds[w.tmp + r] = lds[M + r * n2 + j];
         wave_sync();
-        for (int idx = lane; idx < n * n2; idx += kWave) {
-            const int r = idx / n2, c = idx - r * n2;
+        int r = r0, c = c0;
+        for (int idx = lane; idx < nn; idx += kWave) {
             if (r != j) lds[M + idx] -= lds[w.tmp + r] * lds[M + j * n2 + c];
+            r += dr; c += dc;
+            if (c >= n2) { c -= n2; ++r; }
         }
         wave_sync();
     }
@@ -331,10 +364,6 @@ __device__ bool refresh_inverse(const DevSys& s, const Walker& w, int sp, int la
         for (int idx = lane; idx < n * n; idx += kWave) {
             const int c = idx / n, k = idx - c * n;
             lds[Ai + c * s.ns + k] = lds[M + c * n2 + n + k];
-        }
-        if (lane == 0) {
-            lds[w.scal + kScLogdet0 + sp] = logdet;
-            lds[w.scal + kScSign0 + sp] = sign;
         }
     }
     wave_sync();
@@ -385,6 +414,7 @@ __device__ double jastrow_all(const DevSys& s, const Walker& w, double a, int la
 {
     const int K = s.N + s.M;
     const int Kj = s.has_en ? K : s.N;
+    const double ia = 1.0 / a;
     const int S = w.B;                            // [N][7] point sums
     for (int it = lane; it < 7 * s.N; it += kWave) {
         const int j = it / 7, q = it - 7 * j;
@@ -398,7 +428,8 @@ __device__ double jastrow_all(const DevSys& s, const Walker& w, double a, int la
             double pk[3];
             int jr;
             partner(s, w, j, k, pk, jr);
-            acc += pade_u(lds + w.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+            const double e0 = pq[0] - pk[0], e1 = pq[1] - pk[1], e2 = pq[2] - pk[2];
+            acc += pade_u2(lds + w.jas + 3 * jr, e0 * e0 + e1 * e1 + e2 * e2);
         }
         lds[S + it] = acc;
     }
@@ -414,15 +445,16 @@ __device__ double jastrow_all(const DevSys& s, const Walker& w, double a, int la
             int jr;
             partner(s, w, j, k, pk, jr);
             const double d0 = rj[0] - pk[0], d1 = rj[1] - pk[1], d2 = rj[2] - pk[2];
-            const double r = norm3(d0, d1, d2);
+            const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+            const double ir = rsqrt_nr(r2);
             if (isel || s.has_en) {
                 double u, dur, lp;
-                pade_derivs(lds + w.jas + 3 * jr, r, u, dur, lp);
+                pade_derivs2(lds + w.jas + 3 * jr, r2, ir, u, dur, lp);
                 g0 += dur * d0; g1 += dur * d1; g2 += dur * d2;
                 l += lp;
-                if (isel && k > j) vee += 1.0 / r;
+                if (isel && k > j) vee += ir;
             }
-            if (!isel) nucleus_potential(s, w, k, r, a, nu, nua);
+            if (!isel) nucleus_potential(s, w, k, r2, ir, ia, nu, nua);
         }
         lds[w.Jg + 3 * j] = g0; lds[w.Jg + 3 * j + 1] = g1; lds[w.Jg + 3 * j + 2] = g2;
         lds[w.Jl + j] = l; lds[w.nue + j] = nu; lds[w.nua + j] = nua;
@@ -457,7 +489,7 @@ struct Local { double bbar, W, eL; };
 
 __device__ Local evaluate(const DevSys& s, const Walker& w, double a, int nu_mode, int lane)
 {
-    const double inv2a2 = 1.0 / (2.0 * a * a);
+    const double inv2a2 = 1.0 / (2.0 * a * a), ia2 = 2.0 * inv2a2;
     double bs = 0.0, vs = 0.0;
     int anyneg = 0;
     for (int p = lane; p < s.P; p += kWave) {
@@ -479,9 +511,10 @@ __device__ Local evaluate(const DevSys& s, const Walker& w, double a, int nu_mod
         int nd = 0;
         for (int q = 0; q < 6; ++q) {
             const double r = lds[w.R + 6 * j + q];
-            lapA += (r - 1.0) / (a * a);
+            lapA += r - 1.0;
             if (r < 0) nd = 1;
         }
+        lapA *= ia2;
         if (nu_mode == 1) nd = anynode;
         if (nu_mode == 2) nd = 1;
         const double nuzv = lds[w.nue + j] + 0.5 * (lapA - lap);
@@ -573,10 +606,6 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
         else lds[Ai + cc * s.ns + k] -= lds[rowc + k] * (lds[beta + cc] * iRd);
     }
     for (int k = lane; k < n; k += kWave) lds[w.Arow + i * s.ns + k] = lds[u + k];
-    if (lane == 0) {
-        lds[w.scal + kScLogdet0 + sp] += log(fabs(Rd));
-        if (Rd < 0) lds[w.scal + kScSign0 + sp] = -lds[w.scal + kScSign0 + sp];
-    }
     wave_sync();
 
     LRDMC_T(2);
@@ -602,30 +631,50 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     // with at most 32 partners, each point takes one or two rows of 16 lanes,
     // so 4 or 2 points share a pass and a row reduction; otherwise one point
     // per pass with a wave reduction.
+    const double ia = 1.0 / a;
     const int K = s.N + s.M;
     const int Kj = s.has_en ? K : s.N;
     const int dJi = w.tmp + 3 * s.ns;            // 6 new exponent changes of electron i
-    double Sq[7];
+    const int Sq = w.tmp + 3 * s.ns + 8;         // 7 point sums
     const int rpp = (Kj + 15) >> 4;              // rows of 16 lanes per point
     if (rpp <= 2) {
+        // lane = (point group, partner): the two passes of points q and
+        // q + ppp are evaluated together, then reduced over the row(s)
         const int ppp = 4 / rpp, row = lane >> 4;
-        const int qoff = row / rpp, k = (row % rpp) * 16 + (lane & 15);
+        const int k = (row % rpp) * 16 + (lane & 15);
         double pk[3] = {0.0, 0.0, 0.0};
         int jr = 0;
         const bool kval = k < Kj && k != i;
         if (kval) partner(s, w, i, k, pk, jr);
-        for (int q0 = 0; q0 < 7; q0 += ppp) {
-            const int q = q0 + qoff;
-            double v = 0.0;
-            if (kval && q < 7) {
-                double pq[3];
-                point_q(rnew, q, a, pq);
-                v = pade_u(lds + w.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+        const double* prm = lds + w.jas + 3 * jr;
+        // displaced coordinate of each point, formed as in the move itself
+        const double rp[3] = {rnew[0] + a, rnew[1] + a, rnew[2] + a};
+        const double rm[3] = {rnew[0] + (-a), rnew[1] + (-a), rnew[2] + (-a)};
+        for (int q0 = 0; q0 < 7; q0 += 2 * ppp) {
+            const int qa = q0 + row / rpp, qb = qa + ppp;
+            double va, vb;
+            double pa[3], pb[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                pa[c] = qa == 2 * c + 1 ? rp[c] : rnew[c];
+                pa[c] = qa == 2 * c + 2 ? rm[c] : pa[c];
+                pb[c] = qb == 2 * c + 1 ? rp[c] : rnew[c];
+                pb[c] = qb == 2 * c + 2 ? rm[c] : pb[c];
             }
-            v = rpp == 1 ? row16_sum(v) : row32_sum(v);
-            for (int t = 0; t < ppp; ++t)
-                if (q0 + t < 7) Sq[q0 + t] = lane_value(v, 16 * rpp * (t + 1) - 1);
+            const double a0 = pa[0] - pk[0], a1 = pa[1] - pk[1], a2 = pa[2] - pk[2];
+            const double b0 = pb[0] - pk[0], b1 = pb[1] - pk[1], b2 = pb[2] - pk[2];
+            const double ua = pade_u2(prm, a0 * a0 + a1 * a1 + a2 * a2);
+            const double ub = pade_u2(prm, b0 * b0 + b1 * b1 + b2 * b2);
+            va = kval ? ua : 0.0;
+            vb = (kval && qb < 7) ? ub : 0.0;
+            if (rpp == 1) { va = row16_sum(va); vb = row16_sum(vb); }
+            else { va = row32_sum(va); vb = row32_sum(vb); }
+            if ((lane & (16 * rpp - 1)) == 16 * rpp - 1) {
+                lds[Sq + qa] = va;
+                if (qb < 7) lds[Sq + qb] = vb;
+            }
         }
+        wave_sync();
     } else {
 #pragma unroll 1
         for (int q = 0; q < 7; ++q) {
@@ -638,13 +687,15 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
                 double pk[3];
                 int jr;
                 partner(s, w, i, k, pk, jr);
-                acc += pade_u(lds + w.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+                const double e0 = pq[0] - pk[0], e1 = pq[1] - pk[1], e2 = pq[2] - pk[2];
+                acc += pade_u2(lds + w.jas + 3 * jr, e0 * e0 + e1 * e1 + e2 * e2);
             }
-            Sq[q] = wave_sum(acc);
+            acc = wave_sum(acc);
+            if (lane == 0) lds[Sq + q] = acc;
         }
+        wave_sync();
     }
-    if (lane == 0)
-        for (int q = 1; q < 7; ++q) lds[dJi + q - 1] = Sq[q] - Sq[0];
+    if (lane < 6) lds[dJi + lane] = lds[Sq + lane + 1] - lds[Sq];
     double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0, dvee = 0.0, nu = 0.0, nua = 0.0;
     #pragma unroll 1
     for (int k = lane; k < K; k += kWave) {
@@ -654,43 +705,54 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
         int jr;
         partner(s, w, i, k, pk, jr);
         const double n0 = rnew[0] - pk[0], n1 = rnew[1] - pk[1], n2 = rnew[2] - pk[2];
-        const double rn = norm3(n0, n1, n2);
+        const double rn2 = n0 * n0 + n1 * n1 + n2 * n2;
+        const double irn = rsqrt_nr(rn2);
         if (isel || s.has_en) {
             double un, dnr, lpn;
-            pade_derivs(lds + w.jas + 3 * jr, rn, un, dnr, lpn);
+            pade_derivs2(lds + w.jas + 3 * jr, rn2, irn, un, dnr, lpn);
             g0 += dnr * n0; g1 += dnr * n1; g2 += dnr * n2;
             l += lpn;
             if (isel) {
                 const double o0 = rold[0] - pk[0], o1 = rold[1] - pk[1], o2 = rold[2] - pk[2];
-                const double ro = norm3(o0, o1, o2);
+                const double ro2 = o0 * o0 + o1 * o1 + o2 * o2, iro = rsqrt_nr(ro2);
                 double uo, dor, lpo;
-                pade_derivs(lds + w.jas + 3 * jr, ro, uo, dor, lpo);
+                pade_derivs2(lds + w.jas + 3 * jr, ro2, iro, uo, dor, lpo);
                 lds[w.dje + k] = un - uo;
                 // electron k sees the pair through r_k - r_i = -(r_i - r_k)
                 lds[w.Jg + 3 * k] += -(dnr * n0) + dor * o0;
                 lds[w.Jg + 3 * k + 1] += -(dnr * n1) + dor * o1;
                 lds[w.Jg + 3 * k + 2] += -(dnr * n2) + dor * o2;
                 lds[w.Jl + k] += lpn - lpo;
-                dvee += 1.0 / rn - 1.0 / ro;
+                dvee += irn - iro;
             }
         }
-        if (!isel) nucleus_potential(s, w, k, rn, a, nu, nua);
+        if (!isel) nucleus_potential(s, w, k, rn2, irn, ia, nu, nua);
     }
     g0 = wave_sum(g0); g1 = wave_sum(g1); g2 = wave_sum(g2);
     l = wave_sum(l); dvee = wave_sum(dvee); nu = wave_sum(nu); nua = wave_sum(nua);
     wave_sync();
     LRDMC_T(4);
-    // Jastrow exponent changes of the other electrons' moves
-    for (int q = lane; q < s.P; q += kWave) {
-        const int j = q / 6;
-        if (j == i) continue;
-        const int dd = (q / 2) % 3, s2 = q % 2;
-        const double* prm = lds + w.jas + 3 * ee_row(s, i, j);
-        double r2[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
-        r2[dd] = r2[dd] + (s2 ? -a : a);
-        const double un = pade_u(prm, norm3(r2[0] - rnew[0], r2[1] - rnew[1], r2[2] - rnew[2]));
-        const double uo = pade_u(prm, norm3(r2[0] - rold[0], r2[1] - rold[1], r2[2] - rold[2]));
-        lds[w.dJ + q] += (un - uo) - lds[w.dje + j];
+    // Jastrow exponent changes of the other electrons' moves: moves q and
+    // q + 64 of a lane are evaluated together
+    for (int qa = lane; qa < s.P; qa += 2 * kWave) {
+        const int qb = qa + kWave < s.P ? qa + kWave : qa;
+        const int ja = qa / 6, jb = qb / 6;
+        double dv[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = h ? qb : qa, j = h ? jb : ja;
+            const int dd = (q >> 1) % 3, s2 = q & 1;
+            const double* prm = lds + w.jas + 3 * ee_row(s, i, j);
+            double r2[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
+            r2[dd] = r2[dd] + (s2 ? -a : a);
+            const double n0 = r2[0] - rnew[0], n1 = r2[1] - rnew[1], n2 = r2[2] - rnew[2];
+            const double o0 = r2[0] - rold[0], o1 = r2[1] - rold[1], o2 = r2[2] - rold[2];
+            const double un = pade_u2(prm, n0 * n0 + n1 * n1 + n2 * n2);
+            const double uo = pade_u2(prm, o0 * o0 + o1 * o1 + o2 * o2);
+            dv[h] = (un - uo) - lds[w.dje + j];
+        }
+        if (ja != i) lds[w.dJ + qa] += dv[0];
+        if (qb != qa && jb != i) lds[w.dJ + qb] += dv[1];
     }
     if (lane == 0) {
         for (int q = 0; q < 6; ++q) lds[w.dJ + 6 * i + q] = lds[dJi + q];
@@ -731,7 +793,13 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
         lds[w.gd + it] = val;
     }
     wave_sync();
-    for (int q = lane; q < s.P; q += kWave) lds[w.R + q] = lds[w.Rdet + q] * exp(lds[w.dJ + q]);
+    for (int qa = lane; qa < s.P; qa += 2 * kWave) {
+        const int qb = qa + kWave;
+        const double xa = lds[w.dJ + qa], xb = qb < s.P ? lds[w.dJ + qb] : 0.0;
+        const double ea = exp(xa), eb = exp(xb);
+        lds[w.R + qa] = lds[w.Rdet + qa] * ea;
+        if (qb < s.P) lds[w.R + qb] = lds[w.Rdet + qb] * eb;
+    }
     wave_sync();
     LRDMC_T(6);
     return fabs(Rd) < 1e-6;
@@ -814,7 +882,7 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
             const double den = L.W - E0;
             if (!(den > 0)) { lw = -INFINITY; n_neg++; }
             else if (!(L.bbar > 0)) { lw = -INFINITY; n_nomove++; }
-            else lw += log(L.bbar) - log(den);
+            else lw += log(L.bbar / den);
             q = heat_bath(s, w, lane_value(xmove, slot), lane);
             if (tr && it < s.trace_cap && lane == 0) tr[it] = q;
             ++it;
