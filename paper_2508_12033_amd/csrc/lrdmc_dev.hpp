@@ -40,11 +40,17 @@ struct DevSys {
     int32_t *trace;          // [nw][trace_cap] or null
     int trace_cap;
     // LDS layout of one walker (offsets in doubles)
+    int ldb;                 // row stride (doubles) of the basis block: Nb padded to 4 mod 16
+                             // so that the 16 rows of an MFMA operand read fall in distinct banks
     int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje,
         o_scal, o_B, o_rows, o_tmp, o_C, o_nuc, o_jas, o_gd, lds_doubles;
     // spill layout (offsets in doubles inside a walker's spill block)
     int s_Phi, s_dPhi;
 };
+
+// Nucleus record staged in LDS per walker by the FP64 phase kernel: x, y, z,
+// charge, core radius, soft-core flag, Jastrow parameter row.
+constexpr int kNucLen = 7;
 
 struct PhaseArgs {
     int scheme;              // 0 load-balanced, 1 conventional

@@ -74,6 +74,7 @@ int kind_of(const lrdmc_params& p) { return p.precision == LRDMC_FP64 ? kKindLds
 struct Layout {
     int kind, N, P, ns;
     // FP64 kernel: LDS offsets (doubles), spill layout
+    int ldb;
     int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje, o_scal, o_B,
         o_rows, o_tmp, o_C, o_nuc, o_jas, o_gd, lds_doubles;
     int s_Phi, s_dPhi;
@@ -127,12 +128,13 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.o_nue = take(N);
         L.o_nua = take(N);
         L.o_dje = take(N);
-        L.o_scal = take(kScLen);
-        L.o_B = take(std::max(std::max(11 * Nb, 2 * ns * ns), 7 * N));
+        L.o_scal = take(kScVee + 1);
+        L.ldb = Nb + ((20 - Nb % 16) % 16);
+        L.o_B = take(std::max(std::max(11 * L.ldb, 2 * ns * ns), 7 * N));
         L.o_rows = take(11 * ns);
         L.o_tmp = take(3 * ns + 16);
         L.o_C = take(Nb * ns);
-        L.o_nuc = take(8 * M);
+        L.o_nuc = take(kNucLen * M);
         L.o_jas = take(3 * (2 + s.n_species));
         L.o_gd = take(4 * N);
         L.lds_doubles = o;
@@ -789,7 +791,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             d.o_pos = L.o_pos; d.o_R = L.o_R; d.o_Rdet = L.o_Rdet; d.o_dJ = L.o_dJ;
             d.o_Arow = L.o_Arow; d.o_AinvT = L.o_AinvT; d.o_Jg = L.o_Jg; d.o_Jl = L.o_Jl;
             d.o_nue = L.o_nue; d.o_nua = L.o_nua; d.o_dje = L.o_dje; d.o_scal = L.o_scal;
-            d.o_B = L.o_B; d.o_rows = L.o_rows; d.o_tmp = L.o_tmp; d.o_C = L.o_C;
+            d.ldb = L.ldb; d.o_B = L.o_B; d.o_rows = L.o_rows; d.o_tmp = L.o_tmp; d.o_C = L.o_C;
             d.bK = bK; d.o_nuc = L.o_nuc; d.o_jas = L.o_jas; d.o_gd = L.o_gd;
             d.lds_doubles = L.lds_doubles;
             d.s_Phi = L.s_Phi; d.s_dPhi = L.s_dPhi;

@@ -73,9 +73,6 @@ __device__ __forceinline__ void gst(T* p, T v)
     *(__attribute__((address_space(1))) T*)p = v;
 }
 
-// Nucleus record staged in LDS per walker: x, y, z, charge, core radius,
-// soft-core flag, Jastrow parameter row, padding.
-constexpr int kNucLen = 8;
 // orbital values per lane fetched ahead of the ratio and derivative updates
 constexpr int kPre = 8;
 
@@ -193,7 +190,7 @@ __device__ __forceinline__ void nucleus_potential(const DevSys& s, const Walker&
 // 11..15 and columns >= n are padding).
 __device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, double a, int lane)
 {
-    const int Nb = s.Nb;
+    const int Nb = s.Nb, ldb = s.ldb;
     for (int mu = lane; mu < Nb; mu += kWave) {
         const double4_t c = gld((const double4_t*)(s.btab + 4 * mu));
         const int t = gld(s.btype + mu);
@@ -207,7 +204,7 @@ __device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, do
                 double pq[3];
                 point_q(r, q, a, pq);
                 const double dx = pq[0] - c[0], dy = pq[1] - c[1], dz = pq[2] - c[2];
-                Bm[q * Nb] = basis_value_d(t, al, dx, dy, dz, dx * dx + dy * dy + dz * dz);
+                Bm[q * ldb] = basis_value_d(t, al, dx, dy, dz, dx * dx + dy * dy + dz * dz);
             }
             basis_vgl_d(t, al, d[0], d[1], d[2], d2, v, g, l);
         } else {
@@ -225,8 +222,8 @@ __device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, do
                 const double ep = e * (K * tc), em = e * (K * recip(tc));
                 const double fp = (t != 0 && ax == cc) ? f0 + a : f0;
                 const double fm = (t != 0 && ax == cc) ? f0 - a : f0;
-                Bm[(2 * cc + 1) * Nb] = fp * ep;
-                Bm[(2 * cc + 2) * Nb] = fm * em;
+                Bm[(2 * cc + 1) * ldb] = fp * ep;
+                Bm[(2 * cc + 2) * ldb] = fm * em;
             }
             if (t == 0) {
                 v = e;
@@ -239,49 +236,50 @@ __device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, do
             }
         }
         Bm[0] = v;
-        Bm[7 * Nb] = g[0];
-        Bm[8 * Nb] = g[1];
-        Bm[9 * Nb] = g[2];
-        Bm[10 * Nb] = l;
+        Bm[7 * ldb] = g[0];
+        Bm[8 * ldb] = g[1];
+        Bm[9 * ldb] = g[2];
+        Bm[10 * ldb] = l;
     }
 }
 
+// Orbital rows O[row][col] = sum_mu B[row][mu] C[mu][col] of electron j
+// (rows 0..10) on the four-block FP64 MFMA v_mfma_f64_4x4x4f64: block
+// b = (lane >> 2) & 3 holds A[b][i][k] at lane 16k + 4b + i, B[b][k][c] at
+// lane 16k + 4b + c and D[b][i][c] at lane 16i + 4b + c.  Blocks 2t and 2t+1
+// take column tile t of the pair and the even and odd k-steps; three
+// accumulators cover the row tiles 0..3, 4..7 and 8..10.
 __device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
 {
     wave_sync();
-    const int Nb = s.Nb;
+    const int Nb = s.Nb, ldb = s.ldb;
     const int n = nspin(s, spin_of(s, j));
-    const int i16 = lane & 15, k4 = lane >> 4;
-    const bool arow_ok = i16 < 11;
-    for (int t = 0; t * 16 < n; ++t) {
-        double4_t acc = {0.0, 0.0, 0.0, 0.0};
-        const int col = 16 * t + i16;
-        const bool bcol_ok = col < n;
-        int k0 = 0;
-        // four k-steps per round: operands loaded first, then the MFMA chain
-        for (; k0 + 16 <= Nb; k0 += 16) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int mu = k0 + 4 * u + k4;
-                av[u] = arow_ok ? lds[w.B + i16 * Nb + mu] : 0.0;
-                bv[u] = bcol_ok ? lds[w.C + mu * s.ns + col] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+    const int lk = lane >> 4, lb = (lane >> 2) & 3, l4 = lane & 3;
+    const int par = lb & 1, cb = lb >> 1;
+    for (int ct0 = 0; 4 * ct0 < n; ct0 += 2) {
+        const int col = 4 * (ct0 + cb) + l4;
+        const bool cok = col < n;
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+        for (int k0 = 0; k0 < Nb; k0 += 8) {
+            const int mu = k0 + 4 * par + lk;
+            const bool kok = mu < Nb;
+            const double bv = (cok && kok) ? lds[w.C + mu * s.ns + col] : 0.0;
+            const double a0 = kok ? lds[w.B + l4 * ldb + mu] : 0.0;
+            const double a1 = kok ? lds[w.B + (4 + l4) * ldb + mu] : 0.0;
+            const double a2 = (kok && l4 < 3) ? lds[w.B + (8 + l4) * ldb + mu] : 0.0;
+            acc0 = __builtin_amdgcn_mfma_f64_4x4x4f64(a0, bv, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_4x4x4f64(a1, bv, acc1, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f64_4x4x4f64(a2, bv, acc2, 0, 0, 0);
         }
-        for (; k0 < Nb; k0 += 4) {
-            const int mu = k0 + k4;
-            // A operand: row i16, inner index k4; B operand: inner k4, column i16
-            const double av = (arow_ok && mu < Nb) ? lds[w.B + i16 * Nb + mu] : 0.0;
-            const double bv = (bcol_ok && mu < Nb) ? lds[w.C + mu * s.ns + col] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-        }
-        // D[row][col] with row = (lane >> 4) + 4 v
-        for (int v = 0; v < 4; ++v) {
-            const int row = k4 + 4 * v;
-            if (row < 11 && col < n) lds[w.rows + row * s.ns + col] = acc[v];
+        // odd k-steps (block 2t + 1, four lanes up) into block 2t: row_shl:4
+        acc0 += dpp_mov<0x104, 0xf>(acc0);
+        acc1 += dpp_mov<0x104, 0xf>(acc1);
+        acc2 += dpp_mov<0x104, 0xf>(acc2);
+        const int c = 4 * (ct0 + cb) + l4, i = lane >> 4;
+        if (par == 0 && c < n) {
+            lds[w.rows + i * s.ns + c] = acc0;
+            lds[w.rows + (4 + i) * s.ns + c] = acc1;
+            if (i < 3) lds[w.rows + (8 + i) * s.ns + c] = acc2;
         }
     }
     wave_sync();
@@ -839,7 +837,6 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
         nr[4] = gld(s.rc + I);
         nr[5] = gld(s.core + I) == 0 ? 0.0 : 1.0;
         nr[6] = (double)(2 + gld(s.spec + I));
-        nr[7] = 0.0;
     }
     for (int q = lane; q < 3 * (2 + s.nspec); q += kWave) lds[w.jas + q] = gld(s.jas + q);
     wave_sync();
