@@ -213,7 +213,7 @@ def main():
     kms = phase_kernel_ms(h)
     h.close()
 
-    fl = flops_per_walker_step(N, d["n_up"], d["n_basis"], d["n_atoms"], 0, 16)
+    fl = flops_per_walker_step(N, d["n_up"], d["n_basis"], d["n_atoms"], 0, prm.refresh_every)
     achieved = fl * nw * n_proj / (kms * 1e-3) / 1e12
     tr = traffic_per_launch()
     roof = dict(bound="alu", kernel="phase_fp64", achieved=achieved, peak=FP64_PEAK_TFLOPS,
@@ -225,8 +225,10 @@ def main():
                scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
                config=dict(workload="16-electron 8-atom synthetic molecule (1 C-like and 1 "
                                     "O-like soft core, 6 protons, 80 s/p Gaussians), 4096 "
-                                    "walkers, a=0.2 bohr, load-balanced N_proj=300, FP64",
+                                    "walkers, a=0.2 bohr, load-balanced N_proj=300, FP64, "
+                                    "refresh every 64 moves",
                            walkers=nw, electrons=N, n_proj=n_proj, precision="fp64",
+                           refresh_every=prm.refresh_every,
                            scheme="load-balanced", step="one projection phase + reconfiguration"),
                roofline=roof)
 

@@ -145,12 +145,18 @@ def _sys_struct(d, keep):
         n_walkers, int(d.get("system_id", 0)))
 
 
-def make_params(scheme="lb", a=0.2, tau=0.25, n_proj=300, seed=12033, refresh_every=16,
+def make_params(scheme="lb", a=0.2, tau=0.25, n_proj=300, seed=12033, refresh_every=None,
                 nu_opt_mode=NU_OPT_OWN, p_corr=10, e0_window=50, trace_cap=0, precision="fp64"):
     """precision: "fp64" (every step in FP64), "fp32" or "bf16" (mixed: the
     orbital product on FP32 or BF16 MFMA, FP32 rank-one updates, FP64
-    accumulation and refreshes)."""
+    accumulation and refreshes).
+
+    refresh_every: moves between rebuilds of the inverses and Jastrow caches
+    from scratch; by default 64 in FP64 (the rounding drift of 64 rank-one
+    updates stays far below the FP64 error bar) and 16 in the mixed modes."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    if refresh_every is None:
+        refresh_every = 64 if prec == PRECISIONS["fp64"] else 16
     return lrdmc_params(SCHEME_LB if scheme == "lb" else SCHEME_CONV, prec, float(a), float(tau),
                         int(n_proj), int(seed), int(refresh_every), int(nu_opt_mode), int(p_corr),
                         int(e0_window), int(trace_cap))
