@@ -145,8 +145,7 @@ enum : int { kHistLogW = 0, kHistEbar = 1, kHistE0 = 2, kHistMaxLw = 3, kHistDis
              kHistLen = 8 };
 constexpr int kHistCap = 4096;
 
-// per-walker scalars stored at o_scal
-enum : int { kScLogdet0 = 0, kScLogdet1 = 1, kScSign0 = 2, kScSign1 = 3, kScVee = 4,
-             kScLen = 8 };
+// per-walker scalars stored at o_scal / l_scal: V_ee (slots 0..3 unused)
+enum : int { kScVee = 4, kScLen = 8 };
 
 }  // namespace lrdmc

@@ -9,6 +9,20 @@
 
 namespace lrdmc {
 
+// Loads and stores through pointers known to address global memory (the
+// descriptor's pointers are otherwise generic, and generic accesses also wait
+// on the LDS counter).
+template <class T>
+__device__ __forceinline__ T gld(const T* p)
+{
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ void gst(T* p, T v)
+{
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter (c0..c3), key
 // (k0, k1); uniform = top 53 bits of the first output word times 2^-53.

@@ -280,86 +280,79 @@ __device__ __noinline__ void mixed_store_rows(const DevMix* __restrict__ dm, flo
 
 // FP64 Gauss-Jordan (in place, partial pivoting) of the transposed Slater
 // matrix of spin sp read from Arow ([N][ns], FP32 or FP64); writes the
-// transposed inverse AiT[c][k] (FP32 or FP64, row stride ns) and log|det|,
-// sign into the walker scalars.
+// transposed inverse AiT[c][k] (FP32 or FP64, row stride ns).
+//
+// Per pivot column k: every wavefront finds the pivot row bi (largest
+// |M[r][k]|, r >= k, first among equals: a wavefront maximum, n <= 64); the
+// column k, the pivot row and row k are staged in LDS; one barrier; every
+// thread updates its elements as if rows k and bi had been interchanged
+// first (row k <- pivot row scaled, row bi <- old row k, eliminated); one
+// barrier.  The row interchanges are undone at the end as one column
+// permutation of the output.
 template <class TS, class TD>
 __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
 {
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
     const int n = mnspin(s, sp);
     if (!n) return true;
     const int off = sp ? s.Nup : 0, ns = s.ns;
     double* M = LDSD(s.l_U);                     // [n][n]
-    double* sc = LDSD(s.l_scal);
-    int* piv = reinterpret_cast<int*>(LDSF(s.l_tmp));
+    double* colk = M + n * n;                    // [n] column k
+    double* prow = colk + n;                     // [n] pivot row
+    double* qrow = prow + n;                     // [n] row k
+    int* piv = reinterpret_cast<int*>(LDSF(s.l_tmp));   // [n] pivot rows
+    int* cperm = piv + n;                               // [n] output column permutation
     // fixed column per thread, rows strided: no division in the n^2 loops
-    const int rs = (int)blockDim.x / n, c0 = tid % n, r0 = tid / n;
+    const int rs = nt / n, c0 = tid % n, r0 = tid / n;
     const bool act = tid < rs * n;
     if (act)
         for (int r = r0; r < n; r += rs) M[r * n + c0] = (double)Arow[(long)(off + c0) * ns + r];
     __syncthreads();
-    double logdet = 0.0, sign = 1.0;
     bool ok = true;
     const int lane = tid & 63;
     for (int k = 0; k < n; ++k) {
-        // pivot: largest |M[r][k]|, r >= k, first index among equals; every
-        // wave finds it with a butterfly over its lanes (n <= 64)
-        const int rp = k + lane;
-        double best = rp < n ? fabs(M[rp * n + k]) : -1.0;
-        int bi = rp < n ? rp : n;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const double ob = __shfl_xor(best, o);
-            const int oi = __shfl_xor(bi, o);
-            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
+        const double v = (lane >= k && lane < n) ? fabs(M[lane * n + k]) : -1.0;
+        const double best = wave_max(v);
         if (!(best > 0.0)) { ok = false; break; }
-        __syncthreads();   // every wave has read column k before any row moves
-        if (tid == 0) piv[k] = bi;
-        if (bi != k) {
-            for (int c = tid; c < n; c += (int)blockDim.x) {
-                const double t = M[k * n + c];
-                M[k * n + c] = M[bi * n + c];
-                M[bi * n + c] = t;
-            }
-            sign = -sign;
-            __syncthreads();
+        const int bi = __ffsll((long long)__ballot(v == best)) - 1;
+        for (int r = tid; r < n; r += nt) {
+            colk[r] = M[r * n + k];
+            prow[r] = M[bi * n + r];
+            qrow[r] = M[k * n + r];
         }
-        const double d = M[k * n + k];
-        logdet += log(fabs(d));
-        if (d < 0) sign = -sign;
-        const double id = 1.0 / d;
-        __syncthreads();
-        // row k scaled; column k of the other rows stored before elimination
-        double* colk = LDSD(s.l_U) + n * n;          // [n]
-        for (int r = tid; r < n; r += (int)blockDim.x) colk[r] = M[r * n + k];
-        __syncthreads();
-        for (int c = tid; c < n; c += (int)blockDim.x) M[k * n + c] = (c == k ? 1.0 : M[k * n + c]) * id;
+        if (tid == 0) piv[k] = bi;
         __syncthreads();
         if (act) {
-            const double mk = M[k * n + c0];
+            const double id = 1.0 / prow[k];
+            const double mk = (c0 == k ? 1.0 : prow[c0]) * id;
+            const double qc = qrow[c0], qk = qrow[k];
             for (int r = r0; r < n; r += rs) {
-                if (r == k) continue;
-                M[r * n + c0] = (c0 == k ? 0.0 : M[r * n + c0]) - colk[r] * mk;
+                if (r == k) {
+                    M[k * n + c0] = mk;
+                } else {
+                    const double src = r == bi ? qc : M[r * n + c0];
+                    const double cr = r == bi ? qk : colk[r];
+                    M[r * n + c0] = (c0 == k ? 0.0 : src) - cr * mk;
+                }
             }
         }
         __syncthreads();
     }
     if (ok) {
-        // undo the row interchanges as column interchanges, in reverse order
-        for (int k = n - 1; k >= 0; --k) {
-            const int p = piv[k];
-            if (p != k)
-                for (int r = tid; r < n; r += (int)blockDim.x) {
-                    const double t = M[r * n + k];
-                    M[r * n + k] = M[r * n + p];
-                    M[r * n + p] = t;
-                }
-            __syncthreads();
+        // the interchanges (k, piv[k]) applied to the columns in reverse order
+        if (tid == 0) {
+            for (int c = 0; c < n; ++c) cperm[c] = c;
+            for (int k = n - 1; k >= 0; --k) {
+                const int p = piv[k], t = cperm[k];
+                cperm[k] = cperm[p];
+                cperm[p] = t;
+            }
         }
-        if (act)
-            for (int r = r0; r < n; r += rs) AiT[(long)r * ns + c0] = (TD)M[r * n + c0];
-        if (tid == 0) { sc[kScLogdet0 + sp] = logdet; sc[kScSign0 + sp] = sign; }
+        __syncthreads();
+        if (act) {
+            const int cs = cperm[c0];
+            for (int r = r0; r < n; r += rs) AiT[(long)r * ns + c0] = (TD)M[r * n + cs];
+        }
     }
     global_handoff();
     return ok;
@@ -397,15 +390,20 @@ __device__ __noinline__ void mixed_spin_update(const DevMix* __restrict__ dm, co
         const float* col = isg ? dPhi + q : Phi + q;
         const long stride = isg ? 4L * ns : 6L * ns;
         const float* a = AiL + c * ns;
+        // 16 loads in flight per batch (the walker blocks live in HBM)
         float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-        int k = 0;
-        for (; k + 4 <= n; k += 4) {
-            s0 += col[(long)k * stride] * a[k];
-            s1 += col[(long)(k + 1) * stride] * a[k + 1];
-            s2 += col[(long)(k + 2) * stride] * a[k + 2];
-            s3 += col[(long)(k + 3) * stride] * a[k + 3];
+        for (int k0 = 0; k0 < n; k0 += 16) {
+            float x[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) x[u] = k0 + u < n ? gld(col + (long)(k0 + u) * stride) : 0.f;
+#pragma unroll
+            for (int u = 0; u < 16; u += 4) {
+                if (k0 + u < n) s0 += x[u] * a[k0 + u];
+                if (k0 + u + 1 < n) s1 += x[u + 1] * a[k0 + u + 1];
+                if (k0 + u + 2 < n) s2 += x[u + 2] * a[k0 + u + 2];
+                if (k0 + u + 3 < n) s3 += x[u + 3] * a[k0 + u + 3];
+            }
         }
-        for (; k < n; ++k) s0 += col[(long)k * stride] * a[k];
         const float v = (s0 + s1) + (s2 + s3);
         if (isg) gD[4 * (off + c) + (q & 3)] = v;
         else Rdet[6 * off + q] = v;
@@ -849,11 +847,6 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
         else Ai[(long)cc * ns + k] -= rowc[k] * (beta[cc] * iR);
     }
     for (int k = tid; k < n; k += (int)blockDim.x) st[s.g_Arow + (long)i * ns + k] = u[k];
-    if (tid == 0) {
-        double* sc = LDSD(s.l_scal);
-        sc[kScLogdet0 + sp] += log(fabs((double)Rd));
-        if (Rd < 0) sc[kScSign0 + sp] = -sc[kScSign0 + sp];
-    }
     global_handoff();
 
     mixed_rows(&s, i, rnew, a);

@@ -59,20 +59,6 @@ __device__ __forceinline__ void block_visible()
 // spill area (orbital rows at the 6N moves, orbital derivatives).
 extern __shared__ double lds[];
 
-// Loads and stores through pointers known to address global memory (the
-// descriptor's pointers are otherwise generic, and generic accesses also wait
-// on the LDS counter).
-template <class T>
-__device__ __forceinline__ T gld(const T* p)
-{
-    return *(const __attribute__((address_space(1))) T*)p;
-}
-template <class T>
-__device__ __forceinline__ void gst(T* p, T v)
-{
-    *(__attribute__((address_space(1))) T*)p = v;
-}
-
 // orbital values per lane fetched ahead of the ratio and derivative updates
 constexpr int kPre = 8;
 
