@@ -23,6 +23,22 @@ __device__ __forceinline__ void gst(T* p, T v)
     *(__attribute__((address_space(1))) T*)p = v;
 }
 
+// 1/x to about one ulp: hardware reciprocal estimate and two Newton steps.
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// 1/sqrt(x) to about one ulp: hardware estimate and two Newton steps.
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter (c0..c3), key
 // (k0, k1); uniform = top 53 bits of the first output word times 2^-53.

@@ -92,22 +92,28 @@ __device__ __forceinline__ double block_excl_scan(double v, double* red, double&
     return off + prev;
 }
 
-__device__ __forceinline__ float pade_uf(const double* p, float r)
+// FP32 Pade parameter row and the pair terms from the squared distance
+// (hardware reciprocal square root and reciprocal, about 1 ulp in FP32)
+struct PadeF { float A, B, b; };
+__device__ __forceinline__ PadeF pade_row(const DevMix& s, int jr)
 {
-    const float A = (float)p[0], B = (float)p[1], b = (float)p[2];
-    return (A * r + B * r * r) / (1.0f + b * r);
+    const double* p = s.jas + 3 * jr;
+    return PadeF{(float)gld(p), (float)gld(p + 1), (float)gld(p + 2)};
 }
-
-__device__ __forceinline__ void pade_derivs_f(const double* p, float r, float& u, float& du_r,
-                                              float& lap)
+__device__ __forceinline__ float pade_u2f(const PadeF& p, float r2)
 {
-    const float A = (float)p[0], B = (float)p[1], b = (float)p[2];
-    const float iden = 1.0f / (1.0f + b * r), ir = 1.0f / r;
-    const float i2 = iden * iden;
-    u = (A * r + B * r * r) * iden;
-    const float du = (A + 2.0f * B * r + B * b * r * r) * i2;
+    const float r = r2 * __builtin_amdgcn_rsqf(r2);
+    return r * (p.A + p.B * r) * __builtin_amdgcn_rcpf(1.0f + p.b * r);
+}
+// u, u'/r, u'' + 2u'/r from r and 1/r
+__device__ __forceinline__ void pade_derivs_rf(const PadeF& p, float r, float ir, float& u,
+                                               float& du_r, float& lap)
+{
+    const float iden = __builtin_amdgcn_rcpf(1.0f + p.b * r), i2 = iden * iden;
+    u = (p.A * r + p.B * r * r) * iden;
+    const float du = (p.A + 2.0f * p.B * r + p.B * p.b * r * r) * i2;
     du_r = du * ir;
-    lap = 2.0f * (B - A * b) * i2 * iden + 2.0f * du_r;
+    lap = 2.0f * (p.B - p.A * p.b) * i2 * iden + 2.0f * du_r;
 }
 
 __device__ __forceinline__ int mspin(const DevMix& s, int i) { return i >= s.Nup; }
@@ -127,20 +133,23 @@ __device__ __forceinline__ void mpartner(const DevMix& s, const double* pos, int
         jr = mee_row(s, i, k);
     } else {
         const int I = k - s.N;
-        pk[0] = s.R[3 * I]; pk[1] = s.R[3 * I + 1]; pk[2] = s.R[3 * I + 2];
-        jr = 2 + s.spec[I];
+        pk[0] = gld(s.R + 3 * I); pk[1] = gld(s.R + 3 * I + 1); pk[2] = gld(s.R + 3 * I + 2);
+        jr = 2 + gld(s.spec + I);
     }
 }
 
-// nuclear potential of nucleus I at distance r: nu and its lattice bound nu^a
-__device__ __forceinline__ void nuc_pot(const DevMix& s, int I, double r, double a, double& nu,
-                                        double& nua)
+// nuclear potential of nucleus I from the squared distance r2 and ir = 1/r
+// (FP64): nu and its lattice bound nu^a
+__device__ __forceinline__ void nuc_pot(const DevMix& s, int I, double r2, double ir, double ia,
+                                        double& nu, double& nua)
 {
-    if (s.core[I] == 0) {
-        nu = -s.Z[I] / r;
-        nua = -s.Z[I] / (r > a ? r : a);
+    const double Z = gld(s.Z + I);
+    if (gld(s.core + I) == 0) {
+        nu = -Z * ir;
+        nua = -Z * (ir < ia ? ir : ia);
     } else {
-        nu = nua = -s.Z[I] / sqrt(r * r + s.rc[I] * s.rc[I]);
+        const double rc = gld(s.rc + I);
+        nu = nua = -Z * rsqrt_nr(r2 + rc * rc);
     }
 }
 
@@ -152,7 +161,7 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
 {
     const DevMix& s = *dm;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int Nb = s.Nb, items = 7 * Nb;
+    const int Nb = s.Nb;
     float* B = LDSF(s.l_U);                      // [11][nb32 + 4] basis rows (zero padded; the
                                                  // extra 4 floats spread the rows over the banks)
     float* rows = LDSF(s.l_rows);
@@ -162,17 +171,61 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
         const int row = z / (ldb - Nb);
         B[row * ldb + Nb + (z - row * (ldb - Nb))] = 0.0f;
     }
-    for (int it = tid; it < items; it += (int)blockDim.x) {
-        const int q = it / Nb, mu = it - q * Nb;
-        double p[3];
-        point_q(r, q, a, p);
-        const double* rec = s.btab + 4 * mu;
-        const float dx = (float)(p[0] - rec[0]), dy = (float)(p[1] - rec[1]),
-                    dz = (float)(p[2] - rec[2]);
-        const float d2 = dx * dx + dy * dy + dz * dz, al = (float)rec[3];
-        const int t = s.btype[mu];
-        if (q == 0) {
-            float v, g0, g1, g2, l;
+    // one thread per basis function: a Gaussian factorizes over the
+    // coordinates, so its values at the six neighbours r + s a e_c follow from
+    // exp(-alpha d^2), exp(-alpha a^2) and exp(-+2 alpha a d_c) (d = r - centre);
+    // Slater functions, and exponents beyond the FP32 range, take the seven
+    // points directly
+    const float af = (float)a;
+    for (int mu = tid; mu < Nb; mu += (int)blockDim.x) {
+        const double4_t rec = gld((const double4_t*)(s.btab + 4 * mu));
+        const int t = gld(s.btype + mu);
+        const float d[3] = {(float)(r[0] - rec[0]), (float)(r[1] - rec[1]), (float)(r[2] - rec[2])};
+        const float d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2], al = (float)rec[3];
+        const float s2a = 2.0f * al * af;
+        bool fac = t != 4;
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) fac = fac && fabsf(s2a * d[cc]) < 80.0f;
+        float v, g0, g1, g2, l;
+        if (fac) {
+            const float e = expf(-al * d2), K = expf(-al * af * af);
+            const int ax = t - 1;
+            const float f0 = t == 0 ? 1.0f : (ax == 0 ? d[0] : (ax == 1 ? d[1] : d[2]));
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                const float tc = expf(-s2a * d[cc]);
+                const float ep = e * (K * tc), em = e * (K * __builtin_amdgcn_rcpf(tc));
+                const float fp = (t != 0 && ax == cc) ? f0 + af : f0;
+                const float fm = (t != 0 && ax == cc) ? f0 - af : f0;
+                B[(2 * cc + 1) * ldb + mu] = fp * ep;
+                B[(2 * cc + 2) * ldb + mu] = fm * em;
+            }
+            v = f0 * e;
+            if (t == 0) {
+                g0 = -2.0f * al * d[0] * e; g1 = -2.0f * al * d[1] * e; g2 = -2.0f * al * d[2] * e;
+                l = (4.0f * al * al * d2 - 6.0f * al) * e;
+            } else {
+                g0 = (ax == 0 ? e : 0.0f) - 2.0f * al * f0 * d[0] * e;
+                g1 = (ax == 1 ? e : 0.0f) - 2.0f * al * f0 * d[1] * e;
+                g2 = (ax == 2 ? e : 0.0f) - 2.0f * al * f0 * d[2] * e;
+                l = f0 * e * (4.0f * al * al * d2 - 10.0f * al);
+            }
+        } else {
+            for (int q = 1; q < 7; ++q) {
+                double p[3];
+                point_q(r, q, a, p);
+                const float dx = (float)(p[0] - rec[0]), dy = (float)(p[1] - rec[1]),
+                            dz = (float)(p[2] - rec[2]);
+                const float dq2 = dx * dx + dy * dy + dz * dz;
+                float w;
+                if (t == 4) w = expf(-al * sqrtf(dq2));
+                else {
+                    const float e = expf(-al * dq2);
+                    w = t == 0 ? e : (t == 1 ? dx : (t == 2 ? dy : dz)) * e;
+                }
+                B[q * ldb + mu] = w;
+            }
+            const float dx = d[0], dy = d[1], dz = d[2];
             if (t == 4) {
                 const float dd = sqrtf(d2), e = expf(-al * dd), id = 1.0f / dd;
                 v = e; g0 = -al * dx * id * e; g1 = -al * dy * id * e; g2 = -al * dz * id * e;
@@ -190,18 +243,10 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
                 g2 = (t == 3 ? e : 0.0f) - 2.0f * al * dq * dz * e;
                 l = dq * e * (4.0f * al * al * d2 - 10.0f * al);
             }
-            B[mu] = v;
-            B[7 * ldb + mu] = g0; B[8 * ldb + mu] = g1; B[9 * ldb + mu] = g2;
-            B[10 * ldb + mu] = l;
-        } else {
-            float v;
-            if (t == 4) v = expf(-al * sqrtf(d2));
-            else {
-                const float e = expf(-al * d2);
-                v = t == 0 ? e : (t == 1 ? dx : (t == 2 ? dy : dz)) * e;
-            }
-            B[q * ldb + mu] = v;
         }
+        B[mu] = v;
+        B[7 * ldb + mu] = g0; B[8 * ldb + mu] = g1; B[9 * ldb + mu] = g2;
+        B[10 * ldb + mu] = l;
     }
     __syncthreads();
     const int n = mnspin(s, mspin(s, j));
@@ -296,8 +341,9 @@ __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
     const int n = mnspin(s, sp);
     if (!n) return true;
     const int off = sp ? s.Nup : 0, ns = s.ns;
-    double* M = LDSD(s.l_U);                     // [n][n]
-    double* colk = M + n * n;                    // [n] column k
+    const int ldm = n + 1;                       // odd row stride: columns spread over the banks
+    double* M = LDSD(s.l_U);                     // [n][ldm]
+    double* colk = M + n * ldm;                  // [n] column k
     double* prow = colk + n;                     // [n] pivot row
     double* qrow = prow + n;                     // [n] row k
     int* piv = reinterpret_cast<int*>(LDSF(s.l_tmp));   // [n] pivot rows
@@ -306,19 +352,19 @@ __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
     const int rs = nt / n, c0 = tid % n, r0 = tid / n;
     const bool act = tid < rs * n;
     if (act)
-        for (int r = r0; r < n; r += rs) M[r * n + c0] = (double)Arow[(long)(off + c0) * ns + r];
+        for (int r = r0; r < n; r += rs) M[r * ldm + c0] = (double)Arow[(long)(off + c0) * ns + r];
     __syncthreads();
     bool ok = true;
     const int lane = tid & 63;
     for (int k = 0; k < n; ++k) {
-        const double v = (lane >= k && lane < n) ? fabs(M[lane * n + k]) : -1.0;
+        const double v = (lane >= k && lane < n) ? fabs(M[lane * ldm + k]) : -1.0;
         const double best = wave_max(v);
         if (!(best > 0.0)) { ok = false; break; }
         const int bi = __ffsll((long long)__ballot(v == best)) - 1;
         for (int r = tid; r < n; r += nt) {
-            colk[r] = M[r * n + k];
-            prow[r] = M[bi * n + r];
-            qrow[r] = M[k * n + r];
+            colk[r] = M[r * ldm + k];
+            prow[r] = M[bi * ldm + r];
+            qrow[r] = M[k * ldm + r];
         }
         if (tid == 0) piv[k] = bi;
         __syncthreads();
@@ -326,13 +372,23 @@ __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
             const double id = 1.0 / prow[k];
             const double mk = (c0 == k ? 1.0 : prow[c0]) * id;
             const double qc = qrow[c0], qk = qrow[k];
-            for (int r = r0; r < n; r += rs) {
-                if (r == k) {
-                    M[k * n + c0] = mk;
-                } else {
-                    const double src = r == bi ? qc : M[r * n + c0];
-                    const double cr = r == bi ? qk : colk[r];
-                    M[r * n + c0] = (c0 == k ? 0.0 : src) - cr * mk;
+            // eight rows per batch: all loads before the stores
+            for (int rb = r0; rb < n; rb += 8 * rs) {
+                double mv[8], cv[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int r = rb + t * rs;
+                    mv[t] = r < n ? M[r * ldm + c0] : 0.0;
+                    cv[t] = r < n ? colk[r] : 0.0;
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int r = rb + t * rs;
+                    if (r < n) {
+                        const double src = r == bi ? qc : mv[t];
+                        const double cr = r == bi ? qk : cv[t];
+                        M[r * ldm + c0] = r == k ? mk : (c0 == k ? 0.0 : src) - cr * mk;
+                    }
                 }
             }
         }
@@ -351,7 +407,7 @@ __device__ bool gj_inverse(const DevMix& s, const TS* Arow, TD* AiT, int sp)
         __syncthreads();
         if (act) {
             const int cs = cperm[c0];
-            for (int r = r0; r < n; r += rs) AiT[(long)r * ns + c0] = (TD)M[r * n + cs];
+            for (int r = r0; r < n; r += rs) AiT[(long)r * ns + c0] = (TD)M[r * ldm + cs];
         }
     }
     global_handoff();
@@ -434,50 +490,72 @@ __device__ __noinline__ double mixed_jastrow_all(const DevMix* __restrict__ dm, 
     double* nua = LDSD(s.l_nua);
     float* S = LDSF(s.l_U);                       // [N][7]
     const int K = s.N + s.M, Kj = s.has_en ? K : s.N;
+    const double ia = 1.0 / a;
     for (int it = tid; it < 7 * s.N; it += (int)blockDim.x) {
         const int j = it / 7, q = it - 7 * j;
         double pq[3];
         point_q(pos + 3 * j, q, a, pq);
-        float acc = 0.f;
+        // four partners per round, independent partial sums
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
         #pragma unroll 1
-        for (int k = 0; k < Kj; ++k) {
-            if (k == j) continue;
-            double pk[3];
-            int jr;
-            mpartner(s, pos, j, k, pk, jr);
-            acc += pade_uf(s.jas + 3 * jr, (float)norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+        for (int k0 = 0; k0 < Kj; k0 += 4) {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int k = k0 + h;
+                if (k < Kj && k != j) {
+                    double pk[3];
+                    int jr;
+                    mpartner(s, pos, j, k, pk, jr);
+                    const float e0 = (float)(pq[0] - pk[0]), e1 = (float)(pq[1] - pk[1]),
+                                e2 = (float)(pq[2] - pk[2]);
+                    acc[h] += (double)pade_u2f(pade_row(s, jr), e0 * e0 + e1 * e1 + e2 * e2);
+                }
+            }
         }
-        S[it] = acc;
+        S[it] = (float)((acc[0] + acc[1]) + (acc[2] + acc[3]));
     }
     double vee = 0.0;
-    for (int j = tid; j < s.N; j += (int)blockDim.x) {
-        const double* rj = pos + 3 * j;
+    // two threads per electron (adjacent lanes, partners k = h, h + 2, ...),
+    // combined over the lane pair; every pass keeps both lanes of a pair
+    for (int base = 0; base < 2 * s.N; base += (int)blockDim.x) {
+        const int it = base + tid, j = it >> 1, h = it & 1;
+        const bool jv = it < 2 * s.N;
+        const double* rj = pos + 3 * (jv ? j : 0);
         float g0 = 0.f, g1 = 0.f, g2 = 0.f, l = 0.f;
         double nu = 0.0, nv = 0.0;
         #pragma unroll 1
-        for (int k = 0; k < K; ++k) {
+        for (int k = h; jv && k < K; k += 2) {
             if (k == j) continue;
             const bool isel = k < s.N;
             double pk[3];
             int jr;
             mpartner(s, pos, j, k, pk, jr);
             const double d0 = rj[0] - pk[0], d1 = rj[1] - pk[1], d2 = rj[2] - pk[2];
-            const double r = norm3(d0, d1, d2);
+            const double r2 = d0 * d0 + d1 * d1 + d2 * d2, ir = rsqrt_nr(r2);
             if (isel || s.has_en) {
                 float u, dur, lp;
-                pade_derivs_f(s.jas + 3 * jr, (float)r, u, dur, lp);
+                pade_derivs_rf(pade_row(s, jr), (float)(r2 * ir), (float)ir, u, dur, lp);
                 g0 += dur * (float)d0; g1 += dur * (float)d1; g2 += dur * (float)d2;
                 l += lp;
-                if (isel && k > j) vee += 1.0 / r;
+                if (isel && k > j) vee += ir;
             }
             if (!isel) {
                 double a1, a2;
-                nuc_pot(s, k - s.N, r, a, a1, a2);
+                nuc_pot(s, k - s.N, r2, ir, ia, a1, a2);
                 nu += a1; nv += a2;
             }
         }
-        Jg[3 * j] = g0; Jg[3 * j + 1] = g1; Jg[3 * j + 2] = g2; Jl[j] = l;
-        nue[j] = nu; nua[j] = nv;
+        // quad_perm [1,0,3,2]: the other lane of the pair
+        g0 += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(g0), 0xb1, 0xf, 0xf, false));
+        g1 += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(g1), 0xb1, 0xf, 0xf, false));
+        g2 += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(g2), 0xb1, 0xf, 0xf, false));
+        l += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(l), 0xb1, 0xf, 0xf, false));
+        nu += dpp_mov<0xb1, 0xf>(nu);
+        nv += dpp_mov<0xb1, 0xf>(nv);
+        if (jv && h == 0) {
+            Jg[3 * j] = g0; Jg[3 * j + 1] = g1; Jg[3 * j + 2] = g2; Jl[j] = l;
+            nue[j] = nu; nua[j] = nv;
+        }
     }
     vee = block_sum(vee, LDSD(s.l_red));
     for (int p = tid; p < s.P; p += (int)blockDim.x) {
@@ -703,17 +781,17 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
             int jr;
             mpartner(s, pos, j, k, pk, jr);
             const double d0 = rj[0] - pk[0], d1 = rj[1] - pk[1], d2 = rj[2] - pk[2];
-            const double r = norm3(d0, d1, d2);
+            const double r2 = d0 * d0 + d1 * d1 + d2 * d2, ir = rsqrt_nr(r2);
             if (isel || s.has_en) {
                 double u, dur, lp;
-                pade_derivs(s.jas + 3 * jr, r, u, dur, lp);
+                pade_derivs(s.jas + 3 * jr, r2 * ir, u, dur, lp);
                 g0 += dur * d0; g1 += dur * d1; g2 += dur * d2;
                 l += lp;
-                if (isel && k > j) vee += 1.0 / r;
+                if (isel && k > j) vee += ir;
             }
             if (!isel) {
                 double a1, a2;
-                nuc_pot(s, k - N, r, a, a1, a2);
+                nuc_pot(s, k - N, r2, ir, 1.0 / a, a1, a2);
                 nu += a1; nv += a2;
             }
         }
@@ -815,6 +893,7 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
     const int tid = threadIdx.x, ns = s.ns;
     const int i = p / 6, d = (p / 2) % 3, sg = p % 2;
     const int sp = mspin(s, i), c = mcol(s, i), n = mnspin(s, sp);
+    const double ia = 1.0 / a;
     double* pos = LDSD(s.l_pos);
     float* Rdet = LDSF(s.l_Rdet);
     const float Rd = Rdet[p];
@@ -873,8 +952,9 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
             int jr;
             point_q(rnew, qq, a, pq);
             mpartner(s, pos, i, k, pk, jr);
-            const double u = (double)pade_uf(s.jas + 3 * jr,
-                                             (float)norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
+            const float e0 = (float)(pq[0] - pk[0]), e1 = (float)(pq[1] - pk[1]),
+                        e2 = (float)(pq[2] - pk[2]);
+            const double u = (double)pade_u2f(pade_row(s, jr), e0 * e0 + e1 * e1 + e2 * e2);
 #pragma unroll
             for (int t = 0; t < 7; ++t) acc7[t] += (t == qq) ? u : 0.0;
         }
@@ -902,46 +982,66 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
         double pk[3];
         int jr;
         mpartner(s, pos, i, k, pk, jr);
-        const double* prm = s.jas + 3 * jr;
+        const PadeF prm = pade_row(s, jr);
         const double n0 = rnew[0] - pk[0], n1 = rnew[1] - pk[1], n2 = rnew[2] - pk[2];
-        const double rn = norm3(n0, n1, n2);
+        const double rn2 = n0 * n0 + n1 * n1 + n2 * n2, irn = rsqrt_nr(rn2);
         if (isel || s.has_en) {
             float un, dnr, lpn;
-            pade_derivs_f(prm, (float)rn, un, dnr, lpn);
+            pade_derivs_rf(prm, (float)(rn2 * irn), (float)irn, un, dnr, lpn);
             g0 += dnr * n0; g1 += dnr * n1; g2 += dnr * n2;
             l += lpn;
             if (isel) {
                 const double o0 = rold[0] - pk[0], o1 = rold[1] - pk[1], o2 = rold[2] - pk[2];
-                const double ro = norm3(o0, o1, o2);
+                const double ro2 = o0 * o0 + o1 * o1 + o2 * o2, iro = rsqrt_nr(ro2);
                 float uo, dor, lpo;
-                pade_derivs_f(prm, (float)ro, uo, dor, lpo);
+                pade_derivs_rf(prm, (float)(ro2 * iro), (float)iro, uo, dor, lpo);
                 dje[k] = un - uo;
                 Jg[3 * k] += (float)(-(dnr * n0) + dor * o0);
                 Jg[3 * k + 1] += (float)(-(dnr * n1) + dor * o1);
                 Jg[3 * k + 2] += (float)(-(dnr * n2) + dor * o2);
                 Jl[k] += lpn - lpo;
-                dvee += 1.0 / rn - 1.0 / ro;
+                dvee += irn - iro;
             }
         }
         if (!isel) {
             double a1, a2;
-            nuc_pot(s, k - s.N, rn, a, a1, a2);
+            nuc_pot(s, k - s.N, rn2, irn, ia, a1, a2);
             nu += a1; nua += a2;
         }
     }
-    g0 = block_sum(g0, red); g1 = block_sum(g1, red); g2 = block_sum(g2, red);
-    l = block_sum(l, red); dvee = block_sum(dvee, red);
-    nu = block_sum(nu, red); nua = block_sum(nua, red);
+    {
+        // the seven sums in one block reduction (the 7-point scratch is free)
+        double* red7 = red + 8;
+        const int lane = tid & 63, wv = tid >> 6, nwv = (int)blockDim.x >> 6;
+        double sv[7] = {g0, g1, g2, l, dvee, nu, nua};
+#pragma unroll
+        for (int t = 0; t < 7; ++t) {
+            const double v = wave_sum(sv[t]);
+            if (lane == 0) red7[wv * 7 + t] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 7; ++t) {
+            double v = red7[t];
+            for (int q = 1; q < nwv; ++q) v += red7[q * 7 + t];
+            sv[t] = v;
+        }
+        g0 = sv[0]; g1 = sv[1]; g2 = sv[2]; l = sv[3]; dvee = sv[4]; nu = sv[5]; nua = sv[6];
+    }
     // Jastrow exponent changes of the other electrons' moves
     for (int qp = tid; qp < s.P; qp += (int)blockDim.x) {
         const int j = qp / 6;
         if (j == i) continue;
         const int dd = (qp / 2) % 3, s2 = qp % 2;
-        const double* prm = s.jas + 3 * mee_row(s, i, j);
+        const PadeF prm = pade_row(s, mee_row(s, i, j));
         double r2[3] = {pos[3 * j], pos[3 * j + 1], pos[3 * j + 2]};
         r2[dd] = r2[dd] + (s2 ? -a : a);
-        const float un = pade_uf(prm, (float)norm3(r2[0] - rnew[0], r2[1] - rnew[1], r2[2] - rnew[2]));
-        const float uo = pade_uf(prm, (float)norm3(r2[0] - rold[0], r2[1] - rold[1], r2[2] - rold[2]));
+        const float n0 = (float)(r2[0] - rnew[0]), n1 = (float)(r2[1] - rnew[1]),
+                    n2 = (float)(r2[2] - rnew[2]);
+        const float o0 = (float)(r2[0] - rold[0]), o1 = (float)(r2[1] - rold[1]),
+                    o2 = (float)(r2[2] - rold[2]);
+        const float un = pade_u2f(prm, n0 * n0 + n1 * n1 + n2 * n2);
+        const float uo = pade_u2f(prm, o0 * o0 + o1 * o1 + o2 * o2);
         dJ[qp] += (un - uo) - dje[j];
     }
     __syncthreads();

@@ -107,22 +107,6 @@ __device__ __forceinline__ void partner(const DevSys& s, const Walker& w, int i,
     }
 }
 
-// 1/x to about one ulp: hardware reciprocal estimate and two Newton steps.
-__device__ __forceinline__ double recip(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(r, fma(-x, r, 1.0), r);
-    return fma(r, fma(-x, r, 1.0), r);
-}
-
-// 1/sqrt(x) to about one ulp: hardware estimate and two Newton steps.
-__device__ __forceinline__ double rsqrt_nr(double x)
-{
-    double y = __builtin_amdgcn_rsq(x);
-    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
-}
-
 // Pade pair function u(r) = (A r + B r^2)/(1 + b r) from the squared distance.
 __device__ __forceinline__ double pade_u2(const double* p, double r2)
 {
