@@ -453,19 +453,24 @@ __device__ bool refresh_all(const DevSys& s, const Walker& w, double a, int lane
 
 // Lattice-regularized diagonal and local energy at the current configuration
 // (App. D; Sec. II.C e_L = W - bbar).
-struct Local { double bbar, W, eL; };
+// inc: the lane's inclusive prefix of the positive-ratio sums of the lane
+// chunks (lane l owns moves [l per, (l + 1) per)), reused by the heat bath
+struct Local { double bbar, W, eL, inc; };
 
 __device__ Local evaluate(const DevSys& s, const Walker& w, double a, int nu_mode, int lane)
 {
     const double inv2a2 = 1.0 / (2.0 * a * a), ia2 = 2.0 * inv2a2;
-    double bs = 0.0, vs = 0.0;
+    double loc = 0.0, vs = 0.0;
     int anyneg = 0;
-    for (int p = lane; p < s.P; p += kWave) {
+    const int per = (s.P + kWave - 1) / kWave;
+    const int p0 = lane * per, p1 = min(p0 + per, s.P);
+    for (int p = p0; p < p1; ++p) {
         const double r = lds[w.R + p];
-        if (r > 0) bs += r;
+        if (r > 0) loc += r;
         else if (r < 0) { vs += -r; anyneg = 1; }
     }
-    bs = wave_sum(bs);
+    const double inc = wave_incl_scan(loc, lane);
+    const double bs = lane63(inc);
     vs = wave_sum(vs);
     const bool anynode = __ballot(anyneg) != 0;
     double sum_opt = 0.0;
@@ -496,25 +501,20 @@ __device__ Local evaluate(const DevSys& s, const Walker& w, double a, int nu_mod
     const double vsf = vs * inv2a2;
     L.W = 3.0 * s.N / (a * a) + sum_opt + lds[w.scal + kScVee] + vsf + s.vii;
     L.eL = L.W - L.bbar;
+    L.inc = inc;
     return L;
 }
 
-// Heat-bath choice: first p with cumulative positive ratio > xi * total.
-__device__ int heat_bath(const DevSys& s, const Walker& w, double xi, int lane)
+// Heat-bath choice: first p with cumulative positive ratio > xi * total, from
+// the chunk prefix sums of the evaluation at the same configuration.
+__device__ int heat_bath(const DevSys& s, const Walker& w, double xi, double inc, int lane)
 {
     const int per = (s.P + kWave - 1) / kWave;
     const int p0 = lane * per, p1 = min(p0 + per, s.P);
-    double loc = 0.0;
-    for (int p = p0; p < p1; ++p) {
-        const double r = lds[w.R + p];
-        if (r > 0) loc += r;
-    }
-    const double inc = wave_incl_scan(loc, lane);
     const double tot = lane63(inc);
     if (!(tot > 0)) return -1;
     const double t = xi * tot;
-    double c = __shfl_up(inc, 1);
-    if (lane == 0) c = 0.0;
+    double c = dpp_mov<0x138, 0xf>(inc);   // wave_shr:1, lane 0 receives 0
     int found = -1, lastpos = -1;
     for (int p = p0; p < p1; ++p) {
         const double r = lds[w.R + p];
@@ -562,10 +562,20 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
         lds[rowc + k] = lds[Ai + c * s.ns + k];
     }
     wave_sync();
-    for (int cc = lane; cc < n; cc += kWave) {
-        double acc = 0.0;
-        for (int k = 0; k < n; ++k) acc += lds[u + k] * lds[Ai + cc * s.ns + k];
-        lds[beta + cc] = acc;
+    if (n <= 8) {
+        // lane (cc, k) = (lane >> 3, lane & 7): one product, a sum over the 8 lanes
+        const int cc = lane >> 3, k = lane & 7;
+        double v = (cc < n && k < n) ? lds[u + k] * lds[Ai + cc * s.ns + k] : 0.0;
+        v += dpp_mov<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+        v += dpp_mov<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+        v += dpp_mov<0x114, 0xf>(v);   // row_shr:4: lane 8cc + 7 holds the group sum
+        if (k == 7 && cc < n) lds[beta + cc] = v;
+    } else {
+        for (int cc = lane; cc < n; cc += kWave) {
+            double acc = 0.0;
+            for (int k = 0; k < n; ++k) acc += lds[u + k] * lds[Ai + cc * s.ns + k];
+            lds[beta + cc] = acc;
+        }
     }
     wave_sync();
     for (int idx = lane; idx < n * n; idx += kWave) {
@@ -850,7 +860,7 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
             if (!(den > 0)) { lw = -INFINITY; n_neg++; }
             else if (!(L.bbar > 0)) { lw = -INFINITY; n_nomove++; }
             else lw += log(L.bbar / den);
-            q = heat_bath(s, w, lane_value(xmove, slot), lane);
+            q = heat_bath(s, w, lane_value(xmove, slot), L.inc, lane);
             if (tr && it < s.trace_cap && lane == 0) tr[it] = q;
             ++it;
         } else {
@@ -870,7 +880,7 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
                 if (tr && it - 1 < s.trace_cap && lane == 0) tr[it - 1] = -1;
                 break;
             }
-            q = heat_bath(s, w, lane_value(xmove, slot), lane);
+            q = heat_bath(s, w, lane_value(xmove, slot), L.inc, lane);
             if (tr && it - 1 < s.trace_cap && lane == 0) tr[it - 1] = q;
         }
         LRDMC_T(1);
