@@ -106,7 +106,8 @@ typedef struct lrdmc_params {
     double tau;              /* conventional: projection time per branching */
     int32_t n_proj;          /* load-balanced: steps per branching */
     uint64_t seed;           /* first Philox key word */
-    int32_t refresh_every;   /* FP64 inverse / Jastrow refresh cadence (steps), >= 1 */
+    int32_t refresh_every;   /* moves between FP64 rebuilds of the inverses and Jastrow caches,
+                                >= 1 (the Python binding defaults to 64 in FP64, 16 mixed) */
     int32_t nu_opt_mode;     /* LRDMC_NU_* */
     int32_t p_corr;          /* correcting factors: product of the p previous
                                 average weights (Sec. II.A) */
