@@ -424,16 +424,22 @@ __device__ __noinline__ bool mixed_refresh_inverse(const DevMix* __restrict__ dm
 // determinant ratios Rdet_p = Phi_p . AinvT[c] of every move of the electrons
 // of spin sp, with the inverse staged in LDS (the basis-row block is free
 // here; mixed_rows restores its zero padding).
-__device__ __noinline__ void mixed_spin_update(const DevMix* __restrict__ dm, const float* st, int sp)
+__device__ __noinline__ void mixed_spin_update(const DevMix* __restrict__ dm, const float* st, int sp,
+                                               bool staged)
 {
     const DevMix& s = *dm;
-    const int tid = threadIdx.x, nt = blockDim.x, ns = s.ns;
+    const int tid = threadIdx.x, nt = blockDim.x, ns = s.ns, lda = ns + 1;
     const int n = mnspin(s, sp), off = sp ? s.Nup : 0;
     if (!n) return;
-    float* AiL = LDSF(s.l_U);                    // [n][ns]
-    const float* Ai = st + s.g_AinvT + (long)sp * ns * ns;
-    for (int idx = tid; idx < n * ns; idx += nt) AiL[idx] = Ai[idx];
-    __syncthreads();
+    float* AiL = LDSF(s.l_U);                    // [n][ns + 1]
+    if (!staged) {
+        const float* Ai = st + s.g_AinvT + (long)sp * ns * ns;
+        for (int idx = tid; idx < n * ns; idx += nt) {
+            const int r = idx / ns;
+            AiL[r * lda + idx - r * ns] = Ai[idx];
+        }
+        __syncthreads();
+    }
     float* gD = LDSF(s.l_gD);
     float* Rdet = LDSF(s.l_Rdet);
     const float* dPhi = st + s.g_dPhi + (long)sp * ns * 4 * ns;
@@ -445,7 +451,7 @@ __device__ __noinline__ void mixed_spin_update(const DevMix* __restrict__ dm, co
         const int c = isg ? (q >> 2) : q / 6;
         const float* col = isg ? dPhi + q : Phi + q;
         const long stride = isg ? 4L * ns : 6L * ns;
-        const float* a = AiL + c * ns;
+        const float* a = AiL + c * lda;
         // 16 loads in flight per batch (the walker blocks live in HBM)
         float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
         for (int k0 = 0; k0 < n; k0 += 16) {
@@ -573,8 +579,8 @@ __device__ __noinline__ bool mixed_refresh(const DevMix* __restrict__ dm, float*
     ok = mixed_refresh_inverse(&s, st, 1) && ok;
     const double vee = mixed_jastrow_all(&s, a);
     if (threadIdx.x == 0) LDSD(s.l_scal)[kScVee] = vee;
-    mixed_spin_update(&s, st, 0);
-    mixed_spin_update(&s, st, 1);
+    mixed_spin_update(&s, st, 0, false);
+    mixed_spin_update(&s, st, 1, false);
     mixed_full_ratios(s);
     return ok;
 }
@@ -901,36 +907,57 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
     double rnew[3] = {rold[0], rold[1], rold[2]};
     rnew[d] = rnew[d] + (sg ? -a : a);
 
+    // new orbital rows of electron i first: the basis block is then free for
+    // the LDS copy of the moved spin's inverse
+    mixed_rows(&s, i, rnew, a);
+
+    // Sherman-Morrison on the LDS copy (row stride ns + 1), written back to
+    // HBM; the ratio and gradient products below read the same copy
     float* Ai = st + s.g_AinvT + (long)sp * ns * ns;
     const float* Phi = st + s.g_Phi + (long)sp * ns * 6 * ns;
+    const int lda = ns + 1, nt = (int)blockDim.x;
+    float* AiL = LDSF(s.l_U);
     float* tmp = LDSF(s.l_tmp);
     float* u = tmp;               // [ns] accepted orbital row
     float* rowc = tmp + ns;       // [ns] column c of the inverse
     float* beta = tmp + 2 * ns;   // [ns]
     const int q = 6 * c + (p - 6 * i);
-    for (int k = tid; k < n; k += (int)blockDim.x) {
+    for (int idx = tid; idx < n * ns; idx += nt) {
+        const int r = idx / ns;
+        AiL[r * lda + idx - r * ns] = Ai[idx];
+    }
+    for (int k = tid; k < n; k += nt) {
         u[k] = Phi[(long)k * 6 * ns + q];
         rowc[k] = Ai[(long)c * ns + k];
     }
     __syncthreads();
-    for (int cc = tid; cc < n; cc += (int)blockDim.x) {
-        float acc = 0.f;
-        for (int k = 0; k < n; ++k) acc += u[k] * Ai[(long)cc * ns + k];
-        beta[cc] = acc;
+    {
+        // beta[cc] = u . AiL[cc]: kc threads per row (1, 2 or 4), k strided,
+        // summed over the kc lanes
+        const int kc = nt >= 4 * n ? 4 : (nt >= 2 * n ? 2 : 1);
+        const int cc = tid / kc, ch = tid - cc * kc;
+        for (int c0 = 0; c0 < n; c0 += nt / kc) {
+            const int row = c0 + cc;
+            float v = 0.f;
+            if (row < n)
+                for (int k = ch; k < n; k += kc) v += u[k] * AiL[row * lda + k];
+            if (kc >= 2) v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xb1, 0xf, 0xf, false));
+            if (kc == 4) v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4e, 0xf, 0xf, false));
+            if (row < n && ch == 0) beta[row] = v;
+        }
     }
     __syncthreads();
     const float iR = 1.0f / Rd;
-    for (int idx = tid; idx < n * n; idx += (int)blockDim.x) {
+    for (int idx = tid; idx < n * n; idx += nt) {
         const int cc = idx / n, k = idx - cc * n;
-        if (cc == c) Ai[(long)cc * ns + k] = rowc[k] * iR;
-        else Ai[(long)cc * ns + k] -= rowc[k] * (beta[cc] * iR);
+        const float v = cc == c ? rowc[k] * iR : AiL[cc * lda + k] - rowc[k] * (beta[cc] * iR);
+        AiL[cc * lda + k] = v;
+        Ai[(long)cc * ns + k] = v;
     }
-    for (int k = tid; k < n; k += (int)blockDim.x) st[s.g_Arow + (long)i * ns + k] = u[k];
-    global_handoff();
-
-    mixed_rows(&s, i, rnew, a);
+    for (int k = tid; k < n; k += nt) st[s.g_Arow + (long)i * ns + k] = u[k];
+    __syncthreads();
     mixed_store_rows(&s, st, i, false);
-    mixed_spin_update(&s, st, sp);
+    mixed_spin_update(&s, st, sp, true);
 
     // Jastrow caches of the moved electron (7 points) and of its partners
     const int K = s.N + s.M, Kj = s.has_en ? K : s.N;
