@@ -83,6 +83,7 @@ struct DevMix {
     const uint16_t *Cbf;         // [2][tiles][Nb/32][64 lanes][8] BF16 MFMA B operands:
                                  // high part, then the BF16 residual (low part)
     int nb32;                    // Nb rounded up to a multiple of 32
+    int fkc;                     // basis functions per chunk of the FP64 Slater rows
     const double *C64;           // [Nb][Norb] coefficients, FP64 (estimator evaluation)
     double *s64;                 // [nw][stride64] FP64 scratch: Slater rows, inverses
     long stride64;

@@ -85,6 +85,7 @@ struct Layout {
     long g_Phi, g_dPhi, g_Arow, g_AinvT, m_stride, stride64;
     int nb32, tiles;
     size_t lds_bytes;
+    int fkc = 4;
     // adjoint pass: LDS offsets (doubles)
     int nth;
     int a_pos, a_phi, a_dphi, a_phi6, a_ainv, a_Z, a_T, a_Y, a_G, a_chi, a_gj, a_Lj, a_dJ, a_R,
@@ -153,9 +154,20 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.l_nua = take(N * 8);
         L.l_scal = take(kScLen * 8);
         L.l_red = take(48 * 8);    // block sums, heat-bath picks, 7-way sums
-        L.l_U = take(std::max(std::max(std::max((size_t)11 * (L.nb32 + 4) * 4, (size_t)(ns * (ns + 1) + 3 * ns) * 8),
-                                       (size_t)7 * N * 8),
-                              (size_t)11 * kMixChunk * 8));
+        {
+            const size_t uby = std::max(std::max(std::max((size_t)11 * (L.nb32 + 4) * 4,
+                                                          (size_t)(ns * (ns + 1) + 3 * ns) * 8),
+                                                 (size_t)7 * N * 8),
+                                        (size_t)11 * kMixChunk * 8);
+            // basis-value chunk of the FP64 Slater rows: [N rounded to 16][kc + 1] doubles,
+            // kc the largest multiple of 4 (at most 32) that fits the block, at least 4
+            const size_t rows16 = (size_t)(N + 15) / 16 * 16;
+            int kc = (int)(uby / (rows16 * 8)) - 1;
+            kc = std::min(32, kc) / 4 * 4;
+            if (kc < 4) kc = 4;
+            L.fkc = kc;
+            L.l_U = take(std::max(uby, rows16 * (kc + 1) * 8));
+        }
         L.l_R = take(P * 4);
         L.l_Rdet = take(P * 4);
         L.l_dJ = take(P * 4);
@@ -809,7 +821,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             m.gemm = prm->precision == LRDMC_MIXED_BF16 ? kGemmBF16 : kGemmFP32;
             m.R = R; m.Z = Z; m.rc = rcs; m.jas = jas; m.btab = btab;
             m.core = core; m.spec = spec; m.btype = btype;
-            m.Cf = Cf; m.Cbf = Cbf; m.nb32 = L.nb32;
+            m.Cf = Cf; m.Cbf = Cbf; m.nb32 = L.nb32; m.fkc = L.fkc;
             m.C64 = C;
             m.s64 = (double*)carve(nw * L.stride64 * 8);
             m.stride64 = L.stride64;

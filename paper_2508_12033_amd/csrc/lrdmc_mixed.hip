@@ -641,6 +641,110 @@ __device__ __noinline__ MLocal mixed_evaluate(const DevMix* __restrict__ dm, dou
     return L;
 }
 
+// FP64 16x16x4 MFMA tiles of the phase-end evaluation: A operand lane
+// (row i16, inner k4), B operand lane (inner k4, column i16), accumulator
+// element v of lane (i16, k4) = D[k4 + 4v][i16].
+typedef double double4_m __attribute__((ext_vector_type(4)));
+
+// FP64 Slater rows A64[i][k] = sum_mu chi_mu(r_i) C[mu][k] (k < ns): in rounds
+// of one row tile of 16 electrons per wavefront, the basis values of the
+// round's electrons in chunks of fkc functions ([16 waves][fkc + 1] in LDS),
+// the product on MFMA with every column tile of the row tile.
+__device__ __noinline__ void final_slater_rows(const DevMix& s, const double* pos, double* A64)
+{
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
+    const int N = s.N, Nb = s.Nb, ns = s.ns, kc = max(4, s.fkc), ldc = kc + 1;
+    const int TR = (N + 15) / 16, TC = (ns + 15) / 16;   // TC <= 4
+    const int i16 = lane & 15, k4 = lane >> 4;
+    double* Bc = LDSD(s.l_U);                    // [16 nwv][kc + 1]
+    for (int r0 = 0; r0 < TR; r0 += nwv) {
+        const int rows0 = 16 * r0, nrows = 16 * min(nwv, TR - r0), tr = r0 + wv;
+        double4_m acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = (double4_m){0.0, 0.0, 0.0, 0.0};
+        for (int m0 = 0; m0 < Nb; m0 += kc) {
+            const int cnt = min(kc, Nb - m0);
+            for (int it = tid; it < nrows * kc; it += nt) {
+                const int el = it / kc, m = it - el * kc, e = rows0 + el;
+                double v = 0.0;
+                if (e < N && m < cnt) {
+                    const double* r = pos + 3 * e;
+                    const double4_t rec = gld((const double4_t*)(s.btab + 4 * (m0 + m)));
+                    const double dx = r[0] - rec[0], dy = r[1] - rec[1], dz = r[2] - rec[2];
+                    v = basis_value_d(gld(s.btype + m0 + m), rec[3], dx, dy, dz,
+                                      dx * dx + dy * dy + dz * dz);
+                }
+                Bc[el * ldc + m] = v;
+            }
+            __syncthreads();
+            if (tr < TR) {
+                for (int k0 = 0; k0 < cnt; k0 += 4) {
+                    const int mu = m0 + k0 + k4;
+                    const double av = Bc[(16 * wv + i16) * ldc + k0 + k4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        if (t >= TC) continue;
+                        const int col = 16 * t + i16;
+                        const double bv = (col < ns && k0 + k4 < cnt) ? gld(s.C64 + (long)mu * s.Norb + col) : 0.0;
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (tr < TR) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t >= TC) continue;
+                const int col = 16 * t + i16;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * tr + k4 + 4 * v;
+                    if (row < N && col < ns) A64[(long)row * ns + col] = acc[t][v];
+                }
+            }
+        }
+    }
+}
+
+// Z[mu][c] = sum_k C[mu][k] Ainv[k][c] of spin sp (Ai64 holds AiT[c][k]) on
+// MFMA: each wavefront takes row tiles of 16 basis functions with every
+// column tile.
+__device__ __noinline__ void final_z(const DevMix& s, int sp, const double* AiT, double* Z)
+{
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
+    const int n = mnspin(s, sp), Nb = s.Nb, ns = s.ns;
+    const int TR = (Nb + 15) / 16, TC = (n + 15) / 16;   // TC <= 4
+    const int i16 = lane & 15, k4 = lane >> 4;
+    for (int tr = wv; tr < TR; tr += nwv) {
+        double4_m acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = (double4_m){0.0, 0.0, 0.0, 0.0};
+        const int mu_a = 16 * tr + i16;
+        for (int k0 = 0; k0 < n; k0 += 4) {
+            const int k = k0 + k4;
+            const double av = (mu_a < Nb && k < n) ? gld(s.C64 + (long)mu_a * s.Norb + k) : 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t >= TC) continue;
+                const int c = 16 * t + i16;
+                const double bv = (c < n && k < n) ? AiT[(long)c * ns + k] : 0.0;
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (t >= TC) continue;
+            const int c = 16 * t + i16;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int mu = 16 * tr + k4 + 4 * v;
+                if (mu < Nb && c < n) Z[(long)mu * ns + c] = acc[t][v];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // FP64 estimator evaluation: everything recomputed from the positions in FP64
 // (Slater rows, Gauss-Jordan inverses, ratios, Jastrow, local energy), so that
@@ -671,53 +775,14 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
     double* nua = LDSD(s.l_nua);
     double* red = LDSD(s.l_red);
     double* U = LDSD(s.l_U);
-    // Slater rows, G electrons at a time (G ns <= threads: one item per thread)
-    const int G = min(11, max(1, nt / ns));
-    for (int i0 = 0; i0 < N; i0 += G) {
-        const int g = min(G, N - i0);
-        const int e_it = tid / ns, k_it = tid - e_it * ns;
-        const bool mine = e_it < g && k_it < mnspin(s, mspin(s, i0 + e_it));
-        double acc = 0.0;
-        for (int m0 = 0; m0 < Nb; m0 += kMixChunk) {
-            const int cnt = min(kMixChunk, Nb - m0);
-            for (int it = tid; it < g * kMixChunk; it += nt) {
-                const int e = it / kMixChunk, m = it - e * kMixChunk;
-                if (m >= cnt) continue;
-                const double* r = pos + 3 * (i0 + e);
-                const double* rec = s.btab + 4 * (m0 + m);
-                const double dx = r[0] - rec[0], dy = r[1] - rec[1], dz = r[2] - rec[2];
-                U[e * kMixChunk + m] =
-                    basis_value_d(s.btype[m0 + m], rec[3], dx, dy, dz, dx * dx + dy * dy + dz * dz);
-            }
-            __syncthreads();
-            if (mine)
-                for (int m = 0; m < cnt; ++m)
-                    acc += U[e_it * kMixChunk + m] * s.C64[(long)(m0 + m) * s.Norb + k_it];
-            __syncthreads();
-        }
-        if (mine) A64[(long)(i0 + e_it) * ns + k_it] = acc;
-    }
+    // Slater rows on MFMA
+    final_slater_rows(s, pos, A64);
     global_handoff();
     ok = gj_inverse<double, double>(s, A64, Ai64, 0);
     ok = gj_inverse<double, double>(s, A64, Ai64 + (long)ns * ns, 1) && ok;
-    // Z = C Ainv per spin, with the inverse staged in LDS
-    for (int sp = 0; sp < 2; ++sp) {
-        const int n = mnspin(s, sp);
-        if (!n) continue;
-        for (int idx = tid; idx < n * n; idx += nt) {
-            const int c = idx / n, k = idx - c * n;
-            U[idx] = Ai64[(long)sp * ns * ns + (long)c * ns + k];
-        }
-        __syncthreads();
-        for (int idx = tid; idx < Nb * n; idx += nt) {
-            const int mu = idx / n, c = idx - mu * n;
-            const double* Cm = s.C64 + (long)mu * s.Norb;
-            double acc = 0.0;
-            for (int k = 0; k < n; ++k) acc += Cm[k] * U[c * n + k];
-            Z64[((long)sp * Nb + mu) * ns + c] = acc;
-        }
-        __syncthreads();
-    }
+    // Z = C Ainv per spin on MFMA
+    for (int sp = 0; sp < 2; ++sp)
+        if (mnspin(s, sp)) final_z(s, sp, Ai64 + (long)sp * ns * ns, Z64 + (long)sp * Nb * ns);
     global_handoff();
     // per electron: the 6 neighbour values, gradient and Laplacian of the
     // basis, each contracted with Z[:, c]; partial sums over the basis reduced
