@@ -33,6 +33,7 @@ extern __shared__ double lds[];
 #define LDSF(off) (reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + (off)))
 
 typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef double double4_m __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------------------
@@ -572,11 +573,107 @@ __device__ __noinline__ double mixed_jastrow_all(const DevMix* __restrict__ dm, 
     return vee;
 }
 
-__device__ __noinline__ bool mixed_refresh(const DevMix* __restrict__ dm, float* st, double a)
+// Newton-Schulz correction of the FP32 inverse of spin sp that the
+// Sherman-Morrison updates have carried since the last rebuild:
+// E = I - A X (X = A^-1, X[k][c] = AiT[c][k]), X' = X + X E, both products
+// on FP64 MFMA from the FP32 rows and inverse staged in LDS.  X' has error
+// O(|E|^2); when max|E| >= kNsMax the rows are inverted afresh instead
+// (returns false).
+constexpr double kNsMax = 3e-3;
+__device__ __noinline__ bool mixed_ns_correct(const DevMix* __restrict__ dm, float* st, int sp)
 {
     const DevMix& s = *dm;
-    bool ok = mixed_refresh_inverse(&s, st, 0);
-    ok = mixed_refresh_inverse(&s, st, 1) && ok;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
+    const int n = mnspin(s, sp), off = sp ? s.Nup : 0, ns = s.ns, ld = n + 1;
+    if (!n) return true;
+    float* Rl = LDSF(s.l_U);                     // [n][n + 1] Slater rows, then E
+    float* Tl = Rl + n * ld;                     // [n][n + 1] AiT
+    const float* Arow = st + s.g_Arow + (long)off * ns;
+    float* AiT = st + s.g_AinvT + (long)sp * ns * ns;
+    for (int idx = tid; idx < n * n; idx += nt) {
+        const int r = idx / n, k = idx - r * n;
+        Rl[r * ld + k] = Arow[(long)r * ns + k];
+        Tl[r * ld + k] = AiT[(long)r * ns + k];
+    }
+    __syncthreads();
+    const int TR = (n + 15) / 16, i16 = lane & 15, k4 = lane >> 4;   // TR <= 4
+    double emax = 0.0;
+    // E = I - R T^T: a row tile of R per wavefront; E then replaces those rows
+    for (int rt = wv; rt < TR; rt += nwv) {
+        double4_m acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = (double4_m){0.0, 0.0, 0.0, 0.0};
+        const int j = 16 * rt + i16;
+        for (int k0 = 0; k0 < n; k0 += 4) {
+            const int k = k0 + k4;
+            const double av = (j < n && k < n) ? (double)Rl[j * ld + k] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t >= TR) continue;
+                const int c = 16 * t + i16;
+                const double bv = (c < n && k < n) ? (double)Tl[c * ld + k] : 0.0;
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (t >= TR) continue;
+            const int c = 16 * t + i16;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int jr = 16 * rt + k4 + 4 * v;
+                if (jr < n && c < n) {
+                    const double e = (jr == c ? 1.0 : 0.0) - acc[t][v];
+                    emax = fmax(emax, fabs(e));
+                    Rl[jr * ld + c] = (float)e;
+                }
+            }
+        }
+    }
+    emax = block_max(emax, LDSD(s.l_red));   // also the barrier before E is read
+    if (!(emax < kNsMax)) return false;
+    // X' = X + X E, i.e. AiT'[c][k] = AiT[c][k] + sum_j E[j][c] AiT[j][k]
+    for (int rt = wv; rt < TR; rt += nwv) {
+        double4_m acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = (double4_m){0.0, 0.0, 0.0, 0.0};
+        const int c = 16 * rt + i16;
+        for (int j0 = 0; j0 < n; j0 += 4) {
+            const int j = j0 + k4;
+            const double av = (j < n && c < n) ? (double)Rl[j * ld + c] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t >= TR) continue;
+                const int k = 16 * t + i16;
+                const double bv = (j < n && k < n) ? (double)Tl[j * ld + k] : 0.0;
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (t >= TR) continue;
+            const int k = 16 * t + i16;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int cr = 16 * rt + k4 + 4 * v;
+                if (cr < n && k < n) AiT[(long)cr * ns + k] = (float)((double)Tl[cr * ld + k] + acc[t][v]);
+            }
+        }
+    }
+    global_handoff();
+    return true;
+}
+
+// periodic: the scheduled refresh inside a phase, which first tries the
+// Newton-Schulz correction of each inverse; otherwise (phase start, a tiny
+// determinant ratio) the inverses are rebuilt by Gauss-Jordan
+__device__ __noinline__ bool mixed_refresh(const DevMix* __restrict__ dm, float* st, double a,
+                                           bool periodic)
+{
+    const DevMix& s = *dm;
+    bool ok = true;
+    for (int sp = 0; sp < 2; ++sp)
+        if (!(periodic && mixed_ns_correct(&s, st, sp))) ok = mixed_refresh_inverse(&s, st, sp) && ok;
     const double vee = mixed_jastrow_all(&s, a);
     if (threadIdx.x == 0) LDSD(s.l_scal)[kScVee] = vee;
     mixed_spin_update(&s, st, 0, false);
@@ -644,7 +741,6 @@ __device__ __noinline__ MLocal mixed_evaluate(const DevMix* __restrict__ dm, dou
 // FP64 16x16x4 MFMA tiles of the phase-end evaluation: A operand lane
 // (row i16, inner k4), B operand lane (inner k4, column i16), accumulator
 // element v of lane (i16, k4) = D[k4 + 4v][i16].
-typedef double double4_m __attribute__((ext_vector_type(4)));
 
 // FP64 Slater rows A64[i][k] = sum_mu chi_mu(r_i) C[mu][k] (k < ns): in rounds
 // of one row tile of 16 electrons per wavefront, the basis values of the
@@ -1180,7 +1276,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
     }
     unsigned long long n_neg = 0, n_nomove = 0, n_refresh = 1, n_small = 0, n_sing = 0,
                        n_capped = 0;
-    if (!mixed_refresh(&s, st, a)) n_sing++;
+    if (!mixed_refresh(&s, st, a, false)) n_sing++;
 
     double lw = s.lw[wid];
     double tau_left = pa.tau;
@@ -1227,7 +1323,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
             ++since;
             if (small) n_small++;
             if (small || since >= pa.refresh_every) {
-                if (!mixed_refresh(&s, st, a)) n_sing++;
+                if (!mixed_refresh(&s, st, a, !small)) n_sing++;
                 n_refresh++;
                 since = 0;
             }
