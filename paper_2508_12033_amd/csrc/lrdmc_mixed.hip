@@ -577,15 +577,16 @@ __device__ __noinline__ double mixed_jastrow_all(const DevMix* __restrict__ dm, 
 // Sherman-Morrison updates have carried since the last rebuild:
 // E = I - A X (X = A^-1, X[k][c] = AiT[c][k]), X' = X + X E, both products
 // on FP64 MFMA from the FP32 rows and inverse staged in LDS.  X' has error
-// O(|E|^2); when max|E| >= kNsMax the rows are inverted afresh instead
-// (returns false).
-constexpr double kNsMax = 3e-3;
-__device__ __noinline__ bool mixed_ns_correct(const DevMix* __restrict__ dm, float* st, int sp)
+// O(|E|^2).  Returns 0 when max|E| < kNsTight (corrected, done), 1 when
+// max|E| < kNsLoose (corrected; one more step brings it below the tight
+// bound), 2 otherwise (not applied: the rows are to be inverted afresh).
+constexpr double kNsTight = 3e-4, kNsLoose = 3e-3;
+__device__ __noinline__ int mixed_ns_correct(const DevMix* __restrict__ dm, float* st, int sp)
 {
     const DevMix& s = *dm;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
     const int n = mnspin(s, sp), off = sp ? s.Nup : 0, ns = s.ns, ld = n + 1;
-    if (!n) return true;
+    if (!n) return 0;
     float* Rl = LDSF(s.l_U);                     // [n][n + 1] Slater rows, then E
     float* Tl = Rl + n * ld;                     // [n][n + 1] AiT
     const float* Arow = st + s.g_Arow + (long)off * ns;
@@ -631,7 +632,7 @@ __device__ __noinline__ bool mixed_ns_correct(const DevMix* __restrict__ dm, flo
         }
     }
     emax = block_max(emax, LDSD(s.l_red));   // also the barrier before E is read
-    if (!(emax < kNsMax)) return false;
+    if (!(emax < kNsLoose)) return 2;
     // X' = X + X E, i.e. AiT'[c][k] = AiT[c][k] + sum_j E[j][c] AiT[j][k]
     for (int rt = wv; rt < TR; rt += nwv) {
         double4_m acc[4];
@@ -661,19 +662,25 @@ __device__ __noinline__ bool mixed_ns_correct(const DevMix* __restrict__ dm, flo
         }
     }
     global_handoff();
-    return true;
+    return emax < kNsTight ? 0 : 1;
 }
 
-// periodic: the scheduled refresh inside a phase, which first tries the
-// Newton-Schulz correction of each inverse; otherwise (phase start, a tiny
+// periodic: the scheduled refresh inside a phase, which first tries one or
+// two Newton-Schulz corrections of each inverse; otherwise (phase start, a tiny
 // determinant ratio) the inverses are rebuilt by Gauss-Jordan
 __device__ __noinline__ bool mixed_refresh(const DevMix* __restrict__ dm, float* st, double a,
                                            bool periodic)
 {
     const DevMix& s = *dm;
     bool ok = true;
-    for (int sp = 0; sp < 2; ++sp)
-        if (!(periodic && mixed_ns_correct(&s, st, sp))) ok = mixed_refresh_inverse(&s, st, sp) && ok;
+    for (int sp = 0; sp < 2; ++sp) {
+        int st_ns = 2;
+        if (periodic) {
+            st_ns = mixed_ns_correct(&s, st, sp);
+            if (st_ns == 1) st_ns = mixed_ns_correct(&s, st, sp) == 2 ? 2 : 0;
+        }
+        if (st_ns != 0) ok = mixed_refresh_inverse(&s, st, sp) && ok;
+    }
     const double vee = mixed_jastrow_all(&s, a);
     if (threadIdx.x == 0) LDSD(s.l_scal)[kScVee] = vee;
     mixed_spin_update(&s, st, 0, false);
