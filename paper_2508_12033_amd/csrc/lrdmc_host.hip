@@ -153,7 +153,7 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.l_nue = take(N * 8);
         L.l_nua = take(N * 8);
         L.l_scal = take(kScLen * 8);
-        L.l_red = take(48 * 8);    // block sums, heat-bath picks, 7-way sums
+        L.l_red = take(64 * 8);    // block sums, heat-bath picks, 13-way sums
         {
             const size_t uby = std::max(std::max(std::max((size_t)11 * (L.nb32 + 4) * 4,
                                                           (size_t)(ns * (ns + 1) + 3 * ns) * 8),

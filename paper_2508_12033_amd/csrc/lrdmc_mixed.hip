@@ -443,33 +443,62 @@ __device__ __noinline__ void mixed_spin_update(const DevMix* __restrict__ dm, co
     }
     float* gD = LDSF(s.l_gD);
     float* Rdet = LDSF(s.l_Rdet);
-    const float* dPhi = st + s.g_dPhi + (long)sp * ns * 4 * ns;
-    const float* Phi = st + s.g_Phi + (long)sp * ns * 6 * ns;
-    // 4n gradient items then 6n ratio items
-    for (int it = tid; it < 10 * n; it += nt) {
-        const bool isg = it < 4 * n;
-        const int q = isg ? it : it - 4 * n;
-        const int c = isg ? (q >> 2) : q / 6;
-        const float* col = isg ? dPhi + q : Phi + q;
-        const long stride = isg ? 4L * ns : 6L * ns;
-        const float* a = AiL + c * lda;
-        // 16 loads in flight per batch (the walker blocks live in HBM)
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-        for (int k0 = 0; k0 < n; k0 += 16) {
-            float x[16];
+    // column c of the inverse against electron c's gradient / Laplacian rows
+    // (one float4 per orbital k) and its six neighbour rows (three float2):
+    // kp adjacent lanes per electron split k (k = part, part + kp, ...), KB
+    // k per batch, so that 4 KB loads per lane are in flight (the walker
+    // blocks live in HBM); the kp partial sums are combined across the lanes
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    const f4v* dPhi4 = reinterpret_cast<const f4v*>(st + s.g_dPhi + (long)sp * ns * 4 * ns);
+    const f2v* Phi2 = reinterpret_cast<const f2v*>(st + s.g_Phi + (long)sp * ns * 6 * ns);
+    constexpr int KB = 4;
+    int kp = 1;
+    while (kp < 16 && 2 * kp * n <= nt) kp *= 2;
+    const int per = nt / kp;
+    for (int c0 = 0; c0 < n; c0 += per) {
+        const int c = c0 + tid / kp, part = tid & (kp - 1);
+        float acc[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (c < n) {
+            const float* a = AiL + c * lda;
+            for (int k0 = part; k0 < n; k0 += KB * kp) {
+                f4v G[KB];
+                f2v Q[KB][3];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) x[u] = k0 + u < n ? gld(col + (long)(k0 + u) * stride) : 0.f;
+                for (int u = 0; u < KB; ++u) {
+                    const int k = k0 + u * kp;
+                    if (k < n) {
+                        G[u] = gld(dPhi4 + (long)k * ns + c);
+                        const f2v* q = Phi2 + (long)k * 3 * ns + 3 * c;
+                        Q[u][0] = gld(q); Q[u][1] = gld(q + 1); Q[u][2] = gld(q + 2);
+                    } else {
+                        G[u] = 0.f;
+                        Q[u][0] = Q[u][1] = Q[u][2] = 0.f;
+                    }
+                }
 #pragma unroll
-            for (int u = 0; u < 16; u += 4) {
-                if (k0 + u < n) s0 += x[u] * a[k0 + u];
-                if (k0 + u + 1 < n) s1 += x[u + 1] * a[k0 + u + 1];
-                if (k0 + u + 2 < n) s2 += x[u + 2] * a[k0 + u + 2];
-                if (k0 + u + 3 < n) s3 += x[u + 3] * a[k0 + u + 3];
+                for (int u = 0; u < KB; ++u) {
+                    const int k = k0 + u * kp;
+                    const float av = k < n ? a[k] : 0.f;
+                    acc[0] += G[u].x * av; acc[1] += G[u].y * av;
+                    acc[2] += G[u].z * av; acc[3] += G[u].w * av;
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) {
+                        acc[4 + 2 * m] += Q[u][m].x * av;
+                        acc[5 + 2 * m] += Q[u][m].y * av;
+                    }
+                }
             }
         }
-        const float v = (s0 + s1) + (s2 + s3);
-        if (isg) gD[4 * (off + c) + (q & 3)] = v;
-        else Rdet[6 * off + q] = v;
+        for (int m = 1; m < kp; m <<= 1)
+#pragma unroll
+            for (int t = 0; t < 10; ++t) acc[t] += __shfl_xor(acc[t], m);
+        if (c < n && part == 0) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) gD[4 * (off + c) + t] = acc[t];
+#pragma unroll
+            for (int t = 0; t < 6; ++t) Rdet[6 * (off + c) + t] = acc[4 + t];
+        }
     }
     __syncthreads();
 }
@@ -484,7 +513,31 @@ __device__ __forceinline__ void mixed_full_ratios(const DevMix& s)
     __syncthreads();
 }
 
-// Jastrow caches and potentials of every electron from scratch; returns V_ee
+// sum over the lane pair (quad_perm [1,0,3,2])
+__device__ __forceinline__ float pair_sum(float v)
+{
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xb1, 0xf, 0xf, false));
+}
+
+// Pade terms of the six lattice neighbours of a point at FP32 difference f
+// from a partner (squared distance r2f): squared distances |f|^2 + a^2 +- 2a f_c,
+// kept positive; q adds u(neighbour) - u(point) in move order (+x, -x, +y, ...)
+__device__ __forceinline__ void neighbour_du(const PadeF& p, const float f[3], float r2f, float aa,
+                                             float ta, float q[6])
+{
+    const float u0 = pade_u2f(p, fmaxf(r2f, 1e-30f)), b = r2f + aa;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        q[2 * c] += pade_u2f(p, fmaxf(b + ta * f[c], 1e-30f)) - u0;
+        q[2 * c + 1] += pade_u2f(p, fmaxf(b - ta * f[c], 1e-30f)) - u0;
+    }
+}
+
+// Jastrow caches and potentials of every electron from scratch; returns V_ee.
+// Two threads per electron (adjacent lanes, partners k = h, h + 2, ...),
+// combined over the lane pair; every pass keeps both lanes of a pair.  Each
+// pair's FP64 difference is formed once and serves the gradient, Laplacian,
+// potentials and the exponent changes of the electron's six moves.
 __device__ __noinline__ double mixed_jastrow_all(const DevMix* __restrict__ dm, double a)
 {
     const DevMix& s = *dm;
@@ -495,40 +548,16 @@ __device__ __noinline__ double mixed_jastrow_all(const DevMix* __restrict__ dm, 
     float* Jl = LDSF(s.l_Jl);
     double* nue = LDSD(s.l_nue);
     double* nua = LDSD(s.l_nua);
-    float* S = LDSF(s.l_U);                       // [N][7]
-    const int K = s.N + s.M, Kj = s.has_en ? K : s.N;
+    const int K = s.N + s.M;
     const double ia = 1.0 / a;
-    for (int it = tid; it < 7 * s.N; it += (int)blockDim.x) {
-        const int j = it / 7, q = it - 7 * j;
-        double pq[3];
-        point_q(pos + 3 * j, q, a, pq);
-        // four partners per round, independent partial sums
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        #pragma unroll 1
-        for (int k0 = 0; k0 < Kj; k0 += 4) {
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const int k = k0 + h;
-                if (k < Kj && k != j) {
-                    double pk[3];
-                    int jr;
-                    mpartner(s, pos, j, k, pk, jr);
-                    const float e0 = (float)(pq[0] - pk[0]), e1 = (float)(pq[1] - pk[1]),
-                                e2 = (float)(pq[2] - pk[2]);
-                    acc[h] += (double)pade_u2f(pade_row(s, jr), e0 * e0 + e1 * e1 + e2 * e2);
-                }
-            }
-        }
-        S[it] = (float)((acc[0] + acc[1]) + (acc[2] + acc[3]));
-    }
+    const float aa = (float)(a * a), ta = (float)(2.0 * a);
     double vee = 0.0;
-    // two threads per electron (adjacent lanes, partners k = h, h + 2, ...),
-    // combined over the lane pair; every pass keeps both lanes of a pair
     for (int base = 0; base < 2 * s.N; base += (int)blockDim.x) {
         const int it = base + tid, j = it >> 1, h = it & 1;
         const bool jv = it < 2 * s.N;
         const double* rj = pos + 3 * (jv ? j : 0);
         float g0 = 0.f, g1 = 0.f, g2 = 0.f, l = 0.f;
+        float dq[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         double nu = 0.0, nv = 0.0;
         #pragma unroll 1
         for (int k = h; jv && k < K; k += 2) {
@@ -540,11 +569,14 @@ __device__ __noinline__ double mixed_jastrow_all(const DevMix* __restrict__ dm, 
             const double d0 = rj[0] - pk[0], d1 = rj[1] - pk[1], d2 = rj[2] - pk[2];
             const double r2 = d0 * d0 + d1 * d1 + d2 * d2, ir = rsqrt_nr(r2);
             if (isel || s.has_en) {
+                const PadeF pr = pade_row(s, jr);
                 float u, dur, lp;
-                pade_derivs_rf(pade_row(s, jr), (float)(r2 * ir), (float)ir, u, dur, lp);
+                pade_derivs_rf(pr, (float)(r2 * ir), (float)ir, u, dur, lp);
                 g0 += dur * (float)d0; g1 += dur * (float)d1; g2 += dur * (float)d2;
                 l += lp;
                 if (isel && k > j) vee += ir;
+                const float f[3] = {(float)d0, (float)d1, (float)d2};
+                neighbour_du(pr, f, (float)r2, aa, ta, dq);
             }
             if (!isel) {
                 double a1, a2;
@@ -552,23 +584,19 @@ __device__ __noinline__ double mixed_jastrow_all(const DevMix* __restrict__ dm, 
                 nu += a1; nv += a2;
             }
         }
-        // quad_perm [1,0,3,2]: the other lane of the pair
-        g0 += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(g0), 0xb1, 0xf, 0xf, false));
-        g1 += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(g1), 0xb1, 0xf, 0xf, false));
-        g2 += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(g2), 0xb1, 0xf, 0xf, false));
-        l += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(l), 0xb1, 0xf, 0xf, false));
+        g0 = pair_sum(g0); g1 = pair_sum(g1); g2 = pair_sum(g2); l = pair_sum(l);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) dq[q] = pair_sum(dq[q]);
         nu += dpp_mov<0xb1, 0xf>(nu);
         nv += dpp_mov<0xb1, 0xf>(nv);
         if (jv && h == 0) {
             Jg[3 * j] = g0; Jg[3 * j + 1] = g1; Jg[3 * j + 2] = g2; Jl[j] = l;
             nue[j] = nu; nua[j] = nv;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) dJ[6 * j + q] = dq[q];
         }
     }
     vee = block_sum(vee, LDSD(s.l_red));
-    for (int p = tid; p < s.P; p += (int)blockDim.x) {
-        const int j = p / 6, q = p - 6 * j;
-        dJ[p] = S[7 * j + q + 1] - S[7 * j];
-    }
     __syncthreads();
     return vee;
 }
@@ -925,43 +953,40 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
         __syncthreads();
     }
     // Jastrow: exponent changes of the 6N moves, gradients and Laplacians;
-    // potentials and V_ee
-    double* S = LDSD(s.l_U);                     // [N][7]
-    const int K = N + s.M, Kj = s.has_en ? K : N;
-    for (int it = tid; it < 7 * N; it += (int)blockDim.x) {
-        const int j = it / 7, q = it - 7 * j;
-        double pq[3];
-        point_q(pos + 3 * j, q, a, pq);
-        double acc = 0.0;
-        #pragma unroll 1
-        for (int k = 0; k < Kj; ++k) {
-            if (k == j) continue;
-            double pk[3];
-            int jr;
-            mpartner(s, pos, j, k, pk, jr);
-            acc += pade_u(s.jas + 3 * jr, norm3(pq[0] - pk[0], pq[1] - pk[1], pq[2] - pk[2]));
-        }
-        S[it] = acc;
-    }
+    // potentials and V_ee.  Two threads per electron (adjacent lanes, partners
+    // k = h, h + 2, ...), combined over the lane pair; the six neighbours'
+    // squared distances from each pair's difference d as |d|^2 + a^2 +- 2a d_c
+    const int K = N + s.M;
+    const double aa = a * a, ta = 2.0 * a;
     double vee = 0.0;
-    for (int j = tid; j < N; j += (int)blockDim.x) {
-        const double* rj = pos + 3 * j;
+    for (int base = 0; base < 2 * N; base += nt) {
+        const int it = base + tid, j = it >> 1, h = it & 1;
+        const bool jv = it < 2 * N;
+        const double* rj = pos + 3 * (jv ? j : 0);
         double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0, nu = 0.0, nv = 0.0;
+        double dq[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         #pragma unroll 1
-        for (int k = 0; k < K; ++k) {
+        for (int k = h; jv && k < K; k += 2) {
             if (k == j) continue;
             const bool isel = k < N;
             double pk[3];
             int jr;
             mpartner(s, pos, j, k, pk, jr);
-            const double d0 = rj[0] - pk[0], d1 = rj[1] - pk[1], d2 = rj[2] - pk[2];
-            const double r2 = d0 * d0 + d1 * d1 + d2 * d2, ir = rsqrt_nr(r2);
+            const double d[3] = {rj[0] - pk[0], rj[1] - pk[1], rj[2] - pk[2]};
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2], ir = rsqrt_nr(r2);
             if (isel || s.has_en) {
+                const double* pj = s.jas + 3 * jr;
                 double u, dur, lp;
-                pade_derivs(s.jas + 3 * jr, r2 * ir, u, dur, lp);
-                g0 += dur * d0; g1 += dur * d1; g2 += dur * d2;
+                pade_derivs(pj, r2 * ir, u, dur, lp);
+                g0 += dur * d[0]; g1 += dur * d[1]; g2 += dur * d[2];
                 l += lp;
                 if (isel && k > j) vee += ir;
+                const double b2 = r2 + aa;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    dq[2 * c] += pade_u(pj, sqrt(fmax(b2 + ta * d[c], 0.0))) - u;
+                    dq[2 * c + 1] += pade_u(pj, sqrt(fmax(b2 - ta * d[c], 0.0))) - u;
+                }
             }
             if (!isel) {
                 double a1, a2;
@@ -969,15 +994,19 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
                 nu += a1; nv += a2;
             }
         }
-        Jg64[3 * j] = g0; Jg64[3 * j + 1] = g1; Jg64[3 * j + 2] = g2; Jl64[j] = l;
-        nue[j] = nu; nua[j] = nv;
+        g0 += dpp_mov<0xb1, 0xf>(g0); g1 += dpp_mov<0xb1, 0xf>(g1); g2 += dpp_mov<0xb1, 0xf>(g2);
+        l += dpp_mov<0xb1, 0xf>(l);
+        nu += dpp_mov<0xb1, 0xf>(nu); nv += dpp_mov<0xb1, 0xf>(nv);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) dq[q] += dpp_mov<0xb1, 0xf>(dq[q]);
+        if (jv && h == 0) {
+            Jg64[3 * j] = g0; Jg64[3 * j + 1] = g1; Jg64[3 * j + 2] = g2; Jl64[j] = l;
+            nue[j] = nu; nua[j] = nv;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) dJ64[6 * j + q] = dq[q];
+        }
     }
     vee = block_sum(vee, red);
-    for (int p = tid; p < P; p += (int)blockDim.x) {
-        const int j = p / 6, q = p - 6 * j;
-        dJ64[p] = S[7 * j + q + 1] - S[7 * j];
-    }
-    __syncthreads();
     // ratios, lattice diagonal, local energy (App. D), as in the FP64 kernel
     double bs = 0.0;
     int anyneg = 0;
@@ -1128,48 +1157,19 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
     mixed_spin_update(&s, st, sp, true);
 
     // Jastrow caches of the moved electron (7 points) and of its partners
-    const int K = s.N + s.M, Kj = s.has_en ? K : s.N;
+    const int K = s.N + s.M;
     float* dJ = LDSF(s.l_dJ);
     float* Jg = LDSF(s.l_Jg);
     float* Jl = LDSF(s.l_Jl);
     float* dje = LDSF(s.l_dje);
     double* red = LDSD(s.l_red);
-    // the 7 points of the moved electron: (point, partner) pairs spread over
-    // the workgroup, one 7-way block reduction
-    float* dJi = tmp + 3 * ns;                   // [6] new exponent changes of electron i
-    {
-        double acc7[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        #pragma unroll 1
-        for (int it = tid; it < 7 * Kj; it += (int)blockDim.x) {
-            const int qq = it / Kj, k = it - qq * Kj;
-            if (k == i) continue;
-            double pq[3], pk[3];
-            int jr;
-            point_q(rnew, qq, a, pq);
-            mpartner(s, pos, i, k, pk, jr);
-            const float e0 = (float)(pq[0] - pk[0]), e1 = (float)(pq[1] - pk[1]),
-                        e2 = (float)(pq[2] - pk[2]);
-            const double u = (double)pade_u2f(pade_row(s, jr), e0 * e0 + e1 * e1 + e2 * e2);
-#pragma unroll
-            for (int t = 0; t < 7; ++t) acc7[t] += (t == qq) ? u : 0.0;
-        }
-        double* red7 = red + 8;                  // [waves][7]
-        const int lane = tid & 63, wv = tid >> 6, nwv = (int)blockDim.x >> 6;
-#pragma unroll
-        for (int t = 0; t < 7; ++t) {
-            const double v = wave_sum(acc7[t]);
-            if (lane == 0) red7[wv * 7 + t] = v;
-        }
-        __syncthreads();
-        if (tid < 7) {
-            double v = red7[tid];
-            for (int q = 1; q < nwv; ++q) v += red7[q * 7 + tid];
-            red7[28 + tid] = v;
-        }
-        __syncthreads();
-        if (tid > 0 && tid < 7) dJi[tid - 1] = (float)(red7[28 + tid] - red7[28]);
-    }
+    // every partner of the moved electron once: its gradient, Laplacian and
+    // potentials at the new position, the exponent changes of its six next
+    // moves (from the same FP64 difference), and the pair-term changes of the
+    // partners; one block reduction of the 13 sums
+    const float aa = (float)(a * a), ta = (float)(2.0 * a);
     double g0 = 0, g1 = 0, g2 = 0, l = 0, dvee = 0, nu = 0, nua = 0;
+    float dq[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     #pragma unroll 1
     for (int k = tid; k < K; k += (int)blockDim.x) {
         if (k == i) continue;
@@ -1185,6 +1185,8 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
             pade_derivs_rf(prm, (float)(rn2 * irn), (float)irn, un, dnr, lpn);
             g0 += dnr * n0; g1 += dnr * n1; g2 += dnr * n2;
             l += lpn;
+            const float f[3] = {(float)n0, (float)n1, (float)n2};
+            neighbour_du(prm, f, (float)rn2, aa, ta, dq);
             if (isel) {
                 const double o0 = rold[0] - pk[0], o1 = rold[1] - pk[1], o2 = rold[2] - pk[2];
                 const double ro2 = o0 * o0 + o1 * o1 + o2 * o2, iro = rsqrt_nr(ro2);
@@ -1204,24 +1206,27 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
             nu += a1; nua += a2;
         }
     }
+    float* dJi = tmp + 3 * ns;                   // [6] new exponent changes of electron i
     {
-        // the seven sums in one block reduction (the 7-point scratch is free)
-        double* red7 = red + 8;
+        double* red13 = red + 8;                 // [waves][13]
         const int lane = tid & 63, wv = tid >> 6, nwv = (int)blockDim.x >> 6;
-        double sv[7] = {g0, g1, g2, l, dvee, nu, nua};
+        double sv[13] = {g0, g1, g2, l, dvee, nu, nua, dq[0], dq[1], dq[2], dq[3], dq[4], dq[5]};
 #pragma unroll
-        for (int t = 0; t < 7; ++t) {
+        for (int t = 0; t < 13; ++t) {
             const double v = wave_sum(sv[t]);
-            if (lane == 0) red7[wv * 7 + t] = v;
+            if (lane == 0) red13[wv * 13 + t] = v;
         }
         __syncthreads();
 #pragma unroll
-        for (int t = 0; t < 7; ++t) {
-            double v = red7[t];
-            for (int q = 1; q < nwv; ++q) v += red7[q * 7 + t];
+        for (int t = 0; t < 13; ++t) {
+            double v = red13[t];
+            for (int q = 1; q < nwv; ++q) v += red13[q * 13 + t];
             sv[t] = v;
         }
         g0 = sv[0]; g1 = sv[1]; g2 = sv[2]; l = sv[3]; dvee = sv[4]; nu = sv[5]; nua = sv[6];
+#pragma unroll
+        for (int t = 0; t < 6; ++t)
+            if (tid == t) dJi[t] = (float)sv[7 + t];
     }
     // Jastrow exponent changes of the other electrons' moves
     for (int qp = tid; qp < s.P; qp += (int)blockDim.x) {
