@@ -15,8 +15,8 @@
 //     rows, block-reduction scratch.
 // Precision: basis functions, Jastrow sums and ratios in FP32; the orbital
 // GEMM on MFMA in FP32 or BF16 with FP32 accumulation; positions, potentials,
-// weights, all sums that form W, bbar and e_L, and the periodic Gauss-Jordan
-// refresh in FP64.  The local energy is formed as the continuum local energy
+// weights, all sums that form W, bbar and e_L, and the periodic refresh of
+// the inverses (Newton-Schulz correction or Gauss-Jordan) in FP64.  The local energy is formed as the continuum local energy
 // plus sum_i (nu_opt,i - nu_zv,i) (App. D identity), which avoids the
 // cancellation in W - bbar when bbar is known only to FP32 accuracy.
 #include <hip/hip_runtime.h>
@@ -37,7 +37,8 @@ typedef double double4_m __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------------------
-// block collectives (1, 2 or 4 wavefronts); red is a 4-double LDS scratch
+// block collectives (1, 2 or 4 wavefronts); red is an LDS scratch of 4
+// doubles (8 for block_sum2, 20 for the scan with a flag)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double block_sum(double v, double* red)
 {
@@ -49,6 +50,20 @@ __device__ __forceinline__ double block_sum(double v, double* red)
     double t = red[0];
     for (int q = 1; q < nwv; ++q) t += red[q];
     return t;
+}
+
+// two block sums with one pair of barriers (red holds [waves][2])
+__device__ __forceinline__ void block_sum2(double& v0, double& v1, double* red)
+{
+    v0 = wave_sum(v0);
+    v1 = wave_sum(v1);
+    const int tid = threadIdx.x, nwv = blockDim.x >> 6;
+    __syncthreads();
+    if ((tid & 63) == 0) { red[2 * (tid >> 6)] = v0; red[2 * (tid >> 6) + 1] = v1; }
+    __syncthreads();
+    double t0 = red[0], t1 = red[1];
+    for (int q = 1; q < nwv; ++q) { t0 += red[2 * q]; t1 += red[2 * q + 1]; }
+    v0 = t0; v1 = t1;
 }
 
 // Global-memory data written by some waves of the workgroup and read by others
@@ -77,19 +92,29 @@ __device__ __forceinline__ double block_max(double v, double* red)
 }
 
 // exclusive prefix of v over the block (thread order) and the block total
-__device__ __forceinline__ double block_excl_scan(double v, double* red, double& total)
+// exclusive block scan of v with the block total; when any is given, also the
+// block OR of flag (wave flags in red[16 + wave])
+__device__ __forceinline__ double block_excl_scan(double v, double* red, double& total,
+                                                  int flag = 0, bool* any = nullptr)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
     const double inc = wave_incl_scan(v, lane);
     double prev = __shfl_up(inc, 1);
     if (lane == 0) prev = 0.0;
+    const bool wflag = any && __ballot(flag) != 0;
     __syncthreads();
     if (lane == 63) red[wv] = inc;
+    if (any && lane == 0) red[16 + wv] = wflag ? 1.0 : 0.0;
     __syncthreads();
     double off = 0.0;
     for (int q = 0; q < wv; ++q) off += red[q];
     total = red[0];
-    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) total += red[q];
+    for (int q = 1; q < nwv; ++q) total += red[q];
+    if (any) {
+        double f = 0.0;
+        for (int q = 0; q < nwv; ++q) f += red[16 + q];
+        *any = f > 0.0;
+    }
     return off + prev;
 }
 
@@ -259,41 +284,82 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
         if (s.gemm == kGemmBF16) {
             // 16x16x32 BF16 tiles, lane holds 8 consecutive inner indices.  Each
             // FP32 operand is split into a BF16 high part and a BF16 residual;
-            // hi*hi + hi*lo + lo*hi keeps about 16 significant bits
-            const long plane = (long)((s.ns + 15) / 16) * (s.nb32 / 32) * 64;
-            const bf16x8_t* cb = reinterpret_cast<const bf16x8_t*>(s.Cbf) +
-                                 (long)t * (s.nb32 / 32) * 64;
-            for (int kb = 0; kb < s.nb32 / 32; ++kb) {
-                bf16x8_t ah, alo;
-                const int k0 = 32 * kb + 8 * k4;
-                float xa[8];
-                if (i16 < 11) {
-                    const float4_t* src = reinterpret_cast<const float4_t*>(B + i16 * ldb + k0);
-                    const float4_t v0 = src[0], v1 = src[1];
-                    xa[0] = v0[0]; xa[1] = v0[1]; xa[2] = v0[2]; xa[3] = v0[3];
-                    xa[4] = v1[0]; xa[5] = v1[1]; xa[6] = v1[2]; xa[7] = v1[3];
-                } else {
+            // hi*hi + hi*lo + lo*hi keeps about 16 significant bits.  The
+            // coefficient operands (shared by all walkers, L2-resident) are
+            // loaded KC k-blocks ahead of their use
+            constexpr int KC = 2;
+            const int nkb = s.nb32 / 32;
+            const long plane = (long)((s.ns + 15) / 16) * nkb * 64;
+            const bf16x8_t* cb = reinterpret_cast<const bf16x8_t*>(s.Cbf) + (long)t * nkb * 64;
+            bf16x8_t hc[KC], lc[KC];
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) xa[e] = 0.0f;
+            for (int u = 0; u < KC; ++u)
+                if (u < nkb) {
+                    hc[u] = gld(cb + (long)u * 64 + lane);
+                    lc[u] = gld(cb + plane + (long)u * 64 + lane);
+                }
+            for (int b0 = 0; b0 < nkb; b0 += KC) {
+                bf16x8_t hn[KC], ln[KC];
+#pragma unroll
+                for (int u = 0; u < KC; ++u)
+                    if (b0 + KC + u < nkb) {
+                        hn[u] = gld(cb + (long)(b0 + KC + u) * 64 + lane);
+                        ln[u] = gld(cb + plane + (long)(b0 + KC + u) * 64 + lane);
+                    }
+#pragma unroll
+                for (int u = 0; u < KC; ++u) {
+                    if (b0 + u >= nkb) break;
+                    const int k0 = 32 * (b0 + u) + 8 * k4;
+                    float xa[8];
+                    if (i16 < 11) {
+                        const float4_t* src = reinterpret_cast<const float4_t*>(B + i16 * ldb + k0);
+                        const float4_t v0 = src[0], v1 = src[1];
+                        xa[0] = v0[0]; xa[1] = v0[1]; xa[2] = v0[2]; xa[3] = v0[3];
+                        xa[4] = v1[0]; xa[5] = v1[1]; xa[6] = v1[2]; xa[7] = v1[3];
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) xa[e] = 0.0f;
+                    }
+                    bf16x8_t ah, alo;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const __bf16 h = (__bf16)xa[e];
+                        ah[e] = h;
+                        alo[e] = (__bf16)(xa[e] - (float)h);
+                    }
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, hc[u], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, lc[u], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, hc[u], acc, 0, 0, 0);
                 }
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const __bf16 h = (__bf16)xa[e];
-                    ah[e] = h;
-                    alo[e] = (__bf16)(xa[e] - (float)h);
-                }
-                const bf16x8_t bh = cb[(long)kb * 64 + lane];
-                const bf16x8_t bl = cb[plane + (long)kb * 64 + lane];
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bh, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+                for (int u = 0; u < KC; ++u) { hc[u] = hn[u]; lc[u] = ln[u]; }
             }
         } else {
-            for (int k0 = 0; k0 < Nb; k0 += 4) {
-                const int mu = k0 + k4;
-                const float av = (i16 < 11 && mu < Nb) ? B[i16 * ldb + mu] : 0.0f;
-                const float bv = (col < n && mu < Nb) ? s.Cf[mu * s.ns + col] : 0.0f;
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+            // 16x16x4 FP32 tiles; the coefficient column loads run KF k-steps
+            // ahead of the products
+            constexpr int KF = 8;
+            const int nk = (Nb + 3) / 4;
+            float bc[KF];
+#pragma unroll
+            for (int u = 0; u < KF; ++u) {
+                const int mu = 4 * u + k4;
+                bc[u] = (col < n && mu < Nb) ? gld(s.Cf + (long)mu * s.ns + col) : 0.0f;
+            }
+            for (int s0 = 0; s0 < nk; s0 += KF) {
+                float bn[KF];
+#pragma unroll
+                for (int u = 0; u < KF; ++u) {
+                    const int mu = 4 * (s0 + KF + u) + k4;
+                    bn[u] = (col < n && mu < Nb) ? gld(s.Cf + (long)mu * s.ns + col) : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < KF; ++u) {
+                    const int mu = 4 * (s0 + u) + k4;
+                    const float av = (i16 < 11 && mu < Nb) ? B[i16 * ldb + mu] : 0.0f;
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bc[u], acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int u = 0; u < KF; ++u) bc[u] = bn[u];
             }
         }
         // D[row][col]: row = 4 (lane >> 4) + v
@@ -693,9 +759,10 @@ __device__ __noinline__ int mixed_ns_correct(const DevMix* __restrict__ dm, floa
     return emax < kNsTight ? 0 : 1;
 }
 
-// periodic: the scheduled refresh inside a phase, which first tries one or
-// two Newton-Schulz corrections of each inverse; otherwise (phase start, a tiny
-// determinant ratio) the inverses are rebuilt by Gauss-Jordan
+// periodic: a refresh of carried inverses (scheduled, or at the start of a
+// phase), which first tries one or two Newton-Schulz corrections of each
+// inverse; otherwise (rows rebuilt from positions, a tiny determinant ratio)
+// the inverses are rebuilt by Gauss-Jordan
 __device__ __noinline__ bool mixed_refresh(const DevMix* __restrict__ dm, float* st, double a,
                                            bool periodic)
 {
@@ -717,7 +784,10 @@ __device__ __noinline__ bool mixed_refresh(const DevMix* __restrict__ dm, float*
     return ok;
 }
 
-struct MLocal { double bbar, W, eL; };
+// pre, tot: the thread's exclusive prefix of the positive-ratio sums of the
+// thread chunks (thread t owns moves [t per, (t + 1) per)) and their total,
+// reused by the heat bath at the same configuration
+struct MLocal { double bbar, W, eL, pre, tot; };
 
 // lattice-regularized diagonal and local energy (App. D), e_L formed as the
 // continuum local energy plus sum_i (nu_opt,i - nu_zv,i)
@@ -732,15 +802,18 @@ __device__ __noinline__ MLocal mixed_evaluate(const DevMix* __restrict__ dm, dou
     const double* nue = LDSD(s.l_nue);
     const double* nua = LDSD(s.l_nua);
     double* red = LDSD(s.l_red);
-    double bs = 0.0;
+    const int per = (s.P + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int p0 = tid * per, p1 = min(p0 + per, s.P);
+    double loc = 0.0;
     int anyneg = 0;
-    for (int p = tid; p < s.P; p += (int)blockDim.x) {
+    for (int p = p0; p < p1; ++p) {
         const double r = (double)R[p];
-        if (r > 0) bs += r;
+        if (r > 0) loc += r;
         else if (r < 0) anyneg = 1;
     }
-    const bool anynode = block_sum(anyneg ? 1.0 : 0.0, red) > 0.0;
-    bs = block_sum(bs, red);
+    double bs;
+    bool anynode;
+    const double pre = block_excl_scan(loc, red, bs, anyneg, &anynode);
     double econt = 0.0, dnu = 0.0;
     const double ia2 = 1.0 / (a * a);
     for (int j = tid; j < s.N; j += (int)blockDim.x) {
@@ -764,12 +837,13 @@ __device__ __noinline__ MLocal mixed_evaluate(const DevMix* __restrict__ dm, dou
         econt += -0.5 * lap + nue[j];
         dnu += nuopt - nuzv;
     }
-    econt = block_sum(econt, red);
-    dnu = block_sum(dnu, red);
+    block_sum2(econt, dnu, red + 8);            // clear of the heat-bath picks at red + 4
     MLocal L;
     L.bbar = bs / (2.0 * a * a);
     L.eL = econt + LDSD(s.l_scal)[kScVee] + s.vii + dnu;
     L.W = L.eL + L.bbar;
+    L.pre = pre;
+    L.tot = bs;
     return L;
 }
 
@@ -1050,22 +1124,16 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
 }
 
 // heat-bath choice over the block: first p with cumulative positive ratio > xi * total
-__device__ __noinline__ int mixed_heat_bath(const DevMix* __restrict__ dm, double xi)
+__device__ __noinline__ int mixed_heat_bath(const DevMix* __restrict__ dm, double xi, double pre,
+                                            double tot)
 {
     const DevMix& s = *dm;
     const int tid = threadIdx.x;
     const float* R = LDSF(s.l_R);
-    double* red = LDSD(s.l_red);
     int* pick = reinterpret_cast<int*>(LDSD(s.l_red) + 4);
     const int per = (s.P + (int)blockDim.x - 1) / (int)blockDim.x;
     const int p0 = tid * per, p1 = min(p0 + per, s.P);
-    double loc = 0.0;
-    for (int p = p0; p < p1; ++p) {
-        const double r = (double)R[p];
-        if (r > 0) loc += r;
-    }
-    double tot;
-    double c = block_excl_scan(loc, red, tot);
+    double c = pre;
     if (!(tot > 0)) return -1;
     const double t = xi * tot;
     int found = s.P, lastpos = -1;
@@ -1119,13 +1187,37 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
     float* rowc = tmp + ns;       // [ns] column c of the inverse
     float* beta = tmp + 2 * ns;   // [ns]
     const int q = 6 * c + (p - 6 * i);
-    for (int idx = tid; idx < n * ns; idx += nt) {
-        const int r = idx / ns;
-        AiL[r * lda + idx - r * ns] = Ai[idx];
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    // rows of the inverse in float4 pieces when that still gives every lane
+    // a piece
+    const int q4 = ns >> 2;
+    const bool vec4 = (ns & 3) == 0 && n * q4 >= nt;
+    if (vec4) {
+        const f4v* A4 = reinterpret_cast<const f4v*>(Ai);
+        for (int i0 = tid; i0 < n * q4; i0 += 4 * nt) {
+            f4v v[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (i0 + t * nt < n * q4) v[t] = gld(A4 + i0 + t * nt);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int idx = i0 + t * nt;
+                if (idx < n * q4) {
+                    const int r = idx / q4, k0 = 4 * (idx - r * q4);
+                    float* dst = AiL + r * lda + k0;
+                    dst[0] = v[t].x; dst[1] = v[t].y; dst[2] = v[t].z; dst[3] = v[t].w;
+                }
+            }
+        }
+    } else {
+        for (int idx = tid; idx < n * ns; idx += nt) {
+            const int r = idx / ns;
+            AiL[r * lda + idx - r * ns] = gld(Ai + idx);
+        }
     }
     for (int k = tid; k < n; k += nt) {
-        u[k] = Phi[(long)k * 6 * ns + q];
-        rowc[k] = Ai[(long)c * ns + k];
+        u[k] = gld(Phi + (long)k * 6 * ns + q);
+        rowc[k] = gld(Ai + (long)c * ns + k);
     }
     __syncthreads();
     {
@@ -1145,13 +1237,37 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
     }
     __syncthreads();
     const float iR = 1.0f / Rd;
-    for (int idx = tid; idx < n * n; idx += nt) {
-        const int cc = idx / n, k = idx - cc * n;
-        const float v = cc == c ? rowc[k] * iR : AiL[cc * lda + k] - rowc[k] * (beta[cc] * iR);
-        AiL[cc * lda + k] = v;
-        Ai[(long)cc * ns + k] = v;
+    if (vec4) {
+        // four consecutive k per lane, one float4 store (columns k >= n of a
+        // smaller spin block are padding and receive zeros)
+        f4v* A4 = reinterpret_cast<f4v*>(Ai);
+        for (int idx = tid; idx < n * q4; idx += nt) {
+            const int cc = idx / q4, k0 = 4 * (idx - cc * q4);
+            const float bc = beta[cc] * iR;
+            float o[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = k0 + t;
+                float v = 0.f;
+                if (k < n) {
+                    v = cc == c ? rowc[k] * iR : AiL[cc * lda + k] - rowc[k] * bc;
+                    AiL[cc * lda + k] = v;
+                }
+                o[t] = v;
+            }
+            f4v w;
+            w.x = o[0]; w.y = o[1]; w.z = o[2]; w.w = o[3];
+            gst(A4 + idx, w);
+        }
+    } else {
+        for (int idx = tid; idx < n * n; idx += nt) {
+            const int cc = idx / n, k = idx - cc * n;
+            const float v = cc == c ? rowc[k] * iR : AiL[cc * lda + k] - rowc[k] * (beta[cc] * iR);
+            AiL[cc * lda + k] = v;
+            gst(Ai + (long)cc * ns + k, v);
+        }
     }
-    for (int k = tid; k < n; k += nt) st[s.g_Arow + (long)i * ns + k] = u[k];
+    for (int k = tid; k < n; k += nt) gst(st + s.g_Arow + (long)i * ns + k, u[k]);
     __syncthreads();
     mixed_store_rows(&s, st, i, false);
     mixed_spin_update(&s, st, sp, true);
@@ -1288,7 +1404,10 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
     }
     unsigned long long n_neg = 0, n_nomove = 0, n_refresh = 1, n_small = 0, n_sing = 0,
                        n_capped = 0;
-    if (!mixed_refresh(&s, st, a, false)) n_sing++;
+    // rows rebuilt from positions are inverted afresh; otherwise the carried
+    // inverse (the walker's own, or its parent's after the reconfiguration)
+    // is corrected like a scheduled refresh
+    if (!mixed_refresh(&s, st, a, !build)) n_sing++;
 
     double lw = s.lw[wid];
     double tau_left = pa.tau;
@@ -1306,7 +1425,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
             else lw += log(L.bbar) - log(den);
             const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb,
                                              (uint64_t)it, kMove);
-            q = mixed_heat_bath(&s, xi);
+            q = mixed_heat_bath(&s, xi, L.pre, L.tot);
             if (tr && it < s.trace_cap && tid == 0) tr[it] = q;
             ++it;
         } else {
@@ -1327,7 +1446,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
             }
             const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb,
                                              (uint64_t)(it - 1), kMove);
-            q = mixed_heat_bath(&s, xi);
+            q = mixed_heat_bath(&s, xi, L.pre, L.tot);
             if (tr && it - 1 < s.trace_cap && tid == 0) tr[it - 1] = q;
         }
         if (q >= 0) {
