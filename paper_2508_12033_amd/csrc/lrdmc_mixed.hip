@@ -188,15 +188,21 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
     const DevMix& s = *dm;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int Nb = s.Nb;
+    const bool bf = s.gemm == kGemmBF16;
     float* B = LDSF(s.l_U);                      // [11][nb32 + 4] basis rows (zero padded; the
-                                                 // extra 4 floats spread the rows over the banks)
+    const int ldb = s.nb32 + 4;                  // extra 4 floats spread the rows over the banks)
     float* rows = LDSF(s.l_rows);
-    const int ldb = s.nb32 + 4;
-    // the padding columns [Nb, ldb) of the 11 rows are read by the BF16 path
+    const int n = mnspin(s, mspin(s, j));
+    const int tiles = (n + 15) / 16;
+    const int i16 = lane & 15, k4 = lane >> 4;
+    const int nkb = s.nb32 / 32;
+    const long plane = (long)((s.ns + 15) / 16) * nkb * 64;
+    // the padding columns [Nb, ldb) of the 11 rows are read by the BF16 GEMM
     for (int z = tid; z < 11 * (ldb - Nb); z += (int)blockDim.x) {
         const int row = z / (ldb - Nb);
         B[row * ldb + Nb + (z - row * (ldb - Nb))] = 0.0f;
     }
+    auto put = [&](int row, int mu, float v) { B[row * ldb + mu] = v; };
     // one thread per basis function: a Gaussian factorizes over the
     // coordinates, so its values at the six neighbours r + s a e_c follow from
     // exp(-alpha d^2), exp(-alpha a^2) and exp(-+2 alpha a d_c) (d = r - centre);
@@ -223,8 +229,8 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
                 const float ep = e * (K * tc), em = e * (K * __builtin_amdgcn_rcpf(tc));
                 const float fp = (t != 0 && ax == cc) ? f0 + af : f0;
                 const float fm = (t != 0 && ax == cc) ? f0 - af : f0;
-                B[(2 * cc + 1) * ldb + mu] = fp * ep;
-                B[(2 * cc + 2) * ldb + mu] = fm * em;
+                put(2 * cc + 1, mu, fp * ep);
+                put(2 * cc + 2, mu, fm * em);
             }
             v = f0 * e;
             if (t == 0) {
@@ -249,7 +255,7 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
                     const float e = expf(-al * dq2);
                     w = t == 0 ? e : (t == 1 ? dx : (t == 2 ? dy : dz)) * e;
                 }
-                B[q * ldb + mu] = w;
+                put(q, mu, w);
             }
             const float dx = d[0], dy = d[1], dz = d[2];
             if (t == 4) {
@@ -270,96 +276,93 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
                 l = dq * e * (4.0f * al * al * d2 - 10.0f * al);
             }
         }
-        B[mu] = v;
-        B[7 * ldb + mu] = g0; B[8 * ldb + mu] = g1; B[9 * ldb + mu] = g2;
-        B[10 * ldb + mu] = l;
+        put(0, mu, v);
+        put(7, mu, g0); put(8, mu, g1); put(9, mu, g2);
+        put(10, mu, l);
     }
     __syncthreads();
-    const int n = mnspin(s, mspin(s, j));
-    const int tiles = (n + 15) / 16;
-    const int i16 = lane & 15, k4 = lane >> 4;
     for (int t = wv; t < tiles; t += (int)(blockDim.x >> 6)) {
         float4_t acc = {0.f, 0.f, 0.f, 0.f};
         const int col = 16 * t + i16;
-        if (s.gemm == kGemmBF16) {
-            // 16x16x32 BF16 tiles, lane holds 8 consecutive inner indices.  Each
-            // FP32 operand is split into a BF16 high part and a BF16 residual;
-            // hi*hi + hi*lo + lo*hi keeps about 16 significant bits.  The
-            // coefficient operands (shared by all walkers, L2-resident) are
-            // loaded KC k-blocks ahead of their use
-            constexpr int KC = 2;
-            const int nkb = s.nb32 / 32;
-            const long plane = (long)((s.ns + 15) / 16) * nkb * 64;
+        // rows 11..15 of the A tile are never stored: lanes i16 >= 11 read row 0
+        const int ar = i16 < 11 ? i16 : 0;
+        if (bf) {
+            // 16x16x32 BF16 tiles, lane holds 8 consecutive inner indices.
+            // Each FP32 operand is split into a BF16 high part and a BF16
+            // residual; hi*hi + hi*lo + lo*hi keeps about 16 significant bits.
+            // The coefficient operands (shared by all walkers, L2-resident) are
+            // double-buffered: k-blocks kb + 2, kb + 3 load into one register
+            // pair while kb, kb + 1 are multiplied from the other, with no
+            // copies between them (indices clamped, so that every load stays
+            // in bounds; the tail blocks are skipped)
             const bf16x8_t* cb = reinterpret_cast<const bf16x8_t*>(s.Cbf) + (long)t * nkb * 64;
-            bf16x8_t hc[KC], lc[KC];
+            const float* a_row = B + ar * ldb + 8 * k4;
+            auto ldc = [&](int kb, bf16x8_t& h, bf16x8_t& l) {
+                const long o = (long)min(kb, nkb - 1) * 64 + lane;
+                h = gld(cb + o);
+                l = gld(cb + plane + o);
+            };
+            auto mul = [&](int kb, const bf16x8_t& h, const bf16x8_t& l) {
+                if (kb >= nkb) return;
+                const float4_t* src = reinterpret_cast<const float4_t*>(a_row + 32 * kb);
+                const float4_t v0 = src[0], v1 = src[1];
+                const float xa[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+                bf16x8_t ah, alo;
 #pragma unroll
-            for (int u = 0; u < KC; ++u)
-                if (u < nkb) {
-                    hc[u] = gld(cb + (long)u * 64 + lane);
-                    lc[u] = gld(cb + plane + (long)u * 64 + lane);
+                for (int e = 0; e < 8; ++e) {
+                    const __bf16 hh = (__bf16)xa[e];
+                    ah[e] = hh;
+                    alo[e] = (__bf16)(xa[e] - (float)hh);
                 }
-            for (int b0 = 0; b0 < nkb; b0 += KC) {
-                bf16x8_t hn[KC], ln[KC];
-#pragma unroll
-                for (int u = 0; u < KC; ++u)
-                    if (b0 + KC + u < nkb) {
-                        hn[u] = gld(cb + (long)(b0 + KC + u) * 64 + lane);
-                        ln[u] = gld(cb + plane + (long)(b0 + KC + u) * 64 + lane);
-                    }
-#pragma unroll
-                for (int u = 0; u < KC; ++u) {
-                    if (b0 + u >= nkb) break;
-                    const int k0 = 32 * (b0 + u) + 8 * k4;
-                    float xa[8];
-                    if (i16 < 11) {
-                        const float4_t* src = reinterpret_cast<const float4_t*>(B + i16 * ldb + k0);
-                        const float4_t v0 = src[0], v1 = src[1];
-                        xa[0] = v0[0]; xa[1] = v0[1]; xa[2] = v0[2]; xa[3] = v0[3];
-                        xa[4] = v1[0]; xa[5] = v1[1]; xa[6] = v1[2]; xa[7] = v1[3];
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) xa[e] = 0.0f;
-                    }
-                    bf16x8_t ah, alo;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const __bf16 h = (__bf16)xa[e];
-                        ah[e] = h;
-                        alo[e] = (__bf16)(xa[e] - (float)h);
-                    }
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, hc[u], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, lc[u], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, hc[u], acc, 0, 0, 0);
-                }
-#pragma unroll
-                for (int u = 0; u < KC; ++u) { hc[u] = hn[u]; lc[u] = ln[u]; }
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, h, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, l, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, h, acc, 0, 0, 0);
+            };
+            bf16x8_t h0, l0, h1, l1, h2, l2, h3, l3;
+            ldc(0, h0, l0);
+            ldc(1, h1, l1);
+#pragma unroll 1
+            for (int kb = 0; kb < nkb; kb += 4) {
+                ldc(kb + 2, h2, l2);
+                ldc(kb + 3, h3, l3);
+                mul(kb, h0, l0);
+                mul(kb + 1, h1, l1);
+                ldc(kb + 4, h0, l0);
+                ldc(kb + 5, h1, l1);
+                mul(kb + 2, h2, l2);
+                mul(kb + 3, h3, l3);
             }
         } else {
-            // 16x16x4 FP32 tiles; the coefficient column loads run KF k-steps
-            // ahead of the products
+            // 16x16x4 FP32 tiles; the coefficient column loads are
+            // double-buffered in groups of KF k-steps (indices clamped)
             constexpr int KF = 8;
             const int nk = (Nb + 3) / 4;
-            float bc[KF];
-#pragma unroll
-            for (int u = 0; u < KF; ++u) {
-                const int mu = 4 * u + k4;
-                bc[u] = (col < n && mu < Nb) ? gld(s.Cf + (long)mu * s.ns + col) : 0.0f;
-            }
-            for (int s0 = 0; s0 < nk; s0 += KF) {
-                float bn[KF];
+            const float* cf = s.Cf + min(col, n - 1);
+            auto ldf = [&](int s0, float* v) {
 #pragma unroll
                 for (int u = 0; u < KF; ++u) {
-                    const int mu = 4 * (s0 + KF + u) + k4;
-                    bn[u] = (col < n && mu < Nb) ? gld(s.Cf + (long)mu * s.ns + col) : 0.0f;
+                    const int mu = min(4 * (s0 + u) + k4, Nb - 1);
+                    v[u] = gld(cf + (long)mu * s.ns);
                 }
+            };
+            auto mulf = [&](int s0, const float* v) {
 #pragma unroll
                 for (int u = 0; u < KF; ++u) {
+                    // lane (i16, k4) supplies A[i16][mu] and C[mu][col]
                     const int mu = 4 * (s0 + u) + k4;
-                    const float av = (i16 < 11 && mu < Nb) ? B[i16 * ldb + mu] : 0.0f;
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bc[u], acc, 0, 0, 0);
+                    const float av = mu < Nb ? B[ar * ldb + mu] : 0.0f;
+                    const float bv = (mu < Nb && col < n) ? v[u] : 0.0f;
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
                 }
-#pragma unroll
-                for (int u = 0; u < KF; ++u) bc[u] = bn[u];
+            };
+            float f0[KF], f1[KF];
+            ldf(0, f0);
+#pragma unroll 1
+            for (int s0 = 0; s0 < nk; s0 += 2 * KF) {
+                ldf(s0 + KF, f1);
+                mulf(s0, f0);
+                ldf(s0 + 2 * KF, f0);
+                if (s0 + KF < nk) mulf(s0 + KF, f1);
             }
         }
         // D[row][col]: row = 4 (lane >> 4) + v
