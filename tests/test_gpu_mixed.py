@@ -115,6 +115,28 @@ def test_mixed_c3_sample(prec):
     _check(res, prec, 40, res["report"])
 
 
+def test_mixed_unequal_spins_256_threads():
+    """64 up and 60 down electrons (the 128-electron system without its last
+    four down electrons): the down block is narrower than the padded spin
+    block, so the float4 pieces of its inverse carry padding columns, and its
+    ratio products split 60 electrons over groups of adjacent lanes."""
+    d = dict(I.c3_system(n_walkers=8))
+    d["n_dn"] = 60
+    d["n_elec"] = 124
+    d["init_pos"] = np.ascontiguousarray(d["init_pos"][:, :124, :])
+    say("case mixed unequal spins 64+60, 256 threads, 8 walkers x 30 steps")
+    h, d2, prm = make_handle(d, "lb", 8, precision="fp32", n_proj=30)
+    h.set_launch(256, big_first=True)
+    e0 = h.e0()
+    pos0 = d2["init_pos"][:8].copy()
+    h.step()
+    g = h.walkers(trace=True)
+    rep = h.precision_report()
+    res = compare_phase(d2, prm, "lb", 0, e0, pos0, np.zeros(8), g, np.arange(8), band=FP32_BAND)
+    _check(res, "fp32", 30, rep)
+    h.close()
+
+
 def test_mixed_branching_gathers_state():
     """Three phases with reconfiguration between them: the gathered walker
     blocks (orbital data and inverses in HBM) must continue the trajectories
