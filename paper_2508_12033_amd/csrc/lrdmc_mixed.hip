@@ -947,7 +947,7 @@ __device__ __noinline__ void final_z(const DevMix& s, int sp, const double* AiT,
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int mu = 16 * tr + k4 + 4 * v;
-                if (mu < Nb && c < n) Z[(long)mu * ns + c] = acc[t][v];
+                if (mu < Nb && c < n) Z[(long)c * Nb + mu] = acc[t][v];
             }
         }
     }
@@ -967,11 +967,11 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
 {
     const DevMix& s = *dm;
     const int tid = threadIdx.x, nt = blockDim.x, ns = s.ns, N = s.N, P = s.P, Nb = s.Nb;
-    const int lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
+    const int lane = tid & 63;
     double* g64 = s.s64 + (long)wid * s.stride64;
     double* A64 = g64;                           // [N][ns]       Slater rows
     double* Ai64 = g64 + (long)N * ns;           // [2][ns][ns]   transposed inverses AiT[c][k]
-    double* Z64 = Ai64 + 2L * ns * ns;           // [2][Nb][ns]   Z[mu][c] = sum_k C[mu][k] Ainv[k][c]
+    double* Z64 = Ai64 + 2L * ns * ns;           // [2][ns][Nb]   Z[c][mu] = sum_k C[mu][k] Ainv[k][c]
     const double* pos = LDSD(s.l_pos);
     double* F = LDSD(s.l_F);
     double* R64 = F;                             // [P]
@@ -982,7 +982,6 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
     double* nue = LDSD(s.l_nue);
     double* nua = LDSD(s.l_nua);
     double* red = LDSD(s.l_red);
-    double* U = LDSD(s.l_U);
     // Slater rows on MFMA
     final_slater_rows(s, pos, A64);
     global_handoff();
@@ -993,39 +992,82 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
         if (mnspin(s, sp)) final_z(s, sp, Ai64 + (long)sp * ns * ns, Z64 + (long)sp * Nb * ns);
     global_handoff();
     // per electron: the 6 neighbour values, gradient and Laplacian of the
-    // basis, each contracted with Z[:, c]; partial sums over the basis reduced
-    // across the workgroup (U holds [waves][10])
-    for (int i = 0; i < N; ++i) {
-        const int sp = mspin(s, i), c = mcol(s, i);
-        const double* Zc = Z64 + (long)sp * Nb * ns + c;
-        double t[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-        for (int mu = tid; mu < Nb; mu += nt) {
-            const double z = Zc[(long)mu * ns];
-            const double* rec = s.btab + 4 * mu;
-            const int ty = s.btype[mu];
-            for (int q = 1; q <= 6; ++q) {
-                double p[3];
-                point_q(pos + 3 * i, q, a, p);
-                const double dx = p[0] - rec[0], dy = p[1] - rec[1], dz = p[2] - rec[2];
-                t[q - 1] += z * basis_value_d(ty, rec[3], dx, dy, dz, dx * dx + dy * dy + dz * dz);
-            }
-            const double* r = pos + 3 * i;
-            const double dx = r[0] - rec[0], dy = r[1] - rec[1], dz = r[2] - rec[2];
-            double v, gg[3], l;
-            basis_vgl_d(ty, rec[3], dx, dy, dz, dx * dx + dy * dy + dz * dz, v, gg, l);
-            t[6] += z * gg[0]; t[7] += z * gg[1]; t[8] += z * gg[2]; t[9] += z * l;
-        }
+    // basis, each contracted with Z[c][:].  A group of 16 adjacent lanes serves
+    // one electron (functions mu = g, g + 16, ...: coalesced reads of Z[c]),
+    // its partial sums combined over the group by DPP (row mirrors), with no
+    // barrier per electron.  A Gaussian's values at the six neighbours follow
+    // from exp(-alpha d^2), exp(-alpha a^2) and exp(-+2 alpha a d_c)
+    // (d = r - centre; exponent clamped to +-700, where the value at r has
+    // underflowed); Slater functions take the seven points directly
+    {
+        const int g16 = lane & 15, ngrp = nt >> 4;
+        for (int i0 = 0; i0 < N; i0 += ngrp) {
+            const int i = i0 + (tid >> 4);
+            double t[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+            if (i < N) {
+                const int sp = mspin(s, i), c = mcol(s, i);
+                const double* Zc = Z64 + (long)sp * Nb * ns + (long)c * Nb;
+                const double* ri = pos + 3 * i;
+                for (int mu = g16; mu < Nb; mu += 16) {
+                    const double z = Zc[mu];
+                    const double4_t rec = gld((const double4_t*)(s.btab + 4 * mu));
+                    const int ty = gld(s.btype + mu);
+                    const double al = rec[3];
+                    const double d[3] = {ri[0] - rec[0], ri[1] - rec[1], ri[2] - rec[2]};
+                    const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                    double v, gg[3], l;
+                    if (ty == 4) {
+                        for (int q = 1; q <= 6; ++q) {
+                            double pq[3];
+                            point_q(ri, q, a, pq);
+                            const double dx = pq[0] - rec[0], dy = pq[1] - rec[1], dz = pq[2] - rec[2];
+                            t[q - 1] += z * basis_value_d(ty, al, dx, dy, dz, dx * dx + dy * dy + dz * dz);
+                        }
+                        basis_vgl_d(ty, al, d[0], d[1], d[2], d2, v, gg, l);
+                    } else {
+                        const double e = exp(-al * d2), K = exp(-al * a * a);
+                        const int ax = ty - 1;
+                        const double f0 = ty == 0 ? 1.0 : d[ax];
 #pragma unroll
-        for (int q = 0; q < 10; ++q) {
-            const double w = wave_sum(t[q]);
-            if (lane == 0) U[wv * 10 + q] = w;
-        }
-        __syncthreads();
-        if (tid < 10) {
-            double v = U[tid];
-            for (int w = 1; w < nwv; ++w) v += U[w * 10 + tid];
-            if (tid < 6) R64[6 * i + tid] = v;
-            else gD64[4 * i + tid - 6] = v;
+                        for (int cc = 0; cc < 3; ++cc) {
+                            const double x = fmin(fmax(-2.0 * al * a * d[cc], -700.0), 700.0);
+                            const double tc = exp(x);
+                            const double fp = (ty != 0 && ax == cc) ? f0 + a : f0;
+                            const double fm = (ty != 0 && ax == cc) ? f0 - a : f0;
+                            t[2 * cc] += z * (fp * (e * (K * tc)));
+                            t[2 * cc + 1] += z * (fm * (e * (K * recip(tc))));
+                        }
+                        if (ty == 0) {
+                            v = e;
+#pragma unroll
+                            for (int cc = 0; cc < 3; ++cc) gg[cc] = -2.0 * al * d[cc] * e;
+                            l = (4.0 * al * al * d2 - 6.0 * al) * e;
+                        } else {
+                            v = f0 * e;
+#pragma unroll
+                            for (int cc = 0; cc < 3; ++cc)
+                                gg[cc] = ((cc == ax) ? e : 0.0) - 2.0 * al * f0 * d[cc] * e;
+                            l = f0 * e * (4.0 * al * al * d2 - 10.0 * al);
+                        }
+                    }
+                    t[6] += z * gg[0]; t[7] += z * gg[1]; t[8] += z * gg[2]; t[9] += z * l;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 10; ++q) {
+                double w = t[q];
+                w += dpp_mov<0xb1, 0xf>(w);       // quad_perm [1,0,3,2]
+                w += dpp_mov<0x4e, 0xf>(w);       // quad_perm [2,3,0,1]
+                w += dpp_mov<0x141, 0xf>(w);      // row_half_mirror
+                w += dpp_mov<0x140, 0xf>(w);      // row_mirror
+                t[q] = w;
+            }
+            if (i < N && g16 == 0) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) R64[6 * i + q] = t[q];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) gD64[4 * i + q] = t[6 + q];
+            }
         }
         __syncthreads();
     }
