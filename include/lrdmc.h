@@ -50,12 +50,14 @@ extern "C" {
 #define LRDMC_SCHEME_CONV  1   /* conventional continuous time (Algorithm 1) */
 
 #define LRDMC_FP64         0   /* every step in FP64; walker state in LDS */
-#define LRDMC_MIXED_FP32   1   /* Sec. III.B mixed precision: orbital rows,
+#define LRDMC_MIXED_FP32   1   /* mixed precision (an extension: the paper
+                                  computes in FP64): orbital rows,
                                   Sherman-Morrison updates, ratios and Jastrow
                                   in FP32; positions, weights, local-energy
-                                  accumulation and the periodic refresh of
-                                  the inverse in FP64; orbital product on
-                                  FP32 MFMA */
+                                  accumulation, the periodic refresh of the
+                                  inverse and the estimator values handed to
+                                  the reconfiguration in FP64; orbital
+                                  product on FP32 MFMA */
 #define LRDMC_MIXED_BF16   2   /* as LRDMC_MIXED_FP32, with the orbital
                                   product on BF16 MFMA (FP32 accumulation) */
 
@@ -106,8 +108,13 @@ typedef struct lrdmc_params {
     double tau;              /* conventional: projection time per branching */
     int32_t n_proj;          /* load-balanced: steps per branching */
     uint64_t seed;           /* first Philox key word */
-    int32_t refresh_every;   /* moves between FP64 rebuilds of the inverses and Jastrow caches,
-                                >= 1 (the Python binding defaults to 64 in FP64, 16 mixed) */
+    int32_t refresh_every;   /* moves between FP64 refreshes of the inverses and Jastrow caches,
+                                >= 1 (the Python binding defaults to 64 in FP64, 16 mixed).
+                                FP64: Gauss-Jordan rebuild.  Mixed: one or two Newton-Schulz
+                                corrections of the carried FP32 inverse on FP64 MFMA (also at
+                                the start of every phase), a Gauss-Jordan rebuild when its
+                                residual is 3e-3 or more, after a tiny determinant ratio, and
+                                for rows rebuilt from positions */
     int32_t nu_opt_mode;     /* LRDMC_NU_* */
     int32_t p_corr;          /* correcting factors: product of the p previous
                                 average weights (Sec. II.A) */
