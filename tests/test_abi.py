@@ -44,6 +44,16 @@ def test_workspace_bytes_and_validation():
     assert rc == -1 and not h.value
     bad = B.params_for(d, refresh_every=0)
     assert L.lrdmc_workspace_bytes(ct.byref(s), 1, ct.byref(bad)) == 0
+    # empty phase and empty population are rejected before any device work
+    bad = B.params_for(d, "lb", n_proj=0)
+    assert L.lrdmc_workspace_bytes(ct.byref(s), 1, ct.byref(bad)) == 0
+    assert b"n_proj" in L.lrdmc_last_error()
+    d0 = dict(d)
+    d0["n_walkers_run"] = 0
+    s0 = B._sys_struct(d0, keep)
+    assert s0.n_walkers == 0
+    assert L.lrdmc_workspace_bytes(ct.byref(s0), 1, ct.byref(prm)) == 0
+    assert b"n_walkers" in L.lrdmc_last_error()
 
 
 def test_layout_rejects_oversized_system():
