@@ -229,7 +229,7 @@ def main():
                config=dict(workload="16-electron 8-atom synthetic molecule (1 C-like and 1 "
                                     "O-like soft core, 6 protons, 80 s/p Gaussians), 4096 "
                                     "walkers, a=0.2 bohr, load-balanced N_proj=300, FP64, "
-                                    "refresh every 64 moves",
+                                    "refresh every %d moves" % prm.refresh_every,
                            walkers=nw, electrons=N, n_proj=n_proj, precision="fp64",
                            refresh_every=prm.refresh_every,
                            scheme="load-balanced", step="one projection phase + reconfiguration"),

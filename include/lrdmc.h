@@ -109,7 +109,7 @@ typedef struct lrdmc_params {
     int32_t n_proj;          /* load-balanced: steps per branching */
     uint64_t seed;           /* first Philox key word */
     int32_t refresh_every;   /* moves between FP64 refreshes of the inverses and Jastrow caches,
-                                >= 1 (the Python binding defaults to 64 in FP64, 16 mixed).
+                                >= 1 (the Python binding defaults to 128 in FP64, 16 mixed).
                                 FP64: Gauss-Jordan rebuild.  Mixed: one or two Newton-Schulz
                                 corrections of the carried FP32 inverse on FP64 MFMA (also at
                                 the start of every phase), a Gauss-Jordan rebuild when its

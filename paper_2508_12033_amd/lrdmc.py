@@ -152,11 +152,12 @@ def make_params(scheme="lb", a=0.2, tau=0.25, n_proj=300, seed=12033, refresh_ev
     accumulation and refreshes).
 
     refresh_every: moves between rebuilds of the inverses and Jastrow caches
-    from scratch; by default 64 in FP64 (the rounding drift of 64 rank-one
-    updates stays far below the FP64 error bar) and 16 in the mixed modes."""
+    from scratch; by default 128 in FP64 (the rounding drift of 128 rank-one
+    updates stays far below the FP64 error bar: local energies within 2e-12 Ha
+    of the oracle's from-scratch values) and 16 in the mixed modes."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     if refresh_every is None:
-        refresh_every = 64 if prec == PRECISIONS["fp64"] else 16
+        refresh_every = 128 if prec == PRECISIONS["fp64"] else 16
     return lrdmc_params(SCHEME_LB if scheme == "lb" else SCHEME_CONV, prec, float(a), float(tau),
                         int(n_proj), int(seed), int(refresh_every), int(nu_opt_mode), int(p_corr),
                         int(e0_window), int(trace_cap))
