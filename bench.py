@@ -194,7 +194,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+        print("bench.py: measures one GPU only; --gpus %d is not supported "
               "(the walker population of one GPU is the unit of work)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
