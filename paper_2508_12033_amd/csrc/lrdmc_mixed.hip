@@ -16,8 +16,9 @@
 // Precision: basis functions, Jastrow sums and ratios in FP32; the orbital
 // GEMM on MFMA in FP32 or BF16 with FP32 accumulation; positions, potentials,
 // weights, all sums that form W, bbar and e_L, and the periodic refresh of
-// the inverses (Newton-Schulz correction or Gauss-Jordan) in FP64.  The local energy is formed as the continuum local energy
-// plus sum_i (nu_opt,i - nu_zv,i) (App. D identity), which avoids the
+// the inverses (Newton-Schulz correction or Gauss-Jordan) in FP64.  The local
+// energy is formed as the continuum local energy plus
+// sum_i (nu_opt,i - nu_zv,i) (App. D identity), which avoids the
 // cancellation in W - bbar when bbar is known only to FP32 accuracy.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -514,9 +515,10 @@ __device__ __noinline__ void mixed_spin_update(const DevMix* __restrict__ dm, co
     float* Rdet = LDSF(s.l_Rdet);
     // column c of the inverse against electron c's gradient / Laplacian rows
     // (one float4 per orbital k) and its six neighbour rows (three float2):
-    // kp adjacent lanes per electron split k (k = part, part + kp, ...), KB
-    // k per batch, so that 4 KB loads per lane are in flight (the walker
-    // blocks live in HBM); the kp partial sums are combined across the lanes
+    // kp adjacent lanes per electron split k (k = part, part + kp, ...), KB = 4
+    // orbitals per batch, so that 16 loads (160 bytes) per lane are in flight
+    // (the walker blocks live in HBM); the kp partial sums are combined across
+    // the lanes
     typedef float f4v __attribute__((ext_vector_type(4)));
     typedef float f2v __attribute__((ext_vector_type(2)));
     const f4v* dPhi4 = reinterpret_cast<const f4v*>(st + s.g_dPhi + (long)sp * ns * 4 * ns);
