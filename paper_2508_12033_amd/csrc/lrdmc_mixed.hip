@@ -1457,6 +1457,11 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
     if (!mixed_refresh(&s, st, a, !build)) n_sing++;
 
     double lw = s.lw[wid];
+    // load-balanced weight factors bbar / (W - E_0) are multiplied together
+    // and their log taken every kLogEvery steps (or when the product leaves
+    // [2^-600, 2^600]): one logarithm per block instead of two per step
+    double wprod = 1.0;
+    constexpr int kLogEvery = 32;
     double tau_left = pa.tau;
     int it = 0, since = 0;
     MLocal L;
@@ -1469,7 +1474,13 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
             const double den = L.W - E0;
             if (!(den > 0)) { lw = -INFINITY; n_neg++; }
             else if (!(L.bbar > 0)) { lw = -INFINITY; n_nomove++; }
-            else lw += log(L.bbar) - log(den);
+            else {
+                wprod *= L.bbar / den;
+                if (((it + 1) & (kLogEvery - 1)) == 0 || !(wprod > 0x1p-600 && wprod < 0x1p600)) {
+                    lw += log(wprod);
+                    wprod = 1.0;
+                }
+            }
             const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb,
                                              (uint64_t)it, kMove);
             q = mixed_heat_bath(&s, xi, L.pre, L.tot);
@@ -1507,6 +1518,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
             }
         }
     }
+    lw += log(wprod);
     // estimator values at the final configuration, in FP64; beside them the
     // values the mixed-precision step computed there, and the largest ratio
     // error, for the error report

@@ -831,6 +831,11 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
     if (!refresh_all(s, w, a, lane)) n_sing++;
 
     double lw = s.lw[wid];
+    // load-balanced weight factors bbar / (W - E_0) are multiplied together
+    // and their log taken every kLogEvery steps (or when the product leaves
+    // [2^-600, 2^600]): one logarithm per block instead of one per step
+    double wprod = 1.0;
+    constexpr int kLogEvery = 32;
     double tau_left = pa.tau;
     int it = 0, since = 0;
     Local L;
@@ -859,7 +864,13 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
             const double den = L.W - E0;
             if (!(den > 0)) { lw = -INFINITY; n_neg++; }
             else if (!(L.bbar > 0)) { lw = -INFINITY; n_nomove++; }
-            else lw += log(L.bbar / den);
+            else {
+                wprod *= L.bbar / den;
+                if (((it + 1) & (kLogEvery - 1)) == 0 || !(wprod > 0x1p-600 && wprod < 0x1p600)) {
+                    lw += log(wprod);
+                    wprod = 1.0;
+                }
+            }
             q = heat_bath(s, w, lane_value(xmove, slot), L.inc, lane);
             if (tr && it < s.trace_cap && lane == 0) tr[it] = q;
             ++it;
@@ -904,6 +915,7 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
     if (lane == 0 && pa.timers)
         for (int k = 0; k < 8; ++k) pa.timers[(long)wid * 8 + k] = sect[k];
 #endif
+    lw += log(wprod);
     if (pa.scheme == 0) L = evaluate(s, w, a, pa.nu_mode, lane);
 
     for (int q = lane; q < 3 * s.N; q += kWave) s.pos[(long)wid * 3 * s.N + q] = lds[w.pos + q];
