@@ -65,27 +65,61 @@ class _Prm(ct.Structure):
 _lib = None
 
 
+def _configure(L):
+    vp, i32, u64, dbl = ct.c_void_p, ct.c_int, ct.c_uint64, ct.c_double
+    L.orc_philox4x64_10.argtypes = [vp, vp, vp]
+    L.orc_uniform.argtypes = [u64] * 6
+    L.orc_uniform.restype = dbl
+    L.orc_basis.argtypes = [vp, vp, vp, vp, vp]
+    L.orc_jastrow.argtypes = [vp, vp]
+    L.orc_jastrow.restype = dbl
+    L.orc_log_psi.argtypes = [vp, vp, vp, vp]
+    L.orc_eval.argtypes = [vp, vp, vp] + [vp] * 9
+    L.orc_lb_phase.argtypes = [vp, vp, u64, u64, dbl, vp, vp, vp, vp, vp, vp, vp]
+    L.orc_conv_phase.argtypes = [vp, vp, u64, u64, vp, vp, vp, vp, vp, vp, i32, vp, vp]
+    L.orc_comb.argtypes = [i32, vp, dbl, vp, vp, vp, dbl, vp]
+    L.orc_population_phase.argtypes = [vp, vp, i32, i32, u64, i32, dbl, vp, vp, vp,
+                                       vp, vp, vp, i32, vp, i32, vp, vp]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         build()
-        L = ct.CDLL(LIB)
-        vp, i32, u64, dbl = ct.c_void_p, ct.c_int, ct.c_uint64, ct.c_double
-        L.orc_philox4x64_10.argtypes = [vp, vp, vp]
-        L.orc_uniform.argtypes = [u64] * 6
-        L.orc_uniform.restype = dbl
-        L.orc_basis.argtypes = [vp, vp, vp, vp, vp]
-        L.orc_jastrow.argtypes = [vp, vp]
-        L.orc_jastrow.restype = dbl
-        L.orc_log_psi.argtypes = [vp, vp, vp, vp]
-        L.orc_eval.argtypes = [vp, vp, vp] + [vp] * 9
-        L.orc_lb_phase.argtypes = [vp, vp, u64, u64, dbl, vp, vp, vp, vp, vp, vp, vp]
-        L.orc_conv_phase.argtypes = [vp, vp, u64, u64, vp, vp, vp, vp, vp, vp, i32, vp, vp]
-        L.orc_comb.argtypes = [i32, vp, dbl, vp, vp, vp, dbl, vp]
-        L.orc_population_phase.argtypes = [vp, vp, i32, i32, u64, i32, dbl, vp, vp, vp,
-                                           vp, vp, vp, i32, vp, i32, vp, vp]
-        _lib = L
+        _lib = _configure(ct.CDLL(LIB))
     return _lib
+
+
+def build_variant(src_text, path):
+    """Compile another C source text of the oracle to `path` (the test suite
+    uses it to check that its pins reject deliberately altered arithmetic)."""
+    c = path + ".c"
+    with open(c, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-w", c, "-o", path,
+                           "-lm", "-lpthread"])
+    return path
+
+
+class use_library:
+    """Context manager: every oracle call inside it goes to the library at
+    `path` (a variant built by build_variant)."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        lib()
+        self.saved = _lib
+        _lib = _configure(ct.CDLL(self.path))
+        return _lib
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
 
 
 def _p(a):
