@@ -44,6 +44,23 @@ extern "C" {
 #define LRDMC_ERR_SINGULAR        -4  /* a Slater matrix is exactly singular */
 #define LRDMC_ERR_ALL_DEAD        -5  /* every walker weight is zero at branching */
 #define LRDMC_ERR_UNSUPPORTED     -6  /* sizes beyond what the kernels support */
+#define LRDMC_ERR_NONFINITE       -7  /* a walker ended a phase with a NaN or infinite
+                                         e_L or W, or a NaN or +inf log-weight (-inf is a
+                                         dead walker), or a reconfiguration produced a
+                                         non-finite weight sum or walker average */
+#define LRDMC_ERR_NEG_WEIGHT      -8  /* strict mode only: W - E_0 <= 0 at some
+                                         load-balanced step, so b_x = bbar / (W - E_0) is
+                                         not a weight (Sec. II.C requires W - E_0 > 0) */
+#define LRDMC_ERR_NO_MOVE         -9  /* strict mode only: a configuration with no
+                                         allowed lattice move (bbar = 0) */
+/* A positive return value of lrdmc_step and lrdmc_run (when they fill their
+ * statistics) is a warning count: the number of walker-steps at which
+ * W - E_0 <= 0 or bbar = 0 (n_neg_weight + n_no_move).  In the load-balanced
+ * scheme such a walker's weight is set to zero and it dies at the next
+ * reconfiguration; in the conventional scheme a walker with bbar = 0 stays in
+ * place until its projection time is used up.  With lrdmc_params.strict = 1
+ * the same events return LRDMC_ERR_NEG_WEIGHT / LRDMC_ERR_NO_MOVE instead
+ * (the walker state is updated either way). */
 
 /* ---- enumerations ------------------------------------------------------ */
 #define LRDMC_SCHEME_LB    0   /* load-balanced, fixed N_proj (Algorithm 2) */
@@ -122,6 +139,8 @@ typedef struct lrdmc_params {
                                 local energies (load-balanced, Algorithm 2) */
     int32_t trace_cap;       /* > 0: record every walker's moves, up to this many
                                 per branching, for the parity harness */
+    int32_t strict;          /* 1: weight events are errors (LRDMC_ERR_NEG_WEIGHT,
+                                LRDMC_ERR_NO_MOVE) instead of a warning count */
 } lrdmc_params;
 
 /* ---- statistics returned to the caller --------------------------------- */
@@ -136,6 +155,8 @@ typedef struct lrdmc_step_stats {
     int64_t n_small_ratio;   /* forced refreshes after |R_det| < 1e-6 */
     int64_t n_capped;        /* conventional walkers stopped by the termination
                                 bound of 1000 * tau * 3N / a^2 + 10000 iterations */
+    int64_t n_nonfinite;     /* walkers that ended the phase with a non-finite value
+                                (the call then returns LRDMC_ERR_NONFINITE) */
     double elapsed_ms;       /* device time of the phase (HIP events) */
 } lrdmc_step_stats;
 
@@ -169,7 +190,12 @@ size_t lrdmc_workspace_bytes(const lrdmc_system *sys, int n_sys, const lrdmc_par
 /* Validate the inputs, upload the systems into the workspace, place every
  * walker at init_pos ([sum of n_walkers][n_up+n_dn][3] host FP64, walkers of
  * system 0 first), evaluate the local energies and set E_0 to their
- * unweighted mean.  Synchronises `stream`.  *out receives the handle. */
+ * unweighted mean.  The paper updates E_0 after every branching (Sec. II.C,
+ * Algorithm 2) but states no starting value and no update formula; the
+ * reading taken here is E_0^(0) = unweighted mean of the initial walkers'
+ * e_L, and after branching n the mean of the walker-averaged e_L of the last
+ * e0_window branchings.  A non-finite initial e_L returns
+ * LRDMC_ERR_SINGULAR.  Synchronises `stream`.  *out receives the handle. */
 int lrdmc_init_system(const lrdmc_system *sys, int n_sys, const lrdmc_params *prm,
                       const double *init_pos, void *dev_workspace, size_t ws_bytes,
                       void *stream, struct lrdmc_handle **out);
@@ -178,15 +204,23 @@ int lrdmc_init_system(const lrdmc_system *sys, int n_sys, const lrdmc_params *pr
  * tau_left = 0, or Algorithm 2 inner loop of N_proj steps): ratios of all 6N
  * lattice moves, lattice-regularized local energy with the fixed-node terms
  * on the diagonal, weight update, heat-bath move, Sherman-Morrison update.
- * Asynchronous on the handle's stream when st == NULL; otherwise synchronises
- * and fills *st. */
+ * Load-balanced: after the last move the walker's e_L and W are evaluated at
+ * its final configuration for the estimator weight w / (W - E_0) of
+ * Sec. II.C; W - E_0 <= 0 there also sets the weight to zero (counted in
+ * n_neg_weight).  Asynchronous on the handle's stream when st == NULL (errors
+ * found on the device then surface at the next call that synchronises);
+ * otherwise synchronises, fills *st and returns LRDMC_ERR_SINGULAR,
+ * LRDMC_ERR_NONFINITE, the warning count or (strict) LRDMC_ERR_NEG_WEIGHT /
+ * LRDMC_ERR_NO_MOVE. */
 int lrdmc_step(struct lrdmc_handle *h, lrdmc_step_stats *st);
 
 /* Reconfiguration (Sec. II.A): walker-averaged local energy, FP64 prefix sum
  * of the weights, comb with N_w correlated numbers, gather of the selected
  * walkers, weights reset to 1; then appends (log wbar, e_bar) to the history
  * and updates E_0 (Algorithm 2), both on the device.  Synchronises and copies
- * the new history records to the host. */
+ * the new history records to the host.  Returns LRDMC_ERR_ALL_DEAD when every
+ * weight was zero and LRDMC_ERR_NONFINITE when the weight sums or the walker
+ * average were not finite (nothing is appended to the history then). */
 int lrdmc_branch(struct lrdmc_handle *h, lrdmc_branch_stats *st);
 
 /* n_branchings cycles of (projection phase, reconfiguration) as by

@@ -251,8 +251,9 @@ def walker_average(scheme, lw, eL, W, E0):
     or w / (W - E0) (load-balanced)."""
     mx = np.max(lw)
     w = np.exp(lw - mx)
-    om = w if scheme == "conv" else w / (W - E0)
-    return float(np.sum(om * eL) / np.sum(om))
+    live = w > 0          # dead walkers (weight zero) carry no W - E_0 factor
+    om = w if scheme == "conv" else np.where(live, w / np.where(live, W - E0, 1.0), 0.0)
+    return float(np.sum(om[live] * eL[live]) / np.sum(om[live]))
 
 
 def e0_update(history_e, window=50):

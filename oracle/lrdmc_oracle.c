@@ -568,7 +568,13 @@ int orc_lb_phase(const orc_system *s, const orc_params *prm, uint64_t slot, uint
     }
     if (!rc) {
         if (orc_eval(s, prm, pos, 0, 0, 0, 0, 0, 0, 0, 0, sc)) { cnt[CNT_SINGULAR]++; rc = -1; }
-        else { *eL_out = sc[SC_EL]; *W_out = sc[SC_W]; }
+        else {
+            *eL_out = sc[SC_EL]; *W_out = sc[SC_W];
+            /* Sec. II.C: the walker average weights w by 1/(W - E_0) at the
+             * final configuration, which needs W - E_0 > 0 there as well; a
+             * walker violating it gets weight zero, like any step's factor */
+            if (prm->nproj > 0 && !(sc[SC_W] - E0 > 0)) { cnt[CNT_NEG_WEIGHT]++; *lw = -INFINITY; }
+        }
     }
     free(R);
     return rc;

@@ -14,7 +14,10 @@ enum : int { kMove = 0, kPersist = 1, kComb = 2, kInit = 3 };   // Philox purpos
 // counters accumulated by one projection phase (device, 64-bit)
 enum : int {
     kCntIters = 0, kCntNegW = 1, kCntNoMove = 2, kCntRefresh = 3, kCntSmallR = 4,
-    kCntSingular = 5, kCntMaxIters = 6, kCntMinIters = 7, kCntCapped = 8, kCntLen = 9
+    kCntSingular = 5, kCntMaxIters = 6, kCntMinIters = 7, kCntCapped = 8,
+    kCntNonfinite = 9,   // walkers ending a phase with a NaN or infinite e_L or W, or a
+                         // NaN or +inf log-weight (-inf marks a dead walker)
+    kCntLen = 10
 };
 
 // One molecular system, its walkers, and the per-walker state layout.

@@ -39,6 +39,29 @@ __device__ __forceinline__ double rsqrt_nr(double x)
     return fma(0.5 * y, fma(-x * y, y, 1.0), y);
 }
 
+// Load-balanced weight update (Sec. II.C: w <- w bbar / (W - E_0)) in blocked
+// logarithmic form.  The factors are multiplied into wprod, which stays in
+// [2^-600, 2^600]; its logarithm is added to lw every 32 steps (step_no counts
+// from 1).  A factor that would carry the product out of that range (or that
+// is itself not a finite positive number, as bbar / den can be for a
+// subnormal den) is added to lw as log(bbar) - log(den) together with the
+// product so far, so lw stays what the per-step sum of logarithms gives.
+__host__ __device__ __forceinline__ void lw_block_update(double& lw, double& wprod, double bbar,
+                                                         double den, int step_no)
+{
+    const double np = wprod * (bbar / den);
+    if (np > 0x1p-600 && np < 0x1p600) {
+        wprod = np;
+    } else {
+        lw += log(wprod) + (log(bbar) - log(den));
+        wprod = 1.0;
+    }
+    if ((step_no & 31) == 0) {
+        lw += log(wprod);
+        wprod = 1.0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter (c0..c3), key
 // (k0, k1); uniform = top 53 bits of the first output word times 2^-53.

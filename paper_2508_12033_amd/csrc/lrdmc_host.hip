@@ -290,6 +290,7 @@ struct SysRun {
     int* d_dead;
     long long h_nhist;
     int h_dead;
+    int h_nonfinite = 0;
     // descriptors per slot
     DevSys hsys[2];
     DevSys* dsys[2];
@@ -490,9 +491,9 @@ int drain(lrdmc_handle* h)
     int rc = LRDMC_OK;
     for (auto& r : h->sys) {
         long long n = 0;
-        int dead = 0;
+        int dead[2] = {0, 0};   // all-dead and non-finite reconfigurations
         HIPCHK(hipMemcpy(&n, r.d_nhist, 8, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(&dead, r.d_dead, 4, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(dead, r.d_dead, 8, hipMemcpyDeviceToHost));
         if (n - r.h_nhist > kHistCap) rc = fail(LRDMC_ERR_INVALID_ARG, "branching history overflow");
         const long long q0 = std::max(r.h_nhist, n - kHistCap);
         std::vector<double> buf((size_t)kHistCap * kHistLen);
@@ -512,9 +513,13 @@ int drain(lrdmc_handle* h)
             r.e0 = e[kHistE0];
         }
         r.h_nhist = n;
-        if (dead > r.h_dead) {
-            r.h_dead = dead;
+        if (dead[0] > r.h_dead) {
+            r.h_dead = dead[0];
             rc = fail(LRDMC_ERR_ALL_DEAD, "every walker weight is zero");
+        }
+        if (dead[1] > r.h_nonfinite) {
+            r.h_nonfinite = dead[1];
+            rc = fail(LRDMC_ERR_NONFINITE, "non-finite weight sum or walker average at a reconfiguration");
         }
     }
     return rc;
@@ -559,9 +564,18 @@ int read_counters(lrdmc_handle* h, lrdmc_step_stats* st, float ms)
     st->n_refresh = (int64_t)cnt[kCntRefresh];
     st->n_small_ratio = (int64_t)cnt[kCntSmallR];
     st->n_capped = (int64_t)cnt[kCntCapped];
+    st->n_nonfinite = (int64_t)cnt[kCntNonfinite];
     st->elapsed_ms = ms;
     if (cnt[kCntSingular]) return fail(LRDMC_ERR_SINGULAR, "singular Slater matrix in a refresh");
-    return LRDMC_OK;
+    if (cnt[kCntNonfinite])
+        return fail(LRDMC_ERR_NONFINITE, std::to_string(cnt[kCntNonfinite]) +
+                                             " walkers ended the phase with a non-finite e_L, W or log-weight");
+    if (h->prm.strict && cnt[kCntNegW])
+        return fail(LRDMC_ERR_NEG_WEIGHT, std::to_string(cnt[kCntNegW]) + " walker-steps with W - E_0 <= 0");
+    if (h->prm.strict && cnt[kCntNoMove])
+        return fail(LRDMC_ERR_NO_MOVE, std::to_string(cnt[kCntNoMove]) + " walker-steps with no allowed move");
+    const unsigned long long warn = cnt[kCntNegW] + cnt[kCntNoMove];
+    return warn > 0x7fffffffull ? 0x7fffffff : (int)warn;
 }
 
 void fill_branch_stats(const lrdmc_handle* h, lrdmc_branch_stats* st, float ms)
@@ -748,7 +762,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
         r.h_nhist = 0;
         r.h_dead = 0;
         r.need_build = false;
-        if (up(r.d_nhist, &zero8, 8) || up(r.d_dead, zero4, 4)) {
+        if (up(r.d_nhist, &zero8, 8) || up(r.d_dead, zero4, 8)) {
             rc = fail(LRDMC_ERR_HIP, "upload failed");
             break;
         }

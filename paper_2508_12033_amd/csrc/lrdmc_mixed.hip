@@ -1457,11 +1457,9 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
     if (!mixed_refresh(&s, st, a, !build)) n_sing++;
 
     double lw = s.lw[wid];
-    // load-balanced weight factors bbar / (W - E_0) are multiplied together
-    // and their log taken every kLogEvery steps (or when the product leaves
-    // [2^-600, 2^600]): one logarithm per block instead of two per step
+    // load-balanced weight factors bbar / (W - E_0) multiplied in blocks
+    // (lw_block_update): one logarithm per 32 steps instead of one per step
     double wprod = 1.0;
-    constexpr int kLogEvery = 32;
     double tau_left = pa.tau;
     int it = 0, since = 0;
     MLocal L;
@@ -1475,11 +1473,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
             if (!(den > 0)) { lw = -INFINITY; n_neg++; }
             else if (!(L.bbar > 0)) { lw = -INFINITY; n_nomove++; }
             else {
-                wprod *= L.bbar / den;
-                if (((it + 1) & (kLogEvery - 1)) == 0 || !(wprod > 0x1p-600 && wprod < 0x1p600)) {
-                    lw += log(wprod);
-                    wprod = 1.0;
-                }
+                lw_block_update(lw, wprod, L.bbar, den, it + 1);
             }
             const double xi = philox_uniform(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb,
                                              (uint64_t)it, kMove);
@@ -1528,6 +1522,9 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
         bool ok64 = true;
         L = mixed_final_fp64(&s, wid, a, pa.nu_mode, ok64);
         if (!ok64) n_sing++;
+        // the estimator weight w / (W - E_0) at the final configuration needs
+        // W - E_0 > 0 as every step's factor does: otherwise the walker dies
+        if (pa.scheme == 0 && pa.nproj > 0 && !(L.W - E0 > 0)) { lw = -INFINITY; n_neg++; }
         if (s.diag) {
             const float* R = LDSF(s.l_R);
             const double* R64 = LDSD(s.l_F);
@@ -1542,6 +1539,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
         }
     }
 
+    const bool nonfinite = !(isfinite(L.eL) && isfinite(L.W)) || isnan(lw) || lw == INFINITY;
     for (int q = tid; q < 3 * s.N; q += (int)blockDim.x) s.pos[(long)wid * 3 * s.N + q] = pos[q];
     if (tid == 0) {
         s.lw[wid] = lw;
@@ -1556,6 +1554,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
         if (n_small) atomicAdd(cn + kCntSmallR, n_small);
         if (n_sing) atomicAdd(cn + kCntSingular, n_sing);
         if (n_capped) atomicAdd(cn + kCntCapped, n_capped);
+        if (nonfinite) atomicAdd(cn + kCntNonfinite, 1ull);
         atomicMax(cn + kCntMaxIters, (unsigned long long)it);
         atomicMin(cn + kCntMinIters, (unsigned long long)it);
     }

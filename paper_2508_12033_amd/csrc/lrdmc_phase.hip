@@ -831,11 +831,9 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
     if (!refresh_all(s, w, a, lane)) n_sing++;
 
     double lw = s.lw[wid];
-    // load-balanced weight factors bbar / (W - E_0) are multiplied together
-    // and their log taken every kLogEvery steps (or when the product leaves
-    // [2^-600, 2^600]): one logarithm per block instead of one per step
+    // load-balanced weight factors bbar / (W - E_0) multiplied in blocks
+    // (lw_block_update): one logarithm per 32 steps instead of one per step
     double wprod = 1.0;
-    constexpr int kLogEvery = 32;
     double tau_left = pa.tau;
     int it = 0, since = 0;
     Local L;
@@ -865,11 +863,7 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
             if (!(den > 0)) { lw = -INFINITY; n_neg++; }
             else if (!(L.bbar > 0)) { lw = -INFINITY; n_nomove++; }
             else {
-                wprod *= L.bbar / den;
-                if (((it + 1) & (kLogEvery - 1)) == 0 || !(wprod > 0x1p-600 && wprod < 0x1p600)) {
-                    lw += log(wprod);
-                    wprod = 1.0;
-                }
+                lw_block_update(lw, wprod, L.bbar, den, it + 1);
             }
             q = heat_bath(s, w, lane_value(xmove, slot), L.inc, lane);
             if (tr && it < s.trace_cap && lane == 0) tr[it] = q;
@@ -916,7 +910,13 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
         for (int k = 0; k < 8; ++k) pa.timers[(long)wid * 8 + k] = sect[k];
 #endif
     lw += log(wprod);
-    if (pa.scheme == 0) L = evaluate(s, w, a, pa.nu_mode, lane);
+    if (pa.scheme == 0) {
+        L = evaluate(s, w, a, pa.nu_mode, lane);
+        // the estimator weight w / (W - E_0) at the final configuration needs
+        // W - E_0 > 0 as every step's factor does: otherwise the walker dies
+        if (pa.nproj > 0 && !(L.W - E0 > 0)) { lw = -INFINITY; n_neg++; }
+    }
+    const bool nonfinite = !(isfinite(L.eL) && isfinite(L.W)) || isnan(lw) || lw == INFINITY;
 
     for (int q = lane; q < 3 * s.N; q += kWave) s.pos[(long)wid * 3 * s.N + q] = lds[w.pos + q];
     if (lane == 0) {
@@ -932,6 +932,7 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
         if (n_small) atomicAdd(cn + kCntSmallR, n_small);
         if (n_sing) atomicAdd(cn + kCntSingular, n_sing);
         if (n_capped) atomicAdd(cn + kCntCapped, n_capped);
+        if (nonfinite) atomicAdd(cn + kCntNonfinite, 1ull);
         atomicMax(cn + kCntMaxIters, (unsigned long long)it);
         atomicMin(cn + kCntMinIters, (unsigned long long)it);
     }
@@ -956,14 +957,15 @@ __global__ __launch_bounds__(kMaxBranchBlock) void branch_scan(BranchView s, int
     int last = -1;
     for (int b = b0; b < b1; ++b) {
         const double v = s.lw[b];
-        if (v > mx) mx = v;
+        if (v > mx || isnan(v)) mx = isnan(mx) ? mx : v;   // a NaN log-weight propagates
         if (v > -INFINITY) last = b;
     }
     sh[t] = mx; shi[t] = last;
     __syncthreads();
     for (int o = nt / 2; o > 0; o >>= 1) {
         if (t < o) {
-            sh[t] = fmax(sh[t], sh[t + o]);
+            const double x = sh[t], y = sh[t + o];
+            sh[t] = (isnan(x) || isnan(y)) ? NAN : fmax(x, y);
             shi[t] = max(shi[t], shi[t + o]);
         }
         __syncthreads();
@@ -976,8 +978,11 @@ __global__ __launch_bounds__(kMaxBranchBlock) void branch_scan(BranchView s, int
         const double wv = exp(s.lw[b] - mx);
         loc += wv;
         cum[b] = loc;
-        const double om = scheme == 0 ? wv / (s.Wd[b] - E0) : wv;
-        if (om != 0.0) { se += om * s.eL[b]; so += om; }
+        if (wv > 0.0) {   // dead walkers (weight zero) carry no W - E_0 factor
+            const double om = scheme == 0 ? wv / (s.Wd[b] - E0) : wv;
+            se += om * s.eL[b];
+            so += om;
+        }
     }
     // exclusive scan of the per-thread totals (Hillis-Steele, fixed order)
     sh[t] = loc;
@@ -1057,16 +1062,23 @@ __global__ void branch_gather(BranchView s, const int32_t* sel, const double* po
 // After the gather: the walker-averaged local energy and log wbar of this
 // branching appended to the device history ring, and E_0 updated to the mean
 // of the last `window` e_bar (Algorithm 2).  A branching in which every
-// weight is zero appends nothing and is counted in *n_dead.  bump_j (non-null
-// for the last system of a handle) advances the branching index.
+// weight is zero appends nothing and is counted in n_dead[0]; one whose
+// largest log-weight, weight sum or walker average is not finite (a NaN or
+// +inf log-weight) appends nothing and is counted in n_dead[1].  bump_j
+// (non-null for the last system of a handle) advances the branching index.
 __global__ void branch_finish(int nw, const double* out, const int* n_distinct, double* hist,
                               long long* n_hist, double* e0p, int* n_dead, int window, int cap,
                               int* bump_j)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double mx = out[0], tot = out[1], se = out[2], so = out[3];
-    if (!(mx > -INFINITY) || !(tot > 0.0)) {
-        *n_dead += 1;
+    const bool all_dead = mx == -INFINITY;
+    const bool finite = isfinite(mx) && isfinite(tot) && tot > 0.0 && isfinite(se) &&
+                        isfinite(so) && so != 0.0 && isfinite(se / so);
+    if (all_dead) {
+        n_dead[0] += 1;
+    } else if (!finite) {
+        n_dead[1] += 1;
     } else {
         const long long n = *n_hist;
         double* e = hist + (n % cap) * kHistLen;

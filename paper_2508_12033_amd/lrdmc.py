@@ -22,7 +22,7 @@ PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16": MIXED_BF16}
 NU_OPT_OWN, NU_OPT_ANY, NU_MAX = 0, 1, 2
 
 ERRORS = {-1: "INVALID_ARG", -2: "HIP", -3: "WORKSPACE", -4: "SINGULAR", -5: "ALL_DEAD",
-          -6: "UNSUPPORTED"}
+          -6: "UNSUPPORTED", -7: "NONFINITE", -8: "NEG_WEIGHT", -9: "NO_MOVE"}
 
 
 class LrdmcError(RuntimeError):
@@ -45,7 +45,8 @@ class lrdmc_params(ct.Structure):
     _fields_ = [("scheme", ct.c_int32), ("precision", ct.c_int32), ("a", ct.c_double),
                 ("tau", ct.c_double), ("n_proj", ct.c_int32), ("seed", ct.c_uint64),
                 ("refresh_every", ct.c_int32), ("nu_opt_mode", ct.c_int32),
-                ("p_corr", ct.c_int32), ("e0_window", ct.c_int32), ("trace_cap", ct.c_int32)]
+                ("p_corr", ct.c_int32), ("e0_window", ct.c_int32), ("trace_cap", ct.c_int32),
+                ("strict", ct.c_int32)]
 
 
 class lrdmc_step_stats(ct.Structure):
@@ -53,7 +54,7 @@ class lrdmc_step_stats(ct.Structure):
                 ("min_iters", ct.c_int32), ("n_neg_weight", ct.c_int64),
                 ("n_no_move", ct.c_int64), ("n_refresh", ct.c_int64),
                 ("n_small_ratio", ct.c_int64), ("n_capped", ct.c_int64),
-                ("elapsed_ms", ct.c_double)]
+                ("n_nonfinite", ct.c_int64), ("elapsed_ms", ct.c_double)]
 
 
 class lrdmc_branch_stats(ct.Structure):
@@ -146,7 +147,8 @@ def _sys_struct(d, keep):
 
 
 def make_params(scheme="lb", a=0.2, tau=0.25, n_proj=300, seed=12033, refresh_every=None,
-                nu_opt_mode=NU_OPT_OWN, p_corr=10, e0_window=50, trace_cap=0, precision="fp64"):
+                nu_opt_mode=NU_OPT_OWN, p_corr=10, e0_window=50, trace_cap=0, precision="fp64",
+                strict=False):
     """precision: "fp64" (every step in FP64), "fp32" or "bf16" (mixed: the
     orbital product on FP32 or BF16 MFMA, FP32 rank-one updates, FP64
     accumulation and refreshes).
@@ -160,7 +162,7 @@ def make_params(scheme="lb", a=0.2, tau=0.25, n_proj=300, seed=12033, refresh_ev
         refresh_every = 128 if prec == PRECISIONS["fp64"] else 16
     return lrdmc_params(SCHEME_LB if scheme == "lb" else SCHEME_CONV, prec, float(a), float(tau),
                         int(n_proj), int(seed), int(refresh_every), int(nu_opt_mode), int(p_corr),
-                        int(e0_window), int(trace_cap))
+                        int(e0_window), int(trace_cap), 1 if strict else 0)
 
 
 def params_for(d, scheme="lb", **kw):

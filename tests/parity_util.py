@@ -73,9 +73,13 @@ def compare_phase(d, prm, scheme, j, E0, pos0, lw0, g, idx, nthreads=8, band=1e-
     return res
 
 
-def assert_phase_ok(res, lw_tol=TOL_LW):
+def assert_phase_ok(res, lw_tol=TOL_LW, max_adopted=0):
+    """FP64 bar.  max_adopted: decisions inside the 1e-12 band that the
+    oracle adopted from the GPU (expected count at the FP64 band: ~1e-10 per
+    decision, so none in any test here)."""
     c = res["cnt"]
     assert c["hard_mismatch"] == 0, res
+    assert c["ambig_adopted"] <= max_adopted, res
     assert c["singular"] == 0, res
     assert res["pos_equal"], res
     assert res["iters_equal"], res
