@@ -227,13 +227,19 @@ def one_electron_system(kind="gauss", n_walkers=256, a=0.4, seed=BASE_SEED + 8,
                         origin=(0.13, 0.07, 0.21)):
     """One electron around a bare proton.  kind='gauss': nodeless trial from
     two s Gaussians; kind='nodal': p_z trial (node on the plane z=0) from one
-    p_z Gaussian, which exercises the fixed-node terms.  Every walker starts
-    on the same lattice origin + a*Z^3, so that all walkers sample one lattice
-    Hamiltonian (used by the brute-force lowest-eigenvalue check)."""
+    p_z Gaussian, which exercises the fixed-node terms; kind='soft': the
+    nodeless trial around a softened core -2/sqrt(r^2 + 0.25) (a smooth
+    potential, so the lattice energy approaches the continuum one as a^2).
+    Every walker starts on the same lattice origin + a*Z^3, so that all walkers
+    sample one lattice Hamiltonian (used by the brute-force lowest-eigenvalue
+    check)."""
     rng = np.random.default_rng(seed)
     atom_pos = np.zeros((1, 3))
     o = np.asarray(origin, np.float64)
-    if kind == "gauss":
+    charge, core, rc = np.array([1.0]), np.array([BARE]), np.array([0.0])
+    if kind == "soft":
+        charge, core, rc = np.array([2.0]), np.array([SOFTCORE]), np.array([0.5])
+    if kind in ("gauss", "soft"):
         batom = np.array([0, 0]); btype = np.array([S, S])
         bexp = np.array([0.2, 1.2]); C = np.array([[0.6], [0.5]])
         g = 1.0 * rng.standard_normal((n_walkers, 1, 3))
@@ -244,8 +250,8 @@ def one_electron_system(kind="gauss", n_walkers=256, a=0.4, seed=BASE_SEED + 8,
         g[:, 0, 2] = np.abs(g[:, 0, 2]) + a      # start in the z>0 pocket
     init = o[None, None, :] + a * np.round(g / a)
     return _finish(dict(
-        name="one_e_" + kind, atom_pos=atom_pos, atom_charge=np.array([1.0]),
-        atom_core=np.array([BARE]), core_rc=np.array([0.0]),
+        name="one_e_" + kind, atom_pos=atom_pos, atom_charge=charge,
+        atom_core=core, core_rc=rc,
         atom_species=np.array([0]), basis_atom=batom, basis_type=btype,
         basis_exp=bexp, mo_coeff=C, n_up=1, n_dn=0,
         jastrow=np.zeros((3, 3)), init_pos=init, a=a,
