@@ -24,7 +24,8 @@
  *     stream.  A handle is not thread-safe.
  *   - Units: bohr and hartree.
  *   - Electrons 0..n_up-1 are spin up.  Lattice move p = (3 i + d) * 2 + s
- *     moves electron i by +a (s = 0) or -a (s = 1) along axis d (x, y, z).
+ *     moves electron i by +a (s = 0) or -a (s = 1) along versor d (the axis
+ *     x, y, z, or its randomly rotated image when lrdmc_params.rotate = 1).
  */
 #ifndef LRDMC_H
 #define LRDMC_H
@@ -141,6 +142,15 @@ typedef struct lrdmc_params {
                                 per branching, for the parity harness */
     int32_t strict;          /* 1: weight events are errors (LRDMC_ERR_NEG_WEIGHT,
                                 LRDMC_ERR_NO_MOVE) instead of a warning count */
+    int32_t rotate;          /* 1: randomized lattice (App. D: the versors of the
+                                discretized Laplacian rotate with random angles).
+                                Reading: each walker draws one uniformly random
+                                rotation R at the start of every projection phase
+                                from its own Philox stream (counter (slot, branching,
+                                attempt, 4)), and its 6N moves that phase are
+                                r_i +- a R e_d.  FP64 precision only; the adjoint pass
+                                (lrdmc_walker_derivs) then returns
+                                LRDMC_ERR_UNSUPPORTED.  0: fixed x, y, z axes */
 } lrdmc_params;
 
 /* ---- statistics returned to the caller --------------------------------- */
@@ -301,6 +311,36 @@ int lrdmc_set_walkers(struct lrdmc_handle *h, int isys, const double *pos, const
 /* Current E_0 of system isys; set_e0 overrides it (for the parity harness). */
 double lrdmc_get_e0(struct lrdmc_handle *h, int isys);
 int lrdmc_set_e0(struct lrdmc_handle *h, int isys, double e0);
+
+/* ---- reconfiguration of a population held by the caller --------------- */
+
+/* Device workspace bytes of lrdmc_reconfigure for nw walkers (0 and an error
+ * message for nw < 1): (nw rounded up to 32 + 16) doubles. */
+size_t lrdmc_reconfigure_workspace_bytes(int nw);
+
+/* The reconfiguration of Sec. II.A on device arrays owned by the caller,
+ * without a handle (for callers that keep their walkers themselves, e.g. one
+ * shard of a population): the inclusive FP64 prefix C of exp(lw - max lw) in
+ * walker order, the comb sel[alpha] = min{beta : C_beta > (xi + alpha) C_N / nw}
+ * with one Philox uniform xi = U(seed, sysid; slot 0, branching j, 0, comb),
+ * and the walker average of e_L with weights w (scheme LRDMC_SCHEME_CONV) or
+ * w / (W - E_0) (LRDMC_SCHEME_LB, Sec. II.C); walkers with lw = -inf are dead
+ * and never selected.  Arguments (all pointers device memory, caller-owned):
+ *   lw, eL [nw] (and W [nw] for LB; may be NULL for CONV) -- read only;
+ *   sel [nw] int32 -- written: parent index of each new walker;
+ *   out [8] doubles -- written: [0] log of the average weight
+ *     log(C_N / nw) + max lw, [1] walker-averaged e_L, [2] max lw, [3] number
+ *     of distinct parents, [4] status 0 ok, 1 every weight zero (sel then
+ *     all 0), 2 non-finite sums;
+ *   ws -- scratch of lrdmc_reconfigure_workspace_bytes(nw), 256-byte
+ *     aligned, overwritten.
+ * Enqueued on `stream` (hipStream_t) without synchronising and without
+ * allocating; captures into a HIP graph (no memset or copy nodes).  Returns
+ * LRDMC_ERR_INVALID_ARG / LRDMC_ERR_WORKSPACE for bad arguments before any
+ * device work, LRDMC_ERR_HIP if a launch fails. */
+int lrdmc_reconfigure(int scheme, int nw, const double *lw, const double *eL, const double *W,
+                      double e0, uint64_t seed, uint64_t sysid, int j, int32_t *sel,
+                      double *out, void *ws, size_t ws_bytes, void *stream);
 
 /* Branching index j used in the Philox counters of the next phase. */
 int lrdmc_get_branch_index(struct lrdmc_handle *h);

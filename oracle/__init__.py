@@ -29,7 +29,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "lrdmc_oracle.c")
 
-RNG_MOVE, RNG_PERSIST, RNG_COMB, RNG_INIT = 0, 1, 2, 3
+RNG_MOVE, RNG_PERSIST, RNG_COMB, RNG_INIT, RNG_ROTATE = 0, 1, 2, 3, 4
 CNT_NAMES = ["decisions", "ambig_adopted", "hard_mismatch", "node_ambig",
              "neg_weight", "no_move", "singular", "iters"]
 SC = dict(bbar=0, vsf=1, W=2, eL=3, eL_cont=4, vee=5, vii=6, logabs=7, sign=8,
@@ -41,8 +41,10 @@ def build(force=False):
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB
     tmp = LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
-                           "-Wno-unused-variable", SRC, "-o", tmp, "-lm", "-lpthread"])
+    # no fused multiply-add anywhere: every product and sum is rounded on its
+    # own, as the plain definitions are written
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+                           "-Wall", "-Wno-unused-variable", SRC, "-o", tmp, "-lm", "-lpthread"])
     os.replace(tmp, LIB)
     return LIB
 
@@ -59,7 +61,7 @@ class _Sys(ct.Structure):
 class _Prm(ct.Structure):
     _fields_ = [("a", ct.c_double), ("tau", ct.c_double), ("nproj", ct.c_int),
                 ("nu_opt_mode", ct.c_int), ("seed", ct.c_uint64),
-                ("sysid", ct.c_uint64), ("band", ct.c_double)]
+                ("sysid", ct.c_uint64), ("band", ct.c_double), ("rotate", ct.c_int)]
 
 
 _lib = None
@@ -75,6 +77,8 @@ def _configure(L):
     L.orc_jastrow.restype = dbl
     L.orc_log_psi.argtypes = [vp, vp, vp, vp]
     L.orc_eval.argtypes = [vp, vp, vp] + [vp] * 9
+    L.orc_eval_rot.argtypes = [vp, vp, vp, vp] + [vp] * 9
+    L.orc_rotation.argtypes = [u64, u64, u64, u64, vp]
     L.orc_lb_phase.argtypes = [vp, vp, u64, u64, dbl, vp, vp, vp, vp, vp, vp, vp]
     L.orc_conv_phase.argtypes = [vp, vp, u64, u64, vp, vp, vp, vp, vp, vp, i32, vp, vp]
     L.orc_comb.argtypes = [i32, vp, dbl, vp, vp, vp, dbl, vp]
@@ -97,8 +101,8 @@ def build_variant(src_text, path):
     c = path + ".c"
     with open(c, "w") as f:
         f.write(src_text)
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-w", c, "-o", path,
-                           "-lm", "-lpthread"])
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-w",
+                           c, "-o", path, "-lm", "-lpthread"])
     return path
 
 
@@ -142,14 +146,14 @@ class System:
         self.P = 6 * self.N
 
     def params(self, a=None, tau=None, nproj=None, nu_opt_mode=None, seed=None,
-               sysid=None, band=1e-12):
+               sysid=None, band=1e-12, rotate=False):
         d = self.d
         if nu_opt_mode is None:
             nu_opt_mode = int(d.get("nu_opt_mode", 0))
         return _Prm(d["a"] if a is None else a, d["tau"] if tau is None else tau,
                     d["n_proj"] if nproj is None else nproj, nu_opt_mode,
                     d["seed"] if seed is None else seed,
-                    d["system_id"] if sysid is None else sysid, band)
+                    d["system_id"] if sysid is None else sysid, band, 1 if rotate else 0)
 
 
 def philox(ctr, key):
@@ -185,18 +189,28 @@ def log_psi(sys, pos):
     return la[0], sg[0]
 
 
-def evaluate(sys, prm, pos):
-    """All per-configuration quantities at one configuration (dict)."""
+def rotation(seed, sysid, slot, j):
+    """Random lattice rotation R[x][d] (versor d = column d) of walker slot
+    `slot` for the phase after branching j."""
+    R = np.zeros(9)
+    lib().orc_rotation(seed, sysid, slot, j, R.ctypes.data)
+    return R.reshape(3, 3)
+
+
+def evaluate(sys, prm, pos, rot=None):
+    """All per-configuration quantities at one configuration (dict); rot:
+    lattice rotation R[x][d] (None: fixed axes)."""
     N, P = sys.N, sys.P
     pos = np.ascontiguousarray(pos, np.float64).reshape(N, 3)
     out = dict(R=np.zeros(P), Rdet=np.zeros(P), dJ=np.zeros(P), lap=np.zeros(N),
                grad=np.zeros((N, 3)), nu_zv=np.zeros(N), nu_opt=np.zeros(N),
                node=np.zeros(N, np.int32))
     sc = np.zeros(16)
-    rc = lib().orc_eval(ct.byref(sys.c), ct.byref(prm), pos.ctypes.data,
-                        *[out[k].ctypes.data for k in ("R", "Rdet", "dJ", "lap", "grad",
-                                                       "nu_zv", "nu_opt", "node")],
-                        sc.ctypes.data)
+    rm = None if rot is None else np.ascontiguousarray(rot, np.float64).reshape(9)
+    rc = lib().orc_eval_rot(ct.byref(sys.c), ct.byref(prm), _p(rm), pos.ctypes.data,
+                            *[out[k].ctypes.data for k in ("R", "Rdet", "dJ", "lap", "grad",
+                                                           "nu_zv", "nu_opt", "node")],
+                            sc.ctypes.data)
     if rc:
         raise ArithmeticError("singular Slater matrix")
     for k, i in SC.items():
@@ -288,10 +302,10 @@ def energy_estimate(log_wbar, e_bar, p=10, n_therm=None, block=None):
 
 
 def run(sysd, scheme, n_branch, nproj=None, tau=None, nthreads=None, nu_opt_mode=None,
-        p=10, walkers=None, a=None, block=None):
+        p=10, walkers=None, a=None, block=None, rotate=False):
     """Full oracle LRDMC run for a population: returns dict with history."""
     sys = System(sysd)
-    prm = sys.params(nproj=nproj, tau=tau, nu_opt_mode=nu_opt_mode, a=a)
+    prm = sys.params(nproj=nproj, tau=tau, nu_opt_mode=nu_opt_mode, a=a, rotate=rotate)
     pos = np.array(sysd["init_pos"] if walkers is None else walkers, np.float64, copy=True)
     nw = pos.shape[0]
     lw = np.zeros(nw)

@@ -54,9 +54,12 @@ typedef struct {
                           1: node test on any proposal, 2: nu_max always */
     uint64_t seed, sysid;
     double band;       /* relative width of the ambiguity band (1e-12) */
+    int rotate;        /* 1: every walker's three lattice versors are rotated by a
+                          random rotation drawn at the start of each projection
+                          phase (App. D randomized lattice); 0: fixed x, y, z */
 } orc_params;
 
-enum { RNG_MOVE = 0, RNG_PERSIST = 1, RNG_COMB = 2, RNG_INIT = 3 };
+enum { RNG_MOVE = 0, RNG_PERSIST = 1, RNG_COMB = 2, RNG_INIT = 3, RNG_ROTATE = 4 };
 
 /* counters returned by the phase drivers */
 enum {
@@ -93,6 +96,65 @@ double orc_uniform(uint64_t seed, uint64_t sysid, uint64_t slot, uint64_t j,
     uint64_t ctr[4] = {slot, j, k, purpose}, key[2] = {seed, sysid}, out[4];
     orc_philox4x64_10(ctr, key, out);
     return (double)(out[0] >> 11) * 0x1.0p-53;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Random lattice orientation (App. D: the three versors of the discretized  */
+/* Laplacian rotate with random angles along the simulation)                */
+/* ------------------------------------------------------------------------ */
+/* Rotation matrix R[x][d] (row-major 3x3; versor d is column d) of walker
+ * slot `slot` for the projection phase after branching j.  A uniformly random
+ * rotation is the rotation of a uniformly random unit quaternion; a point
+ * uniform in the unit 4-ball has a uniformly random direction, so q = 2U - 1
+ * componentwise (the four words of one Philox call with counter (slot, j,
+ * attempt, ROTATE)) is accepted once 1e-3 <= |q|^2 <= 1, attempts 0..63
+ * (identity if all are rejected, probability 0.69^64).  R is the textbook
+ * rotation matrix of q divided by |q|^2; every sum and product is rounded on
+ * its own, in the order written (no fused operations), so that another
+ * implementation that evaluates the same expressions in the same order gets
+ * the same bits. */
+void orc_rotation(uint64_t seed, uint64_t sysid, uint64_t slot, uint64_t j, double R[9])
+{
+    for (uint64_t k = 0; k < 64; k++) {
+        uint64_t ctr[4] = {slot, j, k, RNG_ROTATE}, key[2] = {seed, sysid}, out[4];
+        orc_philox4x64_10(ctr, key, out);
+        double q[4];
+        for (int m = 0; m < 4; m++) q[m] = 2.0 * ((double)(out[m] >> 11) * 0x1.0p-53) - 1.0;
+        double w = q[0], x = q[1], y = q[2], z = q[3];
+        double ww = w * w, xx = x * x, yy = y * y, zz = z * z;
+        double n = ((ww + xx) + yy) + zz;
+        if (!(n <= 1.0 && n >= 1e-3)) continue;
+        double xy = x * y, xz = x * z, yz = y * z, wx = w * x, wy = w * y, wz = w * z;
+        R[0] = (((ww + xx) - yy) - zz) / n;
+        R[1] = (2.0 * (xy - wz)) / n;
+        R[2] = (2.0 * (xz + wy)) / n;
+        R[3] = (2.0 * (xy + wz)) / n;
+        R[4] = (((ww - xx) + yy) - zz) / n;
+        R[5] = (2.0 * (yz - wx)) / n;
+        R[6] = (2.0 * (xz - wy)) / n;
+        R[7] = (2.0 * (yz + wx)) / n;
+        R[8] = (((ww - xx) - yy) + zz) / n;
+        return;
+    }
+    for (int m = 0; m < 9; m++) R[m] = (m % 4 == 0) ? 1.0 : 0.0;
+}
+
+/* Lattice step vectors st[d][x] = a * R[x][d] (each product rounded once);
+ * R == NULL gives the fixed axes (a on the diagonal, zeros elsewhere). */
+static void lattice_steps(const double *R, double a, double st[3][3])
+{
+    for (int d = 0; d < 3; d++)
+        for (int x = 0; x < 3; x++)
+            st[d][x] = R ? a * R[3 * x + d] : (x == d ? a : 0.0);
+}
+
+/* Proposal q (0..5 = +d0, -d0, +d1, -d1, +d2, -d2) of a point r: every
+ * coordinate moved by one addition of the signed step vector (with fixed
+ * axes the other two coordinates add zero and stay as they were). */
+static void displaced(const double r[3], const double st[3][3], int q, double out[3])
+{
+    int d = q / 2, sg = q % 2;
+    for (int x = 0; x < 3; x++) out[x] = r[x] + (sg ? -st[d][x] : st[d][x]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -342,12 +404,14 @@ enum {
  *   scal[SC_LEN]: bbar, V_sf, W, e_L, e_L(continuum), V_ee, V_ii, log|Psi|,
  *                 sign, min |R_p| / max |R_p|
  * Returns 0, or -1 for a singular Slater matrix. */
-int orc_eval(const orc_system *s, const orc_params *prm, const double *pos,
-             double *R, double *Rdet, double *dJ, double *lap, double *grad,
-             double *nu_zv, double *nu_opt, int32_t *node, double *scal)
+int orc_eval_rot(const orc_system *s, const orc_params *prm, const double *rot,
+                 const double *pos, double *R, double *Rdet, double *dJ, double *lap,
+                 double *grad, double *nu_zv, double *nu_opt, int32_t *node, double *scal)
 {
     const int N = s->Nup + s->Ndn, P = 6 * N, Nb = s->Nb;
     const double a = prm->a;
+    double st[3][3];
+    lattice_steps(rot, a, st);
     int ns[2] = {s->Nup, s->Ndn}, off[2] = {0, s->Nup};
     double *Ainv[2] = {0, 0};
     double logabs = 0.0, sign = 1.0;
@@ -386,8 +450,8 @@ int orc_eval(const orc_system *s, const orc_params *prm, const double *pos,
         for (int d = 0; d < 3; d++)
             for (int sg = 0; sg < 2; sg++) {
                 int p = (3 * i + d) * 2 + sg;
-                double r[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
-                r[d] = r[d] + (sg ? -a : a);
+                double r[3];
+                displaced(pos + 3 * i, st, 2 * d + sg, r);
                 orc_basis(s, r, chi, 0, 0);
                 orbitals(s, chi, n, phi);
                 double rd = 0.0;   /* det(A with row c -> phi(r'))/det(A) = phi . Ainv[:,c] */
@@ -481,6 +545,14 @@ done:
     return rc;
 }
 
+/* orc_eval_rot with the fixed lattice axes */
+int orc_eval(const orc_system *s, const orc_params *prm, const double *pos,
+             double *R, double *Rdet, double *dJ, double *lap, double *grad,
+             double *nu_zv, double *nu_opt, int32_t *node, double *scal)
+{
+    return orc_eval_rot(s, prm, 0, pos, R, Rdet, dJ, lap, grad, nu_zv, nu_opt, node, scal);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Heat-bath choice among the 6N moves, p_{x',x} of the load-balanced split  */
 /* (Sec. II.C) and of Algorithm 1's move line                                */
@@ -522,10 +594,13 @@ static int choice_within_band(int P, const double *R, double xi, int q, double b
     return (t >= lo - band * tot) && (t < hi + band * tot);
 }
 
-static void apply_move(double *pos, int p, double a)
+static void apply_move(double *pos, int p, const double *rot, double a)
 {
-    int i = p / 6, d = (p / 2) % 3, sg = p % 2;
-    pos[3 * i + d] = pos[3 * i + d] + (sg ? -a : a);
+    double st[3][3], r[3];
+    lattice_steps(rot, a, st);
+    int i = p / 6;
+    displaced(pos + 3 * i, st, p % 6, r);
+    for (int x = 0; x < 3; x++) pos[3 * i + x] = r[x];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -543,10 +618,12 @@ int orc_lb_phase(const orc_system *s, const orc_params *prm, uint64_t slot, uint
 {
     const int N = s->Nup + s->Ndn, P = 6 * N;
     double *R = (double *)malloc(sizeof(double) * P);
-    double sc[SC_LEN];
+    double sc[SC_LEN], rotm[9];
+    const double *rot = 0;
+    if (prm->rotate) { orc_rotation(prm->seed, prm->sysid, slot, j, rotm); rot = rotm; }
     int rc = 0;
     for (int k = 0; k < prm->nproj; k++) {
-        if (orc_eval(s, prm, pos, R, 0, 0, 0, 0, 0, 0, 0, sc)) { cnt[CNT_SINGULAR]++; rc = -1; break; }
+        if (orc_eval_rot(s, prm, rot, pos, R, 0, 0, 0, 0, 0, 0, 0, sc)) { cnt[CNT_SINGULAR]++; rc = -1; break; }
         if (sc[SC_MINREL] <= prm->band) cnt[CNT_NODE_AMBIG]++;
         double bbar = sc[SC_BBAR], W = sc[SC_W];
         if (!(W - E0 > 0)) { cnt[CNT_NEG_WEIGHT]++; *lw = -INFINITY; }
@@ -564,10 +641,10 @@ int orc_lb_phase(const orc_system *s, const orc_params *prm, uint64_t slot, uint
             q = follow[k];
         }
         if (moves_out) moves_out[k] = q;
-        if (q >= 0) apply_move(pos, q, prm->a);
+        if (q >= 0) apply_move(pos, q, rot, prm->a);
     }
     if (!rc) {
-        if (orc_eval(s, prm, pos, 0, 0, 0, 0, 0, 0, 0, 0, sc)) { cnt[CNT_SINGULAR]++; rc = -1; }
+        if (orc_eval_rot(s, prm, rot, pos, 0, 0, 0, 0, 0, 0, 0, 0, sc)) { cnt[CNT_SINGULAR]++; rc = -1; }
         else {
             *eL_out = sc[SC_EL]; *W_out = sc[SC_W];
             /* Sec. II.C: the walker average weights w by 1/(W - E_0) at the
@@ -595,11 +672,13 @@ int orc_conv_phase(const orc_system *s, const orc_params *prm, uint64_t slot, ui
 {
     const int N = s->Nup + s->Ndn, P = 6 * N;
     double *R = (double *)malloc(sizeof(double) * P);
-    double sc[SC_LEN];
+    double sc[SC_LEN], rotm[9];
+    const double *rot = 0;
+    if (prm->rotate) { orc_rotation(prm->seed, prm->sysid, slot, j, rotm); rot = rotm; }
     double tau_left = prm->tau;
     int it = 0, rc = 0;
     for (;;) {
-        if (orc_eval(s, prm, pos, R, 0, 0, 0, 0, 0, 0, 0, sc)) { cnt[CNT_SINGULAR]++; rc = -1; break; }
+        if (orc_eval_rot(s, prm, rot, pos, R, 0, 0, 0, 0, 0, 0, 0, sc)) { cnt[CNT_SINGULAR]++; rc = -1; break; }
         if (sc[SC_MINREL] <= prm->band) cnt[CNT_NODE_AMBIG]++;
         double bbar = sc[SC_BBAR], eL = sc[SC_EL];
         double xt = orc_uniform(prm->seed, prm->sysid, slot, j, (uint64_t)it, RNG_PERSIST);
@@ -633,7 +712,7 @@ int orc_conv_phase(const orc_system *s, const orc_params *prm, uint64_t slot, ui
             q = follow[it - 1];
         }
         if (moves_out && it - 1 < cap) moves_out[it - 1] = q;
-        if (q >= 0) apply_move(pos, q, prm->a);
+        if (q >= 0) apply_move(pos, q, rot, prm->a);
     }
     *n_iter = it;
     cnt[CNT_ITERS] += it;

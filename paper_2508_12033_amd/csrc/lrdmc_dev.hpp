@@ -46,7 +46,7 @@ struct DevSys {
     int ldb;                 // row stride (doubles) of the basis block: Nb padded to 4 mod 16
                              // so that the 16 rows of an MFMA operand read fall in distinct banks
     int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje,
-        o_scal, o_B, o_rows, o_tmp, o_C, o_nuc, o_jas, o_gd, lds_doubles;
+        o_scal, o_B, o_rows, o_tmp, o_C, o_nuc, o_jas, o_gd, o_ev, lds_doubles;
     // spill layout (offsets in doubles inside a walker's spill block)
     int s_Phi, s_dPhi;
 };
@@ -61,6 +61,7 @@ struct PhaseArgs {
     int refresh_every;
     int nu_mode;
     int conv_cap;            // hard bound on conventional iterations per phase
+    int rotate;              // 1: random lattice orientation per walker and phase
     double a, tau;
     uint64_t seed;
     unsigned long long *counters;   // [kCntLen]

@@ -82,6 +82,87 @@ __device__ __forceinline__ double philox_uniform(uint64_t k0, uint64_t k1, uint6
     return (double)(c0 >> 11) * 0x1.0p-53;
 }
 
+// All four output words of one Philox4x64-10 evaluation.
+__device__ __forceinline__ void philox4(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1,
+                                        uint64_t c2, uint64_t c3, uint64_t out[4])
+{
+    const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
+    const uint64_t w0 = 0x9E3779B97F4A7C15ull, w1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += w0; k1 += w1; }
+        const uint64_t h0 = __umul64hi(m0, c0), l0 = m0 * c0;
+        const uint64_t h1 = __umul64hi(m1, c2), l1 = m1 * c2;
+        const uint64_t n0 = h1 ^ c1 ^ k0, n2 = h0 ^ c3 ^ k1;
+        c0 = n0; c1 = l1; c2 = n2; c3 = l0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// Random lattice orientation of one walker for one projection phase (App. D:
+// the versors of the discretized Laplacian rotate with random angles).  A
+// uniformly random rotation is that of a uniformly random unit quaternion; a
+// point uniform in the unit 4-ball has a uniform direction, so q = 2U - 1 per
+// component (the four words of Philox counter (slot, j, attempt, 4)) is
+// accepted once 1e-3 <= |q|^2 <= 1, for attempts 0..63 (identity if all fail).
+// Lattice step vectors st[3 d + x] = a R[x][d], R the quaternion rotation
+// matrix divided by |q|^2.  Every operation is rounded on its own in the order
+// written (no contraction into fused multiply-adds), so the steps, and the
+// positions they move, are reproducible bit for bit by any implementation that
+// evaluates the same expressions in the same order.
+__device__ __forceinline__ void lattice_steps(uint64_t seed, uint64_t sysid, uint64_t slot, uint64_t j,
+                                           double a, double* st)
+{
+#pragma clang fp contract(off)
+    double R[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+    for (uint64_t k = 0; k < 64; ++k) {
+        uint64_t o[4];
+        philox4(seed, sysid, slot, j, k, 4, o);
+        const double w = 2.0 * ((double)(o[0] >> 11) * 0x1.0p-53) - 1.0;
+        const double x = 2.0 * ((double)(o[1] >> 11) * 0x1.0p-53) - 1.0;
+        const double y = 2.0 * ((double)(o[2] >> 11) * 0x1.0p-53) - 1.0;
+        const double z = 2.0 * ((double)(o[3] >> 11) * 0x1.0p-53) - 1.0;
+        const double ww = w * w, xx = x * x, yy = y * y, zz = z * z;
+        const double n = ((ww + xx) + yy) + zz;
+        if (!(n <= 1.0 && n >= 1e-3)) continue;
+        const double xy = x * y, xz = x * z, yz = y * z, wx = w * x, wy = w * y, wz = w * z;
+        R[0] = (((ww + xx) - yy) - zz) / n;
+        R[1] = (2.0 * (xy - wz)) / n;
+        R[2] = (2.0 * (xz + wy)) / n;
+        R[3] = (2.0 * (xy + wz)) / n;
+        R[4] = (((ww - xx) + yy) - zz) / n;
+        R[5] = (2.0 * (yz - wx)) / n;
+        R[6] = (2.0 * (xz - wy)) / n;
+        R[7] = (2.0 * (yz + wx)) / n;
+        R[8] = (((ww - xx) - yy) + zz) / n;
+        break;
+    }
+    for (int d = 0; d < 3; ++d)
+        for (int x = 0; x < 3; ++x) st[3 * d + x] = a * R[3 * x + d];
+}
+
+// Fixed lattice axes: st = a on the diagonal.
+__device__ __forceinline__ void lattice_steps_fixed(double a, double* st)
+{
+    for (int q = 0; q < 9; ++q) st[q] = (q % 4 == 0) ? a : 0.0;
+}
+
+// Point q of electron position r: r itself (q = 0) or its lattice neighbour
+// q = 1..6 in move order (+d0, -d0, +d1, -d1, +d2, -d2) with the step vectors
+// st[3 d + x]: every coordinate moved by one addition of the signed step
+// (the same additions as the move itself; with fixed axes two of them add 0).
+__device__ __forceinline__ void point_qv(const double* r, int q, const double* st, double* o)
+{
+    if (q == 0) { o[0] = r[0]; o[1] = r[1]; o[2] = r[2]; return; }
+    const int d = (q - 1) >> 1;
+    const bool neg = ((q - 1) & 1) != 0;
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        const double v = st[3 * d + x];
+        o[x] = r[x] + (neg ? -v : v);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // wavefront collectives on DPP (data-parallel primitives: lane shuffles that
 // run in the VALU, no LDS round trip).  A double moves as two 32-bit halves.

@@ -23,7 +23,10 @@
 #include "lrdmc_dev.hpp"
 
 namespace lrdmc {
+template <bool kRot>
 __global__ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa);
+extern template __global__ void phase_fp64<false>(const DevSys* __restrict__ sys, PhaseArgs pa);
+extern template __global__ void phase_fp64<true>(const DevSys* __restrict__ sys, PhaseArgs pa);
 __global__ void phase_mixed(MixBatch b, PhaseArgs pa, int build);
 __global__ void branch_scan(BranchView s, int scheme, double* cum, double* out, int* n_distinct);
 __global__ void branch_comb(BranchView s, uint64_t seed, const double* cum, const double* out,
@@ -42,6 +45,34 @@ __global__ void walker_derivs(const DevAdj* __restrict__ sys);
 __global__ void derivs_reduce(int nw, int nth, int scheme, const double* lw, const double* Wd,
                               const double* e0p, const double* eL, const double* deL,
                               const double* dlp, double* out);
+
+// E_0 and the branching index of a caller-held reconfiguration, written by a
+// kernel so that the whole sequence can be captured in a graph
+__global__ void reconf_setup(double* ctl, double e0, int j)
+{
+    if (threadIdx.x == 0) {
+        ctl[0] = e0;
+        *reinterpret_cast<int*>(ctl + 1) = j;
+        *reinterpret_cast<int*>(ctl + 2) = 0;
+    }
+}
+
+// out[0] log wbar = log(C_N / N_w) + max lw, out[1] walker-averaged e_L,
+// out[2] max lw, out[3] distinct parents, out[4] status: 0 ok, 1 every weight
+// zero, 2 non-finite sums (a NaN or +inf log-weight, or W - E_0 = 0)
+__global__ void reconf_finish(int nw, const double* bout, const int* ndist, double* out)
+{
+    if (threadIdx.x != 0) return;
+    const double mx = bout[0], tot = bout[1], se = bout[2], so = bout[3];
+    const bool all_dead = mx == -INFINITY;
+    const bool finite = isfinite(mx) && isfinite(tot) && tot > 0.0 && isfinite(se) &&
+                        isfinite(so) && so != 0.0 && isfinite(se / so);
+    out[0] = finite ? log(tot / (double)nw) + mx : NAN;
+    out[1] = finite ? se / so : NAN;
+    out[2] = mx;
+    out[3] = (double)*ndist;
+    out[4] = all_dead ? 1.0 : (finite ? 0.0 : 2.0);
+}
 }  // namespace lrdmc
 
 using namespace lrdmc;
@@ -76,7 +107,7 @@ struct Layout {
     // FP64 kernel: LDS offsets (doubles), spill layout
     int ldb;
     int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje, o_scal, o_B,
-        o_rows, o_tmp, o_C, o_nuc, o_jas, o_gd, lds_doubles;
+        o_rows, o_tmp, o_C, o_nuc, o_jas, o_gd, o_ev, lds_doubles;
     int s_Phi, s_dPhi;
     long spill_stride;
     // mixed kernel: LDS byte offsets, walker block (floats)
@@ -138,6 +169,7 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.o_nuc = take(kNucLen * M);
         L.o_jas = take(3 * (2 + s.n_species));
         L.o_gd = take(4 * N);
+        L.o_ev = take(9);
         L.lds_doubles = o;
         L.lds_bytes = (size_t)o * 8;
         L.s_Phi = 0;
@@ -227,6 +259,10 @@ std::string validate(const lrdmc_system* sys, int n_sys, const lrdmc_params* prm
     if (prm->refresh_every < 1) return "refresh_every must be >= 1";
     if (prm->nu_opt_mode < 0 || prm->nu_opt_mode > 2) return "bad nu_opt_mode";
     if (prm->trace_cap < 0) return "bad trace_cap";
+    if (prm->strict != 0 && prm->strict != 1) return "strict must be 0 or 1";
+    if (prm->rotate != 0 && prm->rotate != 1) return "rotate must be 0 or 1";
+    if (prm->rotate && prm->precision != LRDMC_FP64)
+        return "random lattice orientation: not supported by the mixed-precision kernel";
     if (prm->e0_window < 0 || prm->e0_window > kHistCap) return "e0_window out of range";
     if (n_sys > kMaxBatch) return "at most 8 systems per handle";
     for (int k = 0; k < n_sys; ++k) {
@@ -399,6 +435,7 @@ PhaseArgs phase_args(const lrdmc_handle* h, int N, int nproj_override)
     pa.refresh_every = h->prm.refresh_every;
     pa.nu_mode = h->prm.nu_opt_mode;
     pa.conv_cap = conv_cap(h->prm, N);
+    pa.rotate = h->prm.rotate;
     pa.a = h->prm.a;
     pa.tau = h->prm.tau;
     pa.seed = h->prm.seed;
@@ -417,7 +454,8 @@ int launch_phases(lrdmc_handle* h, hipStream_t st, int p, int nproj_override, bo
     for (auto& r : h->sys) {
         if (r.kind != kKindLds) continue;
         const PhaseArgs pa = phase_args(h, r.N, nproj_override);
-        hipLaunchKernelGGL(phase_fp64, dim3(r.nw), dim3(kWave), r.L.lds_bytes, st,
+        hipLaunchKernelGGL(pa.rotate ? phase_fp64<true> : phase_fp64<false>, dim3(r.nw), dim3(kWave),
+                           r.L.lds_bytes, st,
                            (const DevSys*)r.dsys[p], pa);
         HIPCHK(hipGetLastError());
     }
@@ -591,6 +629,57 @@ void fill_branch_stats(const lrdmc_handle* h, lrdmc_branch_stats* st, float ms)
     st->n_distinct = (int)r.hist_nd[n - 1];
 }
 
+// ---------------------------------------------------------------------------
+// Reconfiguration of a caller-held population (lrdmc_reconfigure): the comb
+// kernels of lrdmc_branch on device arrays passed by the caller, with their
+// prefix sums and sums in a scratch block of reconf_scratch_doubles(nw)
+// doubles: cum [nw] (padded to 32), the scan results [8], then E_0, the
+// branching index and the distinct-parent count.
+// ---------------------------------------------------------------------------
+long reconf_scratch_doubles(int nw) { return ((long)nw + 31) / 32 * 32 + 16; }
+
+int check_reconf_args(int scheme, int nw, const double* lw, const double* eL, const double* W,
+                      const int32_t* sel, const double* out)
+{
+    if (scheme != LRDMC_SCHEME_LB && scheme != LRDMC_SCHEME_CONV)
+        return fail(LRDMC_ERR_INVALID_ARG, "scheme must be LRDMC_SCHEME_LB or LRDMC_SCHEME_CONV");
+    if (nw < 1) return fail(LRDMC_ERR_INVALID_ARG, "nw must be positive");
+    if (!lw || !eL || !sel || !out || (scheme == LRDMC_SCHEME_LB && !W))
+        return fail(LRDMC_ERR_INVALID_ARG, "null device pointer");
+    return LRDMC_OK;
+}
+
+int enqueue_reconfigure(int scheme, int nw, const double* lw, const double* eL, const double* W,
+                        double e0, uint64_t seed, uint64_t sysid, int j, int32_t* sel, double* out,
+                        double* scr, hipStream_t st)
+{
+    double* cum = scr;
+    double* bout = scr + (reconf_scratch_doubles(nw) - 16);
+    double* ctl = bout + 8;
+    int* jp = reinterpret_cast<int*>(ctl + 1);
+    int* ndist = reinterpret_cast<int*>(ctl + 2);
+    BranchView bv{};
+    bv.nw = nw; bv.N = 0; bv.sysid = sysid;
+    bv.pos = nullptr; bv.lw = const_cast<double*>(lw); bv.eL = const_cast<double*>(eL);
+    bv.Wd = const_cast<double*>(W ? W : eL);
+    bv.jp = jp; bv.e0p = ctl;
+    hipLaunchKernelGGL(reconf_setup, dim3(1), dim3(64), 0, st, ctl, e0, j);
+    HIPCHK(hipGetLastError());
+    const int nt = std::min(kMaxBranchBlock, std::max(64, 1 << (int)std::ceil(std::log2((double)nw))));
+    hipLaunchKernelGGL(branch_scan, dim3(1), dim3(nt), 0, st, bv, scheme, cum, bout, ndist);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(branch_comb, dim3((nw + 255) / 256), dim3(256), 0, st, bv, seed,
+                       (const double*)cum, (const double*)bout, sel);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(branch_count, dim3((nw + 255) / 256), dim3(256), 0, st, (const int32_t*)sel, nw,
+                       ndist);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(reconf_finish, dim3(1), dim3(64), 0, st, nw, (const double*)bout,
+                       (const int*)ndist, out);
+    HIPCHK(hipGetLastError());
+    return LRDMC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -619,7 +708,9 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
     if (!out) return fail(LRDMC_ERR_INVALID_ARG, "null handle pointer");
     *out = nullptr;
     const std::string v = validate(sys, n_sys, prm);
-    if (!v.empty()) return fail(v.find("too large") != std::string::npos ? LRDMC_ERR_UNSUPPORTED
+    if (!v.empty()) return fail(v.find("too large") != std::string::npos ||
+                                        v.find("not supported") != std::string::npos
+                                    ? LRDMC_ERR_UNSUPPORTED
                                                                            : LRDMC_ERR_INVALID_ARG,
                                 v);
     if (!init_pos) return fail(LRDMC_ERR_INVALID_ARG, "null init_pos");
@@ -818,7 +909,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             d.o_Arow = L.o_Arow; d.o_AinvT = L.o_AinvT; d.o_Jg = L.o_Jg; d.o_Jl = L.o_Jl;
             d.o_nue = L.o_nue; d.o_nua = L.o_nua; d.o_dje = L.o_dje; d.o_scal = L.o_scal;
             d.ldb = L.ldb; d.o_B = L.o_B; d.o_rows = L.o_rows; d.o_tmp = L.o_tmp; d.o_C = L.o_C;
-            d.bK = bK; d.o_nuc = L.o_nuc; d.o_jas = L.o_jas; d.o_gd = L.o_gd;
+            d.bK = bK; d.o_nuc = L.o_nuc; d.o_jas = L.o_jas; d.o_gd = L.o_gd; d.o_ev = L.o_ev;
             d.lds_doubles = L.lds_doubles;
             d.s_Phi = L.s_Phi; d.s_dPhi = L.s_dPhi;
             for (int p = 0; p < 2; ++p) {
@@ -890,7 +981,10 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
     if (rc == LRDMC_OK) {
         // allow each phase kernel the LDS that its static allocation leaves free
         for (int kind = 0; kind < 2 && !rc; ++kind) {
-            const void* fn = kind == kKindLds ? (const void*)phase_fp64 : (const void*)phase_mixed;
+            const void* fn = kind == kKindLds
+                                 ? (h->prm.rotate ? (const void*)phase_fp64<true>
+                                                  : (const void*)phase_fp64<false>)
+                                 : (const void*)phase_mixed;
             size_t need_lds = 0;
             for (auto& r : h->sys) if (r.kind == kind) need_lds = std::max(need_lds, r.L.lds_bytes);
             if (!need_lds) continue;
@@ -1222,6 +1316,8 @@ static int run_derivs(lrdmc_handle* h, int isys, const double* theta, double* eL
 {
     SysRun& r = h->sys[isys];
     const Layout& L = r.L;
+    if (h->prm.rotate)
+        return fail(LRDMC_ERR_UNSUPPORTED, "the adjoint pass evaluates the fixed lattice axes only");
     const size_t lds = (size_t)L.a_doubles * 8;
     hipFuncAttributes fa;
     HIPCHK(hipFuncGetAttributes(&fa, (const void*)walker_derivs));
@@ -1342,6 +1438,27 @@ int lrdmc_set_e0(lrdmc_handle* h, int isys, double e0)
 }
 
 int lrdmc_get_branch_index(lrdmc_handle* h) { return h ? h->j : -1; }
+
+size_t lrdmc_reconfigure_workspace_bytes(int nw)
+{
+    if (nw < 1) { (void)fail(LRDMC_ERR_INVALID_ARG, "nw must be positive"); return 0; }
+    return (size_t)reconf_scratch_doubles(nw) * 8;
+}
+
+int lrdmc_reconfigure(int scheme, int nw, const double* lw, const double* eL, const double* W,
+                      double e0, uint64_t seed, uint64_t sysid, int j, int32_t* sel, double* out,
+                      void* ws, size_t ws_bytes, void* stream)
+{
+    int rc = check_reconf_args(scheme, nw, lw, eL, W, sel, out);
+    if (rc) return rc;
+    if (!ws) return fail(LRDMC_ERR_INVALID_ARG, "null workspace");
+    if (ws_bytes < (size_t)reconf_scratch_doubles(nw) * 8)
+        return fail(LRDMC_ERR_WORKSPACE, "workspace smaller than lrdmc_reconfigure_workspace_bytes");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(LRDMC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    return enqueue_reconfigure(scheme, nw, lw, eL, W, e0, seed, sysid, j, sel, out,
+                               static_cast<double*>(ws), (hipStream_t)stream);
+}
+
 
 void lrdmc_destroy(lrdmc_handle* h)
 {

@@ -63,7 +63,7 @@ extern __shared__ double lds[];
 constexpr int kPre = 8;
 
 struct Walker {
-    int pos, R, Rdet, dJ, Arow, AinvT, Jg, Jl, nue, nua, dje, scal, B, rows, tmp, C, nuc, jas, gd;
+    int pos, R, Rdet, dJ, Arow, AinvT, Jg, Jl, nue, nua, dje, scal, B, rows, tmp, C, nuc, jas, gd, ev;
     double* Phi;
     double* dPhi;
 };
@@ -78,6 +78,7 @@ __device__ __forceinline__ Walker walker_view(const DevSys& s)
     w.nuc = s.o_nuc;
     w.jas = s.o_jas;
     w.gd = s.o_gd;
+    w.ev = s.o_ev;
     double* base = s.spill + (long)blockIdx.x * s.spill_stride;
     w.Phi = base + s.s_Phi;
     w.dPhi = base + s.s_dPhi;
@@ -145,22 +146,35 @@ __device__ __forceinline__ void nucleus_potential(const DevSys& s, const Walker&
     }
 }
 
+// Lattice point q of r (0: r itself, 1..6: the neighbours in move order):
+// fixed axes r +- a e_d, or the walker's rotated step vectors st.
+template <bool kRot>
+__device__ __forceinline__ void lattice_point(const double* r, int q, double a, const double* st,
+                                              double* o)
+{
+    if constexpr (kRot) point_qv(r, q, st, o);
+    else point_q(r, q, a, o);
+}
+
 // Orbital rows of electron j at position r (11 rows, columns k < n_j):
 // row 0 the value at r, rows 1..6 the values at the six lattice neighbours
-// r +- a e_d (move order), rows 7..9 the gradient, row 10 the Laplacian.
+// r +- a e_d (move order; e_d the walker's lattice versors, the coordinate
+// axes or a random orientation), rows 7..9 the gradient, row 10 the Laplacian.
 //
-// Basis values: one lane per function.  A Gaussian factorizes over the
-// coordinates, so at the neighbour r + s a e_c (s = +-1)
-//   exp(-alpha |d + s a e_c|^2) = exp(-alpha d^2) exp(-alpha a^2) exp(-2 s alpha a d_c),
+// Basis values: one lane per function.  A Gaussian factorizes along the
+// versors, so at the neighbour r + s a e_c (s = +-1)
+//   exp(-alpha |d + s a e_c|^2) = exp(-alpha d^2) exp(-alpha a^2) exp(-2 s alpha a d.e_c),
 // with d = r - centre: four exponentials (the per-function constant
 // exp(-alpha a^2) is tabulated with the system) and three reciprocals give all
 // seven values, and the value at r gives the gradient and Laplacian.  Slater
 // functions take the seven points directly.  Orbitals: the 11 x Nb basis
 // block times the Nb x n coefficient block on FP64 MFMA (16x16x4 tiles; rows
 // 11..15 and columns >= n are padding).
+template <bool kRot>
 __device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, double a, int lane)
 {
     const int Nb = s.Nb, ldb = s.ldb;
+    const double* st = lds + w.ev;      // lattice step vectors a e_d
     for (int mu = lane; mu < Nb; mu += kWave) {
         const double4_t c = gld((const double4_t*)(s.btab + 4 * mu));
         const int t = gld(s.btype + mu);
@@ -172,7 +186,7 @@ __device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, do
         if (t == 4) {
             for (int q = 1; q < 7; ++q) {
                 double pq[3];
-                point_q(r, q, a, pq);
+                lattice_point<kRot>(r, q, a, st, pq);
                 const double dx = pq[0] - c[0], dy = pq[1] - c[1], dz = pq[2] - c[2];
                 Bm[q * ldb] = basis_value_d(t, al, dx, dy, dz, dx * dx + dy * dy + dz * dz);
             }
@@ -180,18 +194,32 @@ __device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, do
         } else {
             const double e = exp(-al * d2);
             const double K = gld(s.bK + mu);
-            const double s2a = 2.0 * al * a;
+            const double s2a = 2.0 * al * a, m2al = -2.0 * al;
             // polynomial factor: 1 (s) or the displacement along the p axis
             const int ax = t - 1;
             const double f0 = t == 0 ? 1.0 : (ax == 0 ? d[0] : (ax == 1 ? d[1] : d[2]));
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) {
-                // exponent clamped: beyond +-700 the value at r has underflowed
-                const double x = fmin(fmax(-s2a * d[cc], -700.0), 700.0);
+                // -2 alpha a d.e_cc, clamped: beyond +-700 the value at r has
+                // underflowed; the p factor moves by the step's component
+                double x;
+                if constexpr (kRot) {
+                    const double sd = d[0] * st[3 * cc] + d[1] * st[3 * cc + 1] + d[2] * st[3 * cc + 2];
+                    x = fmin(fmax(m2al * sd, -700.0), 700.0);
+                } else {
+                    x = fmin(fmax(-s2a * d[cc], -700.0), 700.0);
+                }
                 const double tc = exp(x);
                 const double ep = e * (K * tc), em = e * (K * recip(tc));
-                const double fp = (t != 0 && ax == cc) ? f0 + a : f0;
-                const double fm = (t != 0 && ax == cc) ? f0 - a : f0;
+                double fp, fm;
+                if constexpr (kRot) {
+                    const double sp = t != 0 ? st[3 * cc + (ax < 0 ? 0 : ax)] : 0.0;
+                    fp = t != 0 ? f0 + sp : f0;
+                    fm = t != 0 ? f0 - sp : f0;
+                } else {
+                    fp = (t != 0 && ax == cc) ? f0 + a : f0;
+                    fm = (t != 0 && ax == cc) ? f0 - a : f0;
+                }
                 Bm[(2 * cc + 1) * ldb] = fp * ep;
                 Bm[(2 * cc + 2) * ldb] = fm * em;
             }
@@ -255,10 +283,11 @@ __device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
     wave_sync();
 }
 
+template <bool kRot>
 __device__ void electron_rows(const DevSys& s, const Walker& w, int j, const double* r, double a,
                               int lane)
 {
-    basis_rows(s, w, r, a, lane);
+    basis_rows<kRot>(s, w, r, a, lane);
     orbital_rows(s, w, j, lane);
 }
 
@@ -378,6 +407,7 @@ __device__ void recompute_gd(const DevSys& s, const Walker& w, int sp, int lane)
 // one lane per (electron, point) pair accumulates over all partners, then one
 // lane per electron accumulates its gradient, Laplacian and potentials.
 // Returns V_ee.
+template <bool kRot>
 __device__ double jastrow_all(const DevSys& s, const Walker& w, double a, int lane)
 {
     const int K = s.N + s.M;
@@ -388,7 +418,7 @@ __device__ double jastrow_all(const DevSys& s, const Walker& w, double a, int la
         const int j = it / 7, q = it - 7 * j;
         const double rj[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
         double pq[3];
-        point_q(rj, q, a, pq);
+        lattice_point<kRot>(rj, q, a, lds + w.ev, pq);
         double acc = 0.0;
         #pragma unroll 1
         for (int k = 0; k < Kj; ++k) {
@@ -439,11 +469,12 @@ __device__ double jastrow_all(const DevSys& s, const Walker& w, double a, int la
 
 // FP64 refresh: inverses and log-determinants from the exact orbital rows,
 // Jastrow caches and V_ee from scratch, all ratios.
+template <bool kRot>
 __device__ bool refresh_all(const DevSys& s, const Walker& w, double a, int lane)
 {
     bool ok = refresh_inverse(s, w, 0, lane);
     ok = refresh_inverse(s, w, 1, lane) && ok;
-    const double vee = jastrow_all(s, w, a, lane);
+    const double vee = jastrow_all<kRot>(s, w, a, lane);
     if (lane == 0) lds[w.scal + kScVee] = vee;
     wave_sync();
     recompute_ratios(s, w, -1, lane);
@@ -534,9 +565,11 @@ __device__ int heat_bath(const DevSys& s, const Walker& w, double xi, double inc
 // new orbital rows of the moved electron, Jastrow / potential caches, ratios.
 // Returns true when the determinant ratio was tiny (a refresh is forced).
 #ifdef LRDMC_SECTION_TIMERS
+template <bool kRot>
 __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, int lane,
                            unsigned long long* sect, unsigned long long& t_mark_)
 #else
+template <bool kRot>
 __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, int lane)
 #endif
 {
@@ -544,14 +577,16 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     const int sp = spin_of(s, i), c = col_of(s, i), n = nspin(s, sp);
     const double Rd = lds[w.Rdet + p], iRd = 1.0 / Rd;
     const double rold[3] = {lds[w.pos + 3 * i], lds[w.pos + 3 * i + 1], lds[w.pos + 3 * i + 2]};
+    const double* st = lds + w.ev;
     double rnew[3] = {rold[0], rold[1], rold[2]};
-    rnew[d] = rnew[d] + (sg ? -a : a);
+    if constexpr (kRot) point_qv(rold, 2 * d + sg + 1, st, rnew);
+    else rnew[d] = rnew[d] + (sg ? -a : a);
 
     // The accepted orbital row u is fetched first and the basis values at
     // the new position are computed while it is in flight.
     double u0 = 0.0;
     if (lane < n) u0 = gld(w.Phi + lane * s.P + p);
-    basis_rows(s, w, rnew, a, lane);
+    basis_rows<kRot>(s, w, rnew, a, lane);
     LRDMC_T(3);
 
     // Sherman-Morrison on AinvT of spin sp with the accepted orbital row u
@@ -625,19 +660,24 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
         const bool kval = k < Kj && k != i;
         if (kval) partner(s, w, i, k, pk, jr);
         const double* prm = lds + w.jas + 3 * jr;
-        // displaced coordinate of each point, formed as in the move itself
+        // displaced coordinates of each point, formed as in the move itself
         const double rp[3] = {rnew[0] + a, rnew[1] + a, rnew[2] + a};
         const double rm[3] = {rnew[0] + (-a), rnew[1] + (-a), rnew[2] + (-a)};
         for (int q0 = 0; q0 < 7; q0 += 2 * ppp) {
             const int qa = q0 + row / rpp, qb = qa + ppp;
             double va, vb;
             double pa[3], pb[3];
+            if constexpr (kRot) {
+                point_qv(rnew, qa, st, pa);
+                point_qv(rnew, qb < 7 ? qb : 0, st, pb);
+            } else {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                pa[c] = qa == 2 * c + 1 ? rp[c] : rnew[c];
-                pa[c] = qa == 2 * c + 2 ? rm[c] : pa[c];
-                pb[c] = qb == 2 * c + 1 ? rp[c] : rnew[c];
-                pb[c] = qb == 2 * c + 2 ? rm[c] : pb[c];
+                for (int c = 0; c < 3; ++c) {
+                    pa[c] = qa == 2 * c + 1 ? rp[c] : rnew[c];
+                    pa[c] = qa == 2 * c + 2 ? rm[c] : pa[c];
+                    pb[c] = qb == 2 * c + 1 ? rp[c] : rnew[c];
+                    pb[c] = qb == 2 * c + 2 ? rm[c] : pb[c];
+                }
             }
             const double a0 = pa[0] - pk[0], a1 = pa[1] - pk[1], a2 = pa[2] - pk[2];
             const double b0 = pb[0] - pk[0], b1 = pb[1] - pk[1], b2 = pb[2] - pk[2];
@@ -657,7 +697,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
 #pragma unroll 1
         for (int q = 0; q < 7; ++q) {
             double pq[3];
-            point_q(rnew, q, a, pq);
+            lattice_point<kRot>(rnew, q, a, st, pq);
             double acc = 0.0;
             #pragma unroll 1
             for (int k = lane; k < Kj; k += kWave) {
@@ -719,10 +759,15 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int q = h ? qb : qa, j = h ? jb : ja;
-            const int dd = (q >> 1) % 3, s2 = q & 1;
             const double* prm = lds + w.jas + 3 * ee_row(s, i, j);
             double r2[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
-            r2[dd] = r2[dd] + (s2 ? -a : a);
+            if constexpr (kRot) {
+                const double rj[3] = {r2[0], r2[1], r2[2]};
+                point_qv(rj, q - 6 * j + 1, st, r2);
+            } else {
+                const int dd = (q >> 1) % 3, s2 = q & 1;
+                r2[dd] = r2[dd] + (s2 ? -a : a);
+            }
             const double n0 = r2[0] - rnew[0], n1 = r2[1] - rnew[1], n2 = r2[2] - rnew[2];
             const double o0 = r2[0] - rold[0], o1 = r2[1] - rold[1], o2 = r2[2] - rold[2];
             const double un = pade_u2(prm, n0 * n0 + n1 * n1 + n2 * n2);
@@ -737,7 +782,11 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
         lds[w.Jg + 3 * i] = g0; lds[w.Jg + 3 * i + 1] = g1; lds[w.Jg + 3 * i + 2] = g2;
         lds[w.Jl + i] = l; lds[w.nue + i] = nu; lds[w.nua + i] = nua;
         lds[w.scal + kScVee] += dvee;
-        lds[w.pos + 3 * i + d] = rnew[d];
+        if constexpr (kRot) {
+            lds[w.pos + 3 * i] = rnew[0]; lds[w.pos + 3 * i + 1] = rnew[1]; lds[w.pos + 3 * i + 2] = rnew[2];
+        } else {
+            lds[w.pos + 3 * i + d] = rnew[d];
+        }
     }
     wave_sync();
     LRDMC_T(5);
@@ -792,6 +841,10 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
 #define LRDMC_PHASE_WAVES 2
 #endif
 
+// The phase kernel, one instantiation per lattice geometry: fixed axes
+// (kRot = false, the cheaper axis-aligned moves) or a random orientation per
+// walker and phase (kRot = true).
+template <bool kRot>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(LRDMC_PHASE_WAVES)))
 void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
 {
@@ -819,16 +872,24 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
         nr[6] = (double)(2 + gld(s.spec + I));
     }
     for (int q = lane; q < 3 * (2 + s.nspec); q += kWave) lds[w.jas + q] = gld(s.jas + q);
+    // lattice step vectors of this walker for this phase: the coordinate axes,
+    // or a random orientation drawn from its own Philox stream
+    if (lane == 0) {
+        double st[9];
+        if constexpr (kRot) lattice_steps(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb, pa.a, st);
+        else lattice_steps_fixed(pa.a, st);
+        for (int q = 0; q < 9; ++q) lds[w.ev + q] = st[q];
+    }
     wave_sync();
     // orbital rows of every electron, then the FP64 refresh
     for (int j = 0; j < s.N; ++j) {
         const double r[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
-        electron_rows(s, w, j, r, a, lane);
+        electron_rows<kRot>(s, w, j, r, a, lane);
         store_rows(s, w, j, lane, true);
     }
     unsigned long long n_neg = 0, n_nomove = 0, n_refresh = 1, n_small = 0, n_sing = 0,
                        n_capped = 0;
-    if (!refresh_all(s, w, a, lane)) n_sing++;
+    if (!refresh_all<kRot>(s, w, a, lane)) n_sing++;
 
     double lw = s.lw[wid];
     // load-balanced weight factors bbar / (W - E_0) multiplied in blocks
@@ -891,14 +952,14 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
         LRDMC_T(1);
         if (q >= 0) {
 #ifdef LRDMC_SECTION_TIMERS
-            const bool small = apply_move(s, w, a, q, lane, sect, t_mark_);
+            const bool small = apply_move<kRot>(s, w, a, q, lane, sect, t_mark_);
 #else
-            const bool small = apply_move(s, w, a, q, lane);
+            const bool small = apply_move<kRot>(s, w, a, q, lane);
 #endif
             ++since;
             if (small) n_small++;
             if (small || since >= pa.refresh_every) {
-                if (!refresh_all(s, w, a, lane)) n_sing++;
+                if (!refresh_all<kRot>(s, w, a, lane)) n_sing++;
                 n_refresh++;
                 since = 0;
             }
@@ -937,6 +998,9 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
         atomicMin(cn + kCntMinIters, (unsigned long long)it);
     }
 }
+
+template __global__ void phase_fp64<false>(const DevSys* __restrict__ sys, PhaseArgs pa);
+template __global__ void phase_fp64<true>(const DevSys* __restrict__ sys, PhaseArgs pa);
 
 // ---------------------------------------------------------------------------
 // reconfiguration (Sec. II.A): one workgroup computes max log-weight, the

@@ -46,7 +46,7 @@ class lrdmc_params(ct.Structure):
                 ("tau", ct.c_double), ("n_proj", ct.c_int32), ("seed", ct.c_uint64),
                 ("refresh_every", ct.c_int32), ("nu_opt_mode", ct.c_int32),
                 ("p_corr", ct.c_int32), ("e0_window", ct.c_int32), ("trace_cap", ct.c_int32),
-                ("strict", ct.c_int32)]
+                ("strict", ct.c_int32), ("rotate", ct.c_int32)]
 
 
 class lrdmc_step_stats(ct.Structure):
@@ -74,7 +74,8 @@ EXPORTS = ["lrdmc_workspace_bytes", "lrdmc_init_system", "lrdmc_step", "lrdmc_br
            "lrdmc_energy_forces", "lrdmc_get_walkers", "lrdmc_set_walkers", "lrdmc_get_e0",
            "lrdmc_set_e0", "lrdmc_get_branch_index", "lrdmc_destroy", "lrdmc_last_error",
            "lrdmc_n_theta", "lrdmc_walker_derivs", "lrdmc_get_precision_report",
-           "lrdmc_run", "lrdmc_autotune", "lrdmc_set_launch"]
+           "lrdmc_run", "lrdmc_autotune", "lrdmc_set_launch",
+           "lrdmc_reconfigure_workspace_bytes", "lrdmc_reconfigure"]
 
 _lib = None
 
@@ -110,6 +111,12 @@ def load(path=LIB_PATH):
     L.lrdmc_autotune.argtypes = [vp, ct.c_int, vp, ct.c_int, vp]
     L.lrdmc_set_launch.argtypes = [vp, ct.c_int, ct.c_int]
     L.lrdmc_walker_derivs.argtypes = [vp, ct.c_int, vp, vp, vp, vp, vp]
+    u64 = ct.c_uint64
+    L.lrdmc_reconfigure_workspace_bytes.argtypes = [ct.c_int]
+    L.lrdmc_reconfigure_workspace_bytes.restype = sz
+    L.lrdmc_reconfigure.argtypes = [ct.c_int, ct.c_int, vp, vp, vp, dbl, u64, u64, ct.c_int, vp, vp,
+                                    vp, sz, vp]
+    L.lrdmc_reconfigure.restype = ct.c_int
     for k in ("lrdmc_init_system", "lrdmc_step", "lrdmc_branch", "lrdmc_energy_forces",
               "lrdmc_get_walkers", "lrdmc_set_walkers", "lrdmc_set_e0",
               "lrdmc_get_branch_index", "lrdmc_n_theta", "lrdmc_walker_derivs",
@@ -148,7 +155,7 @@ def _sys_struct(d, keep):
 
 def make_params(scheme="lb", a=0.2, tau=0.25, n_proj=300, seed=12033, refresh_every=None,
                 nu_opt_mode=NU_OPT_OWN, p_corr=10, e0_window=50, trace_cap=0, precision="fp64",
-                strict=False):
+                strict=False, rotate=False):
     """precision: "fp64" (every step in FP64), "fp32" or "bf16" (mixed: the
     orbital product on FP32 or BF16 MFMA, FP32 rank-one updates, FP64
     accumulation and refreshes).
@@ -162,7 +169,7 @@ def make_params(scheme="lb", a=0.2, tau=0.25, n_proj=300, seed=12033, refresh_ev
         refresh_every = 128 if prec == PRECISIONS["fp64"] else 16
     return lrdmc_params(SCHEME_LB if scheme == "lb" else SCHEME_CONV, prec, float(a), float(tau),
                         int(n_proj), int(seed), int(refresh_every), int(nu_opt_mode), int(p_corr),
-                        int(e0_window), int(trace_cap), 1 if strict else 0)
+                        int(e0_window), int(trace_cap), 1 if strict else 0, 1 if rotate else 0)
 
 
 def params_for(d, scheme="lb", **kw):
@@ -198,7 +205,9 @@ class Handle:
         self.keep.append(init)
         nbytes = L.lrdmc_workspace_bytes(ct.byref(arr), len(systems), ct.byref(prm))
         if nbytes == 0:
-            raise LrdmcError(-1, L.lrdmc_last_error().decode())
+            msg = L.lrdmc_last_error().decode()
+            unsupported = "too large" in msg or "not supported" in msg
+            raise LrdmcError(-6 if unsupported else -1, msg)
         self.device = torch.device(device)
         with torch.cuda.device(self.device):
             self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -364,3 +373,31 @@ def walker_energy(theta, handle, isys=0):
     if _WE is None:
         _WE = _walker_energy_fn()
     return _WE.apply(theta, handle, isys)
+
+
+def reconfigure(lw, eL, W=None, e0=0.0, scheme="lb", seed=12033, sysid=0, j=0, stream=None):
+    """Reconfiguration of a caller-held population (lrdmc_reconfigure): lw, eL
+    (and W for the load-balanced weighting) are float64 CUDA tensors of one
+    length.  Returns (sel int32 tensor, out float64 tensor [8]) on the same
+    device, enqueued on `stream` (default: torch's current stream)."""
+    import torch
+    L = load()
+    nw = int(lw.shape[0])
+    dev = lw.device
+    for t in (lw, eL) + ((W,) if W is not None else ()):
+        if t.dtype != torch.float64 or not t.is_cuda or t.shape != lw.shape or not t.is_contiguous():
+            raise ValueError("lw, eL, W must be contiguous float64 CUDA tensors of one length")
+    sel = torch.empty(nw, dtype=torch.int32, device=dev)
+    out = torch.empty(8, dtype=torch.float64, device=dev)
+    nb = L.lrdmc_reconfigure_workspace_bytes(nw)
+    if nb == 0:
+        raise LrdmcError(-1, L.lrdmc_last_error().decode())
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+    base = ws.data_ptr() + (-ws.data_ptr()) % 256
+    st = stream or torch.cuda.current_stream(dev)
+    _check(L.lrdmc_reconfigure(SCHEME_LB if scheme == "lb" else SCHEME_CONV, nw, lw.data_ptr(),
+                               eL.data_ptr(), None if W is None else W.data_ptr(), float(e0),
+                               int(seed), int(sysid), int(j), sel.data_ptr(), out.data_ptr(), base,
+                               nb, st.cuda_stream))
+    return sel, out
+

@@ -41,7 +41,7 @@ def make_handle(d, scheme, nw, **kw):
 
 def oracle_params(S, prm, band=1e-12):
     return S.params(a=prm.a, tau=prm.tau, nproj=prm.n_proj, nu_opt_mode=prm.nu_opt_mode,
-                    seed=prm.seed, band=band)
+                    seed=prm.seed, band=band, rotate=bool(prm.rotate))
 
 
 def compare_phase(d, prm, scheme, j, E0, pos0, lw0, g, idx, nthreads=8, band=1e-12):

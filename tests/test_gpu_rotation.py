@@ -1,0 +1,87 @@
+"""Randomized lattice on the GPU (App. D: the versors of the discretized
+Laplacian rotate with random angles; reading: one random rotation per walker
+and projection phase from the walker's own Philox stream) against the FP64
+oracle: rotation draws, rotated moves and positions bit-exact, e_L within
+1e-9 Ha, weights to 1e-11, over two phases with the reconfiguration between
+them (each phase draws new orientations); the exact hydrogenic eigenstate
+keeps e_L = -1/2 in every orientation; both schemes sample the same state."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2508_12033_amd import inputs as I
+from paper_2508_12033_amd import lrdmc as B
+from parity_util import assert_phase_ok, compare_phase, make_handle, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("scheme", ["lb", "conv"])
+def test_rotated_phases_match_oracle(scheme):
+    d = I.c1_system(n_walkers=96)
+    nw = 96
+    say("case rotated lattice c1", scheme, "96 walkers, two phases")
+    h, d2, prm = make_handle(d, scheme, nw, n_proj=150, tau=0.125, rotate=True)
+    e0 = h.e0()
+    pos = d2["init_pos"][:nw].copy()
+    lw = np.zeros(nw)
+    for j in range(2):
+        h.step()
+        g = h.walkers(trace=True)
+        res = compare_phase(d2, prm, scheme, j, e0, pos, lw, g, np.arange(nw))
+        say(scheme, j, {k: v for k, v in res.items() if k != "oracle"})
+        assert_phase_ok(res)
+        # every electron moved on its walker's rotated lattice of this phase
+        for w in (0, 17, nw - 1):
+            R = O.rotation(prm.seed, 0, w, j)
+            k = (g["pos"][w] - pos[w]) @ R / prm.a
+            assert np.allclose(k, np.round(k), atol=1e-9)
+        bs = h.branch()
+        after = h.walkers()
+        xi = O.uniform(prm.seed, 0, 0, j, 0, O.RNG_COMB)
+        sel, _, cnt = O.comb(g["lw"], xi, follow=after["sel"])
+        assert cnt["hard_mismatch"] == 0 and np.array_equal(sel, after["sel"])
+        pos = after["pos"].copy()
+        lw = np.zeros(nw)
+        e0 = bs.e0
+    h.close()
+
+
+def test_rotated_exact_eigenstate():
+    d = I.hydrogenic_system(Z=1.0, zeta=1.0, n_walkers=64)
+    say("case rotated lattice, hydrogenic exact state")
+    h, d2, prm = make_handle(d, "conv", 64, rotate=True)
+    h.step()
+    g = h.walkers()
+    assert np.all(np.abs(g["eL"] + 0.5) < 1e-12)
+    assert np.allclose(g["lw"], 0.5 * prm.tau, rtol=1e-12)
+    h.close()
+
+
+def test_rotated_schemes_agree_h2():
+    d = I.h2_system(n_walkers=2048)
+    res = {}
+    for sch in ("lb", "conv"):
+        prm = B.params_for(d, sch, rotate=True)
+        h = B.Handle(d, prm)
+        h.run(120)
+        res[sch] = h.energy()
+        h.close()
+    (e1, s1, _), (e2, s2, _) = res["lb"], res["conv"]
+    z = (e1 - e2) / np.hypot(s1, s2)
+    say("rotated lattice h2: lb %.5f +- %.5f, conv %.5f +- %.5f, z %.2f" % (e1, s1, e2, s2, z))
+    assert abs(z) < 3.5
+
+
+def test_rotation_unsupported_paths():
+    d = I.c1_system(n_walkers=8)
+    d2 = dict(d)
+    d2["n_walkers_run"] = 8
+    with pytest.raises(B.LrdmcError) as ei:
+        B.Handle(d2, B.params_for(d2, "lb", precision="fp32", rotate=True))
+    assert ei.value.code == -6
+    h = B.Handle(d2, B.params_for(d2, "lb", rotate=True, n_proj=4))
+    with pytest.raises(B.LrdmcError) as ei:
+        h.walker_derivs()
+    assert ei.value.code == -6
+    h.close()
