@@ -342,6 +342,26 @@ int lrdmc_reconfigure(int scheme, int nw, const double *lw, const double *eL, co
                       double e0, uint64_t seed, uint64_t sysid, int j, int32_t *sel,
                       double *out, void *ws, size_t ws_bytes, void *stream);
 
+/* Largest population of lrdmc_reconfigure_noalloc. */
+#define LRDMC_NOALLOC_MAX_WALKERS 1048576
+
+/* lrdmc_reconfigure without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): its prefix sums and sums live in a fixed
+ * device array of the library (8 MiB, one copy per GPU, held until the
+ * process ends), so the call allocates nothing.  Same arguments, results and
+ * errors as lrdmc_reconfigure; nw > LRDMC_NOALLOC_MAX_WALKERS returns
+ * LRDMC_ERR_INVALID_ARG before any device work.  The arrays and the stream
+ * must belong to the device current on the calling thread.  The first call on
+ * a device looks up the array's device address (hipGetSymbolAddress); make it
+ * outside a graph capture.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (different streams or threads without
+ * ordering between them) race and give wrong results; calls ordered on one
+ * stream are safe (each call rewrites what it reads). */
+int lrdmc_reconfigure_noalloc(int scheme, int nw, const double *lw, const double *eL,
+                              const double *W, double e0, uint64_t seed, uint64_t sysid, int j,
+                              int32_t *sel, double *out, void *stream);
+
 /* Branching index j used in the Philox counters of the next phase. */
 int lrdmc_get_branch_index(struct lrdmc_handle *h);
 

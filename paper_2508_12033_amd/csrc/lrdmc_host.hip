@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -627,6 +628,37 @@ void fill_branch_stats(const lrdmc_handle* h, lrdmc_branch_stats* st, float ms)
     st->e0 = r.hist_e0[n - 1];
     st->max_lw = r.hist_mx[n - 1];
     st->n_distinct = (int)r.hist_nd[n - 1];
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of lrdmc_reconfigure_noalloc: a fixed device array, one copy per GPU
+// that the library runs on, held until the process ends (8 MiB).  In host code
+// `scratch` is only a host-side stand-in for the symbol; its device address on
+// each GPU comes from hipGetSymbolAddress, called once per device with that
+// device current, and only that address is passed to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[((LRDMC_NOALLOC_MAX_WALKERS + 31) / 32) * 32 + 16];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up on first use)
+int noalloc_scratch(double** out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LRDMC_ERR_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LRDMC_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return LRDMC_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1435,6 +1467,22 @@ int lrdmc_set_e0(lrdmc_handle* h, int isys, double e0)
     HIPCHK(hipMemcpyAsync(r.d_e0, &r.e0, 8, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return LRDMC_OK;
+}
+
+int lrdmc_reconfigure_noalloc(int scheme, int nw, const double* lw, const double* eL,
+                              const double* W, double e0, uint64_t seed, uint64_t sysid, int j,
+                              int32_t* sel, double* out, void* stream)
+{
+    int rc = check_reconf_args(scheme, nw, lw, eL, W, sel, out);
+    if (rc) return rc;
+    if (nw > LRDMC_NOALLOC_MAX_WALKERS)
+        return fail(LRDMC_ERR_INVALID_ARG, "nw = " + std::to_string(nw) +
+                                               " exceeds LRDMC_NOALLOC_MAX_WALKERS = " +
+                                               std::to_string(LRDMC_NOALLOC_MAX_WALKERS));
+    double* scr = nullptr;
+    if ((rc = noalloc_scratch(&scr))) return rc;
+    return enqueue_reconfigure(scheme, nw, lw, eL, W, e0, seed, sysid, j, sel, out, scr,
+                               (hipStream_t)stream);
 }
 
 int lrdmc_get_branch_index(lrdmc_handle* h) { return h ? h->j : -1; }

@@ -75,7 +75,8 @@ EXPORTS = ["lrdmc_workspace_bytes", "lrdmc_init_system", "lrdmc_step", "lrdmc_br
            "lrdmc_set_e0", "lrdmc_get_branch_index", "lrdmc_destroy", "lrdmc_last_error",
            "lrdmc_n_theta", "lrdmc_walker_derivs", "lrdmc_get_precision_report",
            "lrdmc_run", "lrdmc_autotune", "lrdmc_set_launch",
-           "lrdmc_reconfigure_workspace_bytes", "lrdmc_reconfigure"]
+           "lrdmc_reconfigure_workspace_bytes", "lrdmc_reconfigure",
+           "lrdmc_reconfigure_noalloc"]
 
 _lib = None
 
@@ -117,6 +118,9 @@ def load(path=LIB_PATH):
     L.lrdmc_reconfigure.argtypes = [ct.c_int, ct.c_int, vp, vp, vp, dbl, u64, u64, ct.c_int, vp, vp,
                                     vp, sz, vp]
     L.lrdmc_reconfigure.restype = ct.c_int
+    L.lrdmc_reconfigure_noalloc.argtypes = [ct.c_int, ct.c_int, vp, vp, vp, dbl, u64, u64,
+                                            ct.c_int, vp, vp, vp]
+    L.lrdmc_reconfigure_noalloc.restype = ct.c_int
     for k in ("lrdmc_init_system", "lrdmc_step", "lrdmc_branch", "lrdmc_energy_forces",
               "lrdmc_get_walkers", "lrdmc_set_walkers", "lrdmc_set_e0",
               "lrdmc_get_branch_index", "lrdmc_n_theta", "lrdmc_walker_derivs",
