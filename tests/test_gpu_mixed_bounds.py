@@ -1,0 +1,71 @@
+"""Stated errors of the mixed-precision step at production scale (N_proj = 300,
+populations of 256 to 4096 walkers), per precision, against FP64.
+
+The mixed step's own e_L, W and move ratios at the final configuration of a
+phase (lrdmc_get_precision_report) are compared with the FP64 evaluation of
+the same configuration, which the oracle confirms on sampled walkers
+(1e-9 Ha).  Asserted per precision: quantiles (median, 99th percentile) and
+maxima of the relative e_L and W errors and of the ratio error, and the number
+of decisions the oracle adopted inside the decision band.  The bounds are the
+measured values with a margin; the e_L error of the mixed step stems from the
+lattice Laplacian (sum of the six move ratios of an electron minus 6, divided
+by a^2), which turns ratio errors of ~1e-7 (FP32) or ~1e-5 (split BF16) into
+e_L errors of ~1e-6 to ~1e-5 of |e_L|."""
+import numpy as np
+import pytest
+
+from paper_2508_12033_amd import inputs as I
+from parity_util import TOL_EL, compare_phase, make_handle, say
+
+pytestmark = pytest.mark.gpu
+
+BAND = dict(fp32=1e-4, bf16=1e-3)
+# (system, precision) -> bounds: e_L (median, p99, max), W max, ratio max.
+# Measured (MI355X): 128 electrons FP32 e_L 2.3e-6 / 1.4e-5 / 3.3e-5, W 4.2e-6,
+# ratio 8.4e-5; split BF16 e_L 4.1e-5 / 2.8e-4 / 8.7e-4, W 1.5e-4, ratio 2.8e-3;
+# 16 electrons FP32 (4096 walkers) e_L 1.7e-6 / 1.7e-5 / 9.5e-4 (one walker next
+# to a node, where the continuum Laplacian of the trial function is large),
+# W 1.0e-6, ratio 1.4e-5
+BOUNDS = {
+    ("c3", "fp32"): dict(eL=(5e-6, 4e-5, 1e-4), W=2e-5, ratio=3e-4),
+    ("c3", "bf16"): dict(eL=(1e-4, 1e-3, 3e-3), W=5e-4, ratio=1e-2),
+    ("c1", "fp32"): dict(eL=(5e-6, 5e-5, 3e-3), W=5e-6, ratio=5e-5),
+}
+
+
+def _stats(x):
+    return float(np.median(x)), float(np.quantile(x, 0.99)), float(x.max())
+
+
+@pytest.mark.parametrize("sysname,nw,prec", [("c3", 256, "fp32"), ("c3", 256, "bf16"),
+                                             ("c1", 4096, "fp32")])
+def test_mixed_errors_at_scale(sysname, nw, prec):
+    d = I.c3_system(n_walkers=nw) if sysname == "c3" else I.c1_system(n_walkers=nw)
+    say("case mixed bounds", sysname, prec, nw, "walkers x 300 steps")
+    h, d2, prm = make_handle(d, "lb", nw, precision=prec)
+    e0 = h.e0()
+    pos0 = d2["init_pos"][:nw].copy()
+    h.step()
+    g = h.walkers(trace=True)
+    rep = h.precision_report()
+    idx = np.array([0, nw // 2, nw - 1])
+    res = compare_phase(d2, prm, "lb", 0, e0, pos0, np.zeros(nw), g, idx, band=BAND[prec],
+                        nthreads=16)
+    c = res["cnt"]
+    say({k: v for k, v in res.items() if k != "oracle"})
+    assert c["hard_mismatch"] == 0 and c["singular"] == 0, res
+    assert c["ambig_adopted"] <= max(1, 2e-3 * c["decisions"]), res
+    assert res["pos_equal"] and res["eL_err"] < TOL_EL, res
+    # the FP64 reference values of the report are the oracle's on the sample
+    e = np.abs(rep[:, 0] - g["eL"]) / np.abs(g["eL"])
+    w = np.abs(rep[:, 1] - g["W"]) / np.abs(g["W"])
+    r = rep[:, 3]
+    b = BOUNDS[(sysname, prec)]
+    se, sr = _stats(e), _stats(r)
+    say("%s %s: e_L rel err median %.2e p99 %.2e max %.2e; W max %.2e; ratio err median %.2e "
+        "p99 %.2e max %.2e; adopted %d of %d decisions"
+        % (sysname, prec, se[0], se[1], se[2], w.max(), sr[0], sr[1], sr[2], c["ambig_adopted"],
+           c["decisions"]))
+    assert se[0] < b["eL"][0] and se[1] < b["eL"][1] and se[2] < b["eL"][2]
+    assert w.max() < b["W"] and sr[2] < b["ratio"]
+    h.close()
