@@ -45,6 +45,11 @@ KERNEL_SOURCES = ["paper_2508_12033_amd/csrc/lrdmc_phase.hip",
                   "paper_2508_12033_amd/csrc/lrdmc_dev.hpp",
                   "paper_2508_12033_amd/csrc/lrdmc_devfn.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phase_fp64_c1_traffic.json")
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+MIXED_SOURCES = ["paper_2508_12033_amd/csrc/lrdmc_mixed.hip",
+                 "paper_2508_12033_amd/csrc/lrdmc_dev.hpp",
+                 "paper_2508_12033_amd/csrc/lrdmc_devfn.hpp"]
+MIXED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phase_mixed_c3_bf16_traffic.json")
 
 
 def flops_per_walker_step(N, n, Nb, M, has_en, refresh_every):
@@ -64,23 +69,46 @@ def flops_per_walker_step(N, n, Nb, M, has_en, refresh_every):
     return f + refresh / refresh_every
 
 
-def kernel_hash():
+def kernel_hash(sources=None):
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources or KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, p), "rb").read())
     return h.hexdigest()[:16]
 
 
-def traffic_per_launch():
+def traffic_per_launch(path=TRAFFIC_FILE, sources=None):
     """HBM bytes per phase launch from the committed rocprofv3 counter runs,
     or None when the kernel sources changed since they were taken."""
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != kernel_hash():
+    if t.get("kernel_hash") != kernel_hash(sources):
         return None
     return t.get("bytes_per_launch")
+
+
+def mixed_bytes_per_walker_step(n, refresh_every):
+    """Algorithmic HBM bytes of one mixed-precision walker-step (FP32 walker
+    block in HBM, n orbitals of the moved electron's spin): the orbital rows
+    of the spin's 6n moves and its 4n derivative rows read for the ratio and
+    gradient products (10 n^2 floats), the spin's inverse read and written
+    back (2 n^2), the moved electron's new rows written and the accepted row
+    read (12 n), and the refresh, which reads the Slater rows and inverses of
+    both spins and writes the inverses (6 n^2), once every refresh_every
+    moves."""
+    return 4.0 * (10 * n * n + 2 * n * n + 12 * n + 6.0 * n * n / refresh_every)
+
+
+def mixed_roofline(systems, prm, launch_ms, traffic=None):
+    """HBM roofline of one mixed-precision phase launch over all systems."""
+    if isinstance(systems, dict):
+        systems = [systems]
+    byts = sum(mixed_bytes_per_walker_step(max(int(d["n_up"]), int(d["n_dn"])), prm.refresh_every) *
+               int(d.get("n_walkers_run", d["init_pos"].shape[0])) * prm.n_proj for d in systems)
+    gbs = byts / (launch_ms * 1e-3) / 1e9
+    return dict(bound="hbm", kernel="phase_mixed", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=gbs / HBM_PEAK_GBS, traffic=traffic, bytes_per_launch=byts, launch_ms=launch_ms)
 
 
 def _cpu_model():
@@ -215,6 +243,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="headline only (no mixed, batched or adjoint lines)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--profile-workload", choices=["c3_bf16", "c3_fp32", "c1_fp32", "c2_fp32"],
+                    help="run only this mixed-precision workload for --steps cycles (for profilers) "
+                         "and print its line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: measures one GPU only; --gpus %d is not supported "
@@ -230,6 +261,17 @@ def main():
         return
     from paper_2508_12033_amd import inputs as I
     from paper_2508_12033_amd import lrdmc as B
+
+    if args.profile_workload:
+        wl = args.profile_workload
+        sysd = {"c3": lambda: I.c3_system(n_walkers=2048), "c1": lambda: I.c1_system(n_walkers=4096),
+                "c2": I.c2_systems}[wl[:2]]()
+        hx, _, r = run_cycles(B, sysd, "lb", args.steps, args.warmup, precision=wl[3:],
+                              threads=128 if wl == "c2_fp32" else None)
+        hx.close()
+        print(json.dumps(dict(workload=wl, proposals_per_s=r["proposals"] / r["seconds"],
+                              ms_per_branching=r["ms_per_cycle"])), flush=True)
+        return
 
     d = I.c1_system(n_walkers=4096)
     nw, N, n_proj = 4096, d["n_elec"], d["n_proj"]
@@ -306,15 +348,16 @@ def main():
 
     if not args.no_conv:
         # Sec. II.C / Sec. III: both schemes sample the same fixed-node state;
-        # energies with blocking error bars and their z-score, on the H2
-        # system (256 walkers, 100 branchings) and the 16-electron system
-        # (4096 walkers, 40 branchings)
+        # energies with blocking error bars and their z-score after an
+        # equilibration left out of the estimate, on the H2 system (256
+        # walkers) and the 16-electron system (4096 walkers)
         agree = {}
-        for name, dd, nb in (("h2_256w", I.h2_system(n_walkers=256), 100), ("c1_4096w", d, 40)):
-            row = {}
+        for name, dd, nw_, nb in (("h2_256w", I.h2_system(n_walkers=256), 100, 300),
+                                  ("c1_4096w", d, 100, 300)):
+            row = dict(equilibration_branchings=nw_, measured_branchings=nb)
             for sch in ("lb", "conv"):
-                hs = B.Handle(dd, B.params_for(dd, sch))
-                hs.run(nb)
+                hs = B.Handle(dd, B.params_for(dd, sch, n_therm=nw_))
+                hs.run(nw_ + nb)
                 E, sig, n = hs.energy()
                 hs.close()
                 row[sch] = dict(E=E, sigma=sig, n_used=n)
@@ -327,33 +370,36 @@ def main():
         extra = {}
         steps_x = max(2, args.steps // 3)
         # the same 16-electron workload on the mixed-precision path
-        hx, _, r = run_cycles(B, d, "lb", steps_x, 1, precision="fp32", tune=True)
-        hx.step(stats=False)
+        hx, px, r = run_cycles(B, d, "lb", steps_x, 1, precision="fp32", tune=True)
+        stx = hx.step(stats=True)
         extra["c1_mixed_fp32"] = dict(proposals_per_s=r["proposals"] / r["seconds"],
                                       ms_per_branching=r["ms_per_cycle"], tune=r["tune"],
                                       vs_fp64=(r["proposals"] / r["seconds"]) / value,
-                                      error=precision_summary(hx))
+                                      error=precision_summary(hx),
+                                      roofline=mixed_roofline(d, px, stx.elapsed_ms))
         hx.close()
         # 128 electrons, 640 basis functions, 2048 walkers
         c3 = I.c3_system(n_walkers=2048)
         for prec in ("bf16", "fp32"):
-            hx, _, r = run_cycles(B, c3, "lb", 2, 0, precision=prec)
-            hx.step(stats=False)
+            hx, px, r = run_cycles(B, c3, "lb", 2, 0, precision=prec)
+            stx = hx.step(stats=True)
+            tr = traffic_per_launch(MIXED_TRAFFIC_FILE, MIXED_SOURCES) if prec == "bf16" else None
             extra["c3_mixed_" + prec] = dict(
                 workload="128 electrons (64+64), 32 atoms, 640 basis functions, 2048 walkers, "
                          "a=0.15, N_proj=300, refresh every 16",
                 proposals_per_s=r["proposals"] / r["seconds"], ms_per_branching=r["ms_per_cycle"],
-                error=precision_summary(hx))
+                error=precision_summary(hx), roofline=mixed_roofline(c3, px, stx.elapsed_ms, tr))
             hx.close()
         # three uneven systems in one launch, graph-replayed cycles, tuned launch
         c2 = I.c2_systems()
-        hx, _, r = run_cycles(B, c2, "lb", 2, 0, precision="fp32", tune=True)
-        hx.step(stats=False)
+        hx, px, r = run_cycles(B, c2, "lb", 2, 0, precision="fp32", tune=True)
+        stx = hx.step(stats=True)
         extra["c2_batched_fp32"] = dict(
             workload="16e/8 atoms x 8192, 32e/16 atoms x 4096, 64e/32 atoms x 2048 walkers "
                      "in one launch, N_proj=300",
             proposals_per_s=r["proposals"] / r["seconds"], ms_per_branching=r["ms_per_cycle"],
-            tune=r["tune"], error=[precision_summary(hx, k) for k in range(3)])
+            tune=r["tune"], error=[precision_summary(hx, k) for k in range(3)],
+            roofline=mixed_roofline(c2, px, stx.elapsed_ms))
         hx.close()
         # adjoint pass: 4096 walkers, 24 nuclear coordinates + 15 Jastrow parameters
         c4 = I.c4_system(n_walkers=4096)

@@ -151,6 +151,8 @@ typedef struct lrdmc_params {
                                 r_i +- a R e_d.  FP64 precision only; the adjoint pass
                                 (lrdmc_walker_derivs) then returns
                                 LRDMC_ERR_UNSUPPORTED.  0: fixed x, y, z axes */
+    int32_t n_therm;         /* branchings left out of the energy estimate (equilibration);
+                                0: the first 10 % */
 } lrdmc_params;
 
 /* ---- statistics returned to the caller --------------------------------- */
@@ -260,7 +262,7 @@ int lrdmc_autotune(struct lrdmc_handle *h, int n_steps, lrdmc_tune_entry *log, i
 int lrdmc_set_launch(struct lrdmc_handle *h, int threads, int order_big_first);
 
 /* Energy estimate from the branching history (Sec. II.A correcting factors,
- * first 10 % of branchings dropped).  When forces ([n_atoms][3], host) or
+ * the first n_therm branchings, or the first 10 % if n_therm = 0, dropped).  When forces ([n_atoms][3], host) or
  * jgrad ([3 (2 + n_species)], host) is non-NULL, the adjoint pass
  * (lrdmc_walker_derivs) runs over the current walkers of system 0 and the
  * weighted population (omega = w/(W - E_0) load-balanced, w conventional)

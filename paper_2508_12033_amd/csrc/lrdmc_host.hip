@@ -262,6 +262,7 @@ std::string validate(const lrdmc_system* sys, int n_sys, const lrdmc_params* prm
     if (prm->trace_cap < 0) return "bad trace_cap";
     if (prm->strict != 0 && prm->strict != 1) return "strict must be 0 or 1";
     if (prm->rotate != 0 && prm->rotate != 1) return "rotate must be 0 or 1";
+    if (prm->n_therm < 0) return "n_therm must be >= 0";
     if (prm->rotate && prm->precision != LRDMC_FP64)
         return "random lattice orientation: not supported by the mixed-precision kernel";
     if (prm->e0_window < 0 || prm->e0_window > kHistCap) return "e0_window out of range";
@@ -1298,7 +1299,7 @@ int lrdmc_energy_forces(lrdmc_handle* h, lrdmc_energy* e, double* forces, double
     }
     const SysRun& r = h->sys[0];
     const int n = (int)r.hist_e.size(), p = std::max(0, h->prm.p_corr);
-    const int start = std::max(p, n / 10);
+    const int start = std::max(p, h->prm.n_therm > 0 ? h->prm.n_therm : n / 10);
     e->energy = NAN; e->sigma = NAN; e->n_used = 0;
     if (start >= n) return LRDMC_OK;
     std::vector<double> lg(n - start), g(n - start);

@@ -46,7 +46,7 @@ class lrdmc_params(ct.Structure):
                 ("tau", ct.c_double), ("n_proj", ct.c_int32), ("seed", ct.c_uint64),
                 ("refresh_every", ct.c_int32), ("nu_opt_mode", ct.c_int32),
                 ("p_corr", ct.c_int32), ("e0_window", ct.c_int32), ("trace_cap", ct.c_int32),
-                ("strict", ct.c_int32), ("rotate", ct.c_int32)]
+                ("strict", ct.c_int32), ("rotate", ct.c_int32), ("n_therm", ct.c_int32)]
 
 
 class lrdmc_step_stats(ct.Structure):
@@ -159,7 +159,7 @@ def _sys_struct(d, keep):
 
 def make_params(scheme="lb", a=0.2, tau=0.25, n_proj=300, seed=12033, refresh_every=None,
                 nu_opt_mode=NU_OPT_OWN, p_corr=10, e0_window=50, trace_cap=0, precision="fp64",
-                strict=False, rotate=False):
+                strict=False, rotate=False, n_therm=0):
     """precision: "fp64" (every step in FP64), "fp32" or "bf16" (mixed: the
     orbital product on FP32 or BF16 MFMA, FP32 rank-one updates, FP64
     accumulation and refreshes).
@@ -173,7 +173,8 @@ def make_params(scheme="lb", a=0.2, tau=0.25, n_proj=300, seed=12033, refresh_ev
         refresh_every = 128 if prec == PRECISIONS["fp64"] else 16
     return lrdmc_params(SCHEME_LB if scheme == "lb" else SCHEME_CONV, prec, float(a), float(tau),
                         int(n_proj), int(seed), int(refresh_every), int(nu_opt_mode), int(p_corr),
-                        int(e0_window), int(trace_cap), 1 if strict else 0, 1 if rotate else 0)
+                        int(e0_window), int(trace_cap), 1 if strict else 0, 1 if rotate else 0,
+                        int(n_therm))
 
 
 def params_for(d, scheme="lb", **kw):
