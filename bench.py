@@ -401,6 +401,24 @@ def main():
             tune=r["tune"], error=[precision_summary(hx, k) for k in range(3)],
             roofline=mixed_roofline(c2, px, stx.elapsed_ms))
         hx.close()
+        # mixed vs FP64 on one system that both layouts hold: the 32-electron
+        # molecule of the uneven set (16 orbitals per spin, 160 basis
+        # functions), 4096 walkers, N_proj = 300
+        d32 = dict(I.c2_systems()[1])
+        row = dict(workload="32 electrons (16+16), 16 atoms, 160 basis functions, 4096 walkers, "
+                            "a=0.2, N_proj=300")
+        for prec in ("fp64", "fp32", "bf16"):
+            hx, px, r = run_cycles(B, d32, "lb", 2, 1, precision=prec, tune=prec != "fp64")
+            stx = hx.step(stats=True)
+            row[prec] = dict(proposals_per_s=r["proposals"] / r["seconds"],
+                             ms_per_branching=r["ms_per_cycle"])
+            if prec != "fp64":
+                row[prec]["error"] = precision_summary(hx)
+                row[prec]["roofline"] = mixed_roofline(d32, px, stx.elapsed_ms)
+            hx.close()
+        row["fp32_vs_fp64"] = row["fp32"]["proposals_per_s"] / row["fp64"]["proposals_per_s"]
+        row["bf16_vs_fp64"] = row["bf16"]["proposals_per_s"] / row["fp64"]["proposals_per_s"]
+        extra["e32_mixed_vs_fp64"] = row
         # adjoint pass: 4096 walkers, 24 nuclear coordinates + 15 Jastrow parameters
         c4 = I.c4_system(n_walkers=4096)
         ha = B.Handle(c4, B.params_for(c4, "lb", n_proj=10))

@@ -148,9 +148,10 @@ typedef struct lrdmc_params {
                                 rotation R at the start of every projection phase
                                 from its own Philox stream (counter (slot, branching,
                                 attempt, 4)), and its 6N moves that phase are
-                                r_i +- a R e_d.  FP64 precision only; the adjoint pass
-                                (lrdmc_walker_derivs) then returns
-                                LRDMC_ERR_UNSUPPORTED.  0: fixed x, y, z axes */
+                                r_i +- a R e_d (every precision).  The adjoint pass
+                                (lrdmc_walker_derivs) evaluates the fixed axes only
+                                and returns LRDMC_ERR_UNSUPPORTED then.  0: fixed
+                                x, y, z axes */
     int32_t n_therm;         /* branchings left out of the energy estimate (equilibration);
                                 0: the first 10 % */
 } lrdmc_params;

@@ -106,7 +106,9 @@ struct DevMix {
     int trace_cap;
     // LDS layout, byte offsets
     int l_pos, l_nue, l_nua, l_scal, l_red, l_U, l_R, l_Rdet, l_dJ, l_gD, l_Jg, l_Jl, l_dje,
-        l_rows, l_tmp, l_F, l_bytes;
+        l_rows, l_tmp, l_F, l_ev, l_bytes;
+    // l_ev: the walker's lattice step vectors a e_d for the phase, [3 d + x]:
+    // 9 doubles, then the same 9 as floats
 };
 constexpr int kMixChunk = 64;   // basis functions per chunk of the FP64 estimator evaluation
 

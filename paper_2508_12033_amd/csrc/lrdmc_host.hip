@@ -113,7 +113,7 @@ struct Layout {
     long spill_stride;
     // mixed kernel: LDS byte offsets, walker block (floats)
     int l_pos, l_nue, l_nua, l_scal, l_red, l_U, l_R, l_Rdet, l_dJ, l_gD, l_Jg, l_Jl, l_dje, l_rows,
-        l_tmp, l_F, l_bytes;
+        l_tmp, l_F, l_ev, l_bytes;
     long g_Phi, g_dPhi, g_Arow, g_AinvT, m_stride, stride64;
     int nb32, tiles;
     size_t lds_bytes;
@@ -211,6 +211,7 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.l_rows = take(11 * ns * 4);
         L.l_tmp = take((3 * ns + 8) * 4);
         L.l_F = take((size_t)(2 * P + 8 * N) * 8);
+        L.l_ev = take(9 * 8 + 9 * 4);
         L.l_bytes = o;
         L.lds_bytes = o;
         L.g_Phi = 0;
@@ -263,8 +264,6 @@ std::string validate(const lrdmc_system* sys, int n_sys, const lrdmc_params* prm
     if (prm->strict != 0 && prm->strict != 1) return "strict must be 0 or 1";
     if (prm->rotate != 0 && prm->rotate != 1) return "rotate must be 0 or 1";
     if (prm->n_therm < 0) return "n_therm must be >= 0";
-    if (prm->rotate && prm->precision != LRDMC_FP64)
-        return "random lattice orientation: not supported by the mixed-precision kernel";
     if (prm->e0_window < 0 || prm->e0_window > kHistCap) return "e0_window out of range";
     if (n_sys > kMaxBatch) return "at most 8 systems per handle";
     for (int k = 0; k < n_sys; ++k) {
@@ -973,7 +972,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             m.l_pos = L.l_pos; m.l_nue = L.l_nue; m.l_nua = L.l_nua; m.l_scal = L.l_scal;
             m.l_red = L.l_red; m.l_U = L.l_U; m.l_R = L.l_R; m.l_Rdet = L.l_Rdet; m.l_dJ = L.l_dJ;
             m.l_gD = L.l_gD; m.l_Jg = L.l_Jg; m.l_Jl = L.l_Jl; m.l_dje = L.l_dje;
-            m.l_rows = L.l_rows; m.l_tmp = L.l_tmp; m.l_F = L.l_F; m.l_bytes = L.l_bytes;
+            m.l_rows = L.l_rows; m.l_tmp = L.l_tmp; m.l_F = L.l_F; m.l_ev = L.l_ev; m.l_bytes = L.l_bytes;
             for (int p = 0; p < 2; ++p) {
                 r.dmix[p] = (DevMix*)carve(sizeof(DevMix));
                 r.hmix[p] = m;

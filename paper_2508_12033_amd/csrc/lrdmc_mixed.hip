@@ -204,34 +204,55 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
         B[row * ldb + Nb + (z - row * (ldb - Nb))] = 0.0f;
     }
     auto put = [&](int row, int mu, float v) { B[row * ldb + mu] = v; };
-    // one thread per basis function: a Gaussian factorizes over the
-    // coordinates, so its values at the six neighbours r + s a e_c follow from
-    // exp(-alpha d^2), exp(-alpha a^2) and exp(-+2 alpha a d_c) (d = r - centre);
+    // one thread per basis function: a Gaussian factorizes along the lattice
+    // versors, so its values at the six neighbours r + s a e_c follow from
+    // exp(-alpha d^2), exp(-alpha a^2) and exp(-+2 alpha a d.e_c) (d = r - centre);
     // Slater functions, and exponents beyond the FP32 range, take the seven
     // points directly
     const float af = (float)a;
+    const double* st64 = LDSD(s.l_ev);          // step vectors a e_c, [3 c + x]
+    const float* st32 = LDSF(s.l_ev + 72);
     for (int mu = tid; mu < Nb; mu += (int)blockDim.x) {
         const double4_t rec = gld((const double4_t*)(s.btab + 4 * mu));
         const int t = gld(s.btype + mu);
         const float d[3] = {(float)(r[0] - rec[0]), (float)(r[1] - rec[1]), (float)(r[2] - rec[2])};
         const float d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2], al = (float)rec[3];
-        const float s2a = 2.0f * al * af;
+        const float m2al = -2.0f * al;
+        // a d.e_c along each versor
+        float sd[3];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+            sd[cc] = d[0] * st32[3 * cc] + d[1] * st32[3 * cc + 1] + d[2] * st32[3 * cc + 2];
         bool fac = t != 4;
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) fac = fac && fabsf(s2a * d[cc]) < 80.0f;
+        for (int cc = 0; cc < 3; ++cc) fac = fac && fabsf(m2al * sd[cc]) < 80.0f;
         float v, g0, g1, g2, l;
         if (fac) {
-            const float e = expf(-al * d2), K = expf(-al * af * af);
+            // rows 2c+1, 2c+2: the difference D = chi(r + st_c) - chi(r - st_c)
+            // and the second difference S = chi(r + st_c) + chi(r - st_c) - 2 chi(r)
+            // of the neighbour values, from G+- = e K E^+-1 (E = exp(x), x = -2 alpha a d.e_c)
+            // written with m = expm1(x) so that neither cancels:
+            //   G+ - G- = e K (E - 1/E),  E - 1/E = m (1 + 1/E),      m = E - 1
+            //   G+ + G- - 2e = e (K (E + 1/E - 2) + 2 (K - 1)),  E + 1/E - 2 = m^2 / E
+            const float e = expf(-al * d2), km1 = expm1f(-al * af * af), K = 1.0f + km1;
             const int ax = t - 1;
             const float f0 = t == 0 ? 1.0f : (ax == 0 ? d[0] : (ax == 1 ? d[1] : d[2]));
+            const float eK = e * K;
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) {
-                const float tc = expf(-s2a * d[cc]);
-                const float ep = e * (K * tc), em = e * (K * __builtin_amdgcn_rcpf(tc));
-                const float fp = (t != 0 && ax == cc) ? f0 + af : f0;
-                const float fm = (t != 0 && ax == cc) ? f0 - af : f0;
-                put(2 * cc + 1, mu, fp * ep);
-                put(2 * cc + 2, mu, fm * em);
+                // E^-1 from its own exponential (1 + m rounds to 0 for x below
+                // -17 in FP32), m^2 / E as m (m / E), which stays finite for
+                // every |x| < 80
+                const float x = m2al * sd[cc];
+                const float m = expm1f(x), iE = expf(-x);
+                const float sh = m * (1.0f + iE), ch = m * (m * iE);
+                const float gdif = eK * sh;                    // G+ - G-
+                const float gsec = e * (K * ch + 2.0f * km1);  // G+ + G- - 2e
+                // the p factor moves by the step's component h along its axis:
+                //   f+- = f0 +- h, D = f0 (G+ - G-) + h (G+ + G-), S = f0 (G+ + G- - 2e) + h (G+ - G-)
+                const float h = t != 0 ? st32[3 * cc + (ax < 0 ? 0 : ax)] : 0.0f;
+                put(2 * cc + 1, mu, f0 * gdif + h * (eK * (2.0f + ch)));
+                put(2 * cc + 2, mu, f0 * gsec + h * gdif);
             }
             v = f0 * e;
             if (t == 0) {
@@ -244,19 +265,20 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
                 l = f0 * e * (4.0f * al * al * d2 - 10.0f * al);
             }
         } else {
+            // the six neighbour values directly, then their difference and
+            // second difference along each versor (rows 2c+1, 2c+2)
+            float w[6];
             for (int q = 1; q < 7; ++q) {
                 double p[3];
-                point_q(r, q, a, p);
+                point_qv(r, q, st64, p);
                 const float dx = (float)(p[0] - rec[0]), dy = (float)(p[1] - rec[1]),
                             dz = (float)(p[2] - rec[2]);
                 const float dq2 = dx * dx + dy * dy + dz * dz;
-                float w;
-                if (t == 4) w = expf(-al * sqrtf(dq2));
+                if (t == 4) w[q - 1] = expf(-al * sqrtf(dq2));
                 else {
                     const float e = expf(-al * dq2);
-                    w = t == 0 ? e : (t == 1 ? dx : (t == 2 ? dy : dz)) * e;
+                    w[q - 1] = (t == 0 ? 1.0f : (t == 1 ? dx : (t == 2 ? dy : dz))) * e;
                 }
-                put(q, mu, w);
             }
             const float dx = d[0], dy = d[1], dz = d[2];
             if (t == 4) {
@@ -275,6 +297,11 @@ __device__ __noinline__ void mixed_rows(const DevMix* __restrict__ dm, int j, co
                 g1 = (t == 2 ? e : 0.0f) - 2.0f * al * dq * dy * e;
                 g2 = (t == 3 ? e : 0.0f) - 2.0f * al * dq * dz * e;
                 l = dq * e * (4.0f * al * al * d2 - 10.0f * al);
+            }
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                put(2 * cc + 1, mu, w[2 * cc] - w[2 * cc + 1]);
+                put(2 * cc + 2, mu, (w[2 * cc] - v) + (w[2 * cc + 1] - v));
             }
         }
         put(0, mu, v);
@@ -567,20 +594,32 @@ __device__ __noinline__ void mixed_spin_update(const DevMix* __restrict__ dm, co
         if (c < n && part == 0) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) gD[4 * (off + c) + t] = acc[t];
+            // determinant ratio minus one of the moves +-e_m: the electron's
+            // own Slater row times its inverse column is 1, so
+            // R - 1 = (+-D.a + S.a) / 2 with the difference and second
+            // difference rows (no cancellation against 1)
 #pragma unroll
-            for (int t = 0; t < 6; ++t) Rdet[6 * (off + c) + t] = acc[4 + t];
+            for (int m = 0; m < 3; ++m) {
+                const float dd = acc[4 + 2 * m], ss = acc[5 + 2 * m];
+                Rdet[6 * (off + c) + 2 * m] = 0.5f * (ss + dd);
+                Rdet[6 * (off + c) + 2 * m + 1] = 0.5f * (ss - dd);
+            }
         }
     }
     __syncthreads();
 }
 
-// R = Rdet * exp(dJ) for every move
+// Ratios of every move, kept as R - 1 (both arrays): with R_det - 1 = q and
+// the Jastrow exponent change x, R - 1 = q e^x + (e^x - 1)
 __device__ __forceinline__ void mixed_full_ratios(const DevMix& s)
 {
     float* R = LDSF(s.l_R);
     const float* Rdet = LDSF(s.l_Rdet);
     const float* dJ = LDSF(s.l_dJ);
-    for (int p = threadIdx.x; p < s.P; p += (int)blockDim.x) R[p] = Rdet[p] * expf(dJ[p]);
+    for (int p = threadIdx.x; p < s.P; p += (int)blockDim.x) {
+        const float em = expm1f(dJ[p]);
+        R[p] = Rdet[p] * (1.0f + em) + em;
+    }
     __syncthreads();
 }
 
@@ -591,16 +630,30 @@ __device__ __forceinline__ float pair_sum(float v)
 }
 
 // Pade terms of the six lattice neighbours of a point at FP32 difference f
-// from a partner (squared distance r2f): squared distances |f|^2 + a^2 +- 2a f_c,
-// kept positive; q adds u(neighbour) - u(point) in move order (+x, -x, +y, ...)
+// from a partner (squared distance r2f): squared distances |f|^2 + a^2 +- 2 f.st_c
+// (st_c = a e_c, the walker's step vectors), kept positive; q adds
+// u(neighbour) - u(point) in move order (+e_0, -e_0, +e_1, ...)
+// The change u(r') - u(r) is formed without subtracting two values of u:
+// with r'^2 - r^2 = a^2 +- 2 f.st_c (no cancellation) and r' - r = (r'^2 - r^2)/(r' + r),
+//   u(r') - u(r) = (r' - r) (A + B (r + r') + b B r r') / ((1 + b r)(1 + b r')).
 __device__ __forceinline__ void neighbour_du(const PadeF& p, const float f[3], float r2f, float aa,
-                                             float ta, float q[6])
+                                             const float* st32, float q[6])
 {
-    const float u0 = pade_u2f(p, fmaxf(r2f, 1e-30f)), b = r2f + aa;
+    const float r20 = fmaxf(r2f, 1e-30f);
+    const float r = r20 * __builtin_amdgcn_rsqf(r20);
+    const float iden0 = __builtin_amdgcn_rcpf(1.0f + p.b * r);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        q[2 * c] += pade_u2f(p, fmaxf(b + ta * f[c], 1e-30f)) - u0;
-        q[2 * c + 1] += pade_u2f(p, fmaxf(b - ta * f[c], 1e-30f)) - u0;
+        const float t2 = 2.0f * (f[0] * st32[3 * c] + f[1] * st32[3 * c + 1] + f[2] * st32[3 * c + 2]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float dr2 = h ? aa - t2 : aa + t2;
+            const float r2n = fmaxf(r20 + dr2, 1e-30f);
+            const float rn = r2n * __builtin_amdgcn_rsqf(r2n);
+            const float dr = dr2 * __builtin_amdgcn_rcpf(fmaxf(r + rn, 1e-30f));
+            const float num = p.A + p.B * (r + rn) + p.b * p.B * r * rn;
+            q[2 * c + h] += dr * num * iden0 * __builtin_amdgcn_rcpf(1.0f + p.b * rn);
+        }
     }
 }
 
@@ -621,7 +674,8 @@ __device__ __noinline__ double mixed_jastrow_all(const DevMix* __restrict__ dm, 
     double* nua = LDSD(s.l_nua);
     const int K = s.N + s.M;
     const double ia = 1.0 / a;
-    const float aa = (float)(a * a), ta = (float)(2.0 * a);
+    const float aa = (float)(a * a);
+    const float* st32 = LDSF(s.l_ev + 72);
     double vee = 0.0;
     for (int base = 0; base < 2 * s.N; base += (int)blockDim.x) {
         const int it = base + tid, j = it >> 1, h = it & 1;
@@ -647,7 +701,7 @@ __device__ __noinline__ double mixed_jastrow_all(const DevMix* __restrict__ dm, 
                 l += lp;
                 if (isel && k > j) vee += ir;
                 const float f[3] = {(float)d0, (float)d1, (float)d2};
-                neighbour_du(pr, f, (float)r2, aa, ta, dq);
+                neighbour_du(pr, f, (float)r2, aa, st32, dq);
             }
             if (!isel) {
                 double a1, a2;
@@ -812,7 +866,7 @@ __device__ __noinline__ MLocal mixed_evaluate(const DevMix* __restrict__ dm, dou
     double loc = 0.0;
     int anyneg = 0;
     for (int p = p0; p < p1; ++p) {
-        const double r = (double)R[p];
+        const double r = 1.0 + (double)R[p];
         if (r > 0) loc += r;
         else if (r < 0) anyneg = 1;
     }
@@ -830,9 +884,9 @@ __device__ __noinline__ MLocal mixed_evaluate(const DevMix* __restrict__ dm, dou
         double lapA = 0.0;
         int nd = 0;
         for (int q = 0; q < 6; ++q) {
-            const double r = (double)R[6 * j + q];
-            lapA += (r - 1.0) * ia2;
-            if (r < 0) nd = 1;
+            const double rm1 = (double)R[6 * j + q];
+            lapA += rm1 * ia2;
+            if (1.0 + rm1 < 0) nd = 1;
         }
         if (nu_mode == 1) nd = anynode;
         if (nu_mode == 2) nd = 1;
@@ -975,6 +1029,7 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
     double* Ai64 = g64 + (long)N * ns;           // [2][ns][ns]   transposed inverses AiT[c][k]
     double* Z64 = Ai64 + 2L * ns * ns;           // [2][ns][Nb]   Z[c][mu] = sum_k C[mu][k] Ainv[k][c]
     const double* pos = LDSD(s.l_pos);
+    const double* st64 = LDSD(s.l_ev);           // the walker's lattice step vectors
     double* F = LDSD(s.l_F);
     double* R64 = F;                             // [P]
     double* gD64 = F + P;                        // [N][4]
@@ -1021,7 +1076,7 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
                     if (ty == 4) {
                         for (int q = 1; q <= 6; ++q) {
                             double pq[3];
-                            point_q(ri, q, a, pq);
+                            point_qv(ri, q, st64, pq);
                             const double dx = pq[0] - rec[0], dy = pq[1] - rec[1], dz = pq[2] - rec[2];
                             t[q - 1] += z * basis_value_d(ty, al, dx, dy, dz, dx * dx + dy * dy + dz * dz);
                         }
@@ -1032,10 +1087,13 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
                         const double f0 = ty == 0 ? 1.0 : d[ax];
 #pragma unroll
                         for (int cc = 0; cc < 3; ++cc) {
-                            const double x = fmin(fmax(-2.0 * al * a * d[cc], -700.0), 700.0);
+                            const double sdc = d[0] * st64[3 * cc] + d[1] * st64[3 * cc + 1] +
+                                               d[2] * st64[3 * cc + 2];
+                            const double x = fmin(fmax(-2.0 * al * sdc, -700.0), 700.0);
                             const double tc = exp(x);
-                            const double fp = (ty != 0 && ax == cc) ? f0 + a : f0;
-                            const double fm = (ty != 0 && ax == cc) ? f0 - a : f0;
+                            const double sp = ty != 0 ? st64[3 * cc + (ax < 0 ? 0 : ax)] : 0.0;
+                            const double fp = f0 + sp;
+                            const double fm = f0 - sp;
                             t[2 * cc] += z * (fp * (e * (K * tc)));
                             t[2 * cc + 1] += z * (fm * (e * (K * recip(tc))));
                         }
@@ -1076,9 +1134,9 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
     // Jastrow: exponent changes of the 6N moves, gradients and Laplacians;
     // potentials and V_ee.  Two threads per electron (adjacent lanes, partners
     // k = h, h + 2, ...), combined over the lane pair; the six neighbours'
-    // squared distances from each pair's difference d as |d|^2 + a^2 +- 2a d_c
+    // squared distances from each pair's difference d as |d|^2 + a^2 +- 2 d.st_c
     const int K = N + s.M;
-    const double aa = a * a, ta = 2.0 * a;
+    const double aa = a * a;
     double vee = 0.0;
     for (int base = 0; base < 2 * N; base += nt) {
         const int it = base + tid, j = it >> 1, h = it & 1;
@@ -1105,8 +1163,10 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
                 const double b2 = r2 + aa;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    dq[2 * c] += pade_u(pj, sqrt(fmax(b2 + ta * d[c], 0.0))) - u;
-                    dq[2 * c + 1] += pade_u(pj, sqrt(fmax(b2 - ta * d[c], 0.0))) - u;
+                    const double t2 = 2.0 * (d[0] * st64[3 * c] + d[1] * st64[3 * c + 1] +
+                                             d[2] * st64[3 * c + 2]);
+                    dq[2 * c] += pade_u(pj, sqrt(fmax(b2 + t2, 0.0))) - u;
+                    dq[2 * c + 1] += pade_u(pj, sqrt(fmax(b2 - t2, 0.0))) - u;
                 }
             }
             if (!isel) {
@@ -1185,7 +1245,7 @@ __device__ __noinline__ int mixed_heat_bath(const DevMix* __restrict__ dm, doubl
     const double t = xi * tot;
     int found = s.P, lastpos = -1;
     for (int p = p0; p < p1; ++p) {
-        const double r = (double)R[p];
+        const double r = 1.0 + (double)R[p];
         if (r > 0) {
             c += r;
             lastpos = p;
@@ -1214,10 +1274,12 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
     const double ia = 1.0 / a;
     double* pos = LDSD(s.l_pos);
     float* Rdet = LDSF(s.l_Rdet);
-    const float Rd = Rdet[p];
+    const float Rd = 1.0f + Rdet[p];
     const double rold[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
-    double rnew[3] = {rold[0], rold[1], rold[2]};
-    rnew[d] = rnew[d] + (sg ? -a : a);
+    const double* st64 = LDSD(s.l_ev);
+    const float* st32 = LDSF(s.l_ev + 72);
+    double rnew[3];
+    point_qv(rold, 2 * d + sg + 1, st64, rnew);
 
     // new orbital rows of electron i first: the basis block is then free for
     // the LDS copy of the moved spin's inverse
@@ -1233,7 +1295,7 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
     float* u = tmp;               // [ns] accepted orbital row
     float* rowc = tmp + ns;       // [ns] column c of the inverse
     float* beta = tmp + 2 * ns;   // [ns]
-    const int q = 6 * c + (p - 6 * i);
+    const int q2 = 6 * c + 2 * d;                 // difference and second-difference rows
     typedef float f4v __attribute__((ext_vector_type(4)));
     // rows of the inverse in float4 pieces when that still gives every lane
     // a piece
@@ -1262,8 +1324,10 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
             AiL[r * lda + idx - r * ns] = gld(Ai + idx);
         }
     }
+    // the accepted orbital row u = phi(r_i +- st_d) = phi(r_i) + (+-D + S) / 2
     for (int k = tid; k < n; k += nt) {
-        u[k] = gld(Phi + (long)k * 6 * ns + q);
+        const float dd = gld(Phi + (long)k * 6 * ns + q2), ss = gld(Phi + (long)k * 6 * ns + q2 + 1);
+        u[k] = gld(st + s.g_Arow + (long)i * ns + k) + 0.5f * (sg ? ss - dd : ss + dd);
         rowc[k] = gld(Ai + (long)c * ns + k);
     }
     __syncthreads();
@@ -1283,7 +1347,10 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
         }
     }
     __syncthreads();
-    const float iR = 1.0f / Rd;
+    // the Sherman-Morrison denominator u . Ainv[:, c] as the dot product itself
+    // (beta[c]), so that the updated inverse is that of the updated rows to
+    // FP32 rounding even where the ratio is small
+    const float iR = 1.0f / beta[c];
     if (vec4) {
         // four consecutive k per lane, one float4 store (columns k >= n of a
         // smaller spin block are padding and receive zeros)
@@ -1330,7 +1397,7 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
     // potentials at the new position, the exponent changes of its six next
     // moves (from the same FP64 difference), and the pair-term changes of the
     // partners; one block reduction of the 13 sums
-    const float aa = (float)(a * a), ta = (float)(2.0 * a);
+    const float aa = (float)(a * a);
     double g0 = 0, g1 = 0, g2 = 0, l = 0, dvee = 0, nu = 0, nua = 0;
     float dq[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     #pragma unroll 1
@@ -1349,7 +1416,7 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
             g0 += dnr * n0; g1 += dnr * n1; g2 += dnr * n2;
             l += lpn;
             const float f[3] = {(float)n0, (float)n1, (float)n2};
-            neighbour_du(prm, f, (float)rn2, aa, ta, dq);
+            neighbour_du(prm, f, (float)rn2, aa, st32, dq);
             if (isel) {
                 const double o0 = rold[0] - pk[0], o1 = rold[1] - pk[1], o2 = rold[2] - pk[2];
                 const double ro2 = o0 * o0 + o1 * o1 + o2 * o2, iro = rsqrt_nr(ro2);
@@ -1395,10 +1462,9 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
     for (int qp = tid; qp < s.P; qp += (int)blockDim.x) {
         const int j = qp / 6;
         if (j == i) continue;
-        const int dd = (qp / 2) % 3, s2 = qp % 2;
         const PadeF prm = pade_row(s, mee_row(s, i, j));
-        double r2[3] = {pos[3 * j], pos[3 * j + 1], pos[3 * j + 2]};
-        r2[dd] = r2[dd] + (s2 ? -a : a);
+        double r2[3];
+        point_qv(pos + 3 * j, qp - 6 * j + 1, st64, r2);
         const float n0 = (float)(r2[0] - rnew[0]), n1 = (float)(r2[1] - rnew[1]),
                     n2 = (float)(r2[2] - rnew[2]);
         const float o0 = (float)(r2[0] - rold[0]), o1 = (float)(r2[1] - rold[1]),
@@ -1414,7 +1480,7 @@ __device__ __noinline__ bool mixed_apply_move(const DevMix* __restrict__ dm, flo
         Jl[i] = (float)l;
         LDSD(s.l_nue)[i] = nu; LDSD(s.l_nua)[i] = nua;
         LDSD(s.l_scal)[kScVee] += dvee;
-        pos[3 * i + d] = rnew[d];
+        pos[3 * i] = rnew[0]; pos[3 * i + 1] = rnew[1]; pos[3 * i + 2] = rnew[2];
     }
     __syncthreads();
     mixed_full_ratios(s);
@@ -1440,9 +1506,23 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
     float* st = s.state + (long)wid * s.stride;
     double* pos = LDSD(s.l_pos);
     for (int q = tid; q < 3 * s.N; q += (int)blockDim.x) pos[q] = s.pos[(long)wid * 3 * s.N + q];
+    // lattice step vectors of this walker for this phase: the coordinate axes,
+    // or a random orientation drawn from its own Philox stream
+    if (tid == 0) {
+        double stp[9];
+        if (pa.rotate) lattice_steps(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb, pa.a, stp);
+        else lattice_steps_fixed(pa.a, stp);
+        for (int q = 0; q < 9; ++q) {
+            LDSD(s.l_ev)[q] = stp[q];
+            LDSF(s.l_ev + 72)[q] = (float)stp[q];
+        }
+    }
     __syncthreads();
     const double a = pa.a;
-    if (build) {
+    // every electron's orbital rows from its position: for new walkers, and
+    // at every phase of a randomized lattice (the neighbour rows depend on the
+    // orientation drawn for the phase)
+    if (build || pa.rotate) {
         for (int j = 0; j < s.N; ++j) {
             const double r[3] = {pos[3 * j], pos[3 * j + 1], pos[3 * j + 2]};
             mixed_rows(&s, j, r, a);
@@ -1530,7 +1610,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
             const double* R64 = LDSD(s.l_F);
             double e = 0.0;
             for (int p = tid; p < s.P; p += (int)blockDim.x)
-                e = fmax(e, fabs((double)R[p] - R64[p]) / fmax(1.0, fabs(R64[p])));
+                e = fmax(e, fabs((1.0 + (double)R[p]) - R64[p]) / fmax(1.0, fabs(R64[p])));
             e = block_max(e, LDSD(s.l_red));
             if (tid == 0) {
                 double* dg = s.diag + (long)wid * 4;

@@ -3,8 +3,9 @@ Laplacian rotate with random angles; reading: one random rotation per walker
 and projection phase from the walker's own Philox stream) against the FP64
 oracle: rotation draws, rotated moves and positions bit-exact, e_L within
 1e-9 Ha, weights to 1e-11, over two phases with the reconfiguration between
-them (each phase draws new orientations); the exact hydrogenic eigenstate
-keeps e_L = -1/2 in every orientation; both schemes sample the same state."""
+them (each phase draws new orientations), in FP64 and in the mixed precisions;
+the exact hydrogenic eigenstate keeps e_L = -1/2 in every orientation; both
+schemes sample the same state."""
 import numpy as np
 import pytest
 
@@ -73,13 +74,44 @@ def test_rotated_schemes_agree_h2():
     assert abs(z) < 3.5
 
 
+@pytest.mark.parametrize("prec,sysname,nw", [("fp32", "c1", 48), ("bf16", "c3", 8)])
+def test_rotated_mixed_precision(prec, sysname, nw):
+    """The mixed-precision kernel on rotated lattices: positions bit-exact
+    (decisions inside the precision's band adopted), the FP64 estimator
+    values within 1e-9 Ha, two phases with the reconfiguration between."""
+    from test_gpu_mixed import BAND, LW_PER_STEP
+    d = I.c1_system(n_walkers=nw) if sysname == "c1" else I.c3_system(n_walkers=nw)
+    say("case rotated lattice, mixed", prec, sysname, nw, "walkers")
+    nproj = 40
+    h, d2, prm = make_handle(d, "lb", nw, n_proj=nproj, precision=prec, rotate=True)
+    e0 = h.e0()
+    pos = d2["init_pos"][:nw].copy()
+    lw = np.zeros(nw)
+    for j in range(2):
+        h.step()
+        g = h.walkers(trace=True)
+        res = compare_phase(d2, prm, "lb", j, e0, pos, lw, g, np.arange(nw), band=BAND[prec])
+        c = res["cnt"]
+        say(prec, j, {k: v for k, v in res.items() if k != "oracle"})
+        assert c["hard_mismatch"] == 0 and c["singular"] == 0, res
+        assert res["pos_equal"] and res["lw_dead_equal"], res
+        assert res["eL_err"] < 1e-9 and res["lw_err"] < LW_PER_STEP[prec] * nproj, res
+        for w in (0, nw - 1):
+            R = O.rotation(prm.seed, 0, w, j)
+            k = (g["pos"][w] - pos[w]) @ R / prm.a
+            assert np.allclose(k, np.round(k), atol=1e-9)
+        bs = h.branch()
+        after = h.walkers()
+        pos = after["pos"].copy()
+        lw = np.zeros(nw)
+        e0 = bs.e0
+    h.close()
+
+
 def test_rotation_unsupported_paths():
     d = I.c1_system(n_walkers=8)
     d2 = dict(d)
     d2["n_walkers_run"] = 8
-    with pytest.raises(B.LrdmcError) as ei:
-        B.Handle(d2, B.params_for(d2, "lb", precision="fp32", rotate=True))
-    assert ei.value.code == -6
     h = B.Handle(d2, B.params_for(d2, "lb", rotate=True, n_proj=4))
     with pytest.raises(B.LrdmcError) as ei:
         h.walker_derivs()
