@@ -33,7 +33,7 @@ RNG_MOVE, RNG_PERSIST, RNG_COMB, RNG_INIT, RNG_ROTATE = 0, 1, 2, 3, 4
 CNT_NAMES = ["decisions", "ambig_adopted", "hard_mismatch", "node_ambig",
              "neg_weight", "no_move", "singular", "iters"]
 SC = dict(bbar=0, vsf=1, W=2, eL=3, eL_cont=4, vee=5, vii=6, logabs=7, sign=8,
-          minrel=9)
+          minrel=9, vnl=10)
 
 
 def build(force=False):
@@ -55,7 +55,9 @@ class _Sys(ct.Structure):
                 ("Nb", ct.c_int), ("batom", ct.c_void_p), ("btype", ct.c_void_p),
                 ("bexp", ct.c_void_p), ("Norb", ct.c_int), ("C", ct.c_void_p),
                 ("Nup", ct.c_int), ("Ndn", ct.c_int), ("nspec", ct.c_int),
-                ("jas", ct.c_void_p)]
+                ("jas", ct.c_void_p), ("necp", ct.c_int), ("ecp_atom", ct.c_void_p),
+                ("ecp_l", ct.c_void_p), ("ecp_pow", ct.c_void_p), ("ecp_coef", ct.c_void_p),
+                ("ecp_exp", ct.c_void_p), ("ecp_rcut", ct.c_void_p)]
 
 
 class _Prm(ct.Structure):
@@ -130,6 +132,31 @@ def _p(a):
     return None if a is None else a.ctypes.data
 
 
+def ecp_arrays(d):
+    """Non-local pseudopotential arrays of a system dict (empty without one):
+    per term atom, channel l, power k, coefficient c and exponent beta of
+    c r^k exp(-beta r^2), and the per-atom cutoff radius.  The cutoff spheres
+    must not overlap (each electron is inside at most one)."""
+    M = np.asarray(d["atom_pos"]).shape[0]
+    if "ecp_atom" not in d or len(d["ecp_atom"]) == 0:
+        return (np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32),
+                np.zeros(0), np.zeros(0), np.zeros(M))
+    out = (np.ascontiguousarray(d["ecp_atom"], np.int32), np.ascontiguousarray(d["ecp_l"], np.int32),
+           np.ascontiguousarray(d["ecp_pow"], np.int32), np.ascontiguousarray(d["ecp_coef"], np.float64),
+           np.ascontiguousarray(d["ecp_exp"], np.float64), np.ascontiguousarray(d["ecp_rcut"], np.float64))
+    R = np.asarray(d["atom_pos"], np.float64)
+    rc = out[5]
+    for I in range(M):
+        for J in range(I + 1, M):
+            if rc[I] > 0 and rc[J] > 0 and np.linalg.norm(R[I] - R[J]) <= rc[I] + rc[J]:
+                raise ValueError("pseudopotential cutoff spheres of atoms %d and %d overlap" % (I, J))
+    if np.any((out[1] < 0) | (out[1] > 2)) or np.any((out[2] < 0) | (out[2] > 2)):
+        raise ValueError("pseudopotential channel l and power must be 0, 1 or 2")
+    if np.any(rc[out[0]] <= 0):
+        raise ValueError("a pseudopotential term belongs to an atom without a cutoff radius")
+    return out
+
+
 class System:
     """Holds the generator's arrays alive and the C view of them."""
 
@@ -139,11 +166,16 @@ class System:
             "atom_pos", "atom_charge", "atom_core", "core_rc", "atom_species",
             "basis_atom", "basis_type", "basis_exp", "mo_coeff", "jastrow")]
         R, Z, core, rc, spec, ba, bt, be, C, jas = self.keep
+        ecp = ecp_arrays(d)
+        self.keep += list(ecp)
+        e_atom, e_l, e_pow, e_coef, e_exp, e_rcut = ecp
+        ne = e_atom.shape[0]
         self.c = _Sys(R.shape[0], _p(R), _p(Z), _p(core), _p(rc), _p(spec), be.shape[0],
                       _p(ba), _p(bt), _p(be), C.shape[1], _p(C), int(d["n_up"]),
-                      int(d["n_dn"]), jas.shape[0] - 2, _p(jas))
+                      int(d["n_dn"]), jas.shape[0] - 2, _p(jas), ne, _p(e_atom), _p(e_l),
+                      _p(e_pow), _p(e_coef), _p(e_exp), _p(e_rcut) if ne else None)
         self.N = int(d["n_up"] + d["n_dn"])
-        self.P = 6 * self.N
+        self.P = (12 if ne else 6) * self.N
 
     def params(self, a=None, tau=None, nproj=None, nu_opt_mode=None, seed=None,
                sysid=None, band=1e-12, rotate=False):

@@ -17,7 +17,9 @@
  * Conventions (see the accompanying design notes for the readings taken
  * where the paper is silent):
  *   electrons 0..n_up-1 are spin up; proposal p = (3 i + d) * 2 + s moves
- *   electron i by +a (s = 0) or -a (s = 1) along axis d.
+ *   electron i by +a (s = 0) or -a (s = 1) along axis d; with a non-local
+ *   pseudopotential, proposal 6N + 6 i + q moves electron i to quadrature
+ *   point q of the atom whose cutoff sphere holds it.
  */
 #include <math.h>
 #include <pthread.h>
@@ -44,6 +46,17 @@ typedef struct {
     int Nup, Ndn;
     int nspec;
     const double *jas;        /* [2+nspec][3] (A, B, b) */
+    /* semi-local pseudopotential, non-local channels: term t belongs to atom
+     * ecp_atom[t], channel l = ecp_l[t] (0, 1, 2) and contributes
+     * ecp_coef[t] r^ecp_pow[t] exp(-ecp_exp[t] r^2) to v_l(r) of that atom
+     * for r < ecp_rcut[atom]; necp = 0: no non-local part */
+    int necp;
+    const int32_t *ecp_atom;  /* [necp] */
+    const int32_t *ecp_l;     /* [necp] */
+    const int32_t *ecp_pow;   /* [necp] 0, 1 or 2 */
+    const double *ecp_coef;   /* [necp] */
+    const double *ecp_exp;    /* [necp] */
+    const double *ecp_rcut;   /* [M] cutoff radius of each atom's channels, 0: none */
 } orc_system;
 
 typedef struct {
@@ -358,6 +371,65 @@ static double ion_ion(const orc_system *s)
     return v;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Non-local pseudopotential under the determinant locality approximation   */
+/* (App. D: the non-local elements V^nl_{x',x} of the FN Hamiltonian, with  */
+/* the guiding-function ratio replaced by the determinant ratio D(x')/D(x))  */
+/* ------------------------------------------------------------------------ */
+/* The semi-local operator sum_l v_l(r) sum_m |lm><lm| of atom I acting on
+ * electron i is applied with the 6-point octahedral quadrature of the sphere
+ * of radius r = |r_i - R_I| around R_I: points R_I +- r u_d (u_d the walker's
+ * lattice versors, column d of its rotation; the coordinate axes without
+ * one), weights 1/6, exact for spherical harmonics of degree <= 3.  Point q
+ * (0..5 = +u0, -u0, +u1, -u1, +u2, -u2) is the configuration x' with electron
+ * i moved there, and its element is
+ *   V_q = sum_l (2l + 1)/6 v_l(r) P_l(cos theta_q),
+ * theta_q the angle between r_i - R_I and the point's direction. */
+
+/* distance of r from atom I, each product and sum rounded in the order written */
+static double atom_distance(const orc_system *s, int I, const double r[3], double dv[3])
+{
+    const double *RI = s->R + 3 * I;
+    dv[0] = r[0] - RI[0]; dv[1] = r[1] - RI[1]; dv[2] = r[2] - RI[2];
+    return sqrt((dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2]);
+}
+
+/* the atom whose cutoff sphere holds r (the spheres do not overlap), or -1 */
+static int nl_atom(const orc_system *s, const double r[3])
+{
+    for (int I = 0; I < s->M; I++) {
+        double rc = s->ecp_rcut ? s->ecp_rcut[I] : 0.0, dv[3];
+        if (rc > 0 && atom_distance(s, I, r, dv) < rc) return I;
+    }
+    return -1;
+}
+
+/* quadrature point q of the sphere of radius r around atom I */
+static void nl_point(const orc_system *s, int I, double r, const double *rot, int q,
+                     double out[3])
+{
+    const double *RI = s->R + 3 * I;
+    int d = q / 2, sg = q % 2;
+    for (int x = 0; x < 3; x++) {
+        double u = rot ? rot[3 * x + d] : (x == d ? 1.0 : 0.0);
+        double t = r * u;
+        out[x] = RI[x] + (sg ? -t : t);
+    }
+}
+
+/* V_q from the channels of atom I at distance r and cos theta_q */
+static double nl_element(const orc_system *s, int I, double r, double cth)
+{
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = 0; t < s->necp; t++) {
+        if (s->ecp_atom[t] != I) continue;
+        double rp = s->ecp_pow[t] == 0 ? 1.0 : (s->ecp_pow[t] == 1 ? r : r * r);
+        v[s->ecp_l[t]] += s->ecp_coef[t] * rp * exp(-s->ecp_exp[t] * r * r);
+    }
+    double P1 = cth, P2 = 0.5 * (3.0 * cth * cth - 1.0);
+    return (v[0] + 3.0 * v[1] * P1 + 5.0 * v[2] * P2) / 6.0;
+}
+
 /* log|Psi_G| and sign, by LU determinants and the Jastrow sum.  Returns 0 or
  * -1 for a singular Slater matrix. */
 int orc_log_psi(const orc_system *s, const double *pos, double *logabs, double *sign)
@@ -392,23 +464,27 @@ int orc_log_psi(const orc_system *s, const double *pos, double *logabs, double *
 /* ------------------------------------------------------------------------ */
 enum {
     SC_BBAR = 0, SC_VSF, SC_W, SC_EL, SC_ELCONT, SC_VEE, SC_VII, SC_LOGABS,
-    SC_SIGN, SC_MINREL, SC_LEN = 16
+    SC_SIGN, SC_MINREL, SC_VNL, SC_LEN = 16
 };
 
-/* Outputs (any pointer may be NULL except scal):
- *   R[P]     Psi_G(x')/Psi_G(x) for every proposal
- *   Rdet[P]  determinant part of the ratio, dJ[P] Jastrow exponent change
+/* Outputs (any pointer may be NULL except scal); PT = 6N, or 12N with a
+ * non-local pseudopotential:
+ *   R[PT]    Psi_G(x')/Psi_G(x) for every lattice move, then
+ *            -2 a^2 V_q D(x')/D(x) for every non-local proposal
+ *   Rdet[PT] determinant part of the ratio, dJ[PT] Jastrow exponent change
+ *            (0 for the non-local proposals)
  *   lap[N]   continuum lap_i Psi_G / Psi_G
  *   grad[N][3] grad_i Psi_G / Psi_G
  *   nu_zv[N], nu_opt[N], node[N]
  *   scal[SC_LEN]: bbar, V_sf, W, e_L, e_L(continuum), V_ee, V_ii, log|Psi|,
- *                 sign, min |R_p| / max |R_p|
+ *                 sign, min |R_p| / max |R_p| over the lattice moves,
+ *                 non-local energy sum_{i,q} V_q D(x')/D(x)
  * Returns 0, or -1 for a singular Slater matrix. */
 int orc_eval_rot(const orc_system *s, const orc_params *prm, const double *rot,
                  const double *pos, double *R, double *Rdet, double *dJ, double *lap,
                  double *grad, double *nu_zv, double *nu_opt, int32_t *node, double *scal)
 {
-    const int N = s->Nup + s->Ndn, P = 6 * N, Nb = s->Nb;
+    const int N = s->Nup + s->Ndn, P = 6 * N, PT = s->necp ? 12 * N : P, Nb = s->Nb;
     const double a = prm->a;
     double st[3][3];
     lattice_steps(rot, a, st);
@@ -419,7 +495,8 @@ int orc_eval_rot(const orc_system *s, const orc_params *prm, const double *rot,
     double *chig = (double *)malloc(sizeof(double) * Nb * 3);
     double *chil = (double *)malloc(sizeof(double) * Nb);
     double *phi = (double *)malloc(sizeof(double) * (s->Norb + 1));
-    double *Rl = (double *)malloc(sizeof(double) * P);
+    double *Rl = (double *)malloc(sizeof(double) * PT);
+    int *nlneg = (int *)calloc(N, sizeof(int));
     double *lapl = (double *)malloc(sizeof(double) * N);
     double *nuzv = (double *)malloc(sizeof(double) * N);
     double *nuop = (double *)malloc(sizeof(double) * N);
@@ -463,6 +540,40 @@ int orc_eval_rot(const orc_system *s, const orc_params *prm, const double *rot,
             }
     }
 
+    /* non-local proposals (DLA): electron i moved to quadrature point q of the
+     * atom whose sphere holds it, entry -2 a^2 V_q D(x')/D(x) in the units of
+     * the kinetic ratios (a kinetic move weighs R_p / (2 a^2)); slots of
+     * electrons outside every sphere hold 0 */
+    double vnl = 0.0;
+    for (int i = 0; i < N && PT > P; i++) {
+        int sp = i >= s->Nup, n = ns[sp], c = i - off[sp];
+        for (int q = 0; q < 6; q++) {
+            Rl[P + 6 * i + q] = 0.0;
+            if (Rdet) Rdet[P + 6 * i + q] = 0.0;
+            if (dJ) dJ[P + 6 * i + q] = 0.0;
+        }
+        int I = nl_atom(s, pos + 3 * i);
+        if (I < 0) continue;
+        double dv[3];
+        double r = atom_distance(s, I, pos + 3 * i, dv);
+        for (int q = 0; q < 6; q++) {
+            int d = q / 2;
+            double xq[3];
+            nl_point(s, I, r, rot, q, xq);
+            orc_basis(s, xq, chi, 0, 0);
+            orbitals(s, chi, n, phi);
+            double rd = 0.0;
+            for (int k = 0; k < n; k++) rd += phi[k] * Ainv[sp][k * n + c];
+            double ud = rot ? dv[0] * rot[d] + dv[1] * rot[3 + d] + dv[2] * rot[6 + d] : dv[d];
+            double cth = (q % 2 ? -ud : ud) / r;
+            double V = nl_element(s, I, r, cth);
+            Rl[P + 6 * i + q] = -2.0 * a * a * V * rd;
+            if (Rdet) Rdet[P + 6 * i + q] = rd;
+            vnl += V * rd;
+            if (rd < 0) nlneg[i] = 1;
+        }
+    }
+
     /* continuum local energy pieces */
     double vee = 0.0, vii = ion_ion(s), elc = 0.0;
     for (int i = 0; i < N; i++)
@@ -495,18 +606,23 @@ int orc_eval_rot(const orc_system *s, const orc_params *prm, const double *rot,
         nuclear_potential(s, pos + 3 * i, a, &nue[i], &nua[i]);
         elc += -0.5 * lapl[i] + nue[i];
     }
-    elc += vee + vii;
+    elc += vee + vii + vnl;
 
     /* lattice terms with the fixed-node spin-flip contributions (App. D) */
     double bsum = 0.0, vsum = 0.0, maxabs = 0.0, minabs = INFINITY;
     int anynode = 0;
-    for (int p = 0; p < P; p++) {
+    for (int p = 0; p < PT; p++) {
         if (Rl[p] > 0) bsum += Rl[p];
-        else if (Rl[p] < 0) { vsum += -Rl[p]; anynode = 1; }
+        else if (Rl[p] < 0) vsum += -Rl[p];
+        if (p >= P) continue;
+        if (Rl[p] < 0) anynode = 1;
         double m = fabs(Rl[p]);
         if (m > maxabs) maxabs = m;
         if (m < minabs) minabs = m;
     }
+    /* a non-local proposal crosses the node when its determinant ratio is
+     * negative (the Jastrow factor is positive) */
+    for (int i = 0; i < N; i++) if (nlneg[i]) anynode = 1;
     double inv2a2 = 1.0 / (2.0 * a * a);
     double bbar = bsum * inv2a2, vsf = vsum * inv2a2;
     double sum_opt = 0.0;
@@ -518,6 +634,7 @@ int orc_eval_rot(const orc_system *s, const orc_params *prm, const double *rot,
             lapA += (r - 1.0) / (a * a);
             if (r < 0) nd = 1;
         }
+        if (nlneg[i]) nd = 1;
         if (prm->nu_opt_mode == 1) nd = anynode;
         if (prm->nu_opt_mode == 2) nd = 1;
         nuzv[i] = nue[i] + 0.5 * (lapA - lapl[i]);
@@ -529,7 +646,7 @@ int orc_eval_rot(const orc_system *s, const orc_params *prm, const double *rot,
     double W = 3.0 * N / (a * a) + sum_opt + vee + vsf + vii;
     double eL = W - bbar;
 
-    if (R) memcpy(R, Rl, sizeof(double) * P);
+    if (R) memcpy(R, Rl, sizeof(double) * PT);
     if (lap) memcpy(lap, lapl, sizeof(double) * N);
     if (nu_zv) memcpy(nu_zv, nuzv, sizeof(double) * N);
     if (nu_opt) memcpy(nu_opt, nuop, sizeof(double) * N);
@@ -538,10 +655,12 @@ int orc_eval_rot(const orc_system *s, const orc_params *prm, const double *rot,
     scal[SC_ELCONT] = elc; scal[SC_VEE] = vee; scal[SC_VII] = vii;
     scal[SC_LOGABS] = logabs; scal[SC_SIGN] = sign;
     scal[SC_MINREL] = maxabs > 0 ? minabs / maxabs : 0.0;
+    scal[SC_VNL] = vnl;
     free(nua); free(nue);
 done:
     free(Ainv[0]); free(Ainv[1]);
-    free(chi); free(chig); free(chil); free(phi); free(Rl); free(lapl); free(nuzv); free(nuop);
+    free(chi); free(chig); free(chil); free(phi); free(Rl); free(nlneg); free(lapl); free(nuzv);
+    free(nuop);
     return rc;
 }
 
@@ -554,7 +673,7 @@ int orc_eval(const orc_system *s, const orc_params *prm, const double *pos,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Heat-bath choice among the 6N moves, p_{x',x} of the load-balanced split  */
+/* Heat-bath choice among the proposals, p_{x',x} of the load-balanced split */
 /* (Sec. II.C) and of Algorithm 1's move line                                */
 /* ------------------------------------------------------------------------ */
 /* returns the chosen proposal (or -1 if no move has positive weight) and the
@@ -594,9 +713,20 @@ static int choice_within_band(int P, const double *R, double xi, int q, double b
     return (t >= lo - band * tot) && (t < hi + band * tot);
 }
 
-static void apply_move(double *pos, int p, const double *rot, double a)
+/* Move p: a lattice move (p < 6N) or a non-local move (p = 6N + 6i + q:
+ * electron i to quadrature point q of the atom whose sphere holds it). */
+static void apply_move(const orc_system *s, double *pos, int p, const double *rot, double a)
 {
+    const int N = s->Nup + s->Ndn;
     double st[3][3], r[3];
+    if (p >= 6 * N) {
+        int i = (p - 6 * N) / 6, I = nl_atom(s, pos + 3 * i);
+        double dv[3];
+        double rr = atom_distance(s, I, pos + 3 * i, dv);
+        nl_point(s, I, rr, rot, (p - 6 * N) % 6, r);
+        for (int x = 0; x < 3; x++) pos[3 * i + x] = r[x];
+        return;
+    }
     lattice_steps(rot, a, st);
     int i = p / 6;
     displaced(pos + 3 * i, st, p % 6, r);
@@ -616,7 +746,7 @@ int orc_lb_phase(const orc_system *s, const orc_params *prm, uint64_t slot, uint
                  double E0, double *pos, double *lw, double *eL_out, double *W_out,
                  const int32_t *follow, int32_t *moves_out, int64_t *cnt)
 {
-    const int N = s->Nup + s->Ndn, P = 6 * N;
+    const int N = s->Nup + s->Ndn, P = s->necp ? 12 * N : 6 * N;
     double *R = (double *)malloc(sizeof(double) * P);
     double sc[SC_LEN], rotm[9];
     const double *rot = 0;
@@ -641,7 +771,7 @@ int orc_lb_phase(const orc_system *s, const orc_params *prm, uint64_t slot, uint
             q = follow[k];
         }
         if (moves_out) moves_out[k] = q;
-        if (q >= 0) apply_move(pos, q, rot, prm->a);
+        if (q >= 0) apply_move(s, pos, q, rot, prm->a);
     }
     if (!rc) {
         if (orc_eval_rot(s, prm, rot, pos, 0, 0, 0, 0, 0, 0, 0, 0, sc)) { cnt[CNT_SINGULAR]++; rc = -1; }
@@ -670,7 +800,7 @@ int orc_conv_phase(const orc_system *s, const orc_params *prm, uint64_t slot, ui
                    const int32_t *follow, int32_t *moves_out, int cap, int *n_iter,
                    int64_t *cnt)
 {
-    const int N = s->Nup + s->Ndn, P = 6 * N;
+    const int N = s->Nup + s->Ndn, P = s->necp ? 12 * N : 6 * N;
     double *R = (double *)malloc(sizeof(double) * P);
     double sc[SC_LEN], rotm[9];
     const double *rot = 0;
@@ -712,7 +842,7 @@ int orc_conv_phase(const orc_system *s, const orc_params *prm, uint64_t slot, ui
             q = follow[it - 1];
         }
         if (moves_out && it - 1 < cap) moves_out[it - 1] = q;
-        if (q >= 0) apply_move(pos, q, rot, prm->a);
+        if (q >= 0) apply_move(s, pos, q, rot, prm->a);
     }
     *n_iter = it;
     cnt[CNT_ITERS] += it;

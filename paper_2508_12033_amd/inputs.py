@@ -32,6 +32,12 @@ System layout (all arrays numpy, C-contiguous):
                            row 2+s = electron-nucleus pairs of species s
   init_pos     [Nw,N,3] f64  initial electron positions of every walker
   a, tau, n_proj, n_walkers, seed, system_id
+Optional non-local pseudopotential (semi-local channels, App. D non-local
+elements; synthetic parameters, since ccECP tables are not available):
+  ecp_atom, ecp_l, ecp_pow [T] i32, ecp_coef, ecp_exp [T] f64: term t adds
+                           coef r^pow exp(-exp r^2) to channel l of its atom
+  ecp_rcut     [M]   f64   radius inside which an atom's channels act (0: none;
+                           the spheres of different atoms do not overlap)
 """
 from __future__ import annotations
 
@@ -257,6 +263,44 @@ def one_electron_system(kind="gauss", n_walkers=256, a=0.4, seed=BASE_SEED + 8,
         jastrow=np.zeros((3, 3)), init_pos=init, a=a,
         tau=20.0 * a * a / 3.0, n_proj=20, n_walkers=n_walkers, seed=seed,
         system_id=0, lattice_origin=o))
+
+
+# Synthetic non-local channels (l, power, coefficient, exponent): a repulsive
+# s channel with an attractive r^2 tail and an attractive p channel, so that
+# both signs of the non-local elements occur; they decay below 1e-2 Ha by the
+# cutoff radius 1.3 bohr.
+ECP_TERMS = ((0, 0, 10.0, 5.0), (0, 2, -3.0, 4.0), (1, 0, -5.0, 4.5))
+
+
+def with_ecp(d, atoms, terms=ECP_TERMS, rcut=1.3):
+    """Copy of system d with the non-local channels `terms` on every atom in
+    `atoms`, acting inside radius rcut (shrunk to 0.49 of the closest pair of
+    those atoms, so that the spheres never overlap)."""
+    d = dict(d)
+    R = np.asarray(d["atom_pos"], np.float64)
+    atoms = list(atoms)
+    for a_ in range(len(atoms)):
+        for b_ in range(a_ + 1, len(atoms)):
+            rcut = min(rcut, 0.49 * float(np.linalg.norm(R[atoms[a_]] - R[atoms[b_]])))
+    ea, el, ep, ec, ee = [], [], [], [], []
+    for I in atoms:
+        for (l, pw, c, b) in terms:
+            ea.append(I); el.append(l); ep.append(pw); ec.append(c); ee.append(b)
+    rc = np.zeros(R.shape[0])
+    rc[atoms] = rcut
+    d.update(ecp_atom=np.array(ea, np.int32), ecp_l=np.array(el, np.int32),
+             ecp_pow=np.array(ep, np.int32), ecp_coef=np.array(ec, np.float64),
+             ecp_exp=np.array(ee, np.float64), ecp_rcut=rc)
+    d["name"] = d.get("name", "sys") + "_ecp"
+    return d
+
+
+def c1_ecp_system(n_walkers=4096, seed=BASE_SEED + 1):
+    """The 16-electron system of c1_system with the synthetic non-local
+    channels on its two smooth cores (C-like and O-like, 7.0 bohr apart),
+    cutoff radius 1.3 bohr."""
+    d = c1_system(n_walkers, seed)
+    return with_ecp(d, np.where(d["atom_core"] == SOFTCORE)[0])
 
 
 CONFIGS = {
