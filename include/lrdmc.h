@@ -114,6 +114,30 @@ typedef struct lrdmc_system {
                                     e-e, row 1 antiparallel e-e, row 2+s e-n */
     int32_t n_walkers;           /* walkers of this system */
     uint64_t system_id;          /* second Philox key word */
+    /* Non-local (semi-local) pseudopotential, App. D: the non-local elements
+     * V^nl_{x',x} of the fixed-node Hamiltonian under the determinant
+     * locality approximation (the guiding-function ratio of a non-local
+     * element replaced by the determinant ratio D(x')/D(x)).  Term t adds
+     * ecp_coef[t] r^ecp_pow[t] exp(-ecp_exp[t] r^2) to channel ecp_l[t]
+     * (0, 1 or 2) of atom ecp_atom[t]; the channels of atom I act on an
+     * electron at distance r < ecp_rcut[I] from it.  Reading: the projector
+     * onto channel l is integrated by the 6-point octahedral quadrature of
+     * the sphere of radius r around the atom along the walker's lattice
+     * versors (weights 1/6); quadrature point q of electron i is proposal
+     * 6N + 6i + q (after the 6N lattice moves) with element
+     * V_q = sum_l (2l+1)/6 v_l(r) P_l(cos theta_q).  Positive
+     * V_q D(x')/D(x) enter the spin-flip term, negative ones are moves of
+     * rate -V_q D(x')/D(x).  The cutoff spheres of different atoms must not
+     * overlap (LRDMC_ERR_INVALID_ARG otherwise).  n_ecp = 0: no non-local
+     * part (the pointers are ignored).  FP64 precision only; the mixed
+     * kinds and lrdmc_walker_derivs return LRDMC_ERR_UNSUPPORTED. */
+    int32_t n_ecp;
+    const int32_t *ecp_atom;     /* [n_ecp] */
+    const int32_t *ecp_l;        /* [n_ecp] 0, 1, 2 */
+    const int32_t *ecp_pow;      /* [n_ecp] 0, 1, 2 */
+    const double *ecp_coef;      /* [n_ecp] */
+    const double *ecp_exp;       /* [n_ecp] >= 0 */
+    const double *ecp_rcut;      /* [n_atoms] cutoff radius, 0: no channels */
 } lrdmc_system;
 
 /* ---- run parameters ---------------------------------------------------- */

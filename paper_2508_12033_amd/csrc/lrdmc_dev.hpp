@@ -49,6 +49,16 @@ struct DevSys {
         o_scal, o_B, o_rows, o_tmp, o_C, o_nuc, o_jas, o_gd, o_ev, lds_doubles;
     // spill layout (offsets in doubles inside a walker's spill block)
     int s_Phi, s_dPhi;
+    // non-local pseudopotential (App. D non-local elements, determinant
+    // locality approximation): term t adds ecp_coef r^ecp_pow exp(-ecp_exp r^2)
+    // to channel ecp_l of atom ecp_atom, inside radius ecp_rcut of that atom.
+    // PT: proposals per configuration, the 6N lattice moves and, with a
+    // pseudopotential, 6N quadrature points (zero rows for electrons outside
+    // every sphere); PT is also the row length of the spilled orbital rows.
+    int PT, necp;
+    const int32_t *ecp_atom, *ecp_l, *ecp_pow;
+    const double *ecp_coef, *ecp_exp, *ecp_rcut;
+    int o_Vnl;               // LDS [6N]: element V_q of each quadrature point
 };
 
 // Nucleus record staged in LDS per walker by the FP64 phase kernel: x, y, z,

@@ -111,7 +111,7 @@ __device__ __forceinline__ void philox4(uint64_t k0, uint64_t k1, uint64_t c0, u
 // positions they move, are reproducible bit for bit by any implementation that
 // evaluates the same expressions in the same order.
 __device__ __forceinline__ void lattice_steps(uint64_t seed, uint64_t sysid, uint64_t slot, uint64_t j,
-                                           double a, double* st)
+                                           double a, double* st, double* uv = nullptr)
 {
 #pragma clang fp contract(off)
     double R[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
@@ -139,12 +139,43 @@ __device__ __forceinline__ void lattice_steps(uint64_t seed, uint64_t sysid, uin
     }
     for (int d = 0; d < 3; ++d)
         for (int x = 0; x < 3; ++x) st[3 * d + x] = a * R[3 * x + d];
+    // the versors themselves, uv[3 d + x] = R[x][d]
+    if (uv)
+        for (int d = 0; d < 3; ++d)
+            for (int x = 0; x < 3; ++x) uv[3 * d + x] = R[3 * x + d];
 }
 
-// Fixed lattice axes: st = a on the diagonal.
-__device__ __forceinline__ void lattice_steps_fixed(double a, double* st)
+// Fixed lattice axes: st = a on the diagonal (versors uv: the identity).
+__device__ __forceinline__ void lattice_steps_fixed(double a, double* st, double* uv = nullptr)
 {
     for (int q = 0; q < 9; ++q) st[q] = (q % 4 == 0) ? a : 0.0;
+    if (uv)
+        for (int q = 0; q < 9; ++q) uv[q] = (q % 4 == 0) ? 1.0 : 0.0;
+}
+
+// Quadrature point q (0..5 = +u0, -u0, +u1, -u1, +u2, -u2) of the sphere of
+// radius r around the atom at c, along the versors uv[3 d + x]: c +- r u_d,
+// each product and sum rounded on its own, so that a non-local move lands on
+// the same point as in any implementation evaluating the same expressions.
+__device__ __forceinline__ void nl_point(const double* c, double r, const double* uv, int q, double* o)
+{
+#pragma clang fp contract(off)
+    const int d = q >> 1;
+    const bool neg = (q & 1) != 0;
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        const double t = r * uv[3 * d + x];
+        o[x] = c[x] + (neg ? -t : t);
+    }
+}
+
+// |r - c| with the products and sums rounded in the written order and a
+// correctly rounded square root.
+__device__ __forceinline__ double exact_distance(const double* r, const double* c)
+{
+#pragma clang fp contract(off)
+    const double dx = r[0] - c[0], dy = r[1] - c[1], dz = r[2] - c[2];
+    return __builtin_sqrt((dx * dx + dy * dy) + dz * dz);
 }
 
 // Point q of electron position r: r itself (q = 0) or its lattice neighbour

@@ -24,10 +24,19 @@
 #include "lrdmc_dev.hpp"
 
 namespace lrdmc {
-template <bool kRot>
+template <bool kRot, bool kNl>
 __global__ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa);
-extern template __global__ void phase_fp64<false>(const DevSys* __restrict__ sys, PhaseArgs pa);
-extern template __global__ void phase_fp64<true>(const DevSys* __restrict__ sys, PhaseArgs pa);
+extern template __global__ void phase_fp64<false, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
+extern template __global__ void phase_fp64<true, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
+extern template __global__ void phase_fp64<false, true>(const DevSys* __restrict__ sys, PhaseArgs pa);
+extern template __global__ void phase_fp64<true, true>(const DevSys* __restrict__ sys, PhaseArgs pa);
+
+// the FP64 phase kernel for a lattice geometry and Hamiltonian
+inline void (*phase_kernel(bool rot, bool nl))(const DevSys*, PhaseArgs)
+{
+    if (nl) return rot ? phase_fp64<true, true> : phase_fp64<false, true>;
+    return rot ? phase_fp64<true, false> : phase_fp64<false, false>;
+}
 __global__ void phase_mixed(MixBatch b, PhaseArgs pa, int build);
 __global__ void branch_scan(BranchView s, int scheme, double* cum, double* out, int* n_distinct);
 __global__ void branch_comb(BranchView s, uint64_t seed, const double* cum, const double* out,
@@ -105,6 +114,8 @@ int kind_of(const lrdmc_params& p) { return p.precision == LRDMC_FP64 ? kKindLds
 // Per-system sizes and layout, computed identically by workspace_bytes and init.
 struct Layout {
     int kind, N, P, ns;
+    int PT;                  // proposals: 6N, or 12N with a non-local pseudopotential
+    int o_Vnl;
     // FP64 kernel: LDS offsets (doubles), spill layout
     int ldb;
     int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje, o_scal, o_B,
@@ -133,12 +144,16 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
     L.kind = kind_of(p);
     L.N = s.n_up + s.n_dn;
     L.P = 6 * L.N;
+    L.PT = s.n_ecp > 0 ? 12 * L.N : L.P;
     L.ns = std::max(1, std::max(s.n_up, s.n_dn));
-    const int M = s.n_atoms, Nb = s.n_basis, N = L.N, P = L.P, ns = L.ns;
+    const int M = s.n_atoms, Nb = s.n_basis, N = L.N, P = L.P, ns = L.ns, PT = L.PT;
+    const bool nl = s.n_ecp > 0;
     const size_t nw = s.n_walkers;
     L.b_sys = align_up(M * 3 * 8) + 2 * align_up(M * 8) + 2 * align_up(M * 4) +
               2 * align_up(Nb * 4) + align_up(Nb * 8) + align_up((size_t)Nb * s.n_orb * 8) +
-              align_up((2 + s.n_species) * 3 * 8) + align_up((size_t)Nb * 4 * 8) + align_up(Nb * 8);
+              align_up((2 + s.n_species) * 3 * 8) + align_up((size_t)Nb * 4 * 8) + align_up(Nb * 8) +
+              (nl ? 3 * align_up((size_t)s.n_ecp * 4) + 2 * align_up((size_t)s.n_ecp * 8) + align_up(M * 8)
+                  : 0);
     size_t common = 2 * align_up(nw * 3 * N * 8)    // positions, double-buffered
                     + align_up(nw * 8)              // lw
                     + 4 * align_up(nw * 8)          // eL, W double-buffered
@@ -151,8 +166,8 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         int o = 0;
         auto take = [&](int n) { int r = o; o += (n + 1) / 2 * 2; return r; };
         L.o_pos = take(3 * N);
-        L.o_R = take(P);
-        L.o_Rdet = take(P);
+        L.o_R = take(PT);
+        L.o_Rdet = take(PT);
         L.o_dJ = take(P);
         L.o_Arow = take(N * ns);
         L.o_AinvT = take(2 * ns * ns);
@@ -163,19 +178,21 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.o_dje = take(N);
         L.o_scal = take(kScVee + 1);
         L.ldb = Nb + ((20 - Nb % 16) % 16);
-        L.o_B = take(std::max(std::max(11 * L.ldb, 2 * ns * ns), 7 * N));
-        L.o_rows = take(11 * ns);
+        const int nrow = nl ? 17 : 11;       // basis / orbital rows per electron
+        L.o_B = take(std::max(std::max(nrow * L.ldb, 2 * ns * ns), 7 * N));
+        L.o_rows = take(nrow * ns);
         L.o_tmp = take(3 * ns + 16);
         L.o_C = take(Nb * ns);
         L.o_nuc = take(kNucLen * M);
         L.o_jas = take(3 * (2 + s.n_species));
         L.o_gd = take(4 * N);
-        L.o_ev = take(9);
+        L.o_ev = take(nl ? 18 : 9);
+        L.o_Vnl = nl ? take(P) : 0;
         L.lds_doubles = o;
         L.lds_bytes = (size_t)o * 8;
         L.s_Phi = 0;
-        L.s_dPhi = P * ns;
-        L.spill_stride = (long)(align_up((size_t)(P * ns + 4 * N * ns) * 8) / 8);
+        L.s_dPhi = PT * ns;
+        L.spill_stride = (long)(align_up((size_t)(PT * ns + 4 * N * ns) * 8) / 8);
         L.b_state = common + align_up(nw * L.spill_stride * 8) + 2 * align_up(sizeof(DevSys));
     } else {
         L.nb32 = (Nb + 31) / 32 * 32;
@@ -286,6 +303,31 @@ std::string validate(const lrdmc_system* sys, int n_sys, const lrdmc_params* prm
             if (s.basis_type[mu] < 0 || s.basis_type[mu] > 4) return "bad basis_type";
             if (!(s.basis_exp[mu] > 0)) return "basis exponent <= 0";
         }
+        if (s.n_ecp < 0) return "bad n_ecp";
+        if (s.n_ecp > 0) {
+            if (prm->precision != LRDMC_FP64)
+                return "non-local pseudopotential: not supported by the mixed-precision kinds";
+            if (!s.ecp_atom || !s.ecp_l || !s.ecp_pow || !s.ecp_coef || !s.ecp_exp || !s.ecp_rcut)
+                return "null pseudopotential array";
+            for (int I = 0; I < s.n_atoms; ++I)
+                if (!(s.ecp_rcut[I] >= 0)) return "bad ecp_rcut";
+            for (int t = 0; t < s.n_ecp; ++t) {
+                if (s.ecp_atom[t] < 0 || s.ecp_atom[t] >= s.n_atoms) return "bad ecp_atom";
+                if (s.ecp_l[t] < 0 || s.ecp_l[t] > 2) return "ecp_l must be 0, 1 or 2";
+                if (s.ecp_pow[t] < 0 || s.ecp_pow[t] > 2) return "ecp_pow must be 0, 1 or 2";
+                if (!(s.ecp_exp[t] >= 0) || !std::isfinite(s.ecp_coef[t])) return "bad ecp term";
+                if (!(s.ecp_rcut[s.ecp_atom[t]] > 0)) return "ecp term on an atom without a cutoff radius";
+            }
+            for (int I = 0; I < s.n_atoms; ++I)
+                for (int J = I + 1; J < s.n_atoms; ++J) {
+                    if (!(s.ecp_rcut[I] > 0 && s.ecp_rcut[J] > 0)) continue;
+                    const double* A = s.atom_pos + 3 * I;
+                    const double* B = s.atom_pos + 3 * J;
+                    const double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
+                    if (std::sqrt(dx * dx + dy * dy + dz * dz) <= s.ecp_rcut[I] + s.ecp_rcut[J])
+                        return "pseudopotential cutoff spheres overlap";
+                }
+        }
         if (prm->precision != LRDMC_FP64 && std::max(s.n_up, s.n_dn) > 64)
             return "mixed-precision layout: at most 64 electrons per spin (too large)";
         const Layout L = make_layout(s, *prm);
@@ -309,6 +351,7 @@ uint16_t to_bf16(float x)
 
 struct SysRun {
     int kind;
+    bool nl = false;                     // non-local pseudopotential (FP64 kernel)
     Layout L;
     int nw, N;
     uint64_t sysid;
@@ -455,7 +498,7 @@ int launch_phases(lrdmc_handle* h, hipStream_t st, int p, int nproj_override, bo
     for (auto& r : h->sys) {
         if (r.kind != kKindLds) continue;
         const PhaseArgs pa = phase_args(h, r.N, nproj_override);
-        hipLaunchKernelGGL(pa.rotate ? phase_fp64<true> : phase_fp64<false>, dim3(r.nw), dim3(kWave),
+        hipLaunchKernelGGL(phase_kernel(pa.rotate != 0, r.nl), dim3(r.nw), dim3(kWave),
                            r.L.lds_bytes, st,
                            (const DevSys*)r.dsys[p], pa);
         HIPCHK(hipGetLastError());
@@ -783,6 +826,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
         SysRun& r = h->sys.back();
         r.L = make_layout(s, *prm);
         r.kind = r.L.kind;
+        r.nl = s.n_ecp > 0;
         const Layout& L = r.L;
         r.nw = s.n_walkers;
         r.N = L.N;
@@ -827,6 +871,23 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             up(btab, r.btab_host.data(), (size_t)Nb * 32) || up(bK, bK_host.data(), Nb * 8)) {
             rc = fail(LRDMC_ERR_HIP, "upload of system arrays failed");
             break;
+        }
+        int32_t *e_atom = nullptr, *e_l = nullptr, *e_pow = nullptr;
+        double *e_coef = nullptr, *e_exp = nullptr, *e_rcut = nullptr;
+        if (r.nl) {
+            const size_t ne = s.n_ecp;
+            e_atom = (int32_t*)carve(ne * 4);
+            e_l = (int32_t*)carve(ne * 4);
+            e_pow = (int32_t*)carve(ne * 4);
+            e_coef = (double*)carve(ne * 8);
+            e_exp = (double*)carve(ne * 8);
+            e_rcut = (double*)carve(M * 8);
+            if (up(e_atom, s.ecp_atom, ne * 4) || up(e_l, s.ecp_l, ne * 4) || up(e_pow, s.ecp_pow, ne * 4) ||
+                up(e_coef, s.ecp_coef, ne * 8) || up(e_exp, s.ecp_exp, ne * 8) ||
+                up(e_rcut, s.ecp_rcut, M * 8)) {
+                rc = fail(LRDMC_ERR_HIP, "upload of pseudopotential arrays failed");
+                break;
+            }
         }
         float* Cf = nullptr;
         uint16_t* Cbf = nullptr;
@@ -944,6 +1005,9 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             d.bK = bK; d.o_nuc = L.o_nuc; d.o_jas = L.o_jas; d.o_gd = L.o_gd; d.o_ev = L.o_ev;
             d.lds_doubles = L.lds_doubles;
             d.s_Phi = L.s_Phi; d.s_dPhi = L.s_dPhi;
+            d.PT = L.PT; d.necp = r.nl ? s.n_ecp : 0;
+            d.ecp_atom = e_atom; d.ecp_l = e_l; d.ecp_pow = e_pow;
+            d.ecp_coef = e_coef; d.ecp_exp = e_exp; d.ecp_rcut = e_rcut; d.o_Vnl = L.o_Vnl;
             for (int p = 0; p < 2; ++p) {
                 r.dsys[p] = (DevSys*)carve(sizeof(DevSys));
                 r.hsys[p] = d;
@@ -1012,13 +1076,15 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
     }
     if (rc == LRDMC_OK) {
         // allow each phase kernel the LDS that its static allocation leaves free
-        for (int kind = 0; kind < 2 && !rc; ++kind) {
-            const void* fn = kind == kKindLds
-                                 ? (h->prm.rotate ? (const void*)phase_fp64<true>
-                                                  : (const void*)phase_fp64<false>)
-                                 : (const void*)phase_mixed;
+        // (kernel kinds: 0, 1 the FP64 kernel without and with the non-local
+        // pseudopotential, 2 the mixed-precision kernel)
+        for (int kind = 0; kind < 3 && !rc; ++kind) {
+            const void* fn = kind < 2 ? (const void*)phase_kernel(h->prm.rotate != 0, kind == 1)
+                                      : (const void*)phase_mixed;
             size_t need_lds = 0;
-            for (auto& r : h->sys) if (r.kind == kind) need_lds = std::max(need_lds, r.L.lds_bytes);
+            for (auto& r : h->sys)
+                if (kind < 2 ? (r.kind == kKindLds && (int)r.nl == kind) : r.kind == kKindMixed)
+                    need_lds = std::max(need_lds, r.L.lds_bytes);
             if (!need_lds) continue;
             hipFuncAttributes fa;
             if (hipFuncGetAttributes(&fa, fn) != hipSuccess) { rc = fail(LRDMC_ERR_HIP, "hipFuncGetAttributes failed"); break; }
@@ -1350,6 +1416,8 @@ static int run_derivs(lrdmc_handle* h, int isys, const double* theta, double* eL
     const Layout& L = r.L;
     if (h->prm.rotate)
         return fail(LRDMC_ERR_UNSUPPORTED, "the adjoint pass evaluates the fixed lattice axes only");
+    if (r.nl)
+        return fail(LRDMC_ERR_UNSUPPORTED, "the adjoint pass has no non-local pseudopotential");
     const size_t lds = (size_t)L.a_doubles * 8;
     hipFuncAttributes fa;
     HIPCHK(hipFuncGetAttributes(&fa, (const void*)walker_derivs));

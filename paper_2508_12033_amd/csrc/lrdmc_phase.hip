@@ -63,7 +63,8 @@ extern __shared__ double lds[];
 constexpr int kPre = 8;
 
 struct Walker {
-    int pos, R, Rdet, dJ, Arow, AinvT, Jg, Jl, nue, nua, dje, scal, B, rows, tmp, C, nuc, jas, gd, ev;
+    int pos, R, Rdet, dJ, Arow, AinvT, Jg, Jl, nue, nua, dje, scal, B, rows, tmp, C, nuc, jas, gd, ev,
+        Vnl;
     double* Phi;
     double* dPhi;
 };
@@ -79,6 +80,7 @@ __device__ __forceinline__ Walker walker_view(const DevSys& s)
     w.jas = s.o_jas;
     w.gd = s.o_gd;
     w.ev = s.o_ev;
+    w.Vnl = s.o_Vnl;
     double* base = s.spill + (long)blockIdx.x * s.spill_stride;
     w.Phi = base + s.s_Phi;
     w.dPhi = base + s.s_dPhi;
@@ -86,6 +88,10 @@ __device__ __forceinline__ Walker walker_view(const DevSys& s)
 }
 
 __device__ __forceinline__ int spin_of(const DevSys& s, int i) { return i >= s.Nup; }
+// proposals per configuration and row length of the spilled orbital rows:
+// the 6N lattice moves, and 6N quadrature points with a pseudopotential
+template <bool kNl>
+__device__ __forceinline__ int n_prop(const DevSys& s) { return kNl ? s.PT : s.P; }
 __device__ __forceinline__ int col_of(const DevSys& s, int i) { return i >= s.Nup ? i - s.Nup : i; }
 __device__ __forceinline__ int nspin(const DevSys& s, int sp) { return sp ? s.Ndn : s.Nup; }
 __device__ __forceinline__ int ee_row(const DevSys& s, int i, int k)
@@ -146,6 +152,53 @@ __device__ __forceinline__ void nucleus_potential(const DevSys& s, const Walker&
     }
 }
 
+// Non-local pseudopotential (App. D non-local elements under the determinant
+// locality approximation).  The atom whose cutoff sphere holds r (the spheres
+// do not overlap), or -1, and the distance rr to it.
+__device__ __forceinline__ int nl_sphere(const DevSys& s, const Walker& w, const double* r, double& rr)
+{
+    rr = 0.0;
+    for (int I = 0; I < s.M; ++I) {
+        const double rc = gld(s.ecp_rcut + I);
+        if (!(rc > 0.0)) continue;
+        const double d = exact_distance(r, lds + w.nuc + kNucLen * I);
+        if (d < rc) { rr = d; return I; }
+    }
+    return -1;
+}
+
+// Elements V_q = sum_l (2l + 1)/6 v_l(rr) P_l(cos theta_q) of electron j's six
+// quadrature points (octahedral quadrature of the sphere of radius rr around
+// atom I along the walker's versors; theta_q the angle between r - R_I and
+// the point's direction), 0 outside every sphere.  Lanes 0..5, one point each.
+__device__ void nl_elements(const DevSys& s, const Walker& w, int j, const double* r, int I,
+                            double rr, int lane)
+{
+    if (lane < 6) {
+        double V = 0.0;
+        if (I >= 0) {
+            const double* nr = lds + w.nuc + kNucLen * I;
+            const double* uv = lds + w.ev + 9;
+            const int d = lane >> 1;
+            const double ud = (r[0] - nr[0]) * uv[3 * d] + (r[1] - nr[1]) * uv[3 * d + 1] +
+                              (r[2] - nr[2]) * uv[3 * d + 2];
+            const double cth = ((lane & 1) ? -ud : ud) / rr;
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+            for (int t = 0; t < s.necp; ++t) {
+                if (gld(s.ecp_atom + t) != I) continue;
+                const int l = gld(s.ecp_l + t), k = gld(s.ecp_pow + t);
+                const double rp = k == 0 ? 1.0 : (k == 1 ? rr : rr * rr);
+                const double v = gld(s.ecp_coef + t) * rp * exp(-gld(s.ecp_exp + t) * rr * rr);
+                if (l == 0) v0 += v;
+                else if (l == 1) v1 += v;
+                else v2 += v;
+            }
+            V = (v0 + 3.0 * v1 * cth + 5.0 * v2 * (0.5 * (3.0 * cth * cth - 1.0))) / 6.0;
+        }
+        lds[w.Vnl + 6 * j + lane] = V;
+    }
+}
+
 // Lattice point q of r (0: r itself, 1..6: the neighbours in move order):
 // fixed axes r +- a e_d, or the walker's rotated step vectors st.
 template <bool kRot>
@@ -169,9 +222,12 @@ __device__ __forceinline__ void lattice_point(const double* r, int q, double a, 
 // seven values, and the value at r gives the gradient and Laplacian.  Slater
 // functions take the seven points directly.  Orbitals: the 11 x Nb basis
 // block times the Nb x n coefficient block on FP64 MFMA (16x16x4 tiles; rows
-// 11..15 and columns >= n are padding).
-template <bool kRot>
-__device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, double a, int lane)
+// 11..15 and columns >= n are padding).  With a pseudopotential (kNl), rows
+// 11..16 hold the values at the six quadrature points of the sphere of radius
+// nlr around atom nlI (zeros when nlI < 0).
+template <bool kRot, bool kNl = false>
+__device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, double a, int lane,
+                           int nlI = -1, double nlr = 0.0)
 {
     const int Nb = s.Nb, ldb = s.ldb;
     const double* st = lds + w.ev;      // lattice step vectors a e_d
@@ -238,6 +294,19 @@ __device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, do
         Bm[8 * ldb] = g[1];
         Bm[9 * ldb] = g[2];
         Bm[10 * ldb] = l;
+        if constexpr (kNl) {
+            if (nlI >= 0) {
+                const double* nr = lds + w.nuc + kNucLen * nlI;
+                for (int q = 0; q < 6; ++q) {
+                    double pq[3];
+                    nl_point(nr, nlr, lds + w.ev + 9, q, pq);
+                    const double dx = pq[0] - c[0], dy = pq[1] - c[1], dz = pq[2] - c[2];
+                    Bm[(11 + q) * ldb] = basis_value_d(t, al, dx, dy, dz, dx * dx + dy * dy + dz * dz);
+                }
+            } else {
+                for (int q = 0; q < 6; ++q) Bm[(11 + q) * ldb] = 0.0;
+            }
+        }
     }
 }
 
@@ -246,8 +315,11 @@ __device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, do
 // b = (lane >> 2) & 3 holds A[b][i][k] at lane 16k + 4b + i, B[b][k][c] at
 // lane 16k + 4b + c and D[b][i][c] at lane 16i + 4b + c.  Blocks 2t and 2t+1
 // take column tile t of the pair and the even and odd k-steps; three
-// accumulators cover the row tiles 0..3, 4..7 and 8..10.
-__device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
+// accumulators cover the row tiles 0..3, 4..7 and 8..10, and with a
+// pseudopotential two more the quadrature rows 11..14 and 15..16 (skipped,
+// and stored as zeros, when nl_on is false).
+template <bool kNl = false>
+__device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane, bool nl_on = false)
 {
     wave_sync();
     const int Nb = s.Nb, ldb = s.ldb;
@@ -257,7 +329,7 @@ __device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
     for (int ct0 = 0; 4 * ct0 < n; ct0 += 2) {
         const int col = 4 * (ct0 + cb) + l4;
         const bool cok = col < n;
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0, acc4 = 0.0;
         for (int k0 = 0; k0 < Nb; k0 += 8) {
             const int mu = k0 + 4 * par + lk;
             const bool kok = mu < Nb;
@@ -268,39 +340,63 @@ __device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
             acc0 = __builtin_amdgcn_mfma_f64_4x4x4f64(a0, bv, acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f64_4x4x4f64(a1, bv, acc1, 0, 0, 0);
             acc2 = __builtin_amdgcn_mfma_f64_4x4x4f64(a2, bv, acc2, 0, 0, 0);
+            if constexpr (kNl) {
+                if (nl_on) {
+                    const double a3 = kok ? lds[w.B + (11 + l4) * ldb + mu] : 0.0;
+                    const double a4 = (kok && l4 < 2) ? lds[w.B + (15 + l4) * ldb + mu] : 0.0;
+                    acc3 = __builtin_amdgcn_mfma_f64_4x4x4f64(a3, bv, acc3, 0, 0, 0);
+                    acc4 = __builtin_amdgcn_mfma_f64_4x4x4f64(a4, bv, acc4, 0, 0, 0);
+                }
+            }
         }
         // odd k-steps (block 2t + 1, four lanes up) into block 2t: row_shl:4
         acc0 += dpp_mov<0x104, 0xf>(acc0);
         acc1 += dpp_mov<0x104, 0xf>(acc1);
         acc2 += dpp_mov<0x104, 0xf>(acc2);
+        if constexpr (kNl) {
+            acc3 += dpp_mov<0x104, 0xf>(acc3);
+            acc4 += dpp_mov<0x104, 0xf>(acc4);
+        }
         const int c = 4 * (ct0 + cb) + l4, i = lane >> 4;
         if (par == 0 && c < n) {
             lds[w.rows + i * s.ns + c] = acc0;
             lds[w.rows + (4 + i) * s.ns + c] = acc1;
             if (i < 3) lds[w.rows + (8 + i) * s.ns + c] = acc2;
+            if constexpr (kNl) {
+                lds[w.rows + (11 + i) * s.ns + c] = acc3;
+                if (i < 2) lds[w.rows + (15 + i) * s.ns + c] = acc4;
+            }
         }
     }
     wave_sync();
 }
 
-template <bool kRot>
+template <bool kRot, bool kNl = false>
 __device__ void electron_rows(const DevSys& s, const Walker& w, int j, const double* r, double a,
                               int lane)
 {
-    basis_rows<kRot>(s, w, r, a, lane);
-    orbital_rows(s, w, j, lane);
+    int I = -1;
+    double rr = 0.0;
+    if constexpr (kNl) I = nl_sphere(s, w, r, rr);
+    basis_rows<kRot, kNl>(s, w, r, a, lane, I, rr);
+    if constexpr (kNl) nl_elements(s, w, j, r, I, rr, lane);
+    orbital_rows<kNl>(s, w, j, lane, I >= 0);
 }
 
-// Store electron j's rows: Slater row, the 6 neighbour rows, derivatives.
+// Store electron j's rows: Slater row, the 6 neighbour rows, derivatives, and
+// with a pseudopotential the 6 quadrature-point rows (columns 6N + 6j + q).
+template <bool kNl = false>
 __device__ void store_rows(const DevSys& s, const Walker& w, int j, int lane, bool arow)
 {
     const int n = nspin(s, spin_of(s, j));
-    for (int idx = lane; idx < 11 * n; idx += kWave) {
+    const int ld = n_prop<kNl>(s);
+    for (int idx = lane; idx < (kNl ? 17 : 11) * n; idx += kWave) {
         const int row = idx / n, k = idx - row * n;
         const double v = lds[w.rows + row * s.ns + k];
         if (row == 0) { if (arow) lds[w.Arow + j * s.ns + k] = v; }
-        else if (row <= 6) gst(w.Phi + k * s.P + 6 * j + row - 1, v);
-        else gst(w.dPhi + k * 4 * s.N + 4 * j + row - 7, v);
+        else if (row <= 6) gst(w.Phi + k * ld + 6 * j + row - 1, v);
+        else if (row <= 10) gst(w.dPhi + k * 4 * s.N + 4 * j + row - 7, v);
+        else gst(w.Phi + k * ld + s.P + 6 * j + row - 11, v);
     }
     block_visible();
 }
@@ -368,9 +464,14 @@ __device__ bool refresh_inverse(const DevSys& s, const Walker& w, int sp, int la
 }
 
 // Ratios of the moves of spin sp (or of every spin when sp < 0), from the
-// orbital rows, the inverse and the Jastrow exponent changes.
-__device__ void recompute_ratios(const DevSys& s, const Walker& w, int sp, int lane)
+// orbital rows, the inverse and the Jastrow exponent changes.  With a
+// pseudopotential also the determinant ratios D(x')/D(x) of the quadrature
+// points and their entries -2 a^2 V_q D(x')/D(x) (determinant locality
+// approximation: no Jastrow factor), in the units of the lattice ratios.
+template <bool kNl = false>
+__device__ void recompute_ratios(const DevSys& s, const Walker& w, int sp, int lane, double a = 0.0)
 {
+    const int ld = n_prop<kNl>(s);
     for (int p = lane; p < s.P; p += kWave) {
         const int j = p / 6, spj = spin_of(s, j);
         if (sp < 0 || spj == sp) {
@@ -378,10 +479,25 @@ __device__ void recompute_ratios(const DevSys& s, const Walker& w, int sp, int l
             const int ai = w.AinvT + spj * s.ns * s.ns + c * s.ns;
             const double* ph = w.Phi + p;
             double rd = 0.0;
-            for (int k = 0; k < n; ++k) rd += gld(ph + k * s.P) * lds[ai + k];
+            for (int k = 0; k < n; ++k) rd += gld(ph + k * ld) * lds[ai + k];
             lds[w.Rdet + p] = rd;
         }
         lds[w.R + p] = lds[w.Rdet + p] * exp(lds[w.dJ + p]);
+    }
+    if constexpr (kNl) {
+        const double m2a2 = -2.0 * a * a;
+        for (int p = s.P + lane; p < s.PT; p += kWave) {
+            const int j = (p - s.P) / 6, spj = spin_of(s, j);
+            if (sp < 0 || spj == sp) {
+                const int n = nspin(s, spj), c = col_of(s, j);
+                const int ai = w.AinvT + spj * s.ns * s.ns + c * s.ns;
+                const double* ph = w.Phi + p;
+                double rd = 0.0;
+                for (int k = 0; k < n; ++k) rd += gld(ph + k * ld) * lds[ai + k];
+                lds[w.Rdet + p] = rd;
+            }
+            lds[w.R + p] = m2a2 * lds[w.Vnl + p - s.P] * lds[w.Rdet + p];
+        }
     }
     wave_sync();
 }
@@ -469,7 +585,7 @@ __device__ double jastrow_all(const DevSys& s, const Walker& w, double a, int la
 
 // FP64 refresh: inverses and log-determinants from the exact orbital rows,
 // Jastrow caches and V_ee from scratch, all ratios.
-template <bool kRot>
+template <bool kRot, bool kNl = false>
 __device__ bool refresh_all(const DevSys& s, const Walker& w, double a, int lane)
 {
     bool ok = refresh_inverse(s, w, 0, lane);
@@ -477,7 +593,7 @@ __device__ bool refresh_all(const DevSys& s, const Walker& w, double a, int lane
     const double vee = jastrow_all<kRot>(s, w, a, lane);
     if (lane == 0) lds[w.scal + kScVee] = vee;
     wave_sync();
-    recompute_ratios(s, w, -1, lane);
+    recompute_ratios<kNl>(s, w, -1, lane, a);
     recompute_gd(s, w, -1, lane);
     return ok;
 }
@@ -488,17 +604,28 @@ __device__ bool refresh_all(const DevSys& s, const Walker& w, double a, int lane
 // chunks (lane l owns moves [l per, (l + 1) per)), reused by the heat bath
 struct Local { double bbar, W, eL, inc; };
 
+// With a pseudopotential the entries of the quadrature points join the sums:
+// positive ones are move rates (bbar), negative ones spin-flip terms (V_sf);
+// a quadrature point crosses the node when its determinant ratio is negative.
+template <bool kNl = false>
 __device__ Local evaluate(const DevSys& s, const Walker& w, double a, int nu_mode, int lane)
 {
     const double inv2a2 = 1.0 / (2.0 * a * a), ia2 = 2.0 * inv2a2;
     double loc = 0.0, vs = 0.0;
     int anyneg = 0;
-    const int per = (s.P + kWave - 1) / kWave;
-    const int p0 = lane * per, p1 = min(p0 + per, s.P);
+    const int PT = n_prop<kNl>(s);
+    const int per = (PT + kWave - 1) / kWave;
+    const int p0 = lane * per, p1 = min(p0 + per, PT);
     for (int p = p0; p < p1; ++p) {
         const double r = lds[w.R + p];
-        if (r > 0) loc += r;
-        else if (r < 0) { vs += -r; anyneg = 1; }
+        if constexpr (kNl) {
+            if (r > 0) loc += r;
+            else if (r < 0) vs += -r;
+            if (p < s.P ? r < 0 : lds[w.Rdet + p] < 0) anyneg = 1;
+        } else {
+            if (r > 0) loc += r;
+            else if (r < 0) { vs += -r; anyneg = 1; }
+        }
     }
     const double inc = wave_incl_scan(loc, lane);
     const double bs = lane63(inc);
@@ -518,6 +645,9 @@ __device__ Local evaluate(const DevSys& s, const Walker& w, double a, int nu_mod
             lapA += r - 1.0;
             if (r < 0) nd = 1;
         }
+        if constexpr (kNl)
+            for (int q = 0; q < 6; ++q)
+                if (lds[w.Rdet + s.P + 6 * j + q] < 0) nd = 1;
         lapA *= ia2;
         if (nu_mode == 1) nd = anynode;
         if (nu_mode == 2) nd = 1;
@@ -538,10 +668,12 @@ __device__ Local evaluate(const DevSys& s, const Walker& w, double a, int nu_mod
 
 // Heat-bath choice: first p with cumulative positive ratio > xi * total, from
 // the chunk prefix sums of the evaluation at the same configuration.
+template <bool kNl = false>
 __device__ int heat_bath(const DevSys& s, const Walker& w, double xi, double inc, int lane)
 {
-    const int per = (s.P + kWave - 1) / kWave;
-    const int p0 = lane * per, p1 = min(p0 + per, s.P);
+    const int PT = n_prop<kNl>(s);
+    const int per = (PT + kWave - 1) / kWave;
+    const int p0 = lane * per, p1 = min(p0 + per, PT);
     const double tot = lane63(inc);
     if (!(tot > 0)) return -1;
     const double t = xi * tot;
@@ -564,36 +696,51 @@ __device__ int heat_bath(const DevSys& s, const Walker& w, double xi, double inc
 // Apply move p: position, Sherman-Morrison inverse update of the moved spin,
 // new orbital rows of the moved electron, Jastrow / potential caches, ratios.
 // Returns true when the determinant ratio was tiny (a refresh is forced).
+// A move p >= 6N (with a pseudopotential) takes electron (p - 6N) / 6 to
+// quadrature point (p - 6N) % 6 of the atom whose sphere holds it.
 #ifdef LRDMC_SECTION_TIMERS
-template <bool kRot>
+template <bool kRot, bool kNl = false>
 __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, int lane,
                            unsigned long long* sect, unsigned long long& t_mark_)
 #else
-template <bool kRot>
+template <bool kRot, bool kNl = false>
 __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, int lane)
 #endif
 {
-    const int i = p / 6, d = (p / 2) % 3, sg = p % 2;
+    const bool nlm = kNl && p >= s.P;
+    const int pk = nlm ? p - s.P : p;
+    const int i = pk / 6, d = (pk / 2) % 3, sg = pk % 2;
     const int sp = spin_of(s, i), c = col_of(s, i), n = nspin(s, sp);
+    const int ld = n_prop<kNl>(s);
     const double Rd = lds[w.Rdet + p], iRd = 1.0 / Rd;
     const double rold[3] = {lds[w.pos + 3 * i], lds[w.pos + 3 * i + 1], lds[w.pos + 3 * i + 2]};
     const double* st = lds + w.ev;
     double rnew[3] = {rold[0], rold[1], rold[2]};
-    if constexpr (kRot) point_qv(rold, 2 * d + sg + 1, st, rnew);
-    else rnew[d] = rnew[d] + (sg ? -a : a);
+    if (nlm) {
+        double rr;
+        const int I = nl_sphere(s, w, rold, rr);
+        nl_point(lds + w.nuc + kNucLen * (I < 0 ? 0 : I), rr, lds + w.ev + 9, pk % 6, rnew);
+    } else if constexpr (kRot) {
+        point_qv(rold, 2 * d + sg + 1, st, rnew);
+    } else {
+        rnew[d] = rnew[d] + (sg ? -a : a);
+    }
 
     // The accepted orbital row u is fetched first and the basis values at
     // the new position are computed while it is in flight.
     double u0 = 0.0;
-    if (lane < n) u0 = gld(w.Phi + lane * s.P + p);
-    basis_rows<kRot>(s, w, rnew, a, lane);
+    if (lane < n) u0 = gld(w.Phi + lane * ld + p);
+    int In = -1;
+    double rn = 0.0;
+    if constexpr (kNl) In = nl_sphere(s, w, rnew, rn);
+    basis_rows<kRot, kNl>(s, w, rnew, a, lane, In, rn);
     LRDMC_T(3);
 
     // Sherman-Morrison on AinvT of spin sp with the accepted orbital row u
     const int Ai = w.AinvT + sp * s.ns * s.ns;
     const int u = w.tmp, rowc = w.tmp + s.ns, beta = w.tmp + 2 * s.ns;
     for (int k = lane; k < n; k += kWave) {
-        lds[u + k] = k < kWave ? u0 : gld(w.Phi + k * s.P + p);
+        lds[u + k] = k < kWave ? u0 : gld(w.Phi + k * ld + p);
         lds[rowc + k] = lds[Ai + c * s.ns + k];
     }
     wave_sync();
@@ -623,8 +770,9 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
 
     LRDMC_T(2);
     // new orbital rows of electron i at rnew
-    orbital_rows(s, w, i, lane);
-    store_rows(s, w, i, lane, false);
+    orbital_rows<kNl>(s, w, i, lane, In >= 0);
+    store_rows<kNl>(s, w, i, lane, false);
+    if constexpr (kNl) nl_elements(s, w, i, rnew, In, rn, lane);
     LRDMC_T(4);
 
     // Orbital rows of the moves of spin sp and orbital derivatives of its
@@ -635,7 +783,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     const bool rv = lane < 6 * n, gv = lane < 4 * n;
 #pragma unroll
     for (int k = 0; k < kPre; ++k) {
-        pre_r[k] = (rv && k < n) ? gld(w.Phi + k * s.P + 6 * off + lane) : 0.0;
+        pre_r[k] = (rv && k < n) ? gld(w.Phi + k * ld + 6 * off + lane) : 0.0;
         pre_g[k] = (gv && k < n) ? gld(w.dPhi + k * 4 * s.N + 4 * off + lane) : 0.0;
     }
 
@@ -782,7 +930,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
         lds[w.Jg + 3 * i] = g0; lds[w.Jg + 3 * i + 1] = g1; lds[w.Jg + 3 * i + 2] = g2;
         lds[w.Jl + i] = l; lds[w.nue + i] = nu; lds[w.nua + i] = nua;
         lds[w.scal + kScVee] += dvee;
-        if constexpr (kRot) {
+        if (kRot || nlm) {
             lds[w.pos + 3 * i] = rnew[0]; lds[w.pos + 3 * i + 1] = rnew[1]; lds[w.pos + 3 * i + 2] = rnew[2];
         } else {
             lds[w.pos + 3 * i + d] = rnew[d];
@@ -799,11 +947,23 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
 #pragma unroll
             for (int k = 0; k < kPre; ++k)
                 if (k < n) rd += pre_r[k] * lds[ai + k];
-            for (int k = kPre; k < n; ++k) rd += gld(w.Phi + k * s.P + q) * lds[ai + k];
+            for (int k = kPre; k < n; ++k) rd += gld(w.Phi + k * ld + q) * lds[ai + k];
         } else {
-            for (int k = 0; k < n; ++k) rd += gld(w.Phi + k * s.P + q) * lds[ai + k];
+            for (int k = 0; k < n; ++k) rd += gld(w.Phi + k * ld + q) * lds[ai + k];
         }
         lds[w.Rdet + q] = rd;
+    }
+    if constexpr (kNl) {
+        // determinant ratios and entries of spin sp's quadrature points
+        const double m2a2 = -2.0 * a * a;
+        for (int pp = lane; pp < 6 * n; pp += kWave) {
+            const int q = s.P + 6 * off + pp, cj = col_of(s, off + pp / 6);
+            const int ai = Ai + cj * s.ns;
+            double rd = 0.0;
+            for (int k = 0; k < n; ++k) rd += gld(w.Phi + k * ld + q) * lds[ai + k];
+            lds[w.Rdet + q] = rd;
+            lds[w.R + q] = m2a2 * lds[w.Vnl + q - s.P] * rd;
+        }
     }
     for (int gg = lane; gg < 4 * n; gg += kWave) {
         const int it = 4 * off + gg, cj = col_of(s, it >> 2);
@@ -841,10 +1001,11 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
 #define LRDMC_PHASE_WAVES 2
 #endif
 
-// The phase kernel, one instantiation per lattice geometry: fixed axes
+// The phase kernel, one instantiation per lattice geometry -- fixed axes
 // (kRot = false, the cheaper axis-aligned moves) or a random orientation per
-// walker and phase (kRot = true).
-template <bool kRot>
+// walker and phase (kRot = true) -- and per Hamiltonian: local potentials
+// only, or with the non-local pseudopotential (kNl = true: 6N more proposals).
+template <bool kRot, bool kNl>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(LRDMC_PHASE_WAVES)))
 void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
 {
@@ -875,21 +1036,24 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
     // lattice step vectors of this walker for this phase: the coordinate axes,
     // or a random orientation drawn from its own Philox stream
     if (lane == 0) {
-        double st[9];
-        if constexpr (kRot) lattice_steps(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb, pa.a, st);
-        else lattice_steps_fixed(pa.a, st);
+        double st[9], uv[9];
+        if constexpr (kRot)
+            lattice_steps(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb, pa.a, st, kNl ? uv : nullptr);
+        else lattice_steps_fixed(pa.a, st, kNl ? uv : nullptr);
         for (int q = 0; q < 9; ++q) lds[w.ev + q] = st[q];
+        if constexpr (kNl)
+            for (int q = 0; q < 9; ++q) lds[w.ev + 9 + q] = uv[q];
     }
     wave_sync();
     // orbital rows of every electron, then the FP64 refresh
     for (int j = 0; j < s.N; ++j) {
         const double r[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
-        electron_rows<kRot>(s, w, j, r, a, lane);
-        store_rows(s, w, j, lane, true);
+        electron_rows<kRot, kNl>(s, w, j, r, a, lane);
+        store_rows<kNl>(s, w, j, lane, true);
     }
     unsigned long long n_neg = 0, n_nomove = 0, n_refresh = 1, n_small = 0, n_sing = 0,
                        n_capped = 0;
-    if (!refresh_all<kRot>(s, w, a, lane)) n_sing++;
+    if (!refresh_all<kRot, kNl>(s, w, a, lane)) n_sing++;
 
     double lw = s.lw[wid];
     // load-balanced weight factors bbar / (W - E_0) multiplied in blocks
@@ -916,7 +1080,7 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
                                        (uint64_t)(it + lane), kPersist);
         }
         const int slot = it & (kWave - 1);
-        L = evaluate(s, w, a, pa.nu_mode, lane);
+        L = evaluate<kNl>(s, w, a, pa.nu_mode, lane);
         LRDMC_T(0);
         int q;
         if (pa.scheme == 0) {
@@ -926,7 +1090,7 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
             else {
                 lw_block_update(lw, wprod, L.bbar, den, it + 1);
             }
-            q = heat_bath(s, w, lane_value(xmove, slot), L.inc, lane);
+            q = heat_bath<kNl>(s, w, lane_value(xmove, slot), L.inc, lane);
             if (tr && it < s.trace_cap && lane == 0) tr[it] = q;
             ++it;
         } else {
@@ -946,20 +1110,20 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
                 if (tr && it - 1 < s.trace_cap && lane == 0) tr[it - 1] = -1;
                 break;
             }
-            q = heat_bath(s, w, lane_value(xmove, slot), L.inc, lane);
+            q = heat_bath<kNl>(s, w, lane_value(xmove, slot), L.inc, lane);
             if (tr && it - 1 < s.trace_cap && lane == 0) tr[it - 1] = q;
         }
         LRDMC_T(1);
         if (q >= 0) {
 #ifdef LRDMC_SECTION_TIMERS
-            const bool small = apply_move<kRot>(s, w, a, q, lane, sect, t_mark_);
+            const bool small = apply_move<kRot, kNl>(s, w, a, q, lane, sect, t_mark_);
 #else
-            const bool small = apply_move<kRot>(s, w, a, q, lane);
+            const bool small = apply_move<kRot, kNl>(s, w, a, q, lane);
 #endif
             ++since;
             if (small) n_small++;
             if (small || since >= pa.refresh_every) {
-                if (!refresh_all<kRot>(s, w, a, lane)) n_sing++;
+                if (!refresh_all<kRot, kNl>(s, w, a, lane)) n_sing++;
                 n_refresh++;
                 since = 0;
             }
@@ -972,7 +1136,7 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
 #endif
     lw += log(wprod);
     if (pa.scheme == 0) {
-        L = evaluate(s, w, a, pa.nu_mode, lane);
+        L = evaluate<kNl>(s, w, a, pa.nu_mode, lane);
         // the estimator weight w / (W - E_0) at the final configuration needs
         // W - E_0 > 0 as every step's factor does: otherwise the walker dies
         if (pa.nproj > 0 && !(L.W - E0 > 0)) { lw = -INFINITY; n_neg++; }
@@ -999,8 +1163,10 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
     }
 }
 
-template __global__ void phase_fp64<false>(const DevSys* __restrict__ sys, PhaseArgs pa);
-template __global__ void phase_fp64<true>(const DevSys* __restrict__ sys, PhaseArgs pa);
+template __global__ void phase_fp64<false, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
+template __global__ void phase_fp64<true, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
+template __global__ void phase_fp64<false, true>(const DevSys* __restrict__ sys, PhaseArgs pa);
+template __global__ void phase_fp64<true, true>(const DevSys* __restrict__ sys, PhaseArgs pa);
 
 // ---------------------------------------------------------------------------
 // reconfiguration (Sec. II.A): one workgroup computes max log-weight, the

@@ -38,7 +38,10 @@ class lrdmc_system(ct.Structure):
                 ("basis_atom", ct.c_void_p), ("basis_type", ct.c_void_p),
                 ("basis_exp", ct.c_void_p), ("n_orb", ct.c_int32), ("mo_coeff", ct.c_void_p),
                 ("n_up", ct.c_int32), ("n_dn", ct.c_int32), ("n_species", ct.c_int32),
-                ("jastrow", ct.c_void_p), ("n_walkers", ct.c_int32), ("system_id", ct.c_uint64)]
+                ("jastrow", ct.c_void_p), ("n_walkers", ct.c_int32), ("system_id", ct.c_uint64),
+                ("n_ecp", ct.c_int32), ("ecp_atom", ct.c_void_p), ("ecp_l", ct.c_void_p),
+                ("ecp_pow", ct.c_void_p), ("ecp_coef", ct.c_void_p), ("ecp_exp", ct.c_void_p),
+                ("ecp_rcut", ct.c_void_p)]
 
 
 class lrdmc_params(ct.Structure):
@@ -146,6 +149,15 @@ def _sys_struct(d, keep):
         arrs[k] = np.ascontiguousarray(d[k], dtype=dt)
         keep.append(arrs[k])
     n_walkers = int(d.get("n_walkers_run", d["init_pos"].shape[0]))
+    n_ecp = len(d.get("ecp_atom", ()))
+    ecp = [None] * 6
+    if n_ecp:
+        for n, (k, dt) in enumerate((("ecp_atom", np.int32), ("ecp_l", np.int32), ("ecp_pow", np.int32),
+                                     ("ecp_coef", np.float64), ("ecp_exp", np.float64),
+                                     ("ecp_rcut", np.float64))):
+            a = np.ascontiguousarray(d[k], dtype=dt)
+            keep.append(a)
+            ecp[n] = a.ctypes.data
     return lrdmc_system(
         int(arrs["atom_pos"].shape[0]), arrs["atom_pos"].ctypes.data,
         arrs["atom_charge"].ctypes.data, arrs["atom_core"].ctypes.data,
@@ -154,7 +166,7 @@ def _sys_struct(d, keep):
         arrs["basis_type"].ctypes.data, arrs["basis_exp"].ctypes.data,
         int(arrs["mo_coeff"].shape[1]), arrs["mo_coeff"].ctypes.data, int(d["n_up"]),
         int(d["n_dn"]), int(arrs["jastrow"].shape[0] - 2), arrs["jastrow"].ctypes.data,
-        n_walkers, int(d.get("system_id", 0)))
+        n_walkers, int(d.get("system_id", 0)), n_ecp, *ecp)
 
 
 def make_params(scheme="lb", a=0.2, tau=0.25, n_proj=300, seed=12033, refresh_every=None,

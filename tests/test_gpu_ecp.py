@@ -1,0 +1,116 @@
+"""Non-local pseudopotential on the GPU (App. D: the non-local elements of the
+fixed-node Hamiltonian under the determinant locality approximation; octahedral
+quadrature of the sphere through the electron along the walker's lattice
+versors, one proposal per quadrature point) against the FP64 oracle: moves,
+non-local moves included, and positions bit-exact, e_L within 1e-9 Ha, weights
+to 1e-11, over two phases with the reconfiguration between them, in both
+schemes, on fixed and randomly rotated lattices; sampled walkers of the full
+4096-walker population; both schemes sample the same state; the paths without
+a pseudopotential kernel return LRDMC_ERR_UNSUPPORTED."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2508_12033_amd import inputs as I
+from paper_2508_12033_amd import lrdmc as B
+from parity_util import assert_phase_ok, compare_phase, make_handle, say
+
+pytestmark = pytest.mark.gpu
+
+
+def ecp_system(nw):
+    return I.c1_ecp_system(n_walkers=nw)
+
+
+# strong channels (all three l, attractive s and p): non-local moves are then
+# a few per cent of the moves of an electron inside a sphere
+STRONG = ((0, 0, -60.0, 2.5), (1, 0, -40.0, 3.0), (2, 0, 20.0, 3.0), (2, 2, -8.0, 2.0))
+
+
+def strong_system(nw):
+    d0 = I.c1_system(n_walkers=nw)
+    return I.with_ecp(d0, np.where(d0["atom_core"] == I.SOFTCORE)[0], terms=STRONG)
+
+
+@pytest.mark.parametrize("scheme,rotate", [("lb", False), ("conv", False), ("lb", True),
+                                           ("conv", True)])
+def test_ecp_phases_match_oracle(scheme, rotate):
+    nw = 96
+    d = strong_system(nw)
+    say("case pseudopotential c1 (strong channels)", scheme, "rotate" if rotate else "fixed axes", nw, "walkers")
+    h, d2, prm = make_handle(d, scheme, nw, n_proj=150, tau=0.125, rotate=rotate)
+    N = int(d2["n_elec"])
+    e0 = h.e0()
+    pos = d2["init_pos"][:nw].copy()
+    lw = np.zeros(nw)
+    n_nl = 0
+    for j in range(2):
+        h.step()
+        g = h.walkers(trace=True)
+        res = compare_phase(d2, prm, scheme, j, e0, pos, lw, g, np.arange(nw))
+        say(scheme, j, {k: v for k, v in res.items() if k != "oracle"})
+        assert_phase_ok(res)
+        n_nl += int((g["trace"] >= 6 * N).sum())
+        bs = h.branch()
+        after = h.walkers()
+        xi = O.uniform(prm.seed, 0, 0, j, 0, O.RNG_COMB)
+        sel, _, cnt = O.comb(g["lw"], xi, follow=after["sel"])
+        assert cnt["hard_mismatch"] == 0 and np.array_equal(sel, after["sel"])
+        pos = after["pos"].copy()
+        lw = np.zeros(nw)
+        e0 = bs.e0
+    say("non-local moves taken:", n_nl)
+    assert n_nl > 20
+    h.close()
+
+
+@pytest.mark.parametrize("scheme", ["lb", "conv"])
+def test_ecp_full_population_sampled(scheme):
+    """4096 walkers at N_proj = 300 (tau = 0.25), the benchmark's launch; 32
+    sampled walkers against the oracle."""
+    nw = 4096
+    d = ecp_system(nw)
+    say("case pseudopotential c1, full population", scheme)
+    h, d2, prm = make_handle(d, scheme, nw)
+    e0 = h.e0()
+    pos = d2["init_pos"][:nw].copy()
+    h.step()
+    g = h.walkers(trace=True)
+    idx = np.linspace(0, nw - 1, 32).astype(int)
+    res = compare_phase(d2, prm, scheme, 0, e0, pos, np.zeros(nw), g, idx)
+    say(scheme, {k: v for k, v in res.items() if k != "oracle"})
+    assert_phase_ok(res)
+    assert np.all(np.isfinite(g["eL"])) and np.all(np.isfinite(g["W"]))
+    h.close()
+
+
+def test_ecp_schemes_agree():
+    """Conventional and load-balanced estimates of the same fixed-node
+    lattice Hamiltonian with the pseudopotential agree (Sec. II.C, Sec. III)."""
+    d = ecp_system(2048)
+    res = {}
+    for sch in ("lb", "conv"):
+        prm = B.params_for(d, sch, n_therm=60)
+        h = B.Handle(d, prm)
+        h.run(240)
+        res[sch] = h.energy()
+        h.close()
+    (e1, s1, _), (e2, s2, _) = res["lb"], res["conv"]
+    z = (e1 - e2) / np.hypot(s1, s2)
+    say("pseudopotential c1: lb %.4f +- %.4f, conv %.4f +- %.4f, z %.2f" % (e1, s1, e2, s2, z))
+    assert abs(z) < 3.5
+
+
+def test_ecp_unsupported_paths():
+    d = ecp_system(8)
+    d2 = dict(d)
+    d2["n_walkers_run"] = 8
+    for prec in ("fp32", "bf16"):
+        with pytest.raises(B.LrdmcError) as ei:
+            B.Handle(d2, B.params_for(d2, "lb", precision=prec, n_proj=4))
+        assert ei.value.code == -6
+    h = B.Handle(d2, B.params_for(d2, "lb", n_proj=4))
+    with pytest.raises(B.LrdmcError) as ei:
+        h.walker_derivs()
+    assert ei.value.code == -6
+    h.close()
