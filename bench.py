@@ -18,6 +18,8 @@ all 6N move ratios x 6N / wall time.  Printed beside it:
   - the mixed-precision paths with their stated errors: the same 16-electron
     workload in FP32, the 128-electron / 2048-walker system with the BF16
     orbital product (and FP32), the three uneven systems in one launch;
+  - the 16-electron system with a non-local pseudopotential (6N lattice moves
+    plus the quadrature points of the electrons inside a cutoff sphere);
   - the adjoint pass (per-walker parameter derivatives) on the 16-electron
     system with electron-nucleus Jastrow terms;
   - the roofline of the phase kernel and the CPU oracle on a bounded sample.
@@ -243,9 +245,10 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="headline only (no mixed, batched or adjoint lines)")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--profile-workload", choices=["c3_bf16", "c3_fp32", "c1_fp32", "c2_fp32"],
-                    help="run only this mixed-precision workload for --steps cycles (for profilers) "
-                         "and print its line")
+    ap.add_argument("--profile-workload",
+                    choices=["c3_bf16", "c3_fp32", "c1_fp32", "c2_fp32", "ce_fp64"],
+                    help="run only this workload (ce: the 16-electron system with the non-local "
+                         "pseudopotential) for --steps cycles (for profilers) and print its line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: measures one GPU only; --gpus %d is not supported "
@@ -265,7 +268,7 @@ def main():
     if args.profile_workload:
         wl = args.profile_workload
         sysd = {"c3": lambda: I.c3_system(n_walkers=2048), "c1": lambda: I.c1_system(n_walkers=4096),
-                "c2": I.c2_systems}[wl[:2]]()
+                "c2": I.c2_systems, "ce": lambda: I.c1_ecp_system(n_walkers=4096)}[wl[:2]]()
         hx, _, r = run_cycles(B, sysd, "lb", args.steps, args.warmup, precision=wl[3:],
                               threads=128 if wl == "c2_fp32" else None)
         hx.close()
@@ -353,7 +356,8 @@ def main():
         # walkers) and the 16-electron system (4096 walkers)
         agree = {}
         for name, dd, nw_, nb in (("h2_256w", I.h2_system(n_walkers=256), 100, 300),
-                                  ("c1_4096w", d, 100, 300)):
+                                  ("c1_4096w", d, 100, 300),
+                                  ("c1_ecp_4096w", I.c1_ecp_system(n_walkers=4096), 100, 300)):
             row = dict(equilibration_branchings=nw_, measured_branchings=nb)
             for sch in ("lb", "conv"):
                 hs = B.Handle(dd, B.params_for(dd, sch, n_therm=nw_))
@@ -419,6 +423,23 @@ def main():
         row["fp32_vs_fp64"] = row["fp32"]["proposals_per_s"] / row["fp64"]["proposals_per_s"]
         row["bf16_vs_fp64"] = row["bf16"]["proposals_per_s"] / row["fp64"]["proposals_per_s"]
         extra["e32_mixed_vs_fp64"] = row
+        # the 16-electron system with a non-local pseudopotential (synthetic s
+        # and p channels on its two cores, cutoff 1.3 bohr): per step the 6N
+        # lattice moves plus six quadrature points per electron inside a sphere
+        de = I.c1_ecp_system(n_walkers=4096)
+        hx, px, r = run_cycles(B, de, "lb", steps_x, 1)
+        wk = hx.walkers()
+        Ra, rc = np.asarray(de["atom_pos"]), np.asarray(de["ecp_rcut"])
+        dist = np.linalg.norm(wk["pos"].reshape(4096, -1, 1, 3) - Ra[None, None], axis=3)
+        inside = float(((dist < rc[None, None]) & (rc[None, None] > 0)).any(axis=2).mean())
+        extra["c1_ecp_fp64"] = dict(
+            workload="16 electrons, 8 atoms, non-local s and p channels on the two cores, 4096 walkers, "
+                     "a=0.2, N_proj=300, FP64",
+            lattice_proposals_per_s=r["proposals"] / r["seconds"],
+            proposals_per_s=r["proposals"] / r["seconds"] * (1.0 + inside),
+            ms_per_branching=r["ms_per_cycle"], electrons_inside_spheres=inside,
+            time_vs_local_only=r["ms_per_cycle"] / lb["ms_per_cycle"])
+        hx.close()
         # adjoint pass: 4096 walkers, 24 nuclear coordinates + 15 Jastrow parameters
         c4 = I.c4_system(n_walkers=4096)
         ha = B.Handle(c4, B.params_for(c4, "lb", n_proj=10))
