@@ -357,7 +357,7 @@ def main():
         agree = {}
         for name, dd, nw_, nb in (("h2_256w", I.h2_system(n_walkers=256), 100, 300),
                                   ("c1_4096w", d, 100, 300),
-                                  ("c1_ecp_4096w", I.c1_ecp_system(n_walkers=4096), 100, 300)):
+                                  ("c1_ecp_4096w", I.c1_ecp_system(n_walkers=4096), 200, 600)):
             row = dict(equilibration_branchings=nw_, measured_branchings=nb)
             for sch in ("lb", "conv"):
                 hs = B.Handle(dd, B.params_for(dd, sch, n_therm=nw_))

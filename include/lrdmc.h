@@ -156,7 +156,9 @@ typedef struct lrdmc_params {
                                 corrections of the carried FP32 inverse on FP64 MFMA (also at
                                 the start of every phase), a Gauss-Jordan rebuild when its
                                 residual is 3e-3 or more, after a tiny determinant ratio, and
-                                for rows rebuilt from positions */
+                                for rows rebuilt from positions; the FP32 Jastrow caches are
+                                rebuilt at every fourth scheduled refresh (and at the start of
+                                a phase and after a tiny ratio) */
     int32_t nu_opt_mode;     /* LRDMC_NU_* */
     int32_t p_corr;          /* correcting factors: product of the p previous
                                 average weights (Sec. II.A) */

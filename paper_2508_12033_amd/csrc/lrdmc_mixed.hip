@@ -821,9 +821,14 @@ __device__ __noinline__ int mixed_ns_correct(const DevMix* __restrict__ dm, floa
 // periodic: a refresh of carried inverses (scheduled, or at the start of a
 // phase), which first tries one or two Newton-Schulz corrections of each
 // inverse; otherwise (rows rebuilt from positions, a tiny determinant ratio)
-// the inverses are rebuilt by Gauss-Jordan
+// the inverses are rebuilt by Gauss-Jordan.  jas: the Jastrow caches and
+// potentials are rebuilt from the positions as well (the pair-difference
+// updates of one move add a rounding each, far less than the rank-one updates
+// of the inverse, so the scheduled refreshes rebuild them only every
+// kJastrowEvery-th time)
+constexpr int kJastrowEvery = 4;
 __device__ __noinline__ bool mixed_refresh(const DevMix* __restrict__ dm, float* st, double a,
-                                           bool periodic)
+                                           bool periodic, bool jas = true)
 {
     const DevMix& s = *dm;
     bool ok = true;
@@ -835,8 +840,10 @@ __device__ __noinline__ bool mixed_refresh(const DevMix* __restrict__ dm, float*
         }
         if (st_ns != 0) ok = mixed_refresh_inverse(&s, st, sp) && ok;
     }
-    const double vee = mixed_jastrow_all(&s, a);
-    if (threadIdx.x == 0) LDSD(s.l_scal)[kScVee] = vee;
+    if (jas) {
+        const double vee = mixed_jastrow_all(&s, a);
+        if (threadIdx.x == 0) LDSD(s.l_scal)[kScVee] = vee;
+    }
     mixed_spin_update(&s, st, 0, false);
     mixed_spin_update(&s, st, 1, false);
     mixed_full_ratios(s);
@@ -913,7 +920,10 @@ __device__ __noinline__ MLocal mixed_evaluate(const DevMix* __restrict__ dm, dou
 // FP64 Slater rows A64[i][k] = sum_mu chi_mu(r_i) C[mu][k] (k < ns): in rounds
 // of one row tile of 16 electrons per wavefront, the basis values of the
 // round's electrons in chunks of fkc functions ([16 waves][fkc + 1] in LDS),
-// the product on MFMA with every column tile of the row tile.
+// the product on MFMA with every column tile of the row tile.  Where the
+// scratch block has room, the chunk's coefficients are staged in LDS beside
+// the basis values ([fkc][16 TC + 1]) by coalesced loads of all threads, so
+// that the products read both operands from LDS.
 __device__ __noinline__ void final_slater_rows(const DevMix& s, const double* pos, double* A64)
 {
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
@@ -921,6 +931,9 @@ __device__ __noinline__ void final_slater_rows(const DevMix& s, const double* po
     const int TR = (N + 15) / 16, TC = (ns + 15) / 16;   // TC <= 4
     const int i16 = lane & 15, k4 = lane >> 4;
     double* Bc = LDSD(s.l_U);                    // [16 nwv][kc + 1]
+    double* Cc = Bc + 16 * nwv * ldc;            // [kc][16 TC + 1]
+    const int w16 = 16 * TC, ldcc = w16 + 1, ctot = kc * w16;
+    const bool stage = (long)(16 * nwv * ldc + kc * ldcc) * 8 <= (long)(s.l_R - s.l_U);
     for (int r0 = 0; r0 < TR; r0 += nwv) {
         const int rows0 = 16 * r0, nrows = 16 * min(nwv, TR - r0), tr = r0 + wv;
         double4_m acc[4];
@@ -940,6 +953,13 @@ __device__ __noinline__ void final_slater_rows(const DevMix& s, const double* po
                 }
                 Bc[el * ldc + m] = v;
             }
+            if (stage) {
+                for (int idx = tid; idx < ctot; idx += nt) {
+                    const int m = idx / w16, col = idx - m * w16;
+                    Cc[m * ldcc + col] = (m < cnt && col < ns)
+                                             ? gld(s.C64 + (long)(m0 + m) * s.Norb + col) : 0.0;
+                }
+            }
             __syncthreads();
             if (tr < TR) {
                 for (int k0 = 0; k0 < cnt; k0 += 4) {
@@ -949,7 +969,9 @@ __device__ __noinline__ void final_slater_rows(const DevMix& s, const double* po
                     for (int t = 0; t < 4; ++t) {
                         if (t >= TC) continue;
                         const int col = 16 * t + i16;
-                        const double bv = (col < ns && k0 + k4 < cnt) ? gld(s.C64 + (long)mu * s.Norb + col) : 0.0;
+                        const double bv = stage ? Cc[(k0 + k4) * ldcc + col]
+                                                : ((col < ns && k0 + k4 < cnt)
+                                                       ? gld(s.C64 + (long)mu * s.Norb + col) : 0.0);
                         acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
                     }
                 }
@@ -973,27 +995,42 @@ __device__ __noinline__ void final_slater_rows(const DevMix& s, const double* po
 
 // Z[mu][c] = sum_k C[mu][k] Ainv[k][c] of spin sp (Ai64 holds AiT[c][k]) on
 // MFMA: each wavefront takes row tiles of 16 basis functions with every
-// column tile.
+// column tile.  The inverse is staged in LDS once (row stride n + 1), and a
+// tile's coefficient operands (at most 16 k-steps, n <= 64) are all fetched
+// before its products, so that their latencies overlap.
 __device__ __noinline__ void final_z(const DevMix& s, int sp, const double* AiT, double* Z)
 {
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
-    const int n = mnspin(s, sp), Nb = s.Nb, ns = s.ns;
+    const int n = mnspin(s, sp), Nb = s.Nb, ns = s.ns, ldt = n + 1;
     const int TR = (Nb + 15) / 16, TC = (n + 15) / 16;   // TC <= 4
     const int i16 = lane & 15, k4 = lane >> 4;
+    double* T = LDSD(s.l_U);                     // [n][n + 1] AiT of the spin
+    for (int idx = tid; idx < n * n; idx += nt) {
+        const int c = idx / n, k = idx - c * n;
+        T[c * ldt + k] = AiT[(long)c * ns + k];
+    }
+    __syncthreads();
     for (int tr = wv; tr < TR; tr += nwv) {
         double4_m acc[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = (double4_m){0.0, 0.0, 0.0, 0.0};
         const int mu_a = 16 * tr + i16;
-        for (int k0 = 0; k0 < n; k0 += 4) {
-            const int k = k0 + k4;
-            const double av = (mu_a < Nb && k < n) ? gld(s.C64 + (long)mu_a * s.Norb + k) : 0.0;
+        double av[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int k = 4 * q + k4;
+            av[q] = (mu_a < Nb && k < n) ? gld(s.C64 + (long)mu_a * s.Norb + k) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (4 * q >= n) break;
+            const int k = 4 * q + k4;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 if (t >= TC) continue;
                 const int c = 16 * t + i16;
-                const double bv = (c < n && k < n) ? AiT[(long)c * ns + k] : 0.0;
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+                const double bv = (c < n && k < n) ? T[c * ldt + k] : 0.0;
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv, acc[t], 0, 0, 0);
             }
         }
 #pragma unroll
@@ -1007,6 +1044,7 @@ __device__ __noinline__ void final_z(const DevMix& s, int sp, const double* AiT,
             }
         }
     }
+    __syncthreads();   // T is restaged by the next call
 }
 
 // ---------------------------------------------------------------------------
@@ -1065,10 +1103,19 @@ __device__ __noinline__ MLocal mixed_final_fp64(const DevMix* __restrict__ dm, i
                 const int sp = mspin(s, i), c = mcol(s, i);
                 const double* Zc = Z64 + (long)sp * Nb * ns + (long)c * Nb;
                 const double* ri = pos + 3 * i;
+                // the next function's Z entry and record are fetched while
+                // the current one is evaluated
+                double zn = g16 < Nb ? Zc[g16] : 0.0;
+                double4_t recn = gld((const double4_t*)(s.btab + 4 * (g16 < Nb ? g16 : 0)));
+                int tyn = gld(s.btype + (g16 < Nb ? g16 : 0));
                 for (int mu = g16; mu < Nb; mu += 16) {
-                    const double z = Zc[mu];
-                    const double4_t rec = gld((const double4_t*)(s.btab + 4 * mu));
-                    const int ty = gld(s.btype + mu);
+                    const double z = zn;
+                    const double4_t rec = recn;
+                    const int ty = tyn;
+                    const int mn = mu + 16 < Nb ? mu + 16 : mu;
+                    zn = Zc[mn];
+                    recn = gld((const double4_t*)(s.btab + 4 * mn));
+                    tyn = gld(s.btype + mn);
                     const double al = rec[3];
                     const double d[3] = {ri[0] - rec[0], ri[1] - rec[1], ri[2] - rec[2]};
                     const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
@@ -1541,7 +1588,7 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
     // (lw_block_update): one logarithm per 32 steps instead of one per step
     double wprod = 1.0;
     double tau_left = pa.tau;
-    int it = 0, since = 0;
+    int it = 0, since = 0, n_sched = 0;
     MLocal L;
     int32_t* tr = s.trace ? s.trace + (long)wid * s.trace_cap : nullptr;
     for (;;) {
@@ -1586,7 +1633,8 @@ __global__ __launch_bounds__(kMixThreads) void phase_mixed(MixBatch b, PhaseArgs
             ++since;
             if (small) n_small++;
             if (small || since >= pa.refresh_every) {
-                if (!mixed_refresh(&s, st, a, !small)) n_sing++;
+                const bool jas = small || ++n_sched % kJastrowEvery == 0;
+                if (!mixed_refresh(&s, st, a, !small, jas)) n_sing++;
                 n_refresh++;
                 since = 0;
             }
