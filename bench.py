@@ -405,6 +405,14 @@ def main():
             tune=r["tune"], error=[precision_summary(hx, k) for k in range(3)],
             roofline=mixed_roofline(c2, px, stx.elapsed_ms))
         hx.close()
+        # the same three systems as three handles, one launch each (each tuned)
+        sep = []
+        for dk in c2:
+            hk, _, rk = run_cycles(B, dk, "lb", steps_x, 1, precision="fp32", tune=True)
+            sep.append(rk["ms_per_cycle"])
+            hk.close()
+        extra["c2_batched_fp32"]["separate_launches_ms"] = sep
+        extra["c2_batched_fp32"]["one_launch_vs_separate"] = sum(sep) / r["ms_per_cycle"]
         # mixed vs FP64 on one system that both layouts hold: the 32-electron
         # molecule of the uneven set (16 orbitals per spin, 160 basis
         # functions), 4096 walkers, N_proj = 300

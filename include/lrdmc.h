@@ -218,6 +218,9 @@ typedef struct lrdmc_tune_entry {
     int32_t threads;          /* workgroup size of the mixed-precision phase kernel */
     int32_t order_big_first;  /* 1: systems with more electrons first in the launch */
     float ms;                 /* projected time of a full phase */
+    int32_t system;           /* -1: every mixed system in one launch; k >= 0: system k
+                                 launched alone; -2: one launch per system, each with
+                                 its fastest workgroup size (ms: their sum) */
 } lrdmc_tune_entry;
 
 /* ---- calls ------------------------------------------------------------- */
@@ -272,20 +275,25 @@ int lrdmc_branch(struct lrdmc_handle *h, lrdmc_branch_stats *st);
 int lrdmc_run(struct lrdmc_handle *h, int n_branchings, lrdmc_step_stats *st,
               lrdmc_branch_stats *bst);
 
-/* Autotuner of the mixed-precision launch (every mixed-precision system of
- * the handle advances in one launch): each candidate workgroup size (256, 128
- * or 64 threads per walker) and order of the systems in the launch is timed on
- * a copy of the current walkers for n_steps and 2 n_steps load-balanced
- * steps, and the one with the shortest projected full phase (fixed cost plus
- * N_proj times the per-step cost) is kept for later phases.  The walkers, weights, E_0 and random streams of
- * the run are not changed.  log (may be NULL) receives up to log_cap timings,
- * *n_log their number.  Synchronises.  No effect for FP64 handles. */
+/* Autotuner of the mixed-precision launch.  Candidates: every mixed-precision
+ * system of the handle in one launch, for each workgroup size (256, 128 or 64
+ * threads per walker) and order of the systems; and, with several systems,
+ * one launch per system with its own LDS block and its own fastest workgroup
+ * size.  Each is timed on a copy of the current walkers for n_steps and
+ * 2 n_steps load-balanced steps, and the one with the shortest projected full
+ * phase (fixed cost plus N_proj times the per-step cost) is kept for later
+ * phases.  The walkers, weights, E_0 and random streams of the run are not
+ * changed.  log (may be NULL) receives up to log_cap timings, *n_log their
+ * number.  Synchronises.  No effect for FP64 handles. */
 int lrdmc_autotune(struct lrdmc_handle *h, int n_steps, lrdmc_tune_entry *log, int log_cap,
                    int *n_log);
 
-/* Fix the mixed-precision launch instead of tuning it: threads per walker
- * workgroup (64, 128 or 256) and the order of the systems in the launch (1:
- * more electrons first).  No effect on results beyond FP32 summation order. */
+/* Fix the mixed-precision launch instead of tuning it: every mixed system in
+ * one launch with threads per walker workgroup (64, 128 or 256), or threads =
+ * 0: one launch per system, each with its own LDS block and the workgroup size
+ * of the last tuning (256 before any); order_big_first: the order of the
+ * systems (1: more electrons first).  No effect on results beyond FP32
+ * summation order. */
 int lrdmc_set_launch(struct lrdmc_handle *h, int threads, int order_big_first);
 
 /* Energy estimate from the branching history (Sec. II.A correcting factors,

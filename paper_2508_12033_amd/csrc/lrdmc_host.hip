@@ -422,11 +422,14 @@ struct lrdmc_handle {
     unsigned long long* counters;           // [kCntLen] device
     hipEvent_t ev0, ev1;
     unsigned long long* timers = nullptr;   // instrumentation builds: [nw][8]
-    // one launch advances every mixed-precision system
+    // one launch advances every mixed-precision system (batched), or one
+    // launch per system with its own workgroup size and LDS block (separate)
     std::vector<int> mix_order;             // system indices in launch order
     DevMix* mix_tab[2];                     // device descriptor tables per slot
     int mix_threads = kMixThreads;
     size_t mix_lds = 0;
+    int mix_separate = 0;
+    std::vector<int> mix_sys_threads;       // [system] workgroup size when separate
     // captured step + reconfiguration per slot
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -488,6 +491,50 @@ PhaseArgs phase_args(const lrdmc_handle* h, int N, int nproj_override)
     return pa;
 }
 
+// The mixed-precision phase of the systems in launch order, walkers in slot p:
+// one launch for all of them (workgroup b of system k when start[k] <= b <
+// start[k+1]; every system gets the largest LDS block and one workgroup size),
+// or with separate = 1 one launch per system with its own LDS block and
+// workgroup size.  only >= 0: that system alone (the autotuner's timing runs),
+// with workgroup size threads_only.
+int launch_mixed(lrdmc_handle* h, hipStream_t st, int p, int nproj_override, int build, int separate,
+                 int only, int threads_only = 0)
+{
+    const int n = (int)h->mix_order.size();
+    if (!separate && only < 0) {
+        MixBatch b{};
+        b.tab = h->mix_tab[p];
+        b.nsys = n;
+        int tot = 0, maxN = 1;
+        for (int k = 0; k < n; ++k) {
+            SysRun& r = h->sys[h->mix_order[k]];
+            b.start[k] = tot;
+            tot += r.nw;
+            maxN = std::max(maxN, r.N);
+        }
+        b.start[n] = tot;
+        const PhaseArgs pa = phase_args(h, maxN, nproj_override);
+        hipLaunchKernelGGL(phase_mixed, dim3(tot), dim3(h->mix_threads), h->mix_lds, st, b, pa, build);
+        HIPCHK(hipGetLastError());
+        return LRDMC_OK;
+    }
+    for (int k = 0; k < n; ++k) {
+        const int isys = h->mix_order[k];
+        if (only >= 0 && isys != only) continue;
+        SysRun& r = h->sys[isys];
+        MixBatch b{};
+        b.tab = h->mix_tab[p] + k;
+        b.nsys = 1;
+        b.start[0] = 0;
+        b.start[1] = r.nw;
+        const int thr = only >= 0 ? threads_only : h->mix_sys_threads[isys];
+        const PhaseArgs pa = phase_args(h, r.N, nproj_override);
+        hipLaunchKernelGGL(phase_mixed, dim3(r.nw), dim3(thr), r.L.lds_bytes, st, b, pa, build);
+        HIPCHK(hipGetLastError());
+    }
+    return LRDMC_OK;
+}
+
 // One projection phase for every system on stream st with walkers in slot p.
 // nproj_override >= 0: a load-balanced phase of that many steps (0 = evaluate
 // only).  FP64 systems: one launch each; mixed systems: one launch for all.
@@ -505,21 +552,12 @@ int launch_phases(lrdmc_handle* h, hipStream_t st, int p, int nproj_override, bo
     }
     const int n = (int)h->mix_order.size();
     if (n) {
-        MixBatch b{};
-        b.tab = h->mix_tab[p];
-        b.nsys = n;
-        int tot = 0, build = 0;
-        for (int k = 0; k < n; ++k) {
-            SysRun& r = h->sys[h->mix_order[k]];
-            b.start[k] = tot;
-            tot += r.nw;
-            if (r.need_build) build = 1;
-        }
-        b.start[n] = tot;
+        int build = 0;
+        for (int k = 0; k < n; ++k)
+            if (h->sys[h->mix_order[k]].need_build) build = 1;
         if (build && !allow_build) return fail(LRDMC_ERR_INVALID_ARG, "rebuild pending in a capture");
-        const PhaseArgs pa = phase_args(h, maxN, nproj_override);
-        hipLaunchKernelGGL(phase_mixed, dim3(tot), dim3(h->mix_threads), h->mix_lds, st, b, pa, build);
-        HIPCHK(hipGetLastError());
+        const int rc = launch_mixed(h, st, p, nproj_override, build, h->mix_separate, -1);
+        if (rc) return rc;
         for (int k = 0; k < n; ++k) h->sys[h->mix_order[k]].need_build = false;
     }
     return LRDMC_OK;
@@ -1046,6 +1084,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             r.need_build = true;
             h->mix_order.push_back(k);
             h->mix_lds = std::max(h->mix_lds, L.lds_bytes);
+            h->mix_sys_threads.assign(n_sys, kMixThreads);
         }
         if (up(r.pos[0], ip, nw * 3 * L.N * 8) != hipSuccess ||
             hipMemsetAsync(r.lw, 0, nw * 8, h->stream) != hipSuccess) {
@@ -1240,71 +1279,97 @@ int lrdmc_autotune(lrdmc_handle* h, int n_steps, lrdmc_tune_entry* log, int log_
                                                                 : std::vector<std::vector<int>>{big};
     const int threads[3] = {256, 128, 64};
     const std::vector<int> keep_order = h->mix_order;
-    const int keep_threads = h->mix_threads;
+    const int keep_threads = h->mix_threads, keep_sep = h->mix_separate;
+    const std::vector<int> keep_sys_threads = h->mix_sys_threads;
     float best = 1e30f;
     int best_t = keep_threads;
     std::vector<int> best_o = keep_order;
     h->tune_log.clear();
     int rc = LRDMC_OK;
+    const int steps_full = h->prm.scheme == LRDMC_SCHEME_LB
+                               ? h->prm.n_proj
+                               : std::max(1, (int)(h->prm.tau * 3.0 * maxN_all(h) / (h->prm.a * h->prm.a)));
     // the tuning phases update the log-weights in place: keep them
     for (int k : h->mix_order) {
         SysRun& r = h->sys[k];
         HIPCHK(hipMemcpyAsync(r.cum, r.lw, (size_t)r.nw * 8, hipMemcpyDeviceToDevice, h->stream));
     }
+    // projected time of a full phase of one launch configuration: two tuning
+    // phases of n_steps and 2 n_steps on copies of the walkers in the other
+    // slot; the difference is the per-step cost, the rest the fixed cost of a
+    // phase (refresh, FP64 estimator evaluation)
+    auto project = [&](int only, int thr, float& ms_full) -> int {
+        float tms[2] = {0.f, 0.f};
+        for (int rep = 0; rep < 2; ++rep) {
+            for (int k : h->mix_order) {
+                if (only >= 0 && k != only) continue;
+                SysRun& r = h->sys[k];
+                const size_t nw = r.nw;
+                if (hipMemcpyAsync(r.pos[q], r.pos[p], nw * 3 * r.N * 8, hipMemcpyDeviceToDevice, h->stream) ||
+                    hipMemcpyAsync(r.state[q], r.state[p], nw * r.L.m_stride * 4, hipMemcpyDeviceToDevice, h->stream))
+                    return fail(LRDMC_ERR_HIP, "tuning copy failed");
+            }
+            HIPCHK(hipEventRecord(h->ev0, h->stream));
+            int rc1 = launch_mixed(h, h->stream, q, n_steps * (rep + 1), 0, 0, only, thr);
+            if (rc1) return rc1;
+            HIPCHK(hipEventRecord(h->ev1, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+            HIPCHK(hipEventElapsedTime(&tms[rep], h->ev0, h->ev1));
+        }
+        const float per_step = std::max(0.f, (tms[1] - tms[0]) / n_steps);
+        const float fixed = std::max(0.f, tms[0] - per_step * n_steps);
+        ms_full = fixed + per_step * steps_full;
+        return LRDMC_OK;
+    };
+    // one launch for all systems: workgroup size x order
     for (size_t oi = 0; oi < orders.size() && !rc; ++oi)
         for (int ti = 0; ti < 3 && !rc; ++ti) {
             h->mix_order = orders[oi];
             h->mix_threads = threads[ti];
             if ((rc = upload_mix_tables(h))) break;
-            // two tuning phases of n_steps and 2 n_steps: the difference is the
-            // per-step cost, the rest the fixed cost of a phase (refresh, FP64
-            // estimator evaluation); the candidate is ranked by the projected
-            // time of a full phase
-            float tms[2] = {0.f, 0.f};
-            for (int rep = 0; rep < 2 && !rc; ++rep) {
-                for (int k : h->mix_order) {
-                    SysRun& r = h->sys[k];
-                    const size_t nw = r.nw;
-                    if (hipMemcpyAsync(r.pos[q], r.pos[p], nw * 3 * r.N * 8, hipMemcpyDeviceToDevice, h->stream) ||
-                        hipMemcpyAsync(r.state[q], r.state[p], nw * r.L.m_stride * 4, hipMemcpyDeviceToDevice, h->stream))
-                        rc = fail(LRDMC_ERR_HIP, "tuning copy failed");
-                }
-                if (rc) break;
-                HIPCHK(hipEventRecord(h->ev0, h->stream));
-                // mixed systems only, on the copies
-                MixBatch b{};
-                b.tab = h->mix_tab[q];
-                b.nsys = (int)h->mix_order.size();
-                int tot = 0, maxN = 1;
-                for (int k = 0; k < b.nsys; ++k) {
-                    b.start[k] = tot;
-                    tot += h->sys[h->mix_order[k]].nw;
-                    maxN = std::max(maxN, h->sys[h->mix_order[k]].N);
-                }
-                b.start[b.nsys] = tot;
-                const PhaseArgs pa = phase_args(h, maxN, n_steps * (rep + 1));
-                hipLaunchKernelGGL(phase_mixed, dim3(tot), dim3(h->mix_threads), h->mix_lds,
-                                   h->stream, b, pa, 0);
-                HIPCHK(hipGetLastError());
-                HIPCHK(hipEventRecord(h->ev1, h->stream));
-                HIPCHK(hipStreamSynchronize(h->stream));
-                HIPCHK(hipEventElapsedTime(&tms[rep], h->ev0, h->ev1));
-            }
-            const float per_step = std::max(0.f, (tms[1] - tms[0]) / n_steps);
-            const float fixed = std::max(0.f, tms[0] - per_step * n_steps);
-            const int steps_full = h->prm.scheme == LRDMC_SCHEME_LB
-                                       ? h->prm.n_proj
-                                       : std::max(1, (int)(h->prm.tau * 3.0 * maxN_all(h) /
-                                                           (h->prm.a * h->prm.a)));
-            const float ms_best = fixed + per_step * steps_full;
-            if (rc) break;
+            float ms_full = 0.f;
+            if ((rc = project(-1, 0, ms_full))) break;
             lrdmc_tune_entry e;
             e.threads = h->mix_threads;
             e.order_big_first = (oi == 0) ? 1 : 0;
-            e.ms = ms_best;
+            e.ms = ms_full;
+            e.system = -1;
             h->tune_log.push_back(e);
-            if (ms_best < best) { best = ms_best; best_t = h->mix_threads; best_o = h->mix_order; }
+            if (ms_full < best) { best = ms_full; best_t = h->mix_threads; best_o = h->mix_order; }
         }
+    // one launch per system, each with its fastest workgroup size (with a
+    // single system this is the batched launch again)
+    std::vector<int> sep_threads(h->sys.size(), kMixThreads);
+    float sep_total = 0.f;
+    if (!rc && h->mix_order.size() > 1) {
+        h->mix_order = best_o;
+        rc = upload_mix_tables(h);
+        for (int k : best_o) {
+            if (rc) break;
+            float bk = 1e30f;
+            for (int ti = 0; ti < 3 && !rc; ++ti) {
+                float ms_full = 0.f;
+                if ((rc = project(k, threads[ti], ms_full))) break;
+                lrdmc_tune_entry e;
+                e.threads = threads[ti];
+                e.order_big_first = 0;
+                e.ms = ms_full;
+                e.system = k;
+                h->tune_log.push_back(e);
+                if (ms_full < bk) { bk = ms_full; sep_threads[k] = threads[ti]; }
+            }
+            sep_total += bk;
+        }
+        if (!rc) {
+            lrdmc_tune_entry e;
+            e.threads = 0;
+            e.order_big_first = 0;
+            e.ms = sep_total;
+            e.system = -2;
+            h->tune_log.push_back(e);
+        }
+    }
+    const bool use_sep = !rc && h->mix_order.size() > 1 && sep_total < best;
     for (int k : keep_order) {
         SysRun& r = h->sys[k];
         if (hipMemcpyAsync(r.lw, r.cum, (size_t)r.nw * 8, hipMemcpyDeviceToDevice, h->stream) && !rc)
@@ -1312,6 +1377,8 @@ int lrdmc_autotune(lrdmc_handle* h, int n_steps, lrdmc_tune_entry* log, int log_
     }
     h->mix_order = rc ? keep_order : best_o;
     h->mix_threads = rc ? keep_threads : best_t;
+    h->mix_separate = rc ? keep_sep : (use_sep ? 1 : 0);
+    h->mix_sys_threads = rc ? keep_sys_threads : sep_threads;
     const int rc2 = upload_mix_tables(h);
     drop_graphs(h);
     (void)reset_counters(h, h->stream);
@@ -1325,12 +1392,13 @@ int lrdmc_autotune(lrdmc_handle* h, int n_steps, lrdmc_tune_entry* log, int log_
 
 int lrdmc_set_launch(lrdmc_handle* h, int threads, int order_big_first)
 {
-    if (!h || (threads != 64 && threads != 128 && threads != 256))
-        return fail(LRDMC_ERR_INVALID_ARG, "threads must be 64, 128 or 256");
+    if (!h || (threads != 0 && threads != 64 && threads != 128 && threads != 256))
+        return fail(LRDMC_ERR_INVALID_ARG, "threads must be 0, 64, 128 or 256");
     std::stable_sort(h->mix_order.begin(), h->mix_order.end(), [&](int x, int y) {
         return order_big_first ? h->sys[x].N > h->sys[y].N : h->sys[x].N < h->sys[y].N;
     });
-    h->mix_threads = threads;
+    if (threads) h->mix_threads = threads;
+    h->mix_separate = threads == 0 ? 1 : 0;
     drop_graphs(h);
     return upload_mix_tables(h);
 }

@@ -66,7 +66,8 @@ class lrdmc_branch_stats(ct.Structure):
 
 
 class lrdmc_tune_entry(ct.Structure):
-    _fields_ = [("threads", ct.c_int32), ("order_big_first", ct.c_int32), ("ms", ct.c_float)]
+    _fields_ = [("threads", ct.c_int32), ("order_big_first", ct.c_int32), ("ms", ct.c_float),
+                ("system", ct.c_int32)]
 
 
 class lrdmc_energy(ct.Structure):
@@ -257,11 +258,14 @@ class Handle:
 
     def autotune(self, n_steps=8):
         """Time the launch candidates of the mixed-precision phase; returns the
-        list of (threads, big_first, ms) and keeps the fastest."""
-        log = (lrdmc_tune_entry * 16)()
+        list of (threads, big_first, ms, system) -- system -1: all systems in
+        one launch, k: system k alone, -2: one launch per system (sum) -- and
+        keeps the fastest."""
+        log = (lrdmc_tune_entry * 64)()
         n = ct.c_int(0)
-        _check(self.L.lrdmc_autotune(self.h, int(n_steps), log, 16, ct.byref(n)))
-        return [(log[k].threads, log[k].order_big_first, log[k].ms) for k in range(n.value)]
+        _check(self.L.lrdmc_autotune(self.h, int(n_steps), log, 64, ct.byref(n)))
+        return [(log[k].threads, log[k].order_big_first, log[k].ms, log[k].system)
+                for k in range(n.value)]
 
     def set_launch(self, threads, big_first=True):
         _check(self.L.lrdmc_set_launch(self.h, int(threads), 1 if big_first else 0))

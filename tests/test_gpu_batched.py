@@ -102,8 +102,14 @@ def test_autotune_keeps_state_and_parity():
     e0s = [h.e0(k) for k in range(3)]
     log = h.autotune(n_steps=4)
     say("tuning log", log)
-    assert len(log) == 6
-    assert {t for t, _, _ in log} == {64, 128, 256}
+    batched = [e for e in log if e[3] == -1]
+    single = [e for e in log if e[3] >= 0]
+    total = [e for e in log if e[3] == -2]
+    assert len(batched) == 6 and len(single) == 9 and len(total) == 1
+    assert {e[0] for e in batched} == {64, 128, 256}
+    assert {e[3] for e in single} == {0, 1, 2}
+    best_single = [min(e[2] for e in single if e[3] == k) for k in range(3)]
+    assert abs(total[0][2] - sum(best_single)) <= 1e-3 * sum(best_single)
     after = [h.walkers(k) for k in range(3)]
     for a, b in zip(before, after):
         assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["lw"], b["lw"])
@@ -115,6 +121,23 @@ def test_autotune_keeps_state_and_parity():
         g = h.walkers(k, trace=True)
         nw = d["n_walkers_run"]
         _check_system(d, prm, 1, e0s[k], pos0[k], before[k]["lw"], g, np.array([0, nw - 1]))
+    h.close()
+
+
+def test_separate_launches_match_oracle():
+    """One launch per system (each with its own LDS block), larger systems
+    first: the same walkers, decisions and estimator values as the oracle."""
+    ds = _systems((24, 12, 6))
+    say("case separate launches")
+    h, prm = _handle(ds, nproj=20)
+    h.set_launch(0, big_first=True)
+    e0s = [h.e0(k) for k in range(3)]
+    pos0 = [d["init_pos"][:d["n_walkers_run"]].copy() for d in ds]
+    h.step()
+    for k, d in enumerate(ds):
+        g = h.walkers(k, trace=True)
+        nw = d["n_walkers_run"]
+        _check_system(d, prm, 0, e0s[k], pos0[k], np.zeros(nw), g, np.arange(nw))
     h.close()
 
 
