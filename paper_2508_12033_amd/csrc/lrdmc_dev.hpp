@@ -59,6 +59,7 @@ struct DevSys {
     const int32_t *ecp_atom, *ecp_l, *ecp_pow;
     const double *ecp_coef, *ecp_exp, *ecp_rcut;
     int o_Vnl;               // LDS [6N]: element V_q of each quadrature point
+    int o_nlin;              // LDS [N]: 1 for an electron inside a sphere, else 0
 };
 
 // Nucleus record staged in LDS per walker by the FP64 phase kernel: x, y, z,

@@ -115,7 +115,7 @@ int kind_of(const lrdmc_params& p) { return p.precision == LRDMC_FP64 ? kKindLds
 struct Layout {
     int kind, N, P, ns;
     int PT;                  // proposals: 6N, or 12N with a non-local pseudopotential
-    int o_Vnl;
+    int o_Vnl, o_nlin;
     // FP64 kernel: LDS offsets (doubles), spill layout
     int ldb;
     int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje, o_scal, o_B,
@@ -178,9 +178,8 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.o_dje = take(N);
         L.o_scal = take(kScVee + 1);
         L.ldb = Nb + ((20 - Nb % 16) % 16);
-        const int nrow = nl ? 17 : 11;       // basis / orbital rows per electron
-        L.o_B = take(std::max(std::max(nrow * L.ldb, 2 * ns * ns), 7 * N));
-        L.o_rows = take(nrow * ns);
+        L.o_B = take(std::max(std::max(11 * L.ldb, 2 * ns * ns), 7 * N));
+        L.o_rows = take(11 * ns);
         L.o_tmp = take(3 * ns + 16);
         L.o_C = take(Nb * ns);
         L.o_nuc = take(kNucLen * M);
@@ -188,6 +187,7 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.o_gd = take(4 * N);
         L.o_ev = take(nl ? 18 : 9);
         L.o_Vnl = nl ? take(P) : 0;
+        L.o_nlin = nl ? take(N) : 0;
         L.lds_doubles = o;
         L.lds_bytes = (size_t)o * 8;
         L.s_Phi = 0;
@@ -1046,6 +1046,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             d.PT = L.PT; d.necp = r.nl ? s.n_ecp : 0;
             d.ecp_atom = e_atom; d.ecp_l = e_l; d.ecp_pow = e_pow;
             d.ecp_coef = e_coef; d.ecp_exp = e_exp; d.ecp_rcut = e_rcut; d.o_Vnl = L.o_Vnl;
+            d.o_nlin = L.o_nlin;
             for (int p = 0; p < 2; ++p) {
                 r.dsys[p] = (DevSys*)carve(sizeof(DevSys));
                 r.hsys[p] = d;

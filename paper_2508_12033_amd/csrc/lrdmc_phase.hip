@@ -64,7 +64,7 @@ constexpr int kPre = 8;
 
 struct Walker {
     int pos, R, Rdet, dJ, Arow, AinvT, Jg, Jl, nue, nua, dje, scal, B, rows, tmp, C, nuc, jas, gd, ev,
-        Vnl;
+        Vnl, nlin;
     double* Phi;
     double* dPhi;
 };
@@ -81,6 +81,7 @@ __device__ __forceinline__ Walker walker_view(const DevSys& s)
     w.gd = s.o_gd;
     w.ev = s.o_ev;
     w.Vnl = s.o_Vnl;
+    w.nlin = s.o_nlin;
     double* base = s.spill + (long)blockIdx.x * s.spill_stride;
     w.Phi = base + s.s_Phi;
     w.dPhi = base + s.s_dPhi;
@@ -222,12 +223,9 @@ __device__ __forceinline__ void lattice_point(const double* r, int q, double a, 
 // seven values, and the value at r gives the gradient and Laplacian.  Slater
 // functions take the seven points directly.  Orbitals: the 11 x Nb basis
 // block times the Nb x n coefficient block on FP64 MFMA (16x16x4 tiles; rows
-// 11..15 and columns >= n are padding).  With a pseudopotential (kNl), rows
-// 11..16 hold the values at the six quadrature points of the sphere of radius
-// nlr around atom nlI (zeros when nlI < 0).
-template <bool kRot, bool kNl = false>
-__device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, double a, int lane,
-                           int nlI = -1, double nlr = 0.0)
+// 11..15 and columns >= n are padding).
+template <bool kRot>
+__device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, double a, int lane)
 {
     const int Nb = s.Nb, ldb = s.ldb;
     const double* st = lds + w.ev;      // lattice step vectors a e_d
@@ -294,18 +292,25 @@ __device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, do
         Bm[8 * ldb] = g[1];
         Bm[9 * ldb] = g[2];
         Bm[10 * ldb] = l;
-        if constexpr (kNl) {
-            if (nlI >= 0) {
-                const double* nr = lds + w.nuc + kNucLen * nlI;
-                for (int q = 0; q < 6; ++q) {
-                    double pq[3];
-                    nl_point(nr, nlr, lds + w.ev + 9, q, pq);
-                    const double dx = pq[0] - c[0], dy = pq[1] - c[1], dz = pq[2] - c[2];
-                    Bm[(11 + q) * ldb] = basis_value_d(t, al, dx, dy, dz, dx * dx + dy * dy + dz * dz);
-                }
-            } else {
-                for (int q = 0; q < 6; ++q) Bm[(11 + q) * ldb] = 0.0;
-            }
+    }
+}
+
+// Basis values at the six quadrature points of a sphere (radius nlr around
+// atom nlI, along the walker's versors) in rows 0..5 of the basis block: one
+// lane per function, each point formed as the non-local move forms it.
+__device__ void nl_basis_rows(const DevSys& s, const Walker& w, int nlI, double nlr, int lane)
+{
+    const int Nb = s.Nb, ldb = s.ldb;
+    const double* nr = lds + w.nuc + kNucLen * nlI;
+    for (int mu = lane; mu < Nb; mu += kWave) {
+        const double4_t c = gld((const double4_t*)(s.btab + 4 * mu));
+        const int t = gld(s.btype + mu);
+        double* Bm = lds + w.B + mu;
+        for (int q = 0; q < 6; ++q) {
+            double pq[3];
+            nl_point(nr, nlr, lds + w.ev + 9, q, pq);
+            const double dx = pq[0] - c[0], dy = pq[1] - c[1], dz = pq[2] - c[2];
+            Bm[q * ldb] = basis_value_d(t, c[3], dx, dy, dz, dx * dx + dy * dy + dz * dz);
         }
     }
 }
@@ -315,11 +320,10 @@ __device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, do
 // b = (lane >> 2) & 3 holds A[b][i][k] at lane 16k + 4b + i, B[b][k][c] at
 // lane 16k + 4b + c and D[b][i][c] at lane 16i + 4b + c.  Blocks 2t and 2t+1
 // take column tile t of the pair and the even and odd k-steps; three
-// accumulators cover the row tiles 0..3, 4..7 and 8..10, and with a
-// pseudopotential two more the quadrature rows 11..14 and 15..16 (skipped,
-// and stored as zeros, when nl_on is false).
-template <bool kNl = false>
-__device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane, bool nl_on = false)
+// accumulators cover the row tiles 0..3, 4..7 and 8..10.  kQuad: the six
+// quadrature-point rows of a pseudopotential sphere instead (rows 0..5).
+template <bool kQuad = false>
+__device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
 {
     wave_sync();
     const int Nb = s.Nb, ldb = s.ldb;
@@ -329,74 +333,76 @@ __device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane, 
     for (int ct0 = 0; 4 * ct0 < n; ct0 += 2) {
         const int col = 4 * (ct0 + cb) + l4;
         const bool cok = col < n;
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0, acc4 = 0.0;
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
         for (int k0 = 0; k0 < Nb; k0 += 8) {
             const int mu = k0 + 4 * par + lk;
             const bool kok = mu < Nb;
             const double bv = (cok && kok) ? lds[w.C + mu * s.ns + col] : 0.0;
             const double a0 = kok ? lds[w.B + l4 * ldb + mu] : 0.0;
-            const double a1 = kok ? lds[w.B + (4 + l4) * ldb + mu] : 0.0;
-            const double a2 = (kok && l4 < 3) ? lds[w.B + (8 + l4) * ldb + mu] : 0.0;
+            const double a1 = (kok && (!kQuad || l4 < 2)) ? lds[w.B + (4 + l4) * ldb + mu] : 0.0;
+            const double a2 = (!kQuad && kok && l4 < 3) ? lds[w.B + (8 + l4) * ldb + mu] : 0.0;
             acc0 = __builtin_amdgcn_mfma_f64_4x4x4f64(a0, bv, acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f64_4x4x4f64(a1, bv, acc1, 0, 0, 0);
-            acc2 = __builtin_amdgcn_mfma_f64_4x4x4f64(a2, bv, acc2, 0, 0, 0);
-            if constexpr (kNl) {
-                if (nl_on) {
-                    const double a3 = kok ? lds[w.B + (11 + l4) * ldb + mu] : 0.0;
-                    const double a4 = (kok && l4 < 2) ? lds[w.B + (15 + l4) * ldb + mu] : 0.0;
-                    acc3 = __builtin_amdgcn_mfma_f64_4x4x4f64(a3, bv, acc3, 0, 0, 0);
-                    acc4 = __builtin_amdgcn_mfma_f64_4x4x4f64(a4, bv, acc4, 0, 0, 0);
-                }
-            }
+            if constexpr (!kQuad) acc2 = __builtin_amdgcn_mfma_f64_4x4x4f64(a2, bv, acc2, 0, 0, 0);
         }
         // odd k-steps (block 2t + 1, four lanes up) into block 2t: row_shl:4
         acc0 += dpp_mov<0x104, 0xf>(acc0);
         acc1 += dpp_mov<0x104, 0xf>(acc1);
-        acc2 += dpp_mov<0x104, 0xf>(acc2);
-        if constexpr (kNl) {
-            acc3 += dpp_mov<0x104, 0xf>(acc3);
-            acc4 += dpp_mov<0x104, 0xf>(acc4);
-        }
+        if constexpr (!kQuad) acc2 += dpp_mov<0x104, 0xf>(acc2);
         const int c = 4 * (ct0 + cb) + l4, i = lane >> 4;
         if (par == 0 && c < n) {
             lds[w.rows + i * s.ns + c] = acc0;
-            lds[w.rows + (4 + i) * s.ns + c] = acc1;
-            if (i < 3) lds[w.rows + (8 + i) * s.ns + c] = acc2;
-            if constexpr (kNl) {
-                lds[w.rows + (11 + i) * s.ns + c] = acc3;
-                if (i < 2) lds[w.rows + (15 + i) * s.ns + c] = acc4;
-            }
+            if (!kQuad || i < 2) lds[w.rows + (4 + i) * s.ns + c] = acc1;
+            if constexpr (!kQuad)
+                if (i < 3) lds[w.rows + (8 + i) * s.ns + c] = acc2;
         }
     }
     wave_sync();
 }
 
-template <bool kRot, bool kNl = false>
+template <bool kRot>
 __device__ void electron_rows(const DevSys& s, const Walker& w, int j, const double* r, double a,
                               int lane)
 {
-    int I = -1;
-    double rr = 0.0;
-    if constexpr (kNl) I = nl_sphere(s, w, r, rr);
-    basis_rows<kRot, kNl>(s, w, r, a, lane, I, rr);
-    if constexpr (kNl) nl_elements(s, w, j, r, I, rr, lane);
-    orbital_rows<kNl>(s, w, j, lane, I >= 0);
+    basis_rows<kRot>(s, w, r, a, lane);
+    orbital_rows(s, w, j, lane);
 }
 
-// Store electron j's rows: Slater row, the 6 neighbour rows, derivatives, and
-// with a pseudopotential the 6 quadrature-point rows (columns 6N + 6j + q).
+// Store electron j's rows: Slater row, the 6 neighbour rows, derivatives.
 template <bool kNl = false>
 __device__ void store_rows(const DevSys& s, const Walker& w, int j, int lane, bool arow)
 {
     const int n = nspin(s, spin_of(s, j));
     const int ld = n_prop<kNl>(s);
-    for (int idx = lane; idx < (kNl ? 17 : 11) * n; idx += kWave) {
+    for (int idx = lane; idx < 11 * n; idx += kWave) {
         const int row = idx / n, k = idx - row * n;
         const double v = lds[w.rows + row * s.ns + k];
         if (row == 0) { if (arow) lds[w.Arow + j * s.ns + k] = v; }
         else if (row <= 6) gst(w.Phi + k * ld + 6 * j + row - 1, v);
-        else if (row <= 10) gst(w.dPhi + k * 4 * s.N + 4 * j + row - 7, v);
-        else gst(w.Phi + k * ld + s.P + 6 * j + row - 11, v);
+        else gst(w.dPhi + k * 4 * s.N + 4 * j + row - 7, v);
+    }
+    block_visible();
+}
+
+// Non-local part of electron j at position r (after its lattice rows have
+// been stored, so that the basis block and the row buffer are free): its
+// sphere, the elements V_q and the in-sphere flag, and inside a sphere the
+// quadrature-point orbital rows, stored to columns 6N + 6j + q of the spilled
+// rows.  Outside every sphere those columns are not written: the flag keeps
+// every reader off them.
+__device__ void nl_rows(const DevSys& s, const Walker& w, int j, const double* r, int lane)
+{
+    double rr;
+    const int I = nl_sphere(s, w, r, rr);
+    nl_elements(s, w, j, r, I, rr, lane);
+    if (lane == 0) lds[w.nlin + j] = I >= 0 ? 1.0 : 0.0;
+    if (I < 0) { wave_sync(); return; }
+    nl_basis_rows(s, w, I, rr, lane);
+    orbital_rows<true>(s, w, j, lane);
+    const int n = nspin(s, spin_of(s, j));
+    for (int idx = lane; idx < 6 * n; idx += kWave) {
+        const int q = idx / n, k = idx - q * n;
+        gst(w.Phi + k * s.PT + s.P + 6 * j + q, lds[w.rows + q * s.ns + k]);
     }
     block_visible();
 }
@@ -493,7 +499,8 @@ __device__ void recompute_ratios(const DevSys& s, const Walker& w, int sp, int l
                 const int ai = w.AinvT + spj * s.ns * s.ns + c * s.ns;
                 const double* ph = w.Phi + p;
                 double rd = 0.0;
-                for (int k = 0; k < n; ++k) rd += gld(ph + k * ld) * lds[ai + k];
+                if (lds[w.nlin + j] != 0.0)
+                    for (int k = 0; k < n; ++k) rd += gld(ph + k * ld) * lds[ai + k];
                 lds[w.Rdet + p] = rd;
             }
             lds[w.R + p] = m2a2 * lds[w.Vnl + p - s.P] * lds[w.Rdet + p];
@@ -730,10 +737,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     // the new position are computed while it is in flight.
     double u0 = 0.0;
     if (lane < n) u0 = gld(w.Phi + lane * ld + p);
-    int In = -1;
-    double rn = 0.0;
-    if constexpr (kNl) In = nl_sphere(s, w, rnew, rn);
-    basis_rows<kRot, kNl>(s, w, rnew, a, lane, In, rn);
+    basis_rows<kRot>(s, w, rnew, a, lane);
     LRDMC_T(3);
 
     // Sherman-Morrison on AinvT of spin sp with the accepted orbital row u
@@ -770,9 +774,9 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
 
     LRDMC_T(2);
     // new orbital rows of electron i at rnew
-    orbital_rows<kNl>(s, w, i, lane, In >= 0);
+    orbital_rows(s, w, i, lane);
     store_rows<kNl>(s, w, i, lane, false);
-    if constexpr (kNl) nl_elements(s, w, i, rnew, In, rn, lane);
+    if constexpr (kNl) nl_rows(s, w, i, rnew, lane);
     LRDMC_T(4);
 
     // Orbital rows of the moves of spin sp and orbital derivatives of its
@@ -960,7 +964,8 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
             const int q = s.P + 6 * off + pp, cj = col_of(s, off + pp / 6);
             const int ai = Ai + cj * s.ns;
             double rd = 0.0;
-            for (int k = 0; k < n; ++k) rd += gld(w.Phi + k * ld + q) * lds[ai + k];
+            if (lds[w.nlin + off + pp / 6] != 0.0)
+                for (int k = 0; k < n; ++k) rd += gld(w.Phi + k * ld + q) * lds[ai + k];
             lds[w.Rdet + q] = rd;
             lds[w.R + q] = m2a2 * lds[w.Vnl + q - s.P] * rd;
         }
@@ -1048,8 +1053,9 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
     // orbital rows of every electron, then the FP64 refresh
     for (int j = 0; j < s.N; ++j) {
         const double r[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
-        electron_rows<kRot, kNl>(s, w, j, r, a, lane);
+        electron_rows<kRot>(s, w, j, r, a, lane);
         store_rows<kNl>(s, w, j, lane, true);
+        if constexpr (kNl) nl_rows(s, w, j, r, lane);
     }
     unsigned long long n_neg = 0, n_nomove = 0, n_refresh = 1, n_small = 0, n_sing = 0,
                        n_capped = 0;
