@@ -181,7 +181,7 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L.o_B = take(std::max(std::max(11 * L.ldb, 2 * ns * ns), 7 * N));
         L.o_rows = take(11 * ns);
         L.o_tmp = take(3 * ns + 16);
-        L.o_C = take(Nb * ns);
+        L.o_C = take(nl ? 0 : Nb * ns);   // the pseudopotential kernel reads C from global memory
         L.o_nuc = take(kNucLen * M);
         L.o_jas = take(3 * (2 + s.n_species));
         L.o_gd = take(4 * N);

@@ -322,7 +322,10 @@ __device__ void nl_basis_rows(const DevSys& s, const Walker& w, int nlI, double 
 // take column tile t of the pair and the even and odd k-steps; three
 // accumulators cover the row tiles 0..3, 4..7 and 8..10.  kQuad: the six
 // quadrature-point rows of a pseudopotential sphere instead (rows 0..5).
-template <bool kQuad = false>
+// kGlobalC: the coefficient block is read from global memory (L1/L2-resident,
+// shared by every walker) instead of the walker's LDS copy, each k-step's
+// operand fetched one step ahead.
+template <bool kQuad = false, bool kGlobalC = false>
 __device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
 {
     wave_sync();
@@ -334,10 +337,22 @@ __device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
         const int col = 4 * (ct0 + cb) + l4;
         const bool cok = col < n;
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+        double bnext = 0.0;
+        if constexpr (kGlobalC) {
+            const int mu = 4 * par + lk;
+            bnext = (cok && mu < Nb) ? gld(s.C + mu * s.Norb + col) : 0.0;
+        }
         for (int k0 = 0; k0 < Nb; k0 += 8) {
             const int mu = k0 + 4 * par + lk;
             const bool kok = mu < Nb;
-            const double bv = (cok && kok) ? lds[w.C + mu * s.ns + col] : 0.0;
+            double bv;
+            if constexpr (kGlobalC) {
+                bv = bnext;
+                const int mn = mu + 8;
+                bnext = (cok && mn < Nb) ? gld(s.C + mn * s.Norb + col) : 0.0;
+            } else {
+                bv = (cok && kok) ? lds[w.C + mu * s.ns + col] : 0.0;
+            }
             const double a0 = kok ? lds[w.B + l4 * ldb + mu] : 0.0;
             const double a1 = (kok && (!kQuad || l4 < 2)) ? lds[w.B + (4 + l4) * ldb + mu] : 0.0;
             const double a2 = (!kQuad && kok && l4 < 3) ? lds[w.B + (8 + l4) * ldb + mu] : 0.0;
@@ -360,12 +375,12 @@ __device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
     wave_sync();
 }
 
-template <bool kRot>
+template <bool kRot, bool kNl = false>
 __device__ void electron_rows(const DevSys& s, const Walker& w, int j, const double* r, double a,
                               int lane)
 {
     basis_rows<kRot>(s, w, r, a, lane);
-    orbital_rows(s, w, j, lane);
+    orbital_rows<false, kNl>(s, w, j, lane);
 }
 
 // Store electron j's rows: Slater row, the 6 neighbour rows, derivatives.
@@ -398,7 +413,7 @@ __device__ void nl_rows(const DevSys& s, const Walker& w, int j, const double* r
     if (lane == 0) lds[w.nlin + j] = I >= 0 ? 1.0 : 0.0;
     if (I < 0) { wave_sync(); return; }
     nl_basis_rows(s, w, I, rr, lane);
-    orbital_rows<true>(s, w, j, lane);
+    orbital_rows<true, true>(s, w, j, lane);
     const int n = nspin(s, spin_of(s, j));
     for (int idx = lane; idx < 6 * n; idx += kWave) {
         const int q = idx / n, k = idx - q * n;
@@ -774,7 +789,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
 
     LRDMC_T(2);
     // new orbital rows of electron i at rnew
-    orbital_rows(s, w, i, lane);
+    orbital_rows<false, kNl>(s, w, i, lane);
     store_rows<kNl>(s, w, i, lane, false);
     if constexpr (kNl) nl_rows(s, w, i, rnew, lane);
     LRDMC_T(4);
@@ -1023,10 +1038,13 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
     const double E0 = *s.e0p;
 
     for (int q = lane; q < 3 * s.N; q += kWave) lds[w.pos + q] = s.pos[(long)wid * 3 * s.N + q];
-    for (int q = lane; q < s.Nb * s.ns; q += kWave) {
-        const int mu = q / s.ns, k = q - mu * s.ns;
-        lds[w.C + q] = gld(s.C + mu * s.Norb + k);
-    }
+    // the coefficient block in LDS (the pseudopotential kernel reads it from
+    // global memory: its LDS block is larger)
+    if constexpr (!kNl)
+        for (int q = lane; q < s.Nb * s.ns; q += kWave) {
+            const int mu = q / s.ns, k = q - mu * s.ns;
+            lds[w.C + q] = gld(s.C + mu * s.Norb + k);
+        }
     const double a = pa.a;
     // nucleus records and Pade parameter rows
     for (int I = lane; I < s.M; I += kWave) {
@@ -1053,7 +1071,7 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
     // orbital rows of every electron, then the FP64 refresh
     for (int j = 0; j < s.N; ++j) {
         const double r[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
-        electron_rows<kRot>(s, w, j, r, a, lane);
+        electron_rows<kRot, kNl>(s, w, j, r, a, lane);
         store_rows<kNl>(s, w, j, lane, true);
         if constexpr (kNl) nl_rows(s, w, j, r, lane);
     }
