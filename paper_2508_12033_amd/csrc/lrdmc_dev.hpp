@@ -36,8 +36,8 @@ struct DevSys {
     // walker arrays (device)
     double *pos;             // [nw][N][3]
     double *lw, *eL, *Wd;    // [nw]
-    double *spill;           // [nw][spill_stride]: orbital rows at the 6N moves and
-                             // orbital derivatives at the current positions
+    double *spill;           // [nw][spill_stride]: orbital rows at the moves [PT][ns] and
+                             // orbital derivatives at the current positions [4N][ns]
     long spill_stride;
     int32_t *iters;          // [nw]
     int32_t *trace;          // [nw][trace_cap] or null
@@ -53,8 +53,8 @@ struct DevSys {
     // locality approximation): term t adds ecp_coef r^ecp_pow exp(-ecp_exp r^2)
     // to channel ecp_l of atom ecp_atom, inside radius ecp_rcut of that atom.
     // PT: proposals per configuration, the 6N lattice moves and, with a
-    // pseudopotential, 6N quadrature points (zero rows for electrons outside
-    // every sphere); PT is also the row length of the spilled orbital rows.
+    // pseudopotential, 6N quadrature points (zero entries for electrons outside
+    // every sphere); PT is also the number of spilled orbital rows.
     int PT, necp;
     const int32_t *ecp_atom, *ecp_l, *ecp_pow;
     const double *ecp_coef, *ecp_exp, *ecp_rcut;

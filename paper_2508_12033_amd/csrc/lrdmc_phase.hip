@@ -56,7 +56,10 @@ __device__ __forceinline__ void block_visible()
 
 // Per-walker state: offsets (in doubles) of the LDS-resident arrays inside
 // the dynamic shared-memory block, and the walker's block of the global
-// spill area (orbital rows at the 6N moves, orbital derivatives).
+// spill area: the orbital rows at the moves, Phi[p][k] (row p = proposal p,
+// row length n_s), and the orbital derivatives, dPhi[4 j + c][k] (c = x, y, z,
+// Laplacian), so that the rows of one electron are contiguous and are written
+// as whole cache lines when it moves.
 extern __shared__ double lds[];
 
 // orbital values per lane fetched ahead of the ratio and derivative updates
@@ -89,8 +92,8 @@ __device__ __forceinline__ Walker walker_view(const DevSys& s)
 }
 
 __device__ __forceinline__ int spin_of(const DevSys& s, int i) { return i >= s.Nup; }
-// proposals per configuration and row length of the spilled orbital rows:
-// the 6N lattice moves, and 6N quadrature points with a pseudopotential
+// proposals per configuration: the 6N lattice moves, and 6N quadrature
+// points with a pseudopotential
 template <bool kNl>
 __device__ __forceinline__ int n_prop(const DevSys& s) { return kNl ? s.PT : s.P; }
 __device__ __forceinline__ int col_of(const DevSys& s, int i) { return i >= s.Nup ? i - s.Nup : i; }
@@ -388,13 +391,12 @@ template <bool kNl = false>
 __device__ void store_rows(const DevSys& s, const Walker& w, int j, int lane, bool arow)
 {
     const int n = nspin(s, spin_of(s, j));
-    const int ld = n_prop<kNl>(s);
     for (int idx = lane; idx < 11 * n; idx += kWave) {
         const int row = idx / n, k = idx - row * n;
         const double v = lds[w.rows + row * s.ns + k];
         if (row == 0) { if (arow) lds[w.Arow + j * s.ns + k] = v; }
-        else if (row <= 6) gst(w.Phi + k * ld + 6 * j + row - 1, v);
-        else gst(w.dPhi + k * 4 * s.N + 4 * j + row - 7, v);
+        else if (row <= 6) gst(w.Phi + (6 * j + row - 1) * s.ns + k, v);
+        else gst(w.dPhi + (4 * j + row - 7) * s.ns + k, v);
     }
     block_visible();
 }
@@ -402,9 +404,9 @@ __device__ void store_rows(const DevSys& s, const Walker& w, int j, int lane, bo
 // Non-local part of electron j at position r (after its lattice rows have
 // been stored, so that the basis block and the row buffer are free): its
 // sphere, the elements V_q and the in-sphere flag, and inside a sphere the
-// quadrature-point orbital rows, stored to columns 6N + 6j + q of the spilled
-// rows.  Outside every sphere those columns are not written: the flag keeps
-// every reader off them.
+// quadrature-point orbital rows, stored as spilled rows 6N + 6j + q.  Outside
+// every sphere those rows are not written: the flag keeps every reader off
+// them.
 __device__ void nl_rows(const DevSys& s, const Walker& w, int j, const double* r, int lane)
 {
     double rr;
@@ -417,7 +419,7 @@ __device__ void nl_rows(const DevSys& s, const Walker& w, int j, const double* r
     const int n = nspin(s, spin_of(s, j));
     for (int idx = lane; idx < 6 * n; idx += kWave) {
         const int q = idx / n, k = idx - q * n;
-        gst(w.Phi + k * s.PT + s.P + 6 * j + q, lds[w.rows + q * s.ns + k]);
+        gst(w.Phi + (s.P + 6 * j + q) * s.ns + k, lds[w.rows + q * s.ns + k]);
     }
     block_visible();
 }
@@ -492,15 +494,14 @@ __device__ bool refresh_inverse(const DevSys& s, const Walker& w, int sp, int la
 template <bool kNl = false>
 __device__ void recompute_ratios(const DevSys& s, const Walker& w, int sp, int lane, double a = 0.0)
 {
-    const int ld = n_prop<kNl>(s);
     for (int p = lane; p < s.P; p += kWave) {
         const int j = p / 6, spj = spin_of(s, j);
         if (sp < 0 || spj == sp) {
             const int n = nspin(s, spj), c = col_of(s, j);
             const int ai = w.AinvT + spj * s.ns * s.ns + c * s.ns;
-            const double* ph = w.Phi + p;
+            const double* ph = w.Phi + p * s.ns;
             double rd = 0.0;
-            for (int k = 0; k < n; ++k) rd += gld(ph + k * ld) * lds[ai + k];
+            for (int k = 0; k < n; ++k) rd += gld(ph + k) * lds[ai + k];
             lds[w.Rdet + p] = rd;
         }
         lds[w.R + p] = lds[w.Rdet + p] * exp(lds[w.dJ + p]);
@@ -512,10 +513,10 @@ __device__ void recompute_ratios(const DevSys& s, const Walker& w, int sp, int l
             if (sp < 0 || spj == sp) {
                 const int n = nspin(s, spj), c = col_of(s, j);
                 const int ai = w.AinvT + spj * s.ns * s.ns + c * s.ns;
-                const double* ph = w.Phi + p;
+                const double* ph = w.Phi + p * s.ns;
                 double rd = 0.0;
                 if (lds[w.nlin + j] != 0.0)
-                    for (int k = 0; k < n; ++k) rd += gld(ph + k * ld) * lds[ai + k];
+                    for (int k = 0; k < n; ++k) rd += gld(ph + k) * lds[ai + k];
                 lds[w.Rdet + p] = rd;
             }
             lds[w.R + p] = m2a2 * lds[w.Vnl + p - s.P] * lds[w.Rdet + p];
@@ -535,7 +536,7 @@ __device__ void recompute_gd(const DevSys& s, const Walker& w, int sp, int lane)
         const int j = it >> 2, spj = spin_of(s, j), n = nspin(s, spj), c = col_of(s, j);
         const int ai = w.AinvT + spj * s.ns * s.ns + c * s.ns;
         double val = 0.0;
-        for (int k = 0; k < n; ++k) val += gld(w.dPhi + k * N4 + it) * lds[ai + k];
+        for (int k = 0; k < n; ++k) val += gld(w.dPhi + it * s.ns + k) * lds[ai + k];
         lds[w.gd + it] = val;
     }
     wave_sync();
@@ -733,7 +734,6 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     const int pk = nlm ? p - s.P : p;
     const int i = pk / 6, d = (pk / 2) % 3, sg = pk % 2;
     const int sp = spin_of(s, i), c = col_of(s, i), n = nspin(s, sp);
-    const int ld = n_prop<kNl>(s);
     const double Rd = lds[w.Rdet + p], iRd = 1.0 / Rd;
     const double rold[3] = {lds[w.pos + 3 * i], lds[w.pos + 3 * i + 1], lds[w.pos + 3 * i + 2]};
     const double* st = lds + w.ev;
@@ -751,7 +751,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     // The accepted orbital row u is fetched first and the basis values at
     // the new position are computed while it is in flight.
     double u0 = 0.0;
-    if (lane < n) u0 = gld(w.Phi + lane * ld + p);
+    if (lane < n) u0 = gld(w.Phi + p * s.ns + lane);
     basis_rows<kRot>(s, w, rnew, a, lane);
     LRDMC_T(3);
 
@@ -759,7 +759,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     const int Ai = w.AinvT + sp * s.ns * s.ns;
     const int u = w.tmp, rowc = w.tmp + s.ns, beta = w.tmp + 2 * s.ns;
     for (int k = lane; k < n; k += kWave) {
-        lds[u + k] = k < kWave ? u0 : gld(w.Phi + k * ld + p);
+        lds[u + k] = k < kWave ? u0 : gld(w.Phi + p * s.ns + k);
         lds[rowc + k] = lds[Ai + c * s.ns + k];
     }
     wave_sync();
@@ -802,8 +802,8 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     const bool rv = lane < 6 * n, gv = lane < 4 * n;
 #pragma unroll
     for (int k = 0; k < kPre; ++k) {
-        pre_r[k] = (rv && k < n) ? gld(w.Phi + k * ld + 6 * off + lane) : 0.0;
-        pre_g[k] = (gv && k < n) ? gld(w.dPhi + k * 4 * s.N + 4 * off + lane) : 0.0;
+        pre_r[k] = (rv && k < n) ? gld(w.Phi + (6 * off + lane) * s.ns + k) : 0.0;
+        pre_g[k] = (gv && k < n) ? gld(w.dPhi + (4 * off + lane) * s.ns + k) : 0.0;
     }
 
     // Jastrow and potential caches: pairs (i, k) change from rold to rnew.
@@ -966,9 +966,9 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
 #pragma unroll
             for (int k = 0; k < kPre; ++k)
                 if (k < n) rd += pre_r[k] * lds[ai + k];
-            for (int k = kPre; k < n; ++k) rd += gld(w.Phi + k * ld + q) * lds[ai + k];
+            for (int k = kPre; k < n; ++k) rd += gld(w.Phi + q * s.ns + k) * lds[ai + k];
         } else {
-            for (int k = 0; k < n; ++k) rd += gld(w.Phi + k * ld + q) * lds[ai + k];
+            for (int k = 0; k < n; ++k) rd += gld(w.Phi + q * s.ns + k) * lds[ai + k];
         }
         lds[w.Rdet + q] = rd;
     }
@@ -980,7 +980,7 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
             const int ai = Ai + cj * s.ns;
             double rd = 0.0;
             if (lds[w.nlin + off + pp / 6] != 0.0)
-                for (int k = 0; k < n; ++k) rd += gld(w.Phi + k * ld + q) * lds[ai + k];
+                for (int k = 0; k < n; ++k) rd += gld(w.Phi + q * s.ns + k) * lds[ai + k];
             lds[w.Rdet + q] = rd;
             lds[w.R + q] = m2a2 * lds[w.Vnl + q - s.P] * rd;
         }
@@ -993,9 +993,9 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
 #pragma unroll
             for (int k = 0; k < kPre; ++k)
                 if (k < n) val += pre_g[k] * lds[ai + k];
-            for (int k = kPre; k < n; ++k) val += gld(w.dPhi + k * 4 * s.N + it) * lds[ai + k];
+            for (int k = kPre; k < n; ++k) val += gld(w.dPhi + it * s.ns + k) * lds[ai + k];
         } else {
-            for (int k = 0; k < n; ++k) val += gld(w.dPhi + k * 4 * s.N + it) * lds[ai + k];
+            for (int k = 0; k < n; ++k) val += gld(w.dPhi + it * s.ns + k) * lds[ai + k];
         }
         lds[w.gd + it] = val;
     }
