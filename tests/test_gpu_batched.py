@@ -64,13 +64,19 @@ def test_one_launch_three_systems():
     h.close()
 
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("separate", [False, True])
+def test_graph_replay_matches_eager(separate):
     """lrdmc_run (one graph replay per cycle, device-side E_0 and history)
-    against lrdmc_step + lrdmc_branch on an identical second handle."""
+    against lrdmc_step + lrdmc_branch on an identical second handle, with all
+    systems in one launch or one launch per system."""
     ds = _systems((32, 16, 8))
-    say("case batched graph replay vs eager")
+    say("case batched graph replay vs eager, separate launches" if separate else
+        "case batched graph replay vs eager")
     ha, prm = _handle(ds, nproj=16)
     hb, _ = _handle(ds, nproj=16)
+    if separate:
+        ha.set_launch(0)
+        hb.set_launch(0)
     eager = []
     for _ in range(4):
         ha.step()
