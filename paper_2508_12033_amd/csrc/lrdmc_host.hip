@@ -537,11 +537,9 @@ int launch_mixed(lrdmc_handle* h, hipStream_t st, int p, int nproj_override, int
 
 // One projection phase for every system on stream st with walkers in slot p.
 // nproj_override >= 0: a load-balanced phase of that many steps (0 = evaluate
-// only).  FP64 systems: one launch each; mixed systems: one launch for all.
+// only).  FP64 systems: one launch each; mixed systems: launch_mixed.
 int launch_phases(lrdmc_handle* h, hipStream_t st, int p, int nproj_override, bool allow_build)
 {
-    int maxN = 1;
-    for (auto& r : h->sys) maxN = std::max(maxN, r.N);
     for (auto& r : h->sys) {
         if (r.kind != kKindLds) continue;
         const PhaseArgs pa = phase_args(h, r.N, nproj_override);
@@ -1085,7 +1083,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             r.need_build = true;
             h->mix_order.push_back(k);
             h->mix_lds = std::max(h->mix_lds, L.lds_bytes);
-            h->mix_sys_threads.assign(n_sys, kMixThreads);
+            if (h->mix_sys_threads.empty()) h->mix_sys_threads.assign(n_sys, kMixThreads);
         }
         if (up(r.pos[0], ip, nw * 3 * L.N * 8) != hipSuccess ||
             hipMemsetAsync(r.lw, 0, nw * 8, h->stream) != hipSuccess) {
