@@ -4,8 +4,8 @@ quadrature of the sphere through the electron along the walker's lattice
 versors, one proposal per quadrature point) against the FP64 oracle: moves,
 non-local moves included, and positions bit-exact, e_L within 1e-9 Ha, weights
 to 1e-11, over two phases with the reconfiguration between them, in both
-schemes, on fixed and randomly rotated lattices; sampled walkers of the full
-4096-walker population; both schemes sample the same state; the paths without
+schemes, on fixed and randomly rotated lattices, at 16 and 32 electrons;
+sampled walkers of the full 4096-walker population; both schemes sample the same state; the paths without
 a pseudopotential kernel return LRDMC_ERR_UNSUPPORTED."""
 import numpy as np
 import pytest
@@ -61,6 +61,42 @@ def test_ecp_phases_match_oracle(scheme, rotate):
         e0 = bs.e0
     say("non-local moves taken:", n_nl)
     assert n_nl > 20
+    h.close()
+
+
+@pytest.mark.parametrize("scheme,rotate", [("lb", False), ("conv", True)])
+def test_ecp_32_electrons(scheme, rotate):
+    """The pseudopotential kernel at 32 electrons (four soft cores with
+    spheres, 16 orbitals per spin, 384 proposals per configuration): its
+    general loops, two phases and the reconfiguration."""
+    nw = 32
+    d0 = I.c2_systems(n_walkers=(2, nw, 2))[1]
+    d = I.with_ecp(d0, np.where(d0["atom_core"] == I.SOFTCORE)[0], terms=STRONG)
+    say("case pseudopotential 32 electrons", scheme, "rotate" if rotate else "fixed axes")
+    h, d2, prm = make_handle(d, scheme, nw, n_proj=100, tau=0.04, rotate=rotate)
+    N = int(d2["n_elec"])
+    assert N == 32
+    e0 = h.e0()
+    pos = d2["init_pos"][:nw].copy()
+    lw = np.zeros(nw)
+    n_nl = 0
+    for j in range(2):
+        h.step()
+        g = h.walkers(trace=True)
+        res = compare_phase(d2, prm, scheme, j, e0, pos, lw, g, np.arange(nw))
+        say(scheme, j, {k: v for k, v in res.items() if k != "oracle"})
+        assert_phase_ok(res)
+        n_nl += int((g["trace"] >= 6 * N).sum())
+        bs = h.branch()
+        after = h.walkers()
+        xi = O.uniform(prm.seed, int(d2["system_id"]), 0, j, 0, O.RNG_COMB)
+        sel, _, cnt = O.comb(g["lw"], xi, follow=after["sel"])
+        assert cnt["hard_mismatch"] == 0 and np.array_equal(sel, after["sel"])
+        pos = after["pos"].copy()
+        lw = np.zeros(nw)
+        e0 = bs.e0
+    say("non-local moves taken:", n_nl)
+    assert n_nl > 10
     h.close()
 
 
