@@ -13,9 +13,11 @@ load-balanced weighting w/(W - E_0)), and the correcting-factor estimator of
 the ground-state energy (Sec. II.A, product of the previous p average weights)
 with a blocking error bar.
 
-Pinned functions and their pins are listed in the test files under tests/;
-the absolute energies of the synthetic molecules are parity unpinned beyond
-oracle parity and conventional/load-balanced agreement.
+Every function here and in the C source is pinned by tests/test_oracle_*.py
+(closed forms, independent re-evaluations, brute force, invariants).  The
+absolute energies of the synthetic molecules have no external reference value;
+they are checked through those pinned functions, by GPU-oracle parity and by
+the agreement of the two schemes.
 """
 from __future__ import annotations
 
