@@ -8,7 +8,8 @@ products as loops over 16-element rows, ratio and derivative products past
 the first eight fetched values, two 16-lane rows per lattice point in the
 7-point Jastrow pass (32 partners) and, with the electron-nucleus Jastrow
 (48 partners), one point per pass with a wavefront reduction; the
-reconfiguration in between gathers 32-electron walkers.  Bar as for the other
+reconfiguration in between gathers 32-electron walkers.  Unequal spin counts
+give ragged per-spin widths at both sizes.  Bar as for the other
 FP64 tests: moves, stopping decisions, comb selections and positions
 bit-exact, e_L within 1e-9 Ha, W to 1e-12, log-weights to 1e-11."""
 import numpy as np
@@ -97,4 +98,28 @@ def test_32e_full_population_sampled():
     k = (g["pos"] - pos0) / d2["a"]
     assert np.allclose(k, np.round(k), atol=1e-9)
     assert np.all(np.isfinite(g["eL"])) and np.all(g["W"] - e0 > 0)
+    h.close()
+
+
+@pytest.mark.parametrize("which,n_dn,scheme", [("c1", 5, "lb"), ("e32", 13, "lb"), ("e32", 13, "conv")])
+def test_unequal_spins(which, n_dn, scheme):
+    """Fewer down than up electrons (the last down electrons removed): the
+    down block is narrower than the padded spin block (5 of 8 and 13 of 16
+    columns), so every per-spin loop and product runs with a ragged width."""
+    nw = 24
+    d = dict(I.c1_system(n_walkers=nw) if which == "c1" else e32(nw))
+    n = int(d["n_up"]) + n_dn
+    d["n_dn"] = n_dn
+    d["n_elec"] = n
+    d["init_pos"] = np.ascontiguousarray(d["init_pos"][:, :n, :])
+    say("case unequal spins", which, d["n_up"], "+", n_dn, scheme)
+    kw = dict(tau=0.04) if scheme == "conv" else dict(n_proj=140)
+    h, d2, prm = make_handle(d, scheme, nw, **kw)
+    e0 = h.e0()
+    pos0 = d2["init_pos"][:nw].copy()
+    h.step()
+    g = h.walkers(trace=True)
+    res = compare_phase(d2, prm, scheme, 0, e0, pos0, np.zeros(nw), g, np.arange(nw))
+    say({k: v for k, v in res.items() if k != "oracle"})
+    assert_phase_ok(res)
     h.close()
