@@ -72,9 +72,14 @@ def flops_per_walker_step(N, n, Nb, M, has_en, refresh_every):
 
 
 def kernel_hash(sources=None):
+    """Hash of the kernel sources and the compiler flags they are built with
+    (include paths left out), so that stored counters go stale when either
+    changes."""
+    from paper_2508_12033_amd.build import FLAGS
     h = hashlib.sha256()
     for p in sources or KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, p), "rb").read())
+    h.update(" ".join(f for f in FLAGS if not f.startswith("-I")).encode())
     return h.hexdigest()[:16]
 
 

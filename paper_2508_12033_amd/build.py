@@ -13,7 +13,9 @@ LIB = os.path.join(HERE, "liblrdmc.so")
 ARCH = "gfx950"
 
 FLAGS = [
-    "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+    # -O2: the FP64 phase kernel runs 2.5 % faster than at -O3 (measured side
+    # by side); the other kernels time the same at both levels
+    "--offload-arch=" + ARCH, "-O2", "-std=c++17", "-fPIC", "-shared",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # MFMA results in ordinary VGPRs: accumulation registers (AGPRs) would add
