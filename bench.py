@@ -17,7 +17,9 @@ all 6N move ratios x 6N / wall time.  Printed beside it:
     (every walker pays the phase maximum of iterations);
   - the mixed-precision paths with their stated errors: the same 16-electron
     workload in FP32, the 128-electron / 2048-walker system with the BF16
-    orbital product (and FP32), the three uneven systems in one launch;
+    orbital product (and FP32) beside the same system in FP64, the
+    32-electron system in all three precisions, the three uneven systems in
+    one launch;
   - the 16-electron system with a non-local pseudopotential (6N lattice moves
     plus the quadrature points of the electrons inside a cutoff sphere);
   - the adjoint pass (per-walker parameter derivatives) on the 16-electron
@@ -399,6 +401,18 @@ def main():
                 proposals_per_s=r["proposals"] / r["seconds"], ms_per_branching=r["ms_per_cycle"],
                 error=precision_summary(hx), roofline=mixed_roofline(c3, px, stx.elapsed_ms, tr))
             hx.close()
+        # the same system in FP64 (the large-system layout of the FP64 kernel:
+        # one 64-lane walker per CU, coefficient block and Slater rows read
+        # from global memory), one timed branching
+        hx, px, r = run_cycles(B, c3, "lb", 1, 0, precision="fp64")
+        fp64_rate = r["proposals"] / r["seconds"]
+        extra["c3_fp64"] = dict(
+            workload="128 electrons (64+64), 32 atoms, 640 basis functions, 2048 walkers, "
+                     "a=0.15, N_proj=300, FP64 (large-system layout: one walker per CU)",
+            proposals_per_s=fp64_rate, ms_per_branching=r["ms_per_cycle"])
+        hx.close()
+        for prec in ("bf16", "fp32"):
+            extra["c3_mixed_" + prec]["vs_fp64"] = extra["c3_mixed_" + prec]["proposals_per_s"] / fp64_rate
         # three uneven systems in one launch, graph-replayed cycles, tuned launch
         c2 = I.c2_systems()
         hx, px, r = run_cycles(B, c2, "lb", 2, 0, precision="fp32", tune=True)

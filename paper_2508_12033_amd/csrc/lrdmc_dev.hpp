@@ -36,8 +36,9 @@ struct DevSys {
     // walker arrays (device)
     double *pos;             // [nw][N][3]
     double *lw, *eL, *Wd;    // [nw]
-    double *spill;           // [nw][spill_stride]: orbital rows at the moves [PT][ns] and
-                             // orbital derivatives at the current positions [4N][ns]
+    double *spill;           // [nw][spill_stride]: orbital rows at the moves [PT][ns],
+                             // orbital derivatives at the current positions [4N][ns] and,
+                             // for the large-system kernel, the Slater rows [N][ns]
     long spill_stride;
     int32_t *iters;          // [nw]
     int32_t *trace;          // [nw][trace_cap] or null
@@ -49,6 +50,9 @@ struct DevSys {
         o_scal, o_B, o_rows, o_tmp, o_C, o_nuc, o_jas, o_gd, o_ev, lds_doubles;
     // spill layout (offsets in doubles inside a walker's spill block)
     int s_Phi, s_dPhi;
+    // systems too large for the LDS-resident layout (the large-system kernel):
+    // the Slater rows [N][ns] in the spill block at s_Arow (0 otherwise)
+    int s_Arow;
     // non-local pseudopotential (App. D non-local elements, determinant
     // locality approximation): term t adds ecp_coef r^ecp_pow exp(-ecp_exp r^2)
     // to channel ecp_l of atom ecp_atom, inside radius ecp_rcut of that atom.

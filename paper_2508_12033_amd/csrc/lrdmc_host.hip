@@ -24,18 +24,21 @@
 #include "lrdmc_dev.hpp"
 
 namespace lrdmc {
-template <bool kRot, bool kNl>
+template <bool kRot, bool kNl, bool kBig>
 __global__ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa);
-extern template __global__ void phase_fp64<false, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
-extern template __global__ void phase_fp64<true, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
-extern template __global__ void phase_fp64<false, true>(const DevSys* __restrict__ sys, PhaseArgs pa);
-extern template __global__ void phase_fp64<true, true>(const DevSys* __restrict__ sys, PhaseArgs pa);
+extern template __global__ void phase_fp64<false, false, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
+extern template __global__ void phase_fp64<true, false, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
+extern template __global__ void phase_fp64<false, true, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
+extern template __global__ void phase_fp64<true, true, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
+extern template __global__ void phase_fp64<false, false, true>(const DevSys* __restrict__ sys, PhaseArgs pa);
+extern template __global__ void phase_fp64<true, false, true>(const DevSys* __restrict__ sys, PhaseArgs pa);
 
-// the FP64 phase kernel for a lattice geometry and Hamiltonian
-inline void (*phase_kernel(bool rot, bool nl))(const DevSys*, PhaseArgs)
+// the FP64 phase kernel for a lattice geometry, Hamiltonian and layout
+inline void (*phase_kernel(bool rot, bool nl, bool big))(const DevSys*, PhaseArgs)
 {
-    if (nl) return rot ? phase_fp64<true, true> : phase_fp64<false, true>;
-    return rot ? phase_fp64<true, false> : phase_fp64<false, false>;
+    if (nl) return rot ? phase_fp64<true, true, false> : phase_fp64<false, true, false>;
+    if (big) return rot ? phase_fp64<true, false, true> : phase_fp64<false, false, true>;
+    return rot ? phase_fp64<true, false, false> : phase_fp64<false, false, false>;
 }
 __global__ void phase_mixed(MixBatch b, PhaseArgs pa, int build);
 __global__ void branch_scan(BranchView s, int scheme, double* cum, double* out, int* n_distinct);
@@ -120,7 +123,8 @@ struct Layout {
     int ldb;
     int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje, o_scal, o_B,
         o_rows, o_tmp, o_C, o_nuc, o_jas, o_gd, o_ev, lds_doubles;
-    int s_Phi, s_dPhi;
+    bool big;                // large-system layout: coefficient block and Slater rows in global memory
+    int s_Phi, s_dPhi, s_Arow;
     long spill_stride;
     // mixed kernel: LDS byte offsets, walker block (floats)
     int l_pos, l_nue, l_nua, l_scal, l_red, l_U, l_R, l_Rdet, l_dJ, l_gD, l_Jg, l_Jl, l_dje, l_rows,
@@ -163,36 +167,48 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
                     + align_up(8)                   // distinct counter
                     + (p.trace_cap > 0 ? align_up(nw * (size_t)p.trace_cap * 4) : 0);
     if (L.kind == kKindLds) {
-        int o = 0;
-        auto take = [&](int n) { int r = o; o += (n + 1) / 2 * 2; return r; };
-        L.o_pos = take(3 * N);
-        L.o_R = take(PT);
-        L.o_Rdet = take(PT);
-        L.o_dJ = take(P);
-        L.o_Arow = take(N * ns);
-        L.o_AinvT = take(2 * ns * ns);
-        L.o_Jg = take(3 * N);
-        L.o_Jl = take(N);
-        L.o_nue = take(N);
-        L.o_nua = take(N);
-        L.o_dje = take(N);
-        L.o_scal = take(kScVee + 1);
-        L.ldb = Nb + ((20 - Nb % 16) % 16);
-        L.o_B = take(std::max(std::max(11 * L.ldb, 2 * ns * ns), 7 * N));
-        L.o_rows = take(11 * ns);
-        L.o_tmp = take(3 * ns + 16);
-        L.o_C = take(nl ? 0 : Nb * ns);   // the pseudopotential kernel reads C from global memory
-        L.o_nuc = take(kNucLen * M);
-        L.o_jas = take(3 * (2 + s.n_species));
-        L.o_gd = take(4 * N);
-        L.o_ev = take(nl ? 18 : 9);
-        L.o_Vnl = nl ? take(P) : 0;
-        L.o_nlin = nl ? take(N) : 0;
-        L.lds_doubles = o;
-        L.lds_bytes = (size_t)o * 8;
+        // the LDS-resident layout; a system that does not fit it (without a
+        // pseudopotential) takes the large-system layout: coefficient block and
+        // Slater rows in global memory, the basis block sized for the refresh's
+        // n x n half, the pair-term scratch in the basis block
+        for (int pass = 0; pass < 2; ++pass) {
+            const bool big = pass == 1;
+            int o = 0;
+            auto take = [&](int n) { int r = o; o += (n + 1) / 2 * 2; return r; };
+            L.big = big;
+            L.o_pos = take(3 * N);
+            L.o_R = take(PT);
+            L.o_Rdet = take(PT);
+            L.o_dJ = take(P);
+            L.o_Arow = big ? 0 : take(N * ns);
+            L.o_AinvT = take(2 * ns * ns);
+            L.o_Jg = take(3 * N);
+            L.o_Jl = take(N);
+            L.o_nue = take(N);
+            L.o_nua = take(N);
+            L.o_dje = big ? 0 : take(N);
+            L.o_scal = take(kScVee + 1);
+            L.ldb = Nb + ((20 - Nb % 16) % 16);
+            L.o_B = take(std::max(std::max(11 * L.ldb, (big ? 1 : 2) * ns * ns), 7 * N));
+            if (big) L.o_dje = L.o_B;
+            L.o_rows = take(11 * ns);
+            L.o_tmp = take(3 * ns + 16);
+            L.o_C = take(nl || big ? 0 : Nb * ns);   // read from global memory otherwise
+            L.o_nuc = take(kNucLen * M);
+            L.o_jas = take(3 * (2 + s.n_species));
+            L.o_gd = take(4 * N);
+            L.o_ev = take(nl ? 18 : 9);
+            L.o_Vnl = nl ? take(P) : 0;
+            L.o_nlin = nl ? take(N) : 0;
+            L.lds_doubles = o;
+            L.lds_bytes = (size_t)o * 8;
+            if (nl || L.lds_bytes <= (size_t)kMaxLdsBytes) break;
+        }
         L.s_Phi = 0;
         L.s_dPhi = PT * ns;
-        L.spill_stride = (long)(align_up((size_t)(PT * ns + 4 * N * ns) * 8) / 8);
+        L.s_Arow = L.big ? (int)(align_up((size_t)(PT * ns + 4 * N * ns) * 8) / 8) : 0;
+        L.spill_stride = (long)((align_up((size_t)(PT * ns + 4 * N * ns) * 8) +
+                                 (L.big ? align_up((size_t)N * ns * 8) : 0)) / 8);
         L.b_state = common + align_up(nw * L.spill_stride * 8) + 2 * align_up(sizeof(DevSys));
     } else {
         L.nb32 = (Nb + 31) / 32 * 32;
@@ -332,7 +348,7 @@ std::string validate(const lrdmc_system* sys, int n_sys, const lrdmc_params* prm
             return "mixed-precision layout: at most 64 electrons per spin (too large)";
         const Layout L = make_layout(s, *prm);
         if (L.lds_bytes > (size_t)kMaxLdsBytes)
-            return L.kind == kKindLds ? "system too large for the LDS-resident FP64 walker layout "
+            return L.kind == kKindLds ? "system too large for the FP64 walker layouts "
                                         "(use a mixed precision)"
                                       : "system too large for the mixed-precision walker layout";
         if (s.n_walkers > (1 << 24)) return "too many walkers";
@@ -543,7 +559,7 @@ int launch_phases(lrdmc_handle* h, hipStream_t st, int p, int nproj_override, bo
     for (auto& r : h->sys) {
         if (r.kind != kKindLds) continue;
         const PhaseArgs pa = phase_args(h, r.N, nproj_override);
-        hipLaunchKernelGGL(phase_kernel(pa.rotate != 0, r.nl), dim3(r.nw), dim3(kWave),
+        hipLaunchKernelGGL(phase_kernel(pa.rotate != 0, r.nl, r.L.big), dim3(r.nw), dim3(kWave),
                            r.L.lds_bytes, st,
                            (const DevSys*)r.dsys[p], pa);
         HIPCHK(hipGetLastError());
@@ -1040,7 +1056,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             d.ldb = L.ldb; d.o_B = L.o_B; d.o_rows = L.o_rows; d.o_tmp = L.o_tmp; d.o_C = L.o_C;
             d.bK = bK; d.o_nuc = L.o_nuc; d.o_jas = L.o_jas; d.o_gd = L.o_gd; d.o_ev = L.o_ev;
             d.lds_doubles = L.lds_doubles;
-            d.s_Phi = L.s_Phi; d.s_dPhi = L.s_dPhi;
+            d.s_Phi = L.s_Phi; d.s_dPhi = L.s_dPhi; d.s_Arow = L.s_Arow;
             d.PT = L.PT; d.necp = r.nl ? s.n_ecp : 0;
             d.ecp_atom = e_atom; d.ecp_l = e_l; d.ecp_pow = e_pow;
             d.ecp_coef = e_coef; d.ecp_exp = e_exp; d.ecp_rcut = e_rcut; d.o_Vnl = L.o_Vnl;
@@ -1115,14 +1131,16 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
     if (rc == LRDMC_OK) {
         // allow each phase kernel the LDS that its static allocation leaves free
         // (kernel kinds: 0, 1 the FP64 kernel without and with the non-local
-        // pseudopotential, 2 the mixed-precision kernel)
-        for (int kind = 0; kind < 3 && !rc; ++kind) {
-            const void* fn = kind < 2 ? (const void*)phase_kernel(h->prm.rotate != 0, kind == 1)
+        // pseudopotential, 2 the FP64 large-system kernel, 3 the mixed-precision
+        // kernel)
+        for (int kind = 0; kind < 4 && !rc; ++kind) {
+            const void* fn = kind < 3 ? (const void*)phase_kernel(h->prm.rotate != 0, kind == 1, kind == 2)
                                       : (const void*)phase_mixed;
             size_t need_lds = 0;
-            for (auto& r : h->sys)
-                if (kind < 2 ? (r.kind == kKindLds && (int)r.nl == kind) : r.kind == kKindMixed)
-                    need_lds = std::max(need_lds, r.L.lds_bytes);
+            for (auto& r : h->sys) {
+                const int rk = r.kind != kKindLds ? 3 : (r.nl ? 1 : (r.L.big ? 2 : 0));
+                if (rk == kind) need_lds = std::max(need_lds, r.L.lds_bytes);
+            }
             if (!need_lds) continue;
             hipFuncAttributes fa;
             if (hipFuncGetAttributes(&fa, fn) != hipSuccess) { rc = fail(LRDMC_ERR_HIP, "hipFuncGetAttributes failed"); break; }

@@ -70,6 +70,7 @@ struct Walker {
         Vnl, nlin;
     double* Phi;
     double* dPhi;
+    double* ArowG;          // Slater rows in global memory (large-system kernel)
 };
 
 __device__ __forceinline__ Walker walker_view(const DevSys& s)
@@ -88,6 +89,7 @@ __device__ __forceinline__ Walker walker_view(const DevSys& s)
     double* base = s.spill + (long)blockIdx.x * s.spill_stride;
     w.Phi = base + s.s_Phi;
     w.dPhi = base + s.s_dPhi;
+    w.ArowG = base + s.s_Arow;
     return w;
 }
 
@@ -378,24 +380,28 @@ __device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
     wave_sync();
 }
 
-template <bool kRot, bool kNl = false>
+template <bool kRot, bool kNl = false, bool kBig = false>
 __device__ void electron_rows(const DevSys& s, const Walker& w, int j, const double* r, double a,
                               int lane)
 {
     basis_rows<kRot>(s, w, r, a, lane);
-    orbital_rows<false, kNl>(s, w, j, lane);
+    orbital_rows<false, kNl || kBig>(s, w, j, lane);
 }
 
 // Store electron j's rows: Slater row, the 6 neighbour rows, derivatives.
-template <bool kNl = false>
+template <bool kNl = false, bool kBig = false>
 __device__ void store_rows(const DevSys& s, const Walker& w, int j, int lane, bool arow)
 {
     const int n = nspin(s, spin_of(s, j));
     for (int idx = lane; idx < 11 * n; idx += kWave) {
         const int row = idx / n, k = idx - row * n;
         const double v = lds[w.rows + row * s.ns + k];
-        if (row == 0) { if (arow) lds[w.Arow + j * s.ns + k] = v; }
-        else if (row <= 6) gst(w.Phi + (6 * j + row - 1) * s.ns + k, v);
+        if (row == 0) {
+            if (arow) {
+                if constexpr (kBig) gst(w.ArowG + j * s.ns + k, v);
+                else lds[w.Arow + j * s.ns + k] = v;
+            }
+        } else if (row <= 6) gst(w.Phi + (6 * j + row - 1) * s.ns + k, v);
         else gst(w.dPhi + (4 * j + row - 7) * s.ns + k, v);
     }
     block_visible();
@@ -422,6 +428,63 @@ __device__ void nl_rows(const DevSys& s, const Walker& w, int j, const double* r
         gst(w.Phi + (s.P + 6 * j + q) * s.ns + k, lds[w.rows + q * s.ns + k]);
     }
     block_visible();
+}
+
+// The same Gauss-Jordan elimination for the large-system kernel, whose basis
+// block holds n x n but not n x 2n values: the left half of [A^T | I] in the
+// basis block, the right half in the spin's inverse block itself, so that the
+// right half ends as AinvT.  The Slater rows are read from global memory.  On
+// a singular matrix the inverse block is left undefined (the phase reports
+// the singular refresh as an error).
+__device__ bool refresh_inverse_split(const DevSys& s, const Walker& w, int sp, int lane)
+{
+    const int n = nspin(s, sp), off = sp ? s.Nup : 0, n2 = 2 * n, nn = n * n2;
+    if (!n) return true;
+    const int Lh = w.B;                                   // [n][n] left half
+    const int Ai = w.AinvT + sp * s.ns * s.ns;            // [n][ns] right half
+    auto at = [&](int r, int c) -> double& {
+        return c < n ? lds[Lh + r * n + c] : lds[Ai + r * s.ns + c - n];
+    };
+    for (int idx = lane; idx < nn; idx += kWave) {
+        const int r = idx / n2, c = idx - r * n2;
+        at(r, c) = c < n ? gld(w.ArowG + (off + c) * s.ns + r) : (c - n == r ? 1.0 : 0.0);
+    }
+    wave_sync();
+    for (int j = 0; j < n; ++j) {
+        // pivot: the largest |L[r][j]|, r >= j, the first such row on ties
+        double best = -1.0;
+        int bi = -1;
+        for (int r0 = 0; r0 < n; r0 += kWave) {
+            const int r = r0 + lane;
+            const double v = (r >= j && r < n) ? fabs(lds[Lh + r * n + j]) : -1.0;
+            const double m = wave_max(v);
+            if (m > best) {
+                best = m;
+                const unsigned long long hit = __ballot(v == m);
+                bi = r0 + __ffsll((long long)hit) - 1;
+            }
+        }
+        if (!(best > 0.0)) return false;
+        if (bi != j) {
+            for (int c = lane; c < n2; c += kWave) {
+                const double t = at(j, c);
+                at(j, c) = at(bi, c);
+                at(bi, c) = t;
+            }
+            wave_sync();
+        }
+        const double pv = lds[Lh + j * n + j];
+        wave_sync();
+        for (int c = lane; c < n2; c += kWave) at(j, c) = at(j, c) / pv;
+        for (int r = lane; r < n; r += kWave) lds[w.tmp + r] = lds[Lh + r * n + j];
+        wave_sync();
+        for (int idx = lane; idx < nn; idx += kWave) {
+            const int r = idx / n2, c = idx - r * n2;
+            if (r != j) at(r, c) -= lds[w.tmp + r] * at(j, c);
+        }
+        wave_sync();
+    }
+    return true;
 }
 
 // FP64 Gauss-Jordan inverse with partial pivoting of the transposed Slater
@@ -608,11 +671,17 @@ __device__ double jastrow_all(const DevSys& s, const Walker& w, double a, int la
 
 // FP64 refresh: inverses and log-determinants from the exact orbital rows,
 // Jastrow caches and V_ee from scratch, all ratios.
-template <bool kRot, bool kNl = false>
+template <bool kRot, bool kNl = false, bool kBig = false>
 __device__ bool refresh_all(const DevSys& s, const Walker& w, double a, int lane)
 {
-    bool ok = refresh_inverse(s, w, 0, lane);
-    ok = refresh_inverse(s, w, 1, lane) && ok;
+    bool ok;
+    if constexpr (kBig) {
+        ok = refresh_inverse_split(s, w, 0, lane);
+        ok = refresh_inverse_split(s, w, 1, lane) && ok;
+    } else {
+        ok = refresh_inverse(s, w, 0, lane);
+        ok = refresh_inverse(s, w, 1, lane) && ok;
+    }
     const double vee = jastrow_all<kRot>(s, w, a, lane);
     if (lane == 0) lds[w.scal + kScVee] = vee;
     wave_sync();
@@ -722,11 +791,11 @@ __device__ int heat_bath(const DevSys& s, const Walker& w, double xi, double inc
 // A move p >= 6N (with a pseudopotential) takes electron (p - 6N) / 6 to
 // quadrature point (p - 6N) % 6 of the atom whose sphere holds it.
 #ifdef LRDMC_SECTION_TIMERS
-template <bool kRot, bool kNl = false>
+template <bool kRot, bool kNl = false, bool kBig = false>
 __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, int lane,
                            unsigned long long* sect, unsigned long long& t_mark_)
 #else
-template <bool kRot, bool kNl = false>
+template <bool kRot, bool kNl = false, bool kBig = false>
 __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, int lane)
 #endif
 {
@@ -784,13 +853,16 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
         if (cc == c) lds[Ai + cc * s.ns + k] = lds[rowc + k] * iRd;
         else lds[Ai + cc * s.ns + k] -= lds[rowc + k] * (lds[beta + cc] * iRd);
     }
-    for (int k = lane; k < n; k += kWave) lds[w.Arow + i * s.ns + k] = lds[u + k];
+    for (int k = lane; k < n; k += kWave) {
+        if constexpr (kBig) gst(w.ArowG + i * s.ns + k, lds[u + k]);
+        else lds[w.Arow + i * s.ns + k] = lds[u + k];
+    }
     wave_sync();
 
     LRDMC_T(2);
     // new orbital rows of electron i at rnew
-    orbital_rows<false, kNl>(s, w, i, lane);
-    store_rows<kNl>(s, w, i, lane, false);
+    orbital_rows<false, kNl || kBig>(s, w, i, lane);
+    store_rows<kNl, kBig>(s, w, i, lane, false);
     if constexpr (kNl) nl_rows(s, w, i, rnew, lane);
     LRDMC_T(4);
 
@@ -1025,7 +1097,11 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
 // (kRot = false, the cheaper axis-aligned moves) or a random orientation per
 // walker and phase (kRot = true) -- and per Hamiltonian: local potentials
 // only, or with the non-local pseudopotential (kNl = true: 6N more proposals).
-template <bool kRot, bool kNl>
+// kBig: the large-system layout for walkers whose coefficient block and
+// Slater rows do not fit the LDS with the rest of their state (both read from
+// global memory, the refresh's augmented matrix split over the basis block and
+// the inverse block); local potentials only.
+template <bool kRot, bool kNl, bool kBig>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(LRDMC_PHASE_WAVES)))
 void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
 {
@@ -1038,9 +1114,9 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
     const double E0 = *s.e0p;
 
     for (int q = lane; q < 3 * s.N; q += kWave) lds[w.pos + q] = s.pos[(long)wid * 3 * s.N + q];
-    // the coefficient block in LDS (the pseudopotential kernel reads it from
-    // global memory: its LDS block is larger)
-    if constexpr (!kNl)
+    // the coefficient block in LDS (the pseudopotential and large-system
+    // kernels read it from global memory: their LDS blocks are larger)
+    if constexpr (!kNl && !kBig)
         for (int q = lane; q < s.Nb * s.ns; q += kWave) {
             const int mu = q / s.ns, k = q - mu * s.ns;
             lds[w.C + q] = gld(s.C + mu * s.Norb + k);
@@ -1071,13 +1147,13 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
     // orbital rows of every electron, then the FP64 refresh
     for (int j = 0; j < s.N; ++j) {
         const double r[3] = {lds[w.pos + 3 * j], lds[w.pos + 3 * j + 1], lds[w.pos + 3 * j + 2]};
-        electron_rows<kRot, kNl>(s, w, j, r, a, lane);
-        store_rows<kNl>(s, w, j, lane, true);
+        electron_rows<kRot, kNl, kBig>(s, w, j, r, a, lane);
+        store_rows<kNl, kBig>(s, w, j, lane, true);
         if constexpr (kNl) nl_rows(s, w, j, r, lane);
     }
     unsigned long long n_neg = 0, n_nomove = 0, n_refresh = 1, n_small = 0, n_sing = 0,
                        n_capped = 0;
-    if (!refresh_all<kRot, kNl>(s, w, a, lane)) n_sing++;
+    if (!refresh_all<kRot, kNl, kBig>(s, w, a, lane)) n_sing++;
 
     double lw = s.lw[wid];
     // load-balanced weight factors bbar / (W - E_0) multiplied in blocks
@@ -1140,14 +1216,14 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
         LRDMC_T(1);
         if (q >= 0) {
 #ifdef LRDMC_SECTION_TIMERS
-            const bool small = apply_move<kRot, kNl>(s, w, a, q, lane, sect, t_mark_);
+            const bool small = apply_move<kRot, kNl, kBig>(s, w, a, q, lane, sect, t_mark_);
 #else
-            const bool small = apply_move<kRot, kNl>(s, w, a, q, lane);
+            const bool small = apply_move<kRot, kNl, kBig>(s, w, a, q, lane);
 #endif
             ++since;
             if (small) n_small++;
             if (small || since >= pa.refresh_every) {
-                if (!refresh_all<kRot, kNl>(s, w, a, lane)) n_sing++;
+                if (!refresh_all<kRot, kNl, kBig>(s, w, a, lane)) n_sing++;
                 n_refresh++;
                 since = 0;
             }
@@ -1187,10 +1263,12 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
     }
 }
 
-template __global__ void phase_fp64<false, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
-template __global__ void phase_fp64<true, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
-template __global__ void phase_fp64<false, true>(const DevSys* __restrict__ sys, PhaseArgs pa);
-template __global__ void phase_fp64<true, true>(const DevSys* __restrict__ sys, PhaseArgs pa);
+template __global__ void phase_fp64<false, false, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
+template __global__ void phase_fp64<true, false, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
+template __global__ void phase_fp64<false, true, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
+template __global__ void phase_fp64<true, true, false>(const DevSys* __restrict__ sys, PhaseArgs pa);
+template __global__ void phase_fp64<false, false, true>(const DevSys* __restrict__ sys, PhaseArgs pa);
+template __global__ void phase_fp64<true, false, true>(const DevSys* __restrict__ sys, PhaseArgs pa);
 
 // ---------------------------------------------------------------------------
 // reconfiguration (Sec. II.A): one workgroup computes max log-weight, the

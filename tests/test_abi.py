@@ -58,13 +58,19 @@ def test_workspace_bytes_and_validation():
 
 
 def test_layout_rejects_oversized_system():
+    """FP64: the 128-electron system fits the large-system layout (coefficient
+    block and Slater rows in global memory); 256 electrons (128 per spin:
+    256 KB of inverses alone) fit neither FP64 layout nor the mixed one."""
     L = B.load()
     d = I.c3_system(n_walkers=2)
     keep = []
     s = B._sys_struct(d, keep)
-    prm = B.params_for(d)
-    assert L.lrdmc_workspace_bytes(ct.byref(s), 1, ct.byref(prm)) == 0
-    assert b"too large" in L.lrdmc_last_error()
+    assert L.lrdmc_workspace_bytes(ct.byref(s), 1, ct.byref(B.params_for(d))) > 0
+    big = I.molecule_system(64, 0, 0, 4, 2, 2, 0.15, 25.0, I.BASE_SEED + 50)
+    s = B._sys_struct(big, keep)
+    for prec in ("fp64", "fp32"):
+        assert L.lrdmc_workspace_bytes(ct.byref(s), 1, ct.byref(B.params_for(big, precision=prec))) == 0
+        assert b"too large" in L.lrdmc_last_error()
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])

@@ -1,6 +1,7 @@
-"""FP64 phase kernel at the largest system its LDS-resident layout holds: the
+"""FP64 phase kernel at the largest system its LDS-resident layout holds, the
 32-electron molecule of the uneven set (16 atoms, 160 basis functions, 16
-orbitals per spin), against the FP64 oracle (Alg. 1 and 2; App. D).
+orbitals per spin), and at 128 electrons in its large-system layout, against
+the FP64 oracle (Alg. 1 and 2; App. D).
 
 At this size the kernel takes its general paths, which the 16-electron tests
 do not reach: two column tiles of the orbital product, the Sherman-Morrison
@@ -122,4 +123,30 @@ def test_unequal_spins(which, n_dn, scheme):
     res = compare_phase(d2, prm, scheme, 0, e0, pos0, np.zeros(nw), g, np.arange(nw))
     say({k: v for k, v in res.items() if k != "oracle"})
     assert_phase_ok(res)
+    h.close()
+
+
+@pytest.mark.parametrize("scheme", ["lb", "conv"])
+def test_128e_large_system_layout(scheme):
+    """The 128-electron, 640-function system in FP64: its walker does not fit
+    the LDS-resident layout, so the kernel reads the coefficient block and the
+    Slater rows from global memory and splits the refresh's augmented matrix
+    over the basis block and the inverse block (one walker per CU).  Past the
+    128-move refresh in the load-balanced phase; the conventional phase at
+    tau = 0.01 (about 100 moves)."""
+    nw = 6
+    d = I.c3_system(n_walkers=nw)
+    say("case 128 electrons FP64 (large-system layout)", scheme, nw, "walkers")
+    kw = dict(tau=0.01) if scheme == "conv" else dict(n_proj=140)
+    h, d2, prm = make_handle(d, scheme, nw, **kw)
+    e0 = h.e0()
+    pos0 = d2["init_pos"][:nw].copy()
+    st = h.step()
+    g = h.walkers(trace=True)
+    res = compare_phase(d2, prm, scheme, 0, e0, pos0, np.zeros(nw), g, np.arange(nw))
+    say({k: v for k, v in res.items() if k != "oracle"}, "elapsed ms", st.elapsed_ms)
+    assert_phase_ok(res)
+    bs = h.branch()
+    after = h.walkers()
+    assert np.array_equal(after["pos"], g["pos"][after["sel"]])
     h.close()
