@@ -167,10 +167,14 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
                     + align_up(8)                   // distinct counter
                     + (p.trace_cap > 0 ? align_up(nw * (size_t)p.trace_cap * 4) : 0);
     if (L.kind == kKindLds) {
-        // the LDS-resident layout; a system that does not fit it (without a
-        // pseudopotential) takes the large-system layout: coefficient block and
-        // Slater rows in global memory, the basis block sized for the refresh's
-        // n x n half, the pair-term scratch in the basis block
+        // the LDS-resident layout, or (without a pseudopotential) the
+        // large-system layout: coefficient block and Slater rows in global
+        // memory, the basis block sized for the refresh's n x n half, the
+        // pair-term scratch in the basis block.  The layout that puts more
+        // walkers on a CU wins (the kernel's 256 registers allow at most 8);
+        // on a tie the LDS-resident one, whose coefficient reads are faster.
+        Layout keep{};
+        int keep_w = -1;
         for (int pass = 0; pass < 2; ++pass) {
             const bool big = pass == 1;
             int o = 0;
@@ -202,8 +206,12 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
             L.o_nlin = nl ? take(N) : 0;
             L.lds_doubles = o;
             L.lds_bytes = (size_t)o * 8;
-            if (nl || L.lds_bytes <= (size_t)kMaxLdsBytes) break;
+            const int wcu = L.lds_bytes > (size_t)kMaxLdsBytes ? 0
+                            : (int)std::min<size_t>(8, (size_t)kMaxLdsBytes / L.lds_bytes);
+            if (wcu > keep_w) { keep = L; keep_w = wcu; }
+            if (nl) break;
         }
+        L = keep;
         L.s_Phi = 0;
         L.s_dPhi = PT * ns;
         L.s_Arow = L.big ? (int)(align_up((size_t)(PT * ns + 4 * N * ns) * 8) / 8) : 0;

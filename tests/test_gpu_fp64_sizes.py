@@ -1,7 +1,8 @@
-"""FP64 phase kernel at the largest system its LDS-resident layout holds, the
-32-electron molecule of the uneven set (16 atoms, 160 basis functions, 16
-orbitals per spin), and at 128 electrons in its large-system layout, against
-the FP64 oracle (Alg. 1 and 2; App. D).
+"""FP64 phase kernel beyond 16 electrons, against the FP64 oracle (Alg. 1 and
+2; App. D): the 32-electron molecule of the uneven set (16 atoms, 160 basis
+functions, 16 orbitals per spin; it runs in the large-system layout, which
+puts five walkers on a CU against three for the LDS-resident one) and the
+128-electron system (which only the large-system layout holds).
 
 At this size the kernel takes its general paths, which the 16-electron tests
 do not reach: two column tiles of the orbital product, the Sherman-Morrison
