@@ -437,9 +437,9 @@ def main():
         extra["c2_batched_fp32"]["one_launch_128_threads_ms"] = r1["ms_per_cycle"]
         extra["c2_batched_fp32"]["separate_handles_ms"] = sep
         extra["c2_batched_fp32"]["tuned_vs_one_launch"] = r1["ms_per_cycle"] / r["ms_per_cycle"]
-        # mixed vs FP64 on one system that both layouts hold: the 32-electron
-        # molecule of the uneven set (16 orbitals per spin, 160 basis
-        # functions), 4096 walkers, N_proj = 300
+        # mixed vs FP64 on the 32-electron molecule of the uneven set (16
+        # orbitals per spin, 160 basis functions), 4096 walkers, N_proj = 300;
+        # the FP64 kernel holds five such walkers per CU
         d32 = dict(I.c2_systems()[1])
         row = dict(workload="32 electrons (16+16), 16 atoms, 160 basis functions, 4096 walkers, "
                             "a=0.2, N_proj=300")
