@@ -51,8 +51,10 @@ struct DevSys {
     // spill layout (offsets in doubles inside a walker's spill block)
     int s_Phi, s_dPhi;
     // systems too large for the LDS-resident layout (the large-system kernel):
-    // the Slater rows [N][ns] in the spill block at s_Arow (0 otherwise)
+    // the Slater rows [N][ns] in the spill block at s_Arow (0 otherwise), and
+    // the basis functions per chunk of the orbital product (all, or 64)
     int s_Arow;
+    int bchunk;
     // non-local pseudopotential (App. D non-local elements, determinant
     // locality approximation): term t adds ecp_coef r^ecp_pow exp(-ecp_exp r^2)
     // to channel ecp_l of atom ecp_atom, inside radius ecp_rcut of that atom.

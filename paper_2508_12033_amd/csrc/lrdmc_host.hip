@@ -124,6 +124,7 @@ struct Layout {
     int o_pos, o_R, o_Rdet, o_dJ, o_Arow, o_AinvT, o_Jg, o_Jl, o_nue, o_nua, o_dje, o_scal, o_B,
         o_rows, o_tmp, o_C, o_nuc, o_jas, o_gd, o_ev, lds_doubles;
     bool big;                // large-system layout: coefficient block and Slater rows in global memory
+    int bchunk;              // large-system layout: basis functions per chunk of the orbital product
     int s_Phi, s_dPhi, s_Arow;
     long spill_stride;
     // mixed kernel: LDS byte offsets, walker block (floats)
@@ -169,14 +170,17 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
     if (L.kind == kKindLds) {
         // the LDS-resident layout, or (without a pseudopotential) the
         // large-system layout: coefficient block and Slater rows in global
-        // memory, the basis block sized for the refresh's n x n half, the
+        // memory, the basis block sized for the refresh's n x n half and for
+        // one chunk of the orbital product (all functions, or 64), the
         // pair-term scratch in the basis block.  The layout that puts more
         // walkers on a CU wins (the kernel's 256 registers allow at most 8);
-        // on a tie the LDS-resident one, whose coefficient reads are faster.
+        // on a tie the earlier one: LDS-resident (faster coefficient reads),
+        // then the large-system layout in one chunk (less overhead).
         Layout keep{};
         int keep_w = -1;
-        for (int pass = 0; pass < 2; ++pass) {
-            const bool big = pass == 1;
+        for (int pass = 0; pass < 3; ++pass) {
+            const bool big = pass > 0;
+            L.bchunk = pass == 2 ? std::min(Nb, 64) : Nb;
             int o = 0;
             auto take = [&](int n) { int r = o; o += (n + 1) / 2 * 2; return r; };
             L.big = big;
@@ -192,7 +196,9 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
             L.o_nua = take(N);
             L.o_dje = big ? 0 : take(N);
             L.o_scal = take(kScVee + 1);
-            L.ldb = Nb + ((20 - Nb % 16) % 16);
+            // basis block: one chunk of the orbital product
+            const int nbb = L.bchunk;
+            L.ldb = nbb + ((20 - nbb % 16) % 16);
             L.o_B = take(std::max(std::max(11 * L.ldb, (big ? 1 : 2) * ns * ns), 7 * N));
             if (big) L.o_dje = L.o_B;
             L.o_rows = take(11 * ns);
@@ -1064,7 +1070,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             d.ldb = L.ldb; d.o_B = L.o_B; d.o_rows = L.o_rows; d.o_tmp = L.o_tmp; d.o_C = L.o_C;
             d.bK = bK; d.o_nuc = L.o_nuc; d.o_jas = L.o_jas; d.o_gd = L.o_gd; d.o_ev = L.o_ev;
             d.lds_doubles = L.lds_doubles;
-            d.s_Phi = L.s_Phi; d.s_dPhi = L.s_dPhi; d.s_Arow = L.s_Arow;
+            d.s_Phi = L.s_Phi; d.s_dPhi = L.s_dPhi; d.s_Arow = L.s_Arow; d.bchunk = L.bchunk;
             d.PT = L.PT; d.necp = r.nl ? s.n_ecp : 0;
             d.ecp_atom = e_atom; d.ecp_l = e_l; d.ecp_pow = e_pow;
             d.ecp_coef = e_coef; d.ecp_exp = e_exp; d.ecp_rcut = e_rcut; d.o_Vnl = L.o_Vnl;

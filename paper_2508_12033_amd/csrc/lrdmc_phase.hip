@@ -229,18 +229,20 @@ __device__ __forceinline__ void lattice_point(const double* r, int q, double a, 
 // functions take the seven points directly.  Orbitals: the 11 x Nb basis
 // block times the Nb x n coefficient block on FP64 MFMA (16x16x4 tiles; rows
 // 11..15 and columns >= n are padding).
-template <bool kRot>
-__device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, double a, int lane)
+// kChunk: only the functions m0 <= mu < m1, at columns mu - m0 of the block.
+template <bool kRot, bool kChunk = false>
+__device__ void basis_rows(const DevSys& s, const Walker& w, const double* r, double a, int lane,
+                           int m0 = 0, int m1 = 0)
 {
-    const int Nb = s.Nb, ldb = s.ldb;
+    const int Nb = kChunk ? m1 : s.Nb, ldb = s.ldb;
     const double* st = lds + w.ev;      // lattice step vectors a e_d
-    for (int mu = lane; mu < Nb; mu += kWave) {
+    for (int mu = (kChunk ? m0 : 0) + lane; mu < Nb; mu += kWave) {
         const double4_t c = gld((const double4_t*)(s.btab + 4 * mu));
         const int t = gld(s.btype + mu);
         const double al = c[3];
         const double d[3] = {r[0] - c[0], r[1] - c[1], r[2] - c[2]};
         const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        double* Bm = lds + w.B + mu;
+        double* Bm = lds + w.B + (kChunk ? mu - m0 : mu);
         double v, g[3], l;
         if (t == 4) {
             for (int q = 1; q < 7; ++q) {
@@ -330,11 +332,14 @@ __device__ void nl_basis_rows(const DevSys& s, const Walker& w, int nlI, double 
 // kGlobalC: the coefficient block is read from global memory (L1/L2-resident,
 // shared by every walker) instead of the walker's LDS copy, each k-step's
 // operand fetched one step ahead.
-template <bool kQuad = false, bool kGlobalC = false>
-__device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
+// kChunk: the nc functions from m0 on (block columns 0..nc-1), added to the
+// rows unless first.
+template <bool kQuad = false, bool kGlobalC = false, bool kChunk = false>
+__device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane, int m0 = 0, int nc = 0,
+                             bool first = true)
 {
     wave_sync();
-    const int Nb = s.Nb, ldb = s.ldb;
+    const int Nb = kChunk ? nc : s.Nb, ldb = s.ldb;
     const int n = nspin(s, spin_of(s, j));
     const int lk = lane >> 4, lb = (lane >> 2) & 3, l4 = lane & 3;
     const int par = lb & 1, cb = lb >> 1;
@@ -345,7 +350,7 @@ __device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
         double bnext = 0.0;
         if constexpr (kGlobalC) {
             const int mu = 4 * par + lk;
-            bnext = (cok && mu < Nb) ? gld(s.C + mu * s.Norb + col) : 0.0;
+            bnext = (cok && mu < Nb) ? gld(s.C + (kChunk ? m0 + mu : mu) * s.Norb + col) : 0.0;
         }
         for (int k0 = 0; k0 < Nb; k0 += 8) {
             const int mu = k0 + 4 * par + lk;
@@ -354,7 +359,7 @@ __device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
             if constexpr (kGlobalC) {
                 bv = bnext;
                 const int mn = mu + 8;
-                bnext = (cok && mn < Nb) ? gld(s.C + mn * s.Norb + col) : 0.0;
+                bnext = (cok && mn < Nb) ? gld(s.C + (kChunk ? m0 + mn : mn) * s.Norb + col) : 0.0;
             } else {
                 bv = (cok && kok) ? lds[w.C + mu * s.ns + col] : 0.0;
             }
@@ -371,6 +376,13 @@ __device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
         if constexpr (!kQuad) acc2 += dpp_mov<0x104, 0xf>(acc2);
         const int c = 4 * (ct0 + cb) + l4, i = lane >> 4;
         if (par == 0 && c < n) {
+            if constexpr (kChunk) {
+                if (!first) {
+                    acc0 += lds[w.rows + i * s.ns + c];
+                    acc1 += lds[w.rows + (4 + i) * s.ns + c];
+                    if (i < 3) acc2 += lds[w.rows + (8 + i) * s.ns + c];
+                }
+            }
             lds[w.rows + i * s.ns + c] = acc0;
             if (!kQuad || i < 2) lds[w.rows + (4 + i) * s.ns + c] = acc1;
             if constexpr (!kQuad)
@@ -380,12 +392,22 @@ __device__ void orbital_rows(const DevSys& s, const Walker& w, int j, int lane)
     wave_sync();
 }
 
+// kBig: in chunks of s.bchunk basis functions (the basis block holds one
+// chunk; the orbital rows accumulate over the chunks).
 template <bool kRot, bool kNl = false, bool kBig = false>
 __device__ void electron_rows(const DevSys& s, const Walker& w, int j, const double* r, double a,
                               int lane)
 {
-    basis_rows<kRot>(s, w, r, a, lane);
-    orbital_rows<false, kNl || kBig>(s, w, j, lane);
+    if constexpr (kBig) {
+        for (int m0 = 0; m0 < s.Nb; m0 += s.bchunk) {
+            const int m1 = min(m0 + s.bchunk, s.Nb);
+            basis_rows<kRot, true>(s, w, r, a, lane, m0, m1);
+            orbital_rows<false, true, true>(s, w, j, lane, m0, m1 - m0, m0 == 0);
+        }
+    } else {
+        basis_rows<kRot>(s, w, r, a, lane);
+        orbital_rows<false, kNl>(s, w, j, lane);
+    }
 }
 
 // Store electron j's rows: Slater row, the 6 neighbour rows, derivatives.
@@ -818,10 +840,12 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     }
 
     // The accepted orbital row u is fetched first and the basis values at
-    // the new position are computed while it is in flight.
+    // the new position are computed while it is in flight (in the
+    // large-system layout they follow the Sherman-Morrison update, chunk by
+    // chunk with the orbital rows).
     double u0 = 0.0;
     if (lane < n) u0 = gld(w.Phi + p * s.ns + lane);
-    basis_rows<kRot>(s, w, rnew, a, lane);
+    if constexpr (!kBig) basis_rows<kRot>(s, w, rnew, a, lane);
     LRDMC_T(3);
 
     // Sherman-Morrison on AinvT of spin sp with the accepted orbital row u
@@ -861,7 +885,8 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
 
     LRDMC_T(2);
     // new orbital rows of electron i at rnew
-    orbital_rows<false, kNl || kBig>(s, w, i, lane);
+    if constexpr (kBig) electron_rows<kRot, false, true>(s, w, i, rnew, a, lane);
+    else orbital_rows<false, kNl>(s, w, i, lane);
     store_rows<kNl, kBig>(s, w, i, lane, false);
     if constexpr (kNl) nl_rows(s, w, i, rnew, lane);
     LRDMC_T(4);
