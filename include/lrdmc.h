@@ -67,11 +67,14 @@ extern "C" {
 #define LRDMC_SCHEME_LB    0   /* load-balanced, fixed N_proj (Algorithm 2) */
 #define LRDMC_SCHEME_CONV  1   /* conventional continuous time (Algorithm 1) */
 
-#define LRDMC_FP64         0   /* every step in FP64; walker state in LDS
-                                  (a walker too large for that keeps its
-                                  coefficient block and Slater rows in global
-                                  memory, one walker per CU; beyond that
-                                  lrdmc_workspace_bytes returns 0) */
+#define LRDMC_FP64         0   /* every step in FP64, one wavefront per
+                                  walker; per system the layout that puts
+                                  more walkers on a CU: all walker state in
+                                  LDS, or the coefficient block and Slater
+                                  rows in global memory (the only choice
+                                  from 64 electrons on; 64 electrons per spin
+                                  at most, beyond that lrdmc_workspace_bytes
+                                  returns 0) */
 #define LRDMC_MIXED_FP32   1   /* mixed precision (an extension: the paper
                                   computes in FP64): orbital rows,
                                   Sherman-Morrison updates, ratios and Jastrow
