@@ -72,10 +72,9 @@ extern "C" {
                                   more walkers on a CU: all walker state in
                                   LDS, or the coefficient block and Slater
                                   rows in global memory (the only choice
-                                  from 64 electrons on); a system whose state
-                                  exceeds one workgroup's LDS in both (about
-                                  70 electrons per spin) makes
-                                  lrdmc_workspace_bytes return 0 */
+                                  from 64 electrons on); at most 64
+                                  electrons per spin, beyond that
+                                  lrdmc_workspace_bytes returns 0 */
 #define LRDMC_MIXED_FP32   1   /* mixed precision (an extension: the paper
                                   computes in FP64): orbital rows,
                                   Sherman-Morrison updates, ratios and Jastrow

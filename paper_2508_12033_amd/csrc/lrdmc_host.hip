@@ -358,8 +358,10 @@ std::string validate(const lrdmc_system* sys, int n_sys, const lrdmc_params* prm
                         return "pseudopotential cutoff spheres overlap";
                 }
         }
-        if (prm->precision != LRDMC_FP64 && std::max(s.n_up, s.n_dn) > 64)
-            return "mixed-precision layout: at most 64 electrons per spin (too large)";
+        if (std::max(s.n_up, s.n_dn) > 64)
+            return prm->precision != LRDMC_FP64
+                       ? "mixed-precision layout: at most 64 electrons per spin (too large)"
+                       : "FP64 layouts: at most 64 electrons per spin (too large)";
         const Layout L = make_layout(s, *prm);
         if (L.lds_bytes > (size_t)kMaxLdsBytes)
             return L.kind == kKindLds ? "system too large for the FP64 walker layouts "
