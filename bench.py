@@ -253,7 +253,7 @@ def main():
                     help="headline only (no mixed, batched or adjoint lines)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--profile-workload",
-                    choices=["c3_bf16", "c3_fp32", "c1_fp32", "c2_fp32", "ce_fp64"],
+                    choices=["c3_bf16", "c3_fp32", "c3_fp64", "c1_fp32", "c2_fp32", "ce_fp64"],
                     help="run only this workload (ce: the 16-electron system with the non-local "
                          "pseudopotential) for --steps cycles (for profilers) and print its line")
     args = ap.parse_args()
