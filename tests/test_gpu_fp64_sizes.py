@@ -1,8 +1,10 @@
 """FP64 phase kernel beyond 16 electrons, against the FP64 oracle (Alg. 1 and
 2; App. D): the 32-electron molecule of the uneven set (16 atoms, 160 basis
 functions, 16 orbitals per spin; it runs in the large-system layout, which
-puts five walkers on a CU against three for the LDS-resident one) and the
-128-electron system (which only the large-system layout holds).
+puts seven walkers on a CU against three for the LDS-resident one, with the
+orbital product in chunks of 64 basis functions), the 64-electron molecule
+(chunks of 64 over 320 functions) and the 128-electron system (the
+large-system layout in one chunk).
 
 At this size the kernel takes its general paths, which the 16-electron tests
 do not reach: two column tiles of the orbital product, the Sherman-Morrison
@@ -150,4 +152,24 @@ def test_128e_large_system_layout(scheme):
     bs = h.branch()
     after = h.walkers()
     assert np.array_equal(after["pos"], g["pos"][after["sel"]])
+    h.close()
+
+
+def test_64e_chunked_layout():
+    """The 64-electron molecule of the uneven set (32 atoms, 320 basis
+    functions, 32 orbitals per spin) in FP64: the large-system layout with the
+    orbital product in five chunks of 64 functions, three walkers per CU;
+    past the 128-move refresh."""
+    nw = 6
+    d = dict(I.c2_systems(n_walkers=(2, 2, nw))[2])
+    say("case 64 electrons FP64 (large-system layout in chunks)", nw, "walkers")
+    h, d2, prm = make_handle(d, "lb", nw, n_proj=140)
+    assert int(d2["n_elec"]) == 64 and int(d2["n_basis"]) == 320
+    e0 = h.e0()
+    pos0 = d2["init_pos"][:nw].copy()
+    h.step()
+    g = h.walkers(trace=True)
+    res = compare_phase(d2, prm, "lb", 0, e0, pos0, np.zeros(nw), g, np.arange(nw))
+    say({k: v for k, v in res.items() if k != "oracle"})
+    assert_phase_ok(res)
     h.close()
