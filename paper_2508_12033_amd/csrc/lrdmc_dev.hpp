@@ -55,6 +55,11 @@ struct DevSys {
     // the basis functions per chunk of the orbital product (all, or 64)
     int s_Arow;
     int bchunk;
+    // large-system layout with one spin's inverse in LDS (ainv1 = 1): both
+    // inverses [2][ns][ns] at s_AinvG and the refresh's left half [ns][ns] at
+    // s_GJ in the spill block; the moved spin's inverse is staged into LDS
+    int ainv1;
+    long s_AinvG, s_GJ;
     // non-local pseudopotential (App. D non-local elements, determinant
     // locality approximation): term t adds ecp_coef r^ecp_pow exp(-ecp_exp r^2)
     // to channel ecp_l of atom ecp_atom, inside radius ecp_rcut of that atom.
@@ -170,6 +175,6 @@ enum : int { kHistLogW = 0, kHistEbar = 1, kHistE0 = 2, kHistMaxLw = 3, kHistDis
 constexpr int kHistCap = 4096;
 
 // per-walker scalars stored at o_scal / l_scal: V_ee (slots 0..3 unused)
-enum : int { kScVee = 4, kScLen = 8 };
+enum : int { kScVee = 4, kScRes = 5, kScLen = 8 };
 
 }  // namespace lrdmc

@@ -125,6 +125,8 @@ struct Layout {
         o_rows, o_tmp, o_C, o_nuc, o_jas, o_gd, o_ev, lds_doubles;
     bool big;                // large-system layout: coefficient block and Slater rows in global memory
     int bchunk;              // large-system layout: basis functions per chunk of the orbital product
+    bool ainv1;              // large-system layout: one spin's inverse in LDS, both in global memory
+    long s_AinvG, s_GJ;
     int s_Phi, s_dPhi, s_Arow;
     long spill_stride;
     // mixed kernel: LDS byte offsets, walker block (floats)
@@ -175,12 +177,16 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         // pair-term scratch in the basis block.  The layout that puts more
         // walkers on a CU wins (the kernel's 256 registers allow at most 8);
         // on a tie the earlier one: LDS-resident (faster coefficient reads),
-        // then the large-system layout in one chunk (less overhead).
+        // then the large-system layout in one chunk (less overhead), in
+        // chunks, and in chunks with one spin's inverse in LDS (the moved
+        // spin's block staged from global memory, the refresh's left half in
+        // global memory).
         Layout keep{};
         int keep_w = -1;
-        for (int pass = 0; pass < 3; ++pass) {
+        for (int pass = 0; pass < 4; ++pass) {
             const bool big = pass > 0;
-            L.bchunk = pass == 2 ? std::min(Nb, 64) : Nb;
+            L.bchunk = pass >= 2 ? std::min(Nb, 64) : Nb;
+            L.ainv1 = pass == 3;
             int o = 0;
             auto take = [&](int n) { int r = o; o += (n + 1) / 2 * 2; return r; };
             L.big = big;
@@ -189,17 +195,17 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
             L.o_Rdet = take(PT);
             L.o_dJ = take(P);
             L.o_Arow = big ? 0 : take(N * ns);
-            L.o_AinvT = take(2 * ns * ns);
+            L.o_AinvT = take((L.ainv1 ? 1 : 2) * ns * ns);
             L.o_Jg = take(3 * N);
             L.o_Jl = take(N);
             L.o_nue = take(N);
             L.o_nua = take(N);
             L.o_dje = big ? 0 : take(N);
-            L.o_scal = take(kScVee + 1);
+            L.o_scal = take(kScRes + 1);
             // basis block: one chunk of the orbital product
             const int nbb = L.bchunk;
             L.ldb = nbb + ((20 - nbb % 16) % 16);
-            L.o_B = take(std::max(std::max(11 * L.ldb, (big ? 1 : 2) * ns * ns), 7 * N));
+            L.o_B = take(std::max(std::max(11 * L.ldb, L.ainv1 ? 0 : (big ? 1 : 2) * ns * ns), 7 * N));
             if (big) L.o_dje = L.o_B;
             L.o_rows = take(11 * ns);
             L.o_tmp = take(3 * ns + 16);
@@ -220,9 +226,16 @@ Layout make_layout(const lrdmc_system& s, const lrdmc_params& p)
         L = keep;
         L.s_Phi = 0;
         L.s_dPhi = PT * ns;
-        L.s_Arow = L.big ? (int)(align_up((size_t)(PT * ns + 4 * N * ns) * 8) / 8) : 0;
-        L.spill_stride = (long)((align_up((size_t)(PT * ns + 4 * N * ns) * 8) +
-                                 (L.big ? align_up((size_t)N * ns * 8) : 0)) / 8);
+        {
+            size_t sb = align_up((size_t)(PT * ns + 4 * N * ns) * 8);
+            L.s_Arow = L.big ? (int)(sb / 8) : 0;
+            if (L.big) sb += align_up((size_t)N * ns * 8);
+            L.s_AinvG = L.ainv1 ? (long)(sb / 8) : 0;
+            if (L.ainv1) sb += align_up((size_t)2 * ns * ns * 8);
+            L.s_GJ = L.ainv1 ? (long)(sb / 8) : 0;
+            if (L.ainv1) sb += align_up((size_t)ns * ns * 8);
+            L.spill_stride = (long)(sb / 8);
+        }
         L.b_state = common + align_up(nw * L.spill_stride * 8) + 2 * align_up(sizeof(DevSys));
     } else {
         L.nb32 = (Nb + 31) / 32 * 32;
@@ -1073,6 +1086,7 @@ int lrdmc_init_system(const lrdmc_system* sys, int n_sys, const lrdmc_params* pr
             d.bK = bK; d.o_nuc = L.o_nuc; d.o_jas = L.o_jas; d.o_gd = L.o_gd; d.o_ev = L.o_ev;
             d.lds_doubles = L.lds_doubles;
             d.s_Phi = L.s_Phi; d.s_dPhi = L.s_dPhi; d.s_Arow = L.s_Arow; d.bchunk = L.bchunk;
+            d.ainv1 = L.ainv1 ? 1 : 0; d.s_AinvG = L.s_AinvG; d.s_GJ = L.s_GJ;
             d.PT = L.PT; d.necp = r.nl ? s.n_ecp : 0;
             d.ecp_atom = e_atom; d.ecp_l = e_l; d.ecp_pow = e_pow;
             d.ecp_coef = e_coef; d.ecp_exp = e_exp; d.ecp_rcut = e_rcut; d.o_Vnl = L.o_Vnl;

@@ -71,6 +71,8 @@ struct Walker {
     double* Phi;
     double* dPhi;
     double* ArowG;          // Slater rows in global memory (large-system kernel)
+    double* AinvG;          // both inverses in global memory (one-spin LDS residency)
+    double* GJg;            // the refresh's left half in global memory (same)
 };
 
 __device__ __forceinline__ Walker walker_view(const DevSys& s)
@@ -90,6 +92,8 @@ __device__ __forceinline__ Walker walker_view(const DevSys& s)
     w.Phi = base + s.s_Phi;
     w.dPhi = base + s.s_dPhi;
     w.ArowG = base + s.s_Arow;
+    w.AinvG = base + s.s_AinvG;
+    w.GJg = base + s.s_GJ;
     return w;
 }
 
@@ -454,31 +458,32 @@ __device__ void nl_rows(const DevSys& s, const Walker& w, int j, const double* r
 
 // The same Gauss-Jordan elimination for the large-system kernel, whose basis
 // block holds n x n but not n x 2n values: the left half of [A^T | I] in the
-// basis block, the right half in the spin's inverse block itself, so that the
-// right half ends as AinvT.  The Slater rows are read from global memory.  On
-// a singular matrix the inverse block is left undefined (the phase reports
-// the singular refresh as an error).
+// basis block (or in global memory), the right half in the spin's inverse
+// block itself, so that the right half ends as AinvT.  The Slater rows are
+// read from global memory.  On a singular matrix the inverse block is left
+// undefined (the phase reports the singular refresh as an error).
 __device__ bool refresh_inverse_split(const DevSys& s, const Walker& w, int sp, int lane)
 {
     const int n = nspin(s, sp), off = sp ? s.Nup : 0, n2 = 2 * n, nn = n * n2;
     if (!n) return true;
-    const int Lh = w.B;                                   // [n][n] left half
-    const int Ai = w.AinvT + sp * s.ns * s.ns;            // [n][ns] right half
-    auto at = [&](int r, int c) -> double& {
-        return c < n ? lds[Lh + r * n + c] : lds[Ai + r * s.ns + c - n];
-    };
+    // left half [n][n]: the basis block, or global memory with one-spin
+    // residency; right half [n][ns]: the inverse block of spin sp in LDS
+    // (the resident block itself with one-spin residency)
+    double* Lh = s.ainv1 ? w.GJg : lds + w.B;
+    double* Rh = lds + w.AinvT + (s.ainv1 ? 0 : sp * s.ns * s.ns);
+    auto at = [&](int r, int c) -> double& { return c < n ? Lh[r * n + c] : Rh[r * s.ns + c - n]; };
     for (int idx = lane; idx < nn; idx += kWave) {
         const int r = idx / n2, c = idx - r * n2;
         at(r, c) = c < n ? gld(w.ArowG + (off + c) * s.ns + r) : (c - n == r ? 1.0 : 0.0);
     }
-    wave_sync();
+    block_visible();
     for (int j = 0; j < n; ++j) {
         // pivot: the largest |L[r][j]|, r >= j, the first such row on ties
         double best = -1.0;
         int bi = -1;
         for (int r0 = 0; r0 < n; r0 += kWave) {
             const int r = r0 + lane;
-            const double v = (r >= j && r < n) ? fabs(lds[Lh + r * n + j]) : -1.0;
+            const double v = (r >= j && r < n) ? fabs(Lh[r * n + j]) : -1.0;
             const double m = wave_max(v);
             if (m > best) {
                 best = m;
@@ -493,20 +498,48 @@ __device__ bool refresh_inverse_split(const DevSys& s, const Walker& w, int sp, 
                 at(j, c) = at(bi, c);
                 at(bi, c) = t;
             }
-            wave_sync();
+            block_visible();
         }
-        const double pv = lds[Lh + j * n + j];
-        wave_sync();
+        const double pv = Lh[j * n + j];
+        block_visible();
         for (int c = lane; c < n2; c += kWave) at(j, c) = at(j, c) / pv;
-        for (int r = lane; r < n; r += kWave) lds[w.tmp + r] = lds[Lh + r * n + j];
-        wave_sync();
+        for (int r = lane; r < n; r += kWave) lds[w.tmp + r] = Lh[r * n + j];
+        block_visible();
         for (int idx = lane; idx < nn; idx += kWave) {
             const int r = idx / n2, c = idx - r * n2;
             if (r != j) at(r, c) -= lds[w.tmp + r] * at(j, c);
         }
-        wave_sync();
+        block_visible();
     }
     return true;
+}
+
+// One-spin residency of the inverses (large-system layout): make spin sp's
+// inverse the LDS block, writing the other back to global memory.  load =
+// false when the block is about to be overwritten (the refresh).
+__device__ void ainv_resident(const DevSys& s, const Walker& w, int sp, int lane, bool load = true)
+{
+    if (!s.ainv1) return;    // both inverse blocks in LDS
+    const int res = (int)lds[w.scal + kScRes];
+    if (res == sp) return;
+    const int blk = s.ns * s.ns;
+    for (int i = lane; i < blk; i += kWave) {
+        const double v = lds[w.AinvT + i];
+        gst(w.AinvG + (long)res * blk + i, v);
+        if (load) lds[w.AinvT + i] = gld(w.AinvG + (long)sp * blk + i);
+    }
+    block_visible();
+    if (lane == 0) lds[w.scal + kScRes] = (double)sp;
+    wave_sync();
+}
+
+// The walker view whose inverse block of spin sp is the LDS block (offset
+// shifted so that AinvT + sp ns^2 lands on it) under one-spin residency.
+__device__ __forceinline__ Walker ainv_view(const DevSys& s, const Walker& w, int sp)
+{
+    Walker v = w;
+    if (s.ainv1) v.AinvT = w.AinvT - sp * s.ns * s.ns;
+    return v;
 }
 
 // FP64 Gauss-Jordan inverse with partial pivoting of the transposed Slater
@@ -698,7 +731,11 @@ __device__ bool refresh_all(const DevSys& s, const Walker& w, double a, int lane
 {
     bool ok;
     if constexpr (kBig) {
+        // with one-spin residency each spin's block is made resident first
+        // (not loaded: the elimination overwrites it); spin 1 ends resident
+        if (s.ainv1) ainv_resident(s, w, 0, lane, false);
         ok = refresh_inverse_split(s, w, 0, lane);
+        if (s.ainv1) ainv_resident(s, w, 1, lane, false);
         ok = refresh_inverse_split(s, w, 1, lane) && ok;
     } else {
         ok = refresh_inverse(s, w, 0, lane);
@@ -707,6 +744,17 @@ __device__ bool refresh_all(const DevSys& s, const Walker& w, double a, int lane
     const double vee = jastrow_all<kRot>(s, w, a, lane);
     if (lane == 0) lds[w.scal + kScVee] = vee;
     wave_sync();
+    if constexpr (kBig) {
+        if (s.ainv1) {
+            for (int sp = 1; sp >= 0; --sp) {
+                ainv_resident(s, w, sp, lane);
+                const Walker v = ainv_view(s, w, sp);
+                recompute_ratios<kNl>(s, v, sp, lane, a);
+                recompute_gd(s, v, sp, lane);
+            }
+            return ok;
+        }
+    }
     recompute_ratios<kNl>(s, w, -1, lane, a);
     recompute_gd(s, w, -1, lane);
     return ok;
@@ -849,7 +897,8 @@ __device__ bool apply_move(const DevSys& s, const Walker& w, double a, int p, in
     LRDMC_T(3);
 
     // Sherman-Morrison on AinvT of spin sp with the accepted orbital row u
-    const int Ai = w.AinvT + sp * s.ns * s.ns;
+    if constexpr (kBig) ainv_resident(s, w, sp, lane);
+    const int Ai = w.AinvT + ((kBig && s.ainv1) ? 0 : sp * s.ns * s.ns);
     const int u = w.tmp, rowc = w.tmp + s.ns, beta = w.tmp + 2 * s.ns;
     for (int k = lane; k < n; k += kWave) {
         lds[u + k] = k < kWave ? u0 : gld(w.Phi + p * s.ns + k);
@@ -1165,6 +1214,7 @@ void phase_fp64(const DevSys* __restrict__ sys, PhaseArgs pa)
             lattice_steps(pa.seed, s.sysid, (uint64_t)wid, (uint64_t)jb, pa.a, st, kNl ? uv : nullptr);
         else lattice_steps_fixed(pa.a, st, kNl ? uv : nullptr);
         for (int q = 0; q < 9; ++q) lds[w.ev + q] = st[q];
+        if constexpr (kBig) lds[w.scal + kScRes] = 0.0;   // spin 0's inverse block resident
         if constexpr (kNl)
             for (int q = 0; q < 9; ++q) lds[w.ev + 9 + q] = uv[q];
     }
