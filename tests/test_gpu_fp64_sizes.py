@@ -1,10 +1,11 @@
 """FP64 phase kernel beyond 16 electrons, against the FP64 oracle (Alg. 1 and
 2; App. D): the 32-electron molecule of the uneven set (16 atoms, 160 basis
 functions, 16 orbitals per spin; it runs in the large-system layout, which
-puts seven walkers on a CU against three for the LDS-resident one, with the
-orbital product in chunks of 64 basis functions), the 64-electron molecule
-(chunks of 64 over 320 functions) and the 128-electron system (the
-large-system layout in one chunk).
+puts eight walkers on a CU against three for the LDS-resident one: orbital
+product in chunks of 64 basis functions, one spin's inverse in LDS), the
+64-electron molecule and the 128-electron system (the same layout, four and
+two walkers per CU); with unequal spins the 32-electron system takes the
+chunked layout with both inverses in LDS.
 
 At this size the kernel takes its general paths, which the 16-electron tests
 do not reach: two column tiles of the orbital product, the Sherman-Morrison
@@ -133,10 +134,10 @@ def test_unequal_spins(which, n_dn, scheme):
 def test_128e_large_system_layout(scheme):
     """The 128-electron, 640-function system in FP64: its walker does not fit
     the LDS-resident layout, so the kernel reads the coefficient block and the
-    Slater rows from global memory and splits the refresh's augmented matrix
-    over the basis block and the inverse block (one walker per CU).  Past the
+    Slater rows from global memory, keeps one spin's inverse in LDS and the
+    refresh's left half in global memory (two walkers per CU).  Past the
     128-move refresh in the load-balanced phase; the conventional phase at
-    tau = 0.01 (about 100 moves)."""
+    tau = 0.01 (about 170 moves)."""
     nw = 6
     d = I.c3_system(n_walkers=nw)
     say("case 128 electrons FP64 (large-system layout)", scheme, nw, "walkers")
@@ -158,8 +159,8 @@ def test_128e_large_system_layout(scheme):
 def test_64e_chunked_layout():
     """The 64-electron molecule of the uneven set (32 atoms, 320 basis
     functions, 32 orbitals per spin) in FP64: the large-system layout with the
-    orbital product in five chunks of 64 functions, three walkers per CU;
-    past the 128-move refresh."""
+    orbital product in five chunks of 64 functions and one spin's inverse in
+    LDS, four walkers per CU; past the 128-move refresh."""
     nw = 6
     d = dict(I.c2_systems(n_walkers=(2, 2, nw))[2])
     say("case 64 electrons FP64 (large-system layout in chunks)", nw, "walkers")
