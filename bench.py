@@ -402,13 +402,13 @@ def main():
                 error=precision_summary(hx), roofline=mixed_roofline(c3, px, stx.elapsed_ms, tr))
             hx.close()
         # the same system in FP64 (the large-system layout of the FP64 kernel:
-        # one 64-lane walker per CU, coefficient block and Slater rows read
-        # from global memory), one timed branching
+        # two 64-lane walkers per CU, coefficient block, Slater rows and the
+        # inverse of the spin not moving in global memory), one timed branching
         hx, px, r = run_cycles(B, c3, "lb", 1, 0, precision="fp64")
         fp64_rate = r["proposals"] / r["seconds"]
         extra["c3_fp64"] = dict(
             workload="128 electrons (64+64), 32 atoms, 640 basis functions, 2048 walkers, "
-                     "a=0.15, N_proj=300, FP64 (large-system layout: one walker per CU)",
+                     "a=0.15, N_proj=300, FP64 (large-system layout: two walkers per CU)",
             proposals_per_s=fp64_rate, ms_per_branching=r["ms_per_cycle"])
         hx.close()
         for prec in ("bf16", "fp32"):
@@ -439,7 +439,7 @@ def main():
         extra["c2_batched_fp32"]["tuned_vs_one_launch"] = r1["ms_per_cycle"] / r["ms_per_cycle"]
         # mixed vs FP64 on the 32-electron molecule of the uneven set (16
         # orbitals per spin, 160 basis functions), 4096 walkers, N_proj = 300;
-        # the FP64 kernel holds five such walkers per CU
+        # the FP64 kernel holds eight such walkers per CU
         d32 = dict(I.c2_systems()[1])
         row = dict(workload="32 electrons (16+16), 16 atoms, 160 basis functions, 4096 walkers, "
                             "a=0.2, N_proj=300")

@@ -70,9 +70,11 @@ extern "C" {
 #define LRDMC_FP64         0   /* every step in FP64, one wavefront per
                                   walker; per system the layout that puts
                                   more walkers on a CU: all walker state in
-                                  LDS, or the coefficient block and Slater
-                                  rows in global memory (the only choice
-                                  from 64 electrons on); at most 64
+                                  LDS, or the coefficient block, Slater rows
+                                  and (if that fits more walkers) the inverse
+                                  of the spin not moving in global memory
+                                  (the only choice from 64 electrons on); at
+                                  most 64
                                   electrons per spin, beyond that
                                   lrdmc_workspace_bytes returns 0 */
 #define LRDMC_MIXED_FP32   1   /* mixed precision (an extension: the paper
